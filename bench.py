@@ -1,0 +1,186 @@
+"""Benchmark: FP64 Helmholtz action y = (lambda M + L) x on the mixed-element
+mesh (32^3 cells of the unit cube split by quadrant into 8192 hexes, 16384
+prisms, 49152 pyramids and 49152 tets; curved by the sine perturbation; P = 4,
+Q = 6; lambda = 1), one whole-mesh launch per step, inputs resident in HBM.
+
+Prints one JSON line.  value = elemental DOFs per second (GDOF/s) of the
+whole-mesh action; roofline = algorithmic HBM bytes of the launch (16 N_P + 56
+N_Q bytes per element: x, y and 7 FP64 geometric factors per point) over the
+launch's mean duration from HIP events on the launch stream, against the 8 TB/s
+HBM3E peak; cpu_baseline = the FP64 oracle (dense elemental matrices) on a
+bounded sample of the same mesh.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Helmholtz action GDOF/s per shape & P, % of HBM roofline; mixed-vs-FP64 speedup at stated err"
+SHAPES = ("hex", "prism", "pyr", "tet")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def bytes_per_elem(n_modes: int, n_points: int) -> int:
+    return 16 * n_modes + 56 * n_points
+
+
+def build_mesh_plan(torch, shp, W, ncell: int, P: int):
+    mesh = W.quadrant_mesh(ncell)
+    blocks = [(s, P, len(mesh[s]), "curved") for s in SHAPES]
+    plan = shp.Plan(blocks)
+    for b, s in enumerate(SHAPES):
+        xi, _ = shp.quadrature(s, P + 2)
+        jac = torch.from_numpy(W.jacobian(mesh[s], xi, curved=True)).cuda()
+        plan.set_geometry(b, jac)
+        del jac
+        log(f"  geometry {s}: {len(mesh[s])} elements")
+    return mesh, plan
+
+
+def time_launches(torch, fn, steps: int, warmup: int):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record()
+        fn()
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return wall, float(np.mean(ev)), float(np.median(ev))
+
+
+def cpu_baseline(mesh, P: int, budget_s: float = 15.0):
+    """The oracle's Helmholtz action (form H_e by explicit quadrature, then
+    y = H_e x) on a sample of elements drawn in mesh proportions."""
+    from oracle import shp_oracle as O
+    from paper_2604_04644_amd import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    rng = np.random.default_rng(5)
+    per = {s: max(1, len(mesh[s]) // 256) for s in SHAPES}
+    dof = 0
+    t_total = 0.0
+    for s in SHAPES:
+        idx = rng.choice(len(mesh[s]), size=per[s], replace=False)
+        sub = mesh[s].take(idx)
+        jac = W.jacobian(sub, O.reference_points(s, P + 2), curved=True)
+        x = W.coeffs(len(idx), O.num_modes(s, P), 11)
+        t0 = time.perf_counter()
+        O.apply_op("helmholtz", s, P, P + 2, jac, x, lam=1.0, chunk=64)
+        t_total += time.perf_counter() - t0
+        dof += len(idx) * O.num_modes(s, P)
+        if t_total > budget_s:
+            break
+    n = sum(per.values())
+    return {"value": dof / t_total / 1e9, "unit": "GDOF/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} elements (1/256 of each shape, random), P={P}, dense H_e formed by quadrature then "
+                      f"applied, {t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--ncell", type=int, default=32)
+    ap.add_argument("--P", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--per-shape", action="store_true", help="also time each shape's block launch")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU: the elemental action needs no exchange between GPUs, and multi-GPU "
+              "runs are not part of this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2604_04644_amd import shp, workloads as W
+    if not torch.cuda.is_available():
+        print("no HIP device visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    P = a.P
+    log(f"bench: mixed mesh ncell={a.ncell} P={P}")
+    mesh, plan = build_mesh_plan(torch, shp, W, a.ncell, P)
+    nc, npnt = plan.totals()
+    x = torch.from_numpy(np.concatenate([W.coeffs(len(mesh[s]), plan.n_modes[b], W.SEED_MIXED[s]).ravel()
+                                         for b, s in enumerate(SHAPES)])).cuda()
+    y = torch.empty_like(x)
+    fn = lambda: plan.apply(-1, "helmholtz", x, out=y, lam=1.0)
+    log(f"  timing {a.steps} steps after {a.warmup} warm-up")
+    wall, ev_mean_ms, ev_med_ms = time_launches(torch, fn, a.steps, a.warmup)
+    ms = wall / a.steps * 1e3
+    dof = nc
+    value = dof / (wall / a.steps) / 1e9
+    nbytes = sum(len(mesh[s]) * bytes_per_elem(plan.n_modes[b], plan.n_points[b]) for b, s in enumerate(SHAPES))
+    achieved = nbytes / (ev_mean_ms * 1e-3) / 1e9
+    log(f"  {ms:.3f} ms/step, launch {ev_mean_ms:.3f} ms (median {ev_med_ms:.3f}), {value:.2f} GDOF/s, "
+        f"{achieved:.0f} GB/s")
+    per_shape = None
+    if a.per_shape:
+        per_shape = {}
+        for b, s in enumerate(SHAPES):
+            co, _ = plan.offsets(b)
+            ne = len(mesh[s])
+            xb = x[co:co + ne * plan.n_modes[b]].view(ne, -1)
+            yb = torch.empty_like(xb)
+            _, m, _ = time_launches(torch, lambda: plan.apply(b, "helmholtz", xb, out=yb), 20, 3)
+            bb = ne * bytes_per_elem(plan.n_modes[b], plan.n_points[b])
+            per_shape[s] = {"GDOF/s": ne * plan.n_modes[b] / (m * 1e-3) / 1e9,
+                            "hbm_frac": bb / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms": m}
+            log(f"  {s}: {per_shape[s]}")
+    cpu = None
+    if not a.no_cpu:
+        log("  cpu baseline (oracle, bounded sample)")
+        cpu = cpu_baseline(mesh, P)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"mixed-element mesh {a.ncell}^3 cells (hex/prism/pyr/tet quadrants), curved, "
+                               f"P={P}, Q={P + 2}, FP64 Helmholtz action, lambda=1, one whole-mesh launch",
+                   "elements": int(sum(len(mesh[s]) for s in SHAPES)), "dof": int(dof),
+                   "elements_per_shape": {s: len(mesh[s]) for s in SHAPES}},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes": int(nbytes), "launch_ms": round(ev_mean_ms, 5)},
+        "cpu_baseline": cpu,
+        "mixed_vs_fp64": None,
+    }
+    if per_shape is not None:
+        out["per_shape"] = per_shape
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

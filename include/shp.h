@@ -1,0 +1,161 @@
+/*
+ * shp.h - C ABI of libshp, matrix-free elemental spectral/hp operators on one
+ * AMD MI355X (gfx950).
+ *
+ * The operators are those of the Helmholtz problem's elemental Galerkin system
+ * H^e u = f (Sec. 2.1): the backward transform u = B x, the inner product with
+ * the basis B^T W f, the inner product with the basis derivatives, the physical
+ * derivative, and the mass, Laplacian and Helmholtz actions y = (lambda M + L) x
+ * with M = B^T W B (Sec. 2.2, eq. mass) and L the weak Laplacian (Sec. 2.2,
+ * eq. Lap).  Elements are hexahedra, prisms, pyramids and tetrahedra with the
+ * collapsed-coordinate (Duffy) tensorial modal basis (Sec. 2.3).  A "block" is
+ * a batch of elements of one shape, order P, quadrature Q and mapping type,
+ * stored with a constant stride (Sec. 3.3, blocks; App. A.2 Field/Block).
+ *
+ * Conventions
+ * -----------
+ * - Device pointers point to HIP device memory owned by the caller.  Host
+ *   pointers are marked "host".  The library never frees caller memory.
+ * - stream is a hipStream_t passed as void*; NULL means the default stream.
+ *   Work is enqueued on it; calls return before the work completes unless
+ *   stated otherwise.
+ * - Layouts (Sec. App. A.2, default layout: points or modes fastest, then
+ *   elements, then components):
+ *     coefficients  [n_elem][N_P]      modes (p,q,r) lexicographic, r fastest
+ *     point values  [n_elem][N_Q]      N_Q = Q^3, point (i,j,k) at (i*Q+j)*Q+k
+ *     vector field  [3][n_elem][N_Q]   component slowest
+ *   A whole-mesh call (blk = -1) uses block-concatenated buffers: block b
+ *   starts at the element offset given by shp_block_offsets; vector fields are
+ *   [3][total points].
+ * - Mode sets (modified C0 basis; A_p, C_{k,r} built on Jacobi polynomials):
+ *     hex   A_p A_q A_r, 0<=p,q,r<=P
+ *     prism A_p A_q C_{p,r}, r<=P-p
+ *     pyr   A_p A_q C_{max(p,q),r}, r<=P-max(p,q)
+ *     tet   A_p C_{p,q} C_{p+q,r}, p+q+r<=P
+ *   with the collapsed-vertex modes prism (0,q,1), pyramid (0,0,1), tet (0,0,1)
+ *   and (0,1,r) independent of the collapsed coordinate(s).
+ * - Quadrature: Q points per direction; Gauss-Lobatto-Legendre in directions
+ *   that are not collapsed, Gauss-Jacobi(alpha,0) in a direction collapsed
+ *   alpha times (prism eta3: 1, pyramid eta3: 2, tet eta2: 1, eta3: 2).
+ *   This build supports 1 <= P <= 10 and Q = P + 2 (Sec. 2.1: at least P+2
+ *   points per direction).
+ *
+ * Errors: every call returns SHP_OK (0) or a negative code; no C++ exception
+ * crosses the ABI.  shp_last_error() returns a thread-local message describing
+ * the last failure of the calling thread.  Arguments are validated before any
+ * HIP call, so validation errors leave device state untouched.
+ */
+#ifndef SHP_H
+#define SHP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHP_OK 0
+#define SHP_ERR_INVALID_ARG (-1)   /* null pointer, out-of-range enum or index */
+#define SHP_ERR_UNSUPPORTED (-2)   /* P outside [1,10], Q != P+2, mixed P in one launch */
+#define SHP_ERR_BAD_GEOMETRY (-3)  /* det(d x/d xi) <= 0 or non-finite at some point */
+#define SHP_ERR_WORKSPACE (-4)     /* workspace missing, misaligned or too small */
+#define SHP_ERR_STATE (-5)         /* call out of order (e.g. apply before geometry) */
+#define SHP_ERR_DEVICE (-6)        /* a HIP runtime call failed (message included) */
+#define SHP_ERR_NOT_CONVERGED (-7) /* an iterative solve did not reach its tolerance */
+
+typedef enum { SHP_HEX = 0, SHP_PRISM = 1, SHP_PYR = 2, SHP_TET = 3 } shp_shape;
+typedef enum { SHP_AFFINE = 0, SHP_CURVED = 1 } shp_geom;
+typedef enum {
+  SHP_OP_BWDTRANS = 0,       /* [n][N_P] -> [n][N_Q]   u = B x                      */
+  SHP_OP_IPRODUCT = 1,       /* [n][N_Q] -> [n][N_P]   y = B^T W f                  */
+  SHP_OP_PHYSDERIV = 2,      /* [n][N_Q] -> [3][n][N_Q] d u/d x_i of the interpolant */
+  SHP_OP_IPRODUCT_DERIV = 3, /* [3][n][N_Q] -> [n][N_P] y = sum_i (d_i B)^T W f_i   */
+  SHP_OP_MASS = 4,           /* [n][N_P] -> [n][N_P]   y = M x                      */
+  SHP_OP_LAPLACIAN = 5,      /* [n][N_P] -> [n][N_P]   y = L x                      */
+  SHP_OP_HELMHOLTZ = 6       /* [n][N_P] -> [n][N_P]   y = (lambda M + L) x         */
+} shp_op;
+typedef enum {
+  SHP_AUTO = 0,        /* tuned choice if one is cached, else SHP_SUMFAC_COLL     */
+  SHP_SUMFAC = 1,      /* sum-factorisation, non-collocated derivatives (Alg. 5)  */
+  SHP_SUMFAC_COLL = 2  /* sum-factorisation, collocated derivatives (Alg. 6)      */
+} shp_strategy;
+
+typedef struct {
+  int shape;       /* shp_shape */
+  int P;           /* polynomial order, 1..10 */
+  int Q;           /* points per direction, P + 2 */
+  int64_t n_elem;  /* elements in the block, >= 0 */
+  int geom;        /* shp_geom: SHP_CURVED takes d x/d xi per point, SHP_AFFINE per element */
+} shp_block_desc;
+
+typedef struct shp_plan_s* shp_plan;
+
+/* Number of modes N_P of a shape at order P (Sec. 2.1, N_P; the mode sets above). */
+int shp_num_modes(int shape, int P, int* n_modes /* host out */);
+
+/* Number of quadrature points N_Q = Q^3 of a shape. */
+int shp_num_points(int shape, int Q, int* n_points /* host out */);
+
+/* The block's quadrature points in reference coordinates and their weights
+ * (Sec. 2.1 tensor quadrature; Sec. 2.3 collapse).  xi: host [3][Q^3], component
+ * slowest; w: host [Q^3] = product of the three 1D weights, may be NULL.
+ * The mesh's Jacobian d x/d xi is expected at exactly these points. */
+int shp_quadrature(int shape, int Q, double* xi /* host out */, double* w /* host out or NULL */);
+
+/* Create a plan for nblk blocks (host metadata only; copies blk). */
+int shp_plan_create(shp_plan* plan /* host out */, const shp_block_desc* blk /* host [nblk] */,
+                    int nblk);
+
+/* Device workspace the plan needs: reference tables, geometric factors and
+ * launch metadata.  The caller allocates it (256-byte aligned). */
+int shp_plan_workspace_bytes(shp_plan plan, size_t* bytes /* host out */);
+
+/* Attach a caller-owned workspace and upload the reference tables into it
+ * (enqueued on stream).  The workspace must stay allocated while the plan is
+ * used.  Re-binding invalidates the geometry of every block. */
+int shp_plan_bind_workspace(shp_plan plan, void* ws, size_t ws_bytes, void* stream);
+
+/* Geometric factors of block blk (Sec. 4 precomputed geometric factors; the
+ * chain rule of Sec. 2.1 and the collapse Jacobian of Sec. 2.3), computed in
+ * FP64 on the device from jac = d x_i/d xi_j:
+ *   SHP_CURVED: jac [n_elem][9][Q^3], component i*3+j, at shp_quadrature points;
+ *   SHP_AFFINE: jac [n_elem][9], constant per element.
+ * Synchronises stream to report SHP_ERR_BAD_GEOMETRY when det <= 0 or a value
+ * is not finite.  Not safe to call concurrently with applies of the plan. */
+int shp_plan_set_geometry(shp_plan plan, int blk, const double* jac /* device */, void* stream);
+
+/* Element offset of block blk in whole-mesh coefficient and point buffers:
+ * coefficients of block blk start at element coeff_off (in units of doubles:
+ * sum over earlier blocks of n_elem*N_P), points at phys_off (sum of n_elem*N_Q). */
+int shp_block_offsets(shp_plan plan, int blk, int64_t* coeff_off /* host out */,
+                      int64_t* phys_off /* host out */);
+
+/* Apply operator op to block blk, or to the whole mesh with blk = -1 (one
+ * launch over all blocks when they share P and Q; tiles of all blocks are
+ * ordered longest first).  in/out are FP64 device buffers in the layouts
+ * above; in and out must not overlap.  lambda is used by SHP_OP_HELMHOLTZ.
+ * Read-only on the workspace: applies on different streams may run
+ * concurrently. */
+int shp_apply(shp_plan plan, int blk, int op, int strategy, const double* in /* device */,
+              double* out /* device */, double lambda, void* stream);
+
+/* Fix the launch shape used for (blk, op, strategy): elements per work-group
+ * and threads per work-group (0, 0 restores the default).  Used by tuning. */
+int shp_set_tiling(shp_plan plan, int blk, int op, int strategy, int elems_per_wg, int threads);
+
+/* Current launch shape for (blk, op, strategy). */
+int shp_get_tiling(shp_plan plan, int blk, int op, int strategy, int* elems_per_wg /* host out */,
+                   int* threads /* host out */);
+
+/* Destroy a plan (host metadata only; the workspace stays the caller's). */
+int shp_plan_destroy(shp_plan plan);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* shp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHP_H */

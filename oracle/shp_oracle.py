@@ -439,11 +439,15 @@ class Element:
 
     def mass(self) -> np.ndarray:
         """M = B^T W B, [n_elem, N_P, N_P]."""
-        return np.einsum("qm,eq,qn->emn", self.B, self.jw, self.B)
+        return np.matmul(self.B.T[None, :, :], self.jw[:, :, None] * self.B[None, :, :])
 
     def laplacian(self) -> np.ndarray:
         """L[m,n] = sum_q jw sum_i (d phi_m/d x_i)(d phi_n/d x_i)."""
-        return np.einsum("eiqm,eq,eiqn->emn", self.dBx, self.jw, self.dBx)
+        L = np.zeros((self.n_elem, self.B.shape[1], self.B.shape[1]))
+        for i in range(3):
+            Bi = self.dBx[:, i]                                  # [ne, nq, np]
+            L += np.matmul(np.transpose(Bi, (0, 2, 1)), self.jw[:, :, None] * Bi)
+        return L
 
     def helmholtz(self, lam: float) -> np.ndarray:
         return lam * self.mass() + self.laplacian()

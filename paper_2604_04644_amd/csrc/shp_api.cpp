@@ -1,0 +1,466 @@
+// C ABI of libshp (declared in include/shp.h): plans, workspace layout,
+// validation, geometry setup and operator dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/shp.h"
+#include "shp_kernels.hpp"
+
+using namespace shp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int dev_fail(hipError_t e, const char* what) {
+  return fail(SHP_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Tiling {
+  int E = 0;
+  int NT = 0;
+};
+
+struct Block {
+  shp_block_desc d{};
+  int NP = 0, NQ = 0;
+  std::vector<double> tab;
+  std::vector<int> itab;
+  size_t off_tab = 0, off_itab = 0, off_fac = 0, off_dxi = 0;
+  long long coeff_off = 0, phys_off = 0;
+  bool geom_ok = false;
+  Tiling tiling[OPK_COUNT];
+};
+
+}  // namespace
+
+struct shp_plan_s {
+  std::vector<Block> blocks;
+  size_t ws_bytes = 0;
+  char* ws = nullptr;
+  size_t off_status = 0, off_bstat = 0, off_tiles = 0;
+  long long total_elem = 0, total_coeff = 0, total_phys = 0;
+  long long max_tiles = 0;  // tile slots reserved per operator
+  Tiling mixed[OPK_COUNT];
+  int mixed_ntiles[OPK_COUNT] = {};
+  bool mixed_dirty[OPK_COUNT] = {};
+  bool uniform_P = true;
+};
+
+namespace {
+
+bool valid_shape(int s) { return s >= SHP_HEX && s <= SHP_TET; }
+
+int opk_of(int op, int strategy, int* opk) {
+  if (strategy < SHP_AUTO || strategy > SHP_SUMFAC_COLL) return fail(SHP_ERR_INVALID_ARG, "bad strategy %d", strategy);
+  switch (op) {
+    case SHP_OP_BWDTRANS: *opk = OPK_BWD; return SHP_OK;
+    case SHP_OP_IPRODUCT: *opk = OPK_IPR; return SHP_OK;
+    case SHP_OP_PHYSDERIV: *opk = OPK_DERIV; return SHP_OK;
+    case SHP_OP_IPRODUCT_DERIV: *opk = OPK_IPRD; return SHP_OK;
+    case SHP_OP_MASS: *opk = OPK_MASS; return SHP_OK;
+    case SHP_OP_LAPLACIAN:
+    case SHP_OP_HELMHOLTZ:
+      if (strategy == SHP_SUMFAC)
+        return fail(SHP_ERR_UNSUPPORTED, "non-collocated Laplacian/Helmholtz is not built yet");
+      *opk = (op == SHP_OP_LAPLACIAN) ? OPK_LAP : OPK_HELM;
+      return SHP_OK;
+  }
+  return fail(SHP_ERR_INVALID_ARG, "bad operator %d", op);
+}
+
+bool in_is_modes(int opk) { return opk == OPK_BWD || opk == OPK_MASS || opk == OPK_LAP || opk == OPK_HELM || opk == OPK_HELM_NC; }
+bool out_is_modes(int opk) { return !(opk == OPK_BWD || opk == OPK_DERIV); }
+
+// Default launch shape: as many elements per work-group as fit a 64 KiB LDS
+// budget (at most 16), 256 threads.
+Tiling default_tiling(int sh, int P, int opk) {
+  Tiling t;
+  t.NT = 256;
+  int E = 1;
+  while (E < 16 && op_lds_bytes(sh, P, opk, E + 1) <= 64 * 1024) ++E;
+  t.E = E;
+  return t;
+}
+
+Tiling effective(const Tiling& set, int sh, int P, int opk) {
+  return (set.E > 0 && set.NT > 0) ? set : default_tiling(sh, P, opk);
+}
+
+int check_plan(shp_plan p) {
+  if (!p) return fail(SHP_ERR_INVALID_ARG, "null plan");
+  return SHP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* shp_last_error(void) { return g_err.c_str(); }
+
+int shp_num_modes(int shape, int P, int* n) {
+  if (!n) return fail(SHP_ERR_INVALID_ARG, "null output");
+  if (!valid_shape(shape)) return fail(SHP_ERR_INVALID_ARG, "bad shape %d", shape);
+  if (P < 1 || P > MAX_P) return fail(SHP_ERR_UNSUPPORTED, "P=%d outside [1,%d]", P, MAX_P);
+  *n = num_modes(shape, P);
+  return SHP_OK;
+}
+
+int shp_num_points(int shape, int Q, int* n) {
+  if (!n) return fail(SHP_ERR_INVALID_ARG, "null output");
+  if (!valid_shape(shape)) return fail(SHP_ERR_INVALID_ARG, "bad shape %d", shape);
+  if (Q < 3 || Q > MAX_P + 2) return fail(SHP_ERR_UNSUPPORTED, "Q=%d outside [3,%d]", Q, MAX_P + 2);
+  *n = Q * Q * Q;
+  return SHP_OK;
+}
+
+int shp_quadrature(int shape, int Q, double* xi, double* w) {
+  if (!xi) return fail(SHP_ERR_INVALID_ARG, "null xi");
+  if (!valid_shape(shape)) return fail(SHP_ERR_INVALID_ARG, "bad shape %d", shape);
+  if (Q < 3 || Q > MAX_P + 2) return fail(SHP_ERR_UNSUPPORTED, "Q=%d outside [3,%d]", Q, MAX_P + 2);
+  reference_points(shape, Q, xi, w);
+  return SHP_OK;
+}
+
+int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
+  if (!out || !blk) return fail(SHP_ERR_INVALID_ARG, "null argument");
+  if (nblk < 1 || nblk > 64) return fail(SHP_ERR_INVALID_ARG, "nblk=%d outside [1,64]", nblk);
+  for (int b = 0; b < nblk; ++b) {
+    const shp_block_desc& d = blk[b];
+    if (!valid_shape(d.shape)) return fail(SHP_ERR_INVALID_ARG, "block %d: bad shape %d", b, d.shape);
+    if (d.P < 1 || d.P > MAX_P) return fail(SHP_ERR_UNSUPPORTED, "block %d: P=%d outside [1,%d]", b, d.P, MAX_P);
+    if (d.Q != d.P + 2) return fail(SHP_ERR_UNSUPPORTED, "block %d: Q=%d, only Q=P+2 is built", b, d.Q);
+    if (d.n_elem < 0 || d.n_elem > (1LL << 31)) return fail(SHP_ERR_INVALID_ARG, "block %d: n_elem=%lld", b, (long long)d.n_elem);
+    if (d.geom != SHP_AFFINE && d.geom != SHP_CURVED) return fail(SHP_ERR_INVALID_ARG, "block %d: bad geom %d", b, d.geom);
+  }
+  shp_plan p = new (std::nothrow) shp_plan_s;
+  if (!p) return fail(SHP_ERR_INVALID_ARG, "out of host memory");
+  p->blocks.resize(nblk);
+  size_t off = 0;
+  p->off_status = off;
+  off = align_up(off + 256);
+  p->off_bstat = off;
+  off = align_up(off + sizeof(BlockStatic) * nblk);
+  long long cofs = 0, pofs = 0;
+  for (int b = 0; b < nblk; ++b) {
+    Block& B = p->blocks[b];
+    B.d = blk[b];
+    B.NP = num_modes(B.d.shape, B.d.P);
+    B.NQ = B.d.Q * B.d.Q * B.d.Q;
+    build_tables(B.d.shape, B.d.P, B.tab, B.itab);
+    B.coeff_off = cofs;
+    B.phys_off = pofs;
+    cofs += B.d.n_elem * B.NP;
+    pofs += B.d.n_elem * B.NQ;
+    p->total_elem += B.d.n_elem;
+    if (B.d.P != blk[0].P) p->uniform_P = false;
+  }
+  p->total_coeff = cofs;
+  p->total_phys = pofs;
+  p->max_tiles = std::max<long long>(1, p->total_elem);
+  p->off_tiles = off;
+  off = align_up(off + sizeof(Tile) * (size_t)p->max_tiles * OPK_COUNT);
+  for (auto& B : p->blocks) {
+    B.off_tab = off;
+    off = align_up(off + sizeof(double) * B.tab.size());
+    B.off_itab = off;
+    off = align_up(off + sizeof(int) * B.itab.size());
+  }
+  for (auto& B : p->blocks) {
+    B.off_fac = off;
+    off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * NFAC * B.NQ);
+    B.off_dxi = off;
+    off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * NDXI * B.NQ);
+  }
+  p->ws_bytes = off;
+  for (int k = 0; k < OPK_COUNT; ++k) p->mixed_dirty[k] = true;
+  *out = p;
+  return SHP_OK;
+}
+
+int shp_plan_destroy(shp_plan p) {
+  if (!p) return fail(SHP_ERR_INVALID_ARG, "null plan");
+  delete p;
+  return SHP_OK;
+}
+
+int shp_plan_workspace_bytes(shp_plan p, size_t* bytes) {
+  if (int r = check_plan(p)) return r;
+  if (!bytes) return fail(SHP_ERR_INVALID_ARG, "null output");
+  *bytes = p->ws_bytes;
+  return SHP_OK;
+}
+
+static int upload_static(shp_plan p, hipStream_t s) {
+  std::vector<BlockStatic> bs(p->blocks.size());
+  for (size_t b = 0; b < p->blocks.size(); ++b) {
+    const Block& B = p->blocks[b];
+    bs[b].tab = reinterpret_cast<const double*>(p->ws + B.off_tab);
+    bs[b].itab = reinterpret_cast<const int*>(p->ws + B.off_itab);
+    bs[b].fac = reinterpret_cast<const double*>(p->ws + B.off_fac);
+    bs[b].dxi = reinterpret_cast<const double*>(p->ws + B.off_dxi);
+    bs[b].n_elem = B.d.n_elem;
+    bs[b].coeff_off = B.coeff_off;
+    bs[b].phys_off = B.phys_off;
+    bs[b].shape = B.d.shape;
+    bs[b].E = 0;
+  }
+  hipError_t e = hipMemcpyAsync(p->ws + p->off_bstat, bs.data(), sizeof(BlockStatic) * bs.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return dev_fail(e, "hipMemcpyAsync(block table)");
+  return hipStreamSynchronize(s) == hipSuccess ? SHP_OK : dev_fail(hipGetLastError(), "hipStreamSynchronize");
+}
+
+int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!ws) return fail(SHP_ERR_WORKSPACE, "null workspace");
+  if (reinterpret_cast<uintptr_t>(ws) % ALIGN) return fail(SHP_ERR_WORKSPACE, "workspace not %zu-byte aligned", ALIGN);
+  if (ws_bytes < p->ws_bytes) return fail(SHP_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, p->ws_bytes);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  p->ws = static_cast<char*>(ws);
+  for (auto& B : p->blocks) {
+    B.geom_ok = false;
+    hipError_t e = hipMemcpyAsync(p->ws + B.off_tab, B.tab.data(), sizeof(double) * B.tab.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->ws + B.off_itab, B.itab.data(), sizeof(int) * B.itab.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return dev_fail(e, "hipMemcpyAsync(tables)");
+  }
+  for (int k = 0; k < OPK_COUNT; ++k) p->mixed_dirty[k] = true;
+  return upload_static(p, s);
+}
+
+int shp_plan_set_geometry(shp_plan p, int blk, const double* jac, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (blk < 0 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  Block& B = p->blocks[blk];
+  if (B.d.n_elem == 0) {
+    B.geom_ok = true;
+    return SHP_OK;
+  }
+  if (!jac) return fail(SHP_ERR_INVALID_ARG, "null jac");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int* status = reinterpret_cast<int*>(p->ws + p->off_status);
+  hipError_t e = hipMemsetAsync(status, 0, sizeof(int), s);
+  if (e != hipSuccess) return dev_fail(e, "hipMemsetAsync(status)");
+  GeomArgs g;
+  g.tab = reinterpret_cast<const double*>(p->ws + B.off_tab);
+  g.jac = jac;
+  g.fac = reinterpret_cast<double*>(p->ws + B.off_fac);
+  g.dxi = reinterpret_cast<double*>(p->ws + B.off_dxi);
+  g.status = status;
+  g.n_elem = B.d.n_elem;
+  g.affine = (B.d.geom == SHP_AFFINE);
+  e = launch_geometry(B.d.shape, B.d.P, g, s);
+  if (e != hipSuccess) return dev_fail(e, "geometry kernel launch");
+  int h = 0;
+  e = hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_fail(e, "geometry status readback");
+  if (h) {
+    B.geom_ok = false;
+    return fail(SHP_ERR_BAD_GEOMETRY, "block %d: det(dx/dxi) <= 0 or non-finite factor", blk);
+  }
+  B.geom_ok = true;
+  return SHP_OK;
+}
+
+int shp_block_offsets(shp_plan p, int blk, int64_t* coeff_off, int64_t* phys_off) {
+  if (int r = check_plan(p)) return r;
+  if (blk < 0 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
+  if (coeff_off) *coeff_off = p->blocks[blk].coeff_off;
+  if (phys_off) *phys_off = p->blocks[blk].phys_off;
+  return SHP_OK;
+}
+
+int shp_set_tiling(shp_plan p, int blk, int op, int strategy, int E, int NT) {
+  if (int r = check_plan(p)) return r;
+  int opk;
+  if (int r = opk_of(op, strategy, &opk)) return r;
+  if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
+  if (!(E == 0 && NT == 0)) {
+    if (E < 1 || E > 64) return fail(SHP_ERR_INVALID_ARG, "elements per work-group %d outside [1,64]", E);
+    if (NT < 64 || NT > 512 || NT % 64) return fail(SHP_ERR_INVALID_ARG, "threads %d: multiple of 64 in [64,512]", NT);
+    if (blk >= 0) {
+      const Block& B = p->blocks[blk];
+      if (op_lds_bytes(B.d.shape, B.d.P, opk, E) > LDS_LIMIT)
+        return fail(SHP_ERR_UNSUPPORTED, "%d elements exceed the LDS of a work-group", E);
+    } else {
+      for (const auto& B : p->blocks)
+        if (op_lds_bytes(B.d.shape, B.d.P, opk, E) > LDS_LIMIT)
+          return fail(SHP_ERR_UNSUPPORTED, "%d elements exceed the LDS of a work-group", E);
+    }
+  }
+  Tiling t;
+  t.E = E;
+  t.NT = NT;
+  if (blk >= 0)
+    p->blocks[blk].tiling[opk] = t;
+  else {
+    p->mixed[opk] = t;
+    p->mixed_dirty[opk] = true;
+  }
+  return SHP_OK;
+}
+
+static Tiling mixed_tiling(shp_plan p, int opk);
+
+int shp_get_tiling(shp_plan p, int blk, int op, int strategy, int* E, int* NT) {
+  if (int r = check_plan(p)) return r;
+  int opk;
+  if (int r = opk_of(op, strategy, &opk)) return r;
+  if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
+  if (!E || !NT) return fail(SHP_ERR_INVALID_ARG, "null output");
+  Tiling t;
+  if (blk >= 0) {
+    const Block& B = p->blocks[blk];
+    t = effective(B.tiling[opk], B.d.shape, B.d.P, opk);
+  } else {
+    t = mixed_tiling(p, opk);
+  }
+  *E = t.E;
+  *NT = t.NT;
+  return SHP_OK;
+}
+
+// Build and upload the whole-mesh tile list of one operator: tiles of E
+// elements from every block, heaviest first (longest-processing-time order).
+static Tiling mixed_tiling(shp_plan p, int opk) {
+  Tiling t = p->mixed[opk];
+  if (t.E > 0 && t.NT > 0) return t;
+  t = Tiling{64, 512};
+  for (const auto& B : p->blocks) {
+    const Tiling d = default_tiling(B.d.shape, B.d.P, opk);
+    t.E = std::min(t.E, d.E);
+    t.NT = std::min(t.NT, d.NT);
+  }
+  return t;
+}
+
+static int build_tiles(shp_plan p, int opk, hipStream_t s) {
+  const int E = mixed_tiling(p, opk).E;
+  struct T2 {
+    Tile t;
+    double cost;
+  };
+  std::vector<T2> tl;
+  for (int b = 0; b < (int)p->blocks.size(); ++b) {
+    const Block& B = p->blocks[b];
+    // per-element cost weight: streamed bytes (dominant) plus a shape term
+    const double w = 1.0 + 0.02 * B.d.shape;
+    for (long long e0 = 0; e0 < B.d.n_elem; e0 += E) {
+      T2 x;
+      x.t.blk = b;
+      x.t.e0 = e0;
+      x.t.ne = (int)std::min<long long>(E, B.d.n_elem - e0);
+      x.cost = w * x.t.ne;
+      tl.push_back(x);
+    }
+  }
+  std::stable_sort(tl.begin(), tl.end(), [](const T2& a, const T2& b) { return a.cost > b.cost; });
+  if ((long long)tl.size() > p->max_tiles) return fail(SHP_ERR_WORKSPACE, "tile list overflow");
+  std::vector<Tile> host(tl.size());
+  for (size_t i = 0; i < tl.size(); ++i) host[i] = tl[i].t;
+  Tile* dst = reinterpret_cast<Tile*>(p->ws + p->off_tiles) + (size_t)opk * p->max_tiles;
+  hipError_t e = hipSuccess;
+  if (!host.empty()) e = hipMemcpyAsync(dst, host.data(), sizeof(Tile) * host.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_fail(e, "tile list upload");
+  p->mixed_ntiles[opk] = (int)host.size();
+  p->mixed_dirty[opk] = false;
+  return SHP_OK;
+}
+
+int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, double* out, double lambda, void* stream) {
+  if (int r = check_plan(p)) return r;
+  int opk;
+  if (int r = opk_of(op, strategy, &opk)) return r;
+  if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
+  if (!in || !out) return fail(SHP_ERR_INVALID_ARG, "null in/out");
+  if (!std::isfinite(lambda)) return fail(SHP_ERR_INVALID_ARG, "lambda not finite");
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  const bool needs_geom = !(opk == OPK_BWD);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (blk >= 0) {
+    Block& B = p->blocks[blk];
+    if (needs_geom && !B.geom_ok) return fail(SHP_ERR_STATE, "block %d: geometry not set", blk);
+    const Tiling t = effective(B.tiling[opk], B.d.shape, B.d.P, opk);
+    OpArgs a{};
+    a.tab = reinterpret_cast<const double*>(p->ws + B.off_tab);
+    a.itab = reinterpret_cast<const int*>(p->ws + B.off_itab);
+    a.fac = reinterpret_cast<const double*>(p->ws + B.off_fac);
+    a.dxi = reinterpret_cast<const double*>(p->ws + B.off_dxi);
+    a.in = in;
+    a.out = out;
+    a.n_elem = B.d.n_elem;
+    a.in_cs = B.d.n_elem * (long long)B.NQ;
+    a.out_cs = a.in_cs;
+    a.lambda = lambda;
+    a.E = t.E;
+    hipError_t e = launch_block(B.d.shape, B.d.P, opk, a, t.NT, s);
+    if (e != hipSuccess) return dev_fail(e, "operator launch");
+    return SHP_OK;
+  }
+  // whole mesh
+  for (size_t b = 0; b < p->blocks.size(); ++b)
+    if (needs_geom && !p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
+  if (!p->uniform_P) {
+    // blocks of different order: one launch per block on the stream
+    for (size_t b = 0; b < p->blocks.size(); ++b) {
+      Block& B = p->blocks[b];
+      const double* bin = in + (in_is_modes(opk) ? B.coeff_off : B.phys_off);
+      double* bout = out + (out_is_modes(opk) ? B.coeff_off : B.phys_off);
+      const Tiling t = effective(B.tiling[opk], B.d.shape, B.d.P, opk);
+      OpArgs a{};
+      a.tab = reinterpret_cast<const double*>(p->ws + B.off_tab);
+      a.itab = reinterpret_cast<const int*>(p->ws + B.off_itab);
+      a.fac = reinterpret_cast<const double*>(p->ws + B.off_fac);
+      a.dxi = reinterpret_cast<const double*>(p->ws + B.off_dxi);
+      a.in = bin;
+      a.out = bout;
+      a.n_elem = B.d.n_elem;
+      a.in_cs = p->total_phys;
+      a.out_cs = p->total_phys;
+      a.lambda = lambda;
+      a.E = t.E;
+      hipError_t e = launch_block(B.d.shape, B.d.P, opk, a, t.NT, s);
+      if (e != hipSuccess) return dev_fail(e, "operator launch");
+    }
+    return SHP_OK;
+  }
+  if (p->mixed_dirty[opk])
+    if (int r = build_tiles(p, opk, s)) return r;
+  const Tiling mt = mixed_tiling(p, opk);
+  const int E = mt.E, NT = mt.NT;
+  size_t lds = 0;
+  for (const auto& B : p->blocks) lds = std::max(lds, op_lds_bytes(B.d.shape, B.d.P, opk, E));
+  const Tile* tiles = reinterpret_cast<const Tile*>(p->ws + p->off_tiles) + (size_t)opk * p->max_tiles;
+  hipError_t e = launch_mixed(p->blocks[0].d.P, opk, reinterpret_cast<const BlockStatic*>(p->ws + p->off_bstat), tiles,
+                              p->mixed_ntiles[opk], in, out, p->total_phys, p->total_phys, lambda, NT, lds, s);
+  if (e != hipSuccess) return dev_fail(e, "mixed launch");
+  return SHP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,48 @@
+// Internal declarations of libshp shared by the host API and the kernel
+// launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "shp_layout.hpp"
+
+namespace shp {
+
+struct OpArgs;
+struct Tile;
+struct GeomArgs;
+
+// Static per-block data of a mixed launch (device copy in the workspace).
+struct BlockStatic {
+  const double* tab;
+  const int* itab;
+  const double* fac;
+  const double* dxi;
+  long long n_elem;
+  long long coeff_off;  // element offset * N_P of the block in whole-mesh coefficient buffers
+  long long phys_off;   // element offset * N_Q in whole-mesh point buffers
+  int shape;
+  int E;
+};
+
+// host tables (shp_tables.cpp)
+void gauss_jacobi(int Q, double a, double b, double* x, double* w);
+void gauss_lobatto(int Q, double* x, double* w);
+void rule_1d(int Q, int alpha, double* x, double* w);
+void build_tables(int sh, int P, std::vector<double>& tab, std::vector<int>& itab);
+void reference_points(int sh, int Q, double* xi, double* w);
+
+// launchers (shp_k_*.hip); return hipSuccess or the launch error
+size_t op_lds_bytes(int sh, int P, int opk, int E);
+hipError_t launch_block(int sh, int P, int opk, const OpArgs& a, int threads, hipStream_t s);
+hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s);
+hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
+                        double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds,
+                        hipStream_t s);
+
+constexpr int MAX_P = 10;
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+}  // namespace shp

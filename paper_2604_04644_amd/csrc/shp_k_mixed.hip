@@ -1,0 +1,76 @@
+// Mixed-shape kernels (one launch over every block of a whole mesh) and the
+// dispatch from runtime (shape, P, operator) to the templated launchers.
+#include "shp_kernels.hpp"
+
+namespace shp {
+
+hipError_t launch_block_hex(int P, int opk, const OpArgs& a, int threads, hipStream_t s);
+hipError_t launch_block_prism(int P, int opk, const OpArgs& a, int threads, hipStream_t s);
+hipError_t launch_block_pyr(int P, int opk, const OpArgs& a, int threads, hipStream_t s);
+hipError_t launch_block_tet(int P, int opk, const OpArgs& a, int threads, hipStream_t s);
+hipError_t launch_geometry_hex(int P, const GeomArgs& g, hipStream_t s);
+hipError_t launch_geometry_prism(int P, const GeomArgs& g, hipStream_t s);
+hipError_t launch_geometry_pyr(int P, const GeomArgs& g, hipStream_t s);
+hipError_t launch_geometry_tet(int P, const GeomArgs& g, hipStream_t s);
+size_t lds_bytes_hex(int P, int E);
+size_t lds_bytes_prism(int P, int E);
+size_t lds_bytes_pyr(int P, int E);
+size_t lds_bytes_tet(int P, int E);
+
+size_t op_lds_bytes(int sh, int P, int opk, int E) {
+  (void)opk;
+  switch (sh) {
+    case HEX: return lds_bytes_hex(P, E);
+    case PRISM: return lds_bytes_prism(P, E);
+    case PYR: return lds_bytes_pyr(P, E);
+    default: return lds_bytes_tet(P, E);
+  }
+}
+
+hipError_t launch_block(int sh, int P, int opk, const OpArgs& a, int threads, hipStream_t s) {
+  switch (sh) {
+    case HEX: return launch_block_hex(P, opk, a, threads, s);
+    case PRISM: return launch_block_prism(P, opk, a, threads, s);
+    case PYR: return launch_block_pyr(P, opk, a, threads, s);
+    default: return launch_block_tet(P, opk, a, threads, s);
+  }
+}
+
+hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s) {
+  switch (sh) {
+    case HEX: return launch_geometry_hex(P, g, s);
+    case PRISM: return launch_geometry_prism(P, g, s);
+    case PYR: return launch_geometry_pyr(P, g, s);
+    default: return launch_geometry_tet(P, g, s);
+  }
+}
+
+template <int P>
+static hipError_t launch_mixed_p(int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
+                                 double* out, long long in_cs, long long out_cs, double lambda, int threads,
+                                 size_t lds, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const dim3 g((unsigned)ntiles), b((unsigned)threads);
+  switch (opk) {
+#define K_(op) \
+  case op: hipLaunchKernelGGL((k_mixed<P, op>), g, b, lds, s, blocks, tiles, ntiles, in, out, in_cs, out_cs, lambda); break;
+    K_(OPK_BWD) K_(OPK_IPR) K_(OPK_DERIV) K_(OPK_IPRD) K_(OPK_MASS) K_(OPK_LAP) K_(OPK_HELM)
+#undef K_
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
+                        double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds,
+                        hipStream_t s) {
+  switch (P) {
+#define C_(p) \
+  case p: return launch_mixed_p<p>(opk, blocks, tiles, ntiles, in, out, in_cs, out_cs, lambda, threads, lds, s);
+    C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10)
+#undef C_
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace shp

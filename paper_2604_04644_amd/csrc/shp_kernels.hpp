@@ -1,0 +1,754 @@
+// HIP kernels of libshp for gfx950: LDS-staged sum-factorisation over tiles of
+// elements, one work-group per tile.
+//
+// Work decomposition.  A work-group holds E elements in LDS.  Every stage of an
+// operator is a set of independent "line" tasks (a 1D contraction producing Q or
+// n outputs from one line of its input), strided over the work-group's threads;
+// a barrier separates stages.  1D tables (basis functions and collocation
+// derivatives at the quadrature points of each direction) sit in LDS.
+//
+// Stages (Sec. 3.3.2 sum-factorisation; Sec. 2.3 collapsed tensor structure):
+//   bwd_r : x (modes)      -> F[col][k]   contract r with C_{kappa,r}(z3_k)
+//   bwd_q : F              -> G[p][j][k]  contract q with B2_{p,q}(z2_j)
+//   bwd_p : G              -> U[i][j][k]  contract p with A_p(z1_i)
+//   ipr_p, ipr_q, ipr_r    the transposed contractions (B^T)
+//   grad  : U              -> G0,G1,G2    collocation derivatives D_d (eq. dphitodh)
+//   gradT : V_d            -> D_d^T V_d   in place
+// The collapsed-vertex modes (functions independent of a collapsed coordinate)
+// are split with A_0 + A_1 = 1 into the p = 0 and p = 1 (and q = 0, 1) columns;
+// each stage adds the extra terms, and the transposed stages add their adjoints.
+//
+// The collocated Helmholtz action (Sec. 2.2.1 eq. helm1, Alg. 6) is
+//   y = B^T [ sum_d D_d^T ( sum_e g_de D_e u ) + lambda jw u ],  u = B x,
+// with g = jw (d eta/d x)(d eta/d x)^T and jw the quadrature weight times |J|.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "shp_internal.hpp"
+#include "shp_layout.hpp"
+
+namespace shp {
+
+enum : int {
+  OPK_BWD = 0,
+  OPK_IPR = 1,
+  OPK_DERIV = 2,
+  OPK_IPRD = 3,
+  OPK_MASS = 4,
+  OPK_LAP = 5,
+  OPK_HELM = 6,
+  OPK_HELM_NC = 7,  // non-collocated Helmholtz (Alg. 5)
+  OPK_COUNT = 8
+};
+
+// Arguments of one block for one operator call.
+struct OpArgs {
+  const double* tab;  // reference tables (tab_layout)
+  const int* itab;    // column table [NC][ICOL]
+  const double* fac;  // [n_elem][NFAC][Q^3]
+  const double* dxi;  // [n_elem][NDXI][Q^3]
+  const double* in;
+  double* out;
+  long long n_elem;
+  long long in_cs;   // component stride of a vector-field input (points)
+  long long out_cs;  // component stride of a vector-field output (points)
+  double lambda;
+  int E;             // elements per tile
+  int pad_;
+};
+
+// A tile of a mixed launch: block index, first element, element count.
+struct Tile {
+  int blk;
+  int ne;
+  long long e0;
+};
+
+template <int SH, int P_>
+struct Dims {
+  static constexpr int P = P_;
+  static constexpr int n = P + 1;
+  static constexpr int Q = P + 2;
+  static constexpr int Q2 = Q * Q;
+  static constexpr int Q3 = Q * Q * Q;
+  static constexpr int QP = qpad(Q);
+  static constexpr int S3 = Q * Q * QP;  // one padded point buffer in LDS
+  static constexpr int NP = num_modes(SH, P);
+  static constexpr int NC = num_cols(SH, P);
+  static constexpr TabLayout L = tab_layout(SH, P);
+  static constexpr int NTAB = L.total;
+  static constexpr int NITAB = NC * ICOL;
+  // LDS words (doubles) before the per-element region
+  static constexpr int HEAD = NTAB + (NITAB + 1) / 2;
+  static constexpr int PER_ELEM = 4 * S3;
+  __device__ __host__ static constexpr int pidx(int i, int j, int k) { return (i * Q + j) * QP + k; }
+};
+
+// LDS view of one tile.
+template <int SH, int P>
+struct Tile_ {
+  using D = Dims<SH, P>;
+  double* tab;
+  int* itab;
+  double* el;  // E * PER_ELEM
+  __device__ double* U(int e) const { return el + e * D::PER_ELEM; }
+  __device__ double* G(int e, int d) const { return el + e * D::PER_ELEM + (d + 1) * D::S3; }
+};
+
+__device__ __forceinline__ int tid() { return threadIdx.x; }
+__device__ __forceinline__ int nthr() { return blockDim.x; }
+
+template <int SH, int P>
+__device__ void load_tables(const OpArgs& a, const Tile_<SH, P>& T) {
+  using D = Dims<SH, P>;
+  for (int t = tid(); t < D::NTAB; t += nthr()) T.tab[t] = a.tab[t];
+  for (int t = tid(); t < D::NITAB; t += nthr()) T.itab[t] = a.itab[t];
+}
+
+// ---------------------------------------------------------------------------
+// modes -> points
+// ---------------------------------------------------------------------------
+
+// stage r: X (modes of element e at xo(e)) -> F[c][k] at fo(e) + c*QP + k
+template <int SH, int P, bool DER>
+__device__ void bwd_r(const Tile_<SH, P>& T, int ne, int xbuf, int fbuf) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q;
+  const double* C3 = T.tab + (DER ? D::L.dC3 : D::L.C3);
+  const double* V1 = C3 + 1 * Q;  // family (0,1): v1 or its derivative 1/2
+  for (int t = tid(); t < ne * D::NC; t += nthr()) {
+    const int e = t / D::NC, c = t - e * D::NC;
+    const int* ct = T.itab + c * ICOL;
+    const int p = ct[0], q = ct[1], off = ct[2], R = ct[3], fb = ct[4];
+    const double* x = (xbuf < 0 ? T.U(e) : T.G(e, xbuf));
+    const double* cf = C3 + fb * Q;
+    double acc[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) acc[k] = 0.0;
+    for (int r = 0; r < R; ++r) {
+      const double xr = x[off + r];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) acc[k] = fma(cf[r * Q + k], xr, acc[k]);
+    }
+    // collapsed-vertex modes: extra eta3 term v1 in columns p = 1 (and q = 1)
+    double xe = 0.0;
+    bool extra = false;
+    if (SH == PRISM) {
+      if (p == 1) { xe = x[q * (P + 1) + 1]; extra = true; }
+    } else if (SH == PYR) {
+      if ((p == 1 && q <= 1) || (p == 0 && q == 1)) { xe = x[1]; extra = true; }
+    } else if (SH == TET) {
+      if ((p == 1 && q == 0) || (p == 0 && q == 1)) { xe = x[1]; extra = true; }
+    }
+    if (extra) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) acc[k] = fma(V1[k], xe, acc[k]);
+    }
+    double* f = T.G(e, fbuf) + c * D::QP;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f[k] = acc[k];
+  }
+}
+
+// stage q: F[c][k] -> G[p][j][k] (p*Q*QP + j*QP + k)
+template <int SH, int P, bool DER>
+__device__ void bwd_q(const Tile_<SH, P>& T, int ne, int fbuf, int gbuf) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  const double* B2 = T.tab + (DER ? D::L.dB2 : D::L.B2);
+  // v1 in eta2 (or its derivative) is the A_1 row of the eta2 table for the
+  // non-tet shapes; for the tet it is the family (0,1) row: index 1 either way
+  const double* V1 = B2 + 1 * Q;
+  for (int t = tid(); t < ne * n * Q; t += nthr()) {
+    const int e = t / (n * Q);
+    const int rem = t - e * (n * Q);
+    const int p = rem / Q, k = rem - p * Q;
+    const double* F = T.G(e, fbuf);
+    const int nq = nq_of(SH, P, p), cb = col_base(SH, P, p);
+    const int bfam = (SH == TET) ? fam_index(P, p, 0) : 0;
+    double acc[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) acc[j] = 0.0;
+    for (int q = 0; q < nq; ++q) {
+      const double fv = F[(cb + q) * QP + k];
+      const double* b = B2 + (bfam + q) * Q;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) acc[j] = fma(b[j], fv, acc[j]);
+    }
+    if (SH == TET && p == 1) {
+      const double fv = F[1 * QP + k];  // column (0,1)
+#pragma unroll
+      for (int j = 0; j < Q; ++j) acc[j] = fma(V1[j], fv, acc[j]);
+    }
+    double* G = T.G(e, gbuf) + p * Q * QP + k;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) G[j * QP] = acc[j];
+  }
+}
+
+// stage p: G[p][j][k] -> U[i][j][k] (U buffer index ubuf: -1 = U, else G(ubuf))
+template <int SH, int P, bool DER>
+__device__ void bwd_p(const Tile_<SH, P>& T, int ne, int gbuf, int ubuf) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  const double* A1 = T.tab + (DER ? D::L.dA1 : D::L.A1);
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const int e = t / (Q * Q);
+    const int rem = t - e * (Q * Q);
+    const int j = rem / Q, k = rem - j * Q;
+    const double* G = T.G(e, gbuf) + j * QP + k;
+    double g[n];
+#pragma unroll
+    for (int p = 0; p < n; ++p) g[p] = G[p * Q * QP];
+    double* U = (ubuf < 0 ? T.U(e) : T.G(e, ubuf)) + j * QP + k;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int p = 0; p < n; ++p) s = fma(A1[p * Q + i], g[p], s);
+      U[i * Q * QP] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// points -> modes (transposed stages)
+// ---------------------------------------------------------------------------
+
+// stage p^T: s(i,j,k) = sum over the buffers in mask (bit0: U, bit1..3: G0..G2)
+// -> Gp[p][j][k], written in place into buffer dst (-1 = U) at (p, j, k).
+template <int SH, int P, bool DER>
+__device__ void ipr_p(const Tile_<SH, P>& T, int ne, int mask, int dst) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  const double* A1 = T.tab + (DER ? D::L.dA1 : D::L.A1);
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const int e = t / (Q * Q);
+    const int rem = t - e * (Q * Q);
+    const int j = rem / Q, k = rem - j * Q;
+    const int o = j * QP + k;
+    double s[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s[i] = 0.0;
+    if (mask & 1) {
+      const double* b = T.U(e) + o;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) s[i] += b[i * Q * QP];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (mask & (2 << d)) {
+        const double* b = T.G(e, d) + o;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) s[i] += b[i * Q * QP];
+      }
+    }
+    double* G = (dst < 0 ? T.U(e) : T.G(e, dst)) + o;
+#pragma unroll
+    for (int p = 0; p < n; ++p) {
+      double a = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) a = fma(A1[p * Q + i], s[i], a);
+      G[p * Q * QP] = a;
+    }
+  }
+}
+
+// stage q^T: Gp[p][j][k] (buffer gbuf) -> F[c][k] (buffer fbuf)
+template <int SH, int P, bool DER>
+__device__ void ipr_q(const Tile_<SH, P>& T, int ne, int gbuf, int fbuf) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  const double* B2 = T.tab + (DER ? D::L.dB2 : D::L.B2);
+  const double* V1 = B2 + 1 * Q;
+  for (int t = tid(); t < ne * n * Q; t += nthr()) {
+    const int e = t / (n * Q);
+    const int rem = t - e * (n * Q);
+    const int p = rem / Q, k = rem - p * Q;
+    const double* G = (gbuf < 0 ? T.U(e) : T.G(e, gbuf)) + p * Q * QP + k;
+    double g[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) g[j] = G[j * QP];
+    const int nq = nq_of(SH, P, p), cb = col_base(SH, P, p);
+    const int bfam = (SH == TET) ? fam_index(P, p, 0) : 0;
+    double* F = T.G(e, fbuf);
+    for (int q = 0; q < nq; ++q) {
+      const double* b = B2 + (bfam + q) * Q;
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) a = fma(b[j], g[j], a);
+      if (SH == TET && p == 0 && q == 1) {
+        // adjoint of the tet's extra eta2 term: column (0,1) also collects v1 * Gp[1]
+        const double* G1 = G + 1 * Q * QP;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) a = fma(V1[j], G1[j * QP], a);
+      }
+      F[(cb + q) * QP + k] = a;
+    }
+  }
+}
+
+// stage r^T: F[c][k] (buffer fbuf) -> y modes into buffer ybuf (-1 = U), [NP]
+template <int SH, int P, bool DER>
+__device__ void ipr_r(const Tile_<SH, P>& T, int ne, int fbuf, int ybuf, bool accumulate) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, QP = D::QP;
+  const double* C3 = T.tab + (DER ? D::L.dC3 : D::L.C3);
+  const double* V1 = C3 + 1 * Q;
+  for (int t = tid(); t < ne * D::NC; t += nthr()) {
+    const int e = t / D::NC, c = t - e * D::NC;
+    const int* ct = T.itab + c * ICOL;
+    const int p = ct[0], q = ct[1], off = ct[2], R = ct[3], fb = ct[4];
+    const double* F = T.G(e, fbuf);
+    double f[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f[k] = F[c * QP + k];
+    double* y = (ybuf < 0 ? T.U(e) : T.G(e, ybuf)) + off;
+    const double* cf = C3 + fb * Q;
+    for (int r = 0; r < R; ++r) {
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) a = fma(cf[r * Q + k], f[k], a);
+      // adjoints of the collapsed-vertex splits
+      const bool vx = (r == 1) && ((SH == PRISM && p == 0) || ((SH == PYR || SH == TET) && p == 0 && q == 0));
+      if (vx) {
+        double s[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) s[k] = 0.0;
+        if (SH == PRISM) {
+          const double* Fe = F + ((P + 1) + q) * QP;  // column (1,q)
+#pragma unroll
+          for (int k = 0; k < Q; ++k) s[k] = Fe[k];
+        } else if (SH == PYR) {
+          const double* Fa = F + (P + 1) * QP;  // (1,0)
+          const double* Fb = F + 1 * QP;        // (0,1)
+          const double* Fc = F + (P + 2) * QP;  // (1,1)
+#pragma unroll
+          for (int k = 0; k < Q; ++k) s[k] = Fa[k] + Fb[k] + Fc[k];
+        } else {
+          const double* Fa = F + 1 * QP;        // (0,1)
+          const double* Fb = F + (P + 1) * QP;  // (1,0)
+#pragma unroll
+          for (int k = 0; k < Q; ++k) s[k] = Fa[k] + Fb[k];
+        }
+#pragma unroll
+        for (int k = 0; k < Q; ++k) a = fma(V1[k], s[k], a);
+      }
+      if (accumulate)
+        y[r] += a;
+      else
+        y[r] = a;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// collocation derivatives
+// ---------------------------------------------------------------------------
+
+// G_d = D_d U for d = 0,1,2 (all three in one pass)
+template <int SH, int P>
+__device__ void grad3(const Tile_<SH, P>& T, int ne) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, QP = D::QP;
+  const int per = ne * Q * Q;
+  for (int t = tid(); t < 3 * per; t += nthr()) {
+    const int d = t / per;
+    const int r1 = t - d * per;
+    const int e = r1 / (Q * Q);
+    const int r2 = r1 - e * (Q * Q);
+    const int a = r2 / Q, b = r2 - a * Q;
+    const double* Dm = T.tab + D::L.D + d * Q * Q;
+    int base, stride;
+    if (d == 0) { base = a * QP + b; stride = Q * QP; }          // line (j,k) along i
+    else if (d == 1) { base = a * Q * QP + b; stride = QP; }     // line (i,k) along j
+    else { base = (a * Q + b) * QP; stride = 1; }                 // line (i,j) along k
+    const double* u = T.U(e) + base;
+    double v[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) v[l] = u[l * stride];
+    double* g = T.G(e, d) + base;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) s = fma(Dm[i * Q + l], v[l], s);
+      g[i * stride] = s;
+    }
+  }
+}
+
+// G_d <- D_d^T G_d in place, d = 0,1,2
+template <int SH, int P>
+__device__ void grad3T(const Tile_<SH, P>& T, int ne) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, QP = D::QP;
+  const int per = ne * Q * Q;
+  for (int t = tid(); t < 3 * per; t += nthr()) {
+    const int d = t / per;
+    const int r1 = t - d * per;
+    const int e = r1 / (Q * Q);
+    const int r2 = r1 - e * (Q * Q);
+    const int a = r2 / Q, b = r2 - a * Q;
+    const double* Dm = T.tab + D::L.D + d * Q * Q;
+    int base, stride;
+    if (d == 0) { base = a * QP + b; stride = Q * QP; }
+    else if (d == 1) { base = a * Q * QP + b; stride = QP; }
+    else { base = (a * Q + b) * QP; stride = 1; }
+    double* g = T.G(e, d) + base;
+    double v[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) v[l] = g[l * stride];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) s = fma(Dm[i * Q + l], v[i], s);
+      g[l * stride] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// global <-> LDS
+// ---------------------------------------------------------------------------
+
+template <int SH, int P>
+__device__ void load_modes(const Tile_<SH, P>& T, const double* __restrict__ in, long long e0, int ne, int buf) {
+  using D = Dims<SH, P>;
+  const double* src = in + e0 * D::NP;
+  for (int t = tid(); t < ne * D::NP; t += nthr()) {
+    const int e = t / D::NP, m = t - e * D::NP;
+    (buf < 0 ? T.U(e) : T.G(e, buf))[m] = src[t];
+  }
+}
+
+template <int SH, int P>
+__device__ void store_modes(const Tile_<SH, P>& T, double* __restrict__ out, long long e0, int ne, int buf) {
+  using D = Dims<SH, P>;
+  double* dst = out + e0 * D::NP;
+  for (int t = tid(); t < ne * D::NP; t += nthr()) {
+    const int e = t / D::NP, m = t - e * D::NP;
+    dst[t] = (buf < 0 ? T.U(e) : T.G(e, buf))[m];
+  }
+}
+
+template <int SH, int P>
+__device__ __forceinline__ int lds_pt(int pt) {
+  using D = Dims<SH, P>;
+  const int i = pt / D::Q2;
+  const int r = pt - i * D::Q2;
+  const int j = r / D::Q, k = r - j * D::Q;
+  return D::pidx(i, j, k);
+}
+
+// ---------------------------------------------------------------------------
+// tile bodies, one per operator
+// ---------------------------------------------------------------------------
+
+template <int SH, int P>
+__device__ void bwd_chain(const Tile_<SH, P>& T, int ne) {
+  // modes in G0 -> F in G1 -> G in G2 -> U
+  bwd_r<SH, P, false>(T, ne, 0, 1);
+  __syncthreads();
+  bwd_q<SH, P, false>(T, ne, 1, 2);
+  __syncthreads();
+  bwd_p<SH, P, false>(T, ne, 2, -1);
+  __syncthreads();
+}
+
+// points summed over mask -> modes in buffer G1; returns after a barrier
+template <int SH, int P>
+__device__ void ipr_chain(const Tile_<SH, P>& T, int ne, int mask) {
+  ipr_p<SH, P, false>(T, ne, mask, -1);
+  __syncthreads();
+  ipr_q<SH, P, false>(T, ne, -1, 0);
+  __syncthreads();
+  ipr_r<SH, P, false>(T, ne, 0, 1, false);
+  __syncthreads();
+}
+
+template <int SH, int P, int OP>
+__device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH, P>& T) {
+  using D = Dims<SH, P>;
+  constexpr int Q3 = D::Q3;
+  load_tables<SH, P>(a, T);
+  if (OP == OPK_BWD || OP == OPK_MASS || OP == OPK_LAP || OP == OPK_HELM) {
+    load_modes<SH, P>(T, a.in, e0, ne, 0);
+    __syncthreads();
+    bwd_chain<SH, P>(T, ne);
+  } else {
+    __syncthreads();
+  }
+
+  if (OP == OPK_BWD) {
+    double* dst = a.out + e0 * Q3;
+    for (int t = tid(); t < ne * Q3; t += nthr()) {
+      const int e = t / Q3, pt = t - e * Q3;
+      dst[t] = T.U(e)[lds_pt<SH, P>(pt)];
+    }
+    return;
+  }
+
+  if (OP == OPK_IPR || OP == OPK_MASS) {
+    const double* fac = a.fac + e0 * (long long)(NFAC * Q3);
+    const double* src = a.in + e0 * Q3;
+    for (int t = tid(); t < ne * Q3; t += nthr()) {
+      const int e = t / Q3, pt = t - e * Q3;
+      const double jw = fac[e * (NFAC * Q3) + pt];
+      double* u = T.U(e) + lds_pt<SH, P>(pt);
+      const double f = (OP == OPK_IPR) ? src[t] : *u;
+      *u = jw * f;
+    }
+    __syncthreads();
+    ipr_chain<SH, P>(T, ne, 1);
+    store_modes<SH, P>(T, a.out, e0, ne, 1);
+    return;
+  }
+
+  if (OP == OPK_DERIV) {
+    const double* src = a.in + e0 * Q3;
+    for (int t = tid(); t < ne * Q3; t += nthr()) {
+      const int e = t / Q3, pt = t - e * Q3;
+      T.U(e)[lds_pt<SH, P>(pt)] = src[t];
+    }
+    __syncthreads();
+    grad3<SH, P>(T, ne);
+    __syncthreads();
+    const double* dxi = a.dxi + e0 * (long long)(NDXI * Q3);
+    for (int t = tid(); t < ne * Q3; t += nthr()) {
+      const int e = t / Q3, pt = t - e * Q3;
+      const int lp = lds_pt<SH, P>(pt);
+      const double g0 = T.G(e, 0)[lp], g1 = T.G(e, 1)[lp], g2 = T.G(e, 2)[lp];
+      const double* m = dxi + e * (NDXI * Q3) + pt;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double v = m[(0 * 3 + i) * Q3] * g0 + m[(1 * 3 + i) * Q3] * g1 + m[(2 * 3 + i) * Q3] * g2;
+        a.out[i * a.out_cs + e0 * Q3 + t] = v;
+      }
+    }
+    return;
+  }
+
+  if (OP == OPK_IPRD) {
+    const double* dxi = a.dxi + e0 * (long long)(NDXI * Q3);
+    const double* fac = a.fac + e0 * (long long)(NFAC * Q3);
+    for (int t = tid(); t < ne * Q3; t += nthr()) {
+      const int e = t / Q3, pt = t - e * Q3;
+      const int lp = lds_pt<SH, P>(pt);
+      const double f0 = a.in[0 * a.in_cs + e0 * Q3 + t];
+      const double f1 = a.in[1 * a.in_cs + e0 * Q3 + t];
+      const double f2 = a.in[2 * a.in_cs + e0 * Q3 + t];
+      const double jw = fac[e * (NFAC * Q3) + pt];
+      const double* m = dxi + e * (NDXI * Q3) + pt;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double v = m[(d * 3 + 0) * Q3] * f0 + m[(d * 3 + 1) * Q3] * f1 + m[(d * 3 + 2) * Q3] * f2;
+        T.G(e, d)[lp] = jw * v;
+      }
+    }
+    __syncthreads();
+    grad3T<SH, P>(T, ne);
+    __syncthreads();
+    ipr_chain<SH, P>(T, ne, 2 | 4 | 8);
+    store_modes<SH, P>(T, a.out, e0, ne, 1);
+    return;
+  }
+
+  if (OP == OPK_LAP || OP == OPK_HELM) {
+    grad3<SH, P>(T, ne);
+    __syncthreads();
+    const double* fac = a.fac + e0 * (long long)(NFAC * Q3);
+    const double lam = (OP == OPK_HELM) ? a.lambda : 0.0;
+    for (int t = tid(); t < ne * Q3; t += nthr()) {
+      const int e = t / Q3, pt = t - e * Q3;
+      const int lp = lds_pt<SH, P>(pt);
+      const double* g = fac + e * (NFAC * Q3) + pt;
+      const double jw = g[0];
+      const double g00 = g[1 * Q3], g01 = g[2 * Q3], g02 = g[3 * Q3];
+      const double g11 = g[4 * Q3], g12 = g[5 * Q3], g22 = g[6 * Q3];
+      double* u = T.U(e) + lp;
+      double* p0 = T.G(e, 0) + lp;
+      double* p1 = T.G(e, 1) + lp;
+      double* p2 = T.G(e, 2) + lp;
+      const double d0 = *p0, d1 = *p1, d2 = *p2;
+      *p0 = g00 * d0 + g01 * d1 + g02 * d2;
+      *p1 = g01 * d0 + g11 * d1 + g12 * d2;
+      *p2 = g02 * d0 + g12 * d1 + g22 * d2;
+      if (OP == OPK_HELM) *u = lam * jw * (*u);
+    }
+    __syncthreads();
+    grad3T<SH, P>(T, ne);
+    __syncthreads();
+    ipr_chain<SH, P>(T, ne, (OP == OPK_HELM ? 1 : 0) | 2 | 4 | 8);
+    store_modes<SH, P>(T, a.out, e0, ne, 1);
+    return;
+  }
+}
+
+template <int SH, int P>
+__device__ Tile_<SH, P> make_tile(double* smem) {
+  using D = Dims<SH, P>;
+  Tile_<SH, P> T;
+  T.tab = smem;
+  T.itab = reinterpret_cast<int*>(smem + D::NTAB);
+  T.el = smem + D::HEAD;
+  return T;
+}
+
+// one tile per work-group, tiles of one block
+template <int SH, int P, int OP>
+__global__ void __launch_bounds__(512) k_block(OpArgs a) {
+  extern __shared__ double smem[];
+  const long long e0 = (long long)blockIdx.x * a.E;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < a.E ? (int)rem : a.E;
+  if (ne <= 0) return;
+  const Tile_<SH, P> T = make_tile<SH, P>(smem);
+  tile_body<SH, P, OP>(a, e0, ne, T);
+}
+
+// Mixed-shape launch: one tile per work-group from a tile list that spans every
+// block (all blocks share P).  Block b's part of the whole-mesh buffers starts
+// at its coefficient or point offset.
+template <int P, int OP>
+__global__ void __launch_bounds__(512) k_mixed(const BlockStatic* __restrict__ blocks, const Tile* __restrict__ tiles,
+                                               int ntiles, const double* in, double* out, long long in_cs,
+                                               long long out_cs, double lambda) {
+  extern __shared__ double smem[];
+  const int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  const BlockStatic b = blocks[tl.blk];
+  constexpr bool in_modes = (OP == OPK_BWD || OP == OPK_MASS || OP == OPK_LAP || OP == OPK_HELM || OP == OPK_HELM_NC);
+  constexpr bool out_modes = !(OP == OPK_BWD || OP == OPK_DERIV);
+  OpArgs a;
+  a.tab = b.tab;
+  a.itab = b.itab;
+  a.fac = b.fac;
+  a.dxi = b.dxi;
+  a.n_elem = b.n_elem;
+  a.in = in + (in_modes ? b.coeff_off : b.phys_off);
+  a.out = out + (out_modes ? b.coeff_off : b.phys_off);
+  a.in_cs = in_cs;
+  a.out_cs = out_cs;
+  a.lambda = lambda;
+  a.E = b.E;
+  a.pad_ = 0;
+  switch (b.shape) {
+    case HEX: tile_body<HEX, P, OP>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem)); break;
+    case PRISM: tile_body<PRISM, P, OP>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem)); break;
+    case PYR: tile_body<PYR, P, OP>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem)); break;
+    default: tile_body<TET, P, OP>(a, tl.e0, tl.ne, make_tile<TET, P>(smem)); break;
+  }
+}
+
+// LDS bytes of a tile of E elements
+template <int SH, int P>
+constexpr size_t lds_bytes(int E) {
+  using D = Dims<SH, P>;
+  return sizeof(double) * (size_t)(D::HEAD + E * D::PER_ELEM);
+}
+
+// ---------------------------------------------------------------------------
+// geometric factors (FP64): from d x/d xi at the points to jw, g and d eta/d x
+// ---------------------------------------------------------------------------
+
+struct GeomArgs {
+  const double* tab;
+  const double* jac;  // curved [n][9][Q3], affine [n][9]
+  double* fac;        // [n][NFAC][Q3]
+  double* dxi;        // [n][NDXI][Q3]
+  int* status;        // set to 1 when a det <= 0 or a non-finite value is met
+  long long n_elem;
+  int affine;
+};
+
+template <int SH, int P>
+__global__ void __launch_bounds__(256) k_geometry(GeomArgs g) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, Q3 = D::Q3;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.n_elem * Q3) return;
+  const long long e = t / Q3;
+  const int pt = (int)(t - e * Q3);
+  const int i = pt / (Q * Q), j = (pt / Q) % Q, k = pt % Q;
+  const double* z = g.tab + D::L.z;
+  const double* w = g.tab + D::L.w;
+  const double e1 = z[0 * Q + i], e2 = z[1 * Q + j], e3 = z[2 * Q + k];
+  const double wq = w[0 * Q + i] * w[1 * Q + j] * w[2 * Q + k];
+  double J[9];
+  if (g.affine) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) J[c] = g.jac[e * 9 + c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) J[c] = g.jac[(e * 9 + c) * Q3 + pt];
+  }
+  // inverse of d x/d xi by cofactors
+  const double c00 = J[4] * J[8] - J[5] * J[7];
+  const double c01 = J[5] * J[6] - J[3] * J[8];
+  const double c02 = J[3] * J[7] - J[4] * J[6];
+  const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+  bool bad = !(det > 0.0) || !isfinite(det);
+  const double id = 1.0 / det;
+  double X[9];  // d xi_a / d x_i at a*3+i
+  X[0] = c00 * id;
+  X[1] = (J[2] * J[7] - J[1] * J[8]) * id;
+  X[2] = (J[1] * J[5] - J[2] * J[4]) * id;
+  X[3] = c01 * id;
+  X[4] = (J[0] * J[8] - J[2] * J[6]) * id;
+  X[5] = (J[2] * J[3] - J[0] * J[5]) * id;
+  X[6] = c02 * id;
+  X[7] = (J[1] * J[6] - J[0] * J[7]) * id;
+  X[8] = (J[0] * J[4] - J[1] * J[3]) * id;
+  // d eta / d xi of the collapse (rows eta_d, columns xi_a)
+  double Gc[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  double scale = 1.0;  // 2^{-sum alpha}
+  if (SH == PRISM) {
+    Gc[0] = 2.0 / (1.0 - e3);
+    Gc[2] = (1.0 + e1) / (1.0 - e3);
+    scale = 0.5;
+  } else if (SH == PYR) {
+    Gc[0] = 2.0 / (1.0 - e3);
+    Gc[2] = (1.0 + e1) / (1.0 - e3);
+    Gc[4] = 2.0 / (1.0 - e3);
+    Gc[5] = (1.0 + e2) / (1.0 - e3);
+    scale = 0.25;
+  } else if (SH == TET) {
+    const double s = (1.0 - e2) * (1.0 - e3);
+    Gc[0] = 4.0 / s;
+    Gc[1] = 2.0 * (1.0 + e1) / s;
+    Gc[2] = 2.0 * (1.0 + e1) / s;
+    Gc[4] = 2.0 / (1.0 - e3);
+    Gc[5] = (1.0 + e2) / (1.0 - e3);
+    scale = 0.125;
+  }
+  double M[9];  // d eta_d / d x_i
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii)
+      M[d * 3 + ii] = Gc[d * 3 + 0] * X[0 * 3 + ii] + Gc[d * 3 + 1] * X[1 * 3 + ii] + Gc[d * 3 + 2] * X[2 * 3 + ii];
+  const double jw = wq * scale * det;
+  double gm[6];
+  gm[0] = jw * (M[0] * M[0] + M[1] * M[1] + M[2] * M[2]);
+  gm[1] = jw * (M[0] * M[3] + M[1] * M[4] + M[2] * M[5]);
+  gm[2] = jw * (M[0] * M[6] + M[1] * M[7] + M[2] * M[8]);
+  gm[3] = jw * (M[3] * M[3] + M[4] * M[4] + M[5] * M[5]);
+  gm[4] = jw * (M[3] * M[6] + M[4] * M[7] + M[5] * M[8]);
+  gm[5] = jw * (M[6] * M[6] + M[7] * M[7] + M[8] * M[8]);
+  double* f = g.fac + e * (NFAC * Q3) + pt;
+  f[0] = jw;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) f[(c + 1) * Q3] = gm[c];
+  double* m = g.dxi + e * (NDXI * Q3) + pt;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    m[c * Q3] = M[c];
+    bad = bad || !isfinite(M[c]);
+  }
+  if (bad) atomicOr(g.status, 1);
+}
+
+}  // namespace shp

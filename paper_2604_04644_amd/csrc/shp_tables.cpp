@@ -1,0 +1,218 @@
+// Host construction of the reference tables of libshp: 1D quadrature rules,
+// modal basis functions and derivatives at the points, collocation
+// differentiation matrices and the sum-factorisation column table.
+//
+// Quadrature (Sec. 2.1): Gauss-Jacobi zeros by Newton iteration on the Jacobi
+// polynomial with deflation of the zeros already found, weights from the
+// Christoffel closed form; Gauss-Lobatto-Legendre as the end points plus the
+// Gauss-Jacobi(1,1) zeros, weights 2 / (Q (Q-1) P_{Q-1}(x)^2).
+// Collocation derivative (Sec. 2.2, eq. dphitodh): barycentric form of the
+// derivative of the Lagrange interpolant, D_ij = (l_j / l_i) / (x_i - x_j),
+// D_ii = -sum_{j != i} D_ij.
+#include <cmath>
+#include <vector>
+
+#include "shp_internal.hpp"
+
+namespace shp {
+
+static double jac_p(int n, double a, double b, double x) {
+  if (n == 0) return 1.0;
+  double p0 = 1.0, p1 = 0.5 * (a - b + (a + b + 2.0) * x);
+  for (int k = 2; k <= n; ++k) {
+    const double c = 2.0 * k + a + b;
+    const double a1 = 2.0 * k * (k + a + b) * (c - 2.0);
+    const double a2 = (c - 1.0) * (a * a - b * b);
+    const double a3 = (c - 2.0) * (c - 1.0) * c;
+    const double a4 = 2.0 * (k + a - 1.0) * (k + b - 1.0) * c;
+    const double p2 = ((a2 + a3 * x) * p1 - a4 * p0) / a1;
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+static double jac_dp(int n, double a, double b, double x) {
+  if (n == 0) return 0.0;
+  return 0.5 * (n + a + b + 1.0) * jac_p(n - 1, a + 1.0, b + 1.0, x);
+}
+
+void gauss_jacobi(int Q, double a, double b, double* x, double* w) {
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < Q; ++k) {
+    double r = -std::cos((2.0 * k + 1.0) * pi / (2.0 * Q));
+    if (k > 0) r = 0.5 * (r + x[k - 1]);
+    for (int it = 0; it < 100; ++it) {
+      double defl = 0.0;
+      for (int j = 0; j < k; ++j) defl += 1.0 / (r - x[j]);
+      const double f = jac_p(Q, a, b, r);
+      const double df = jac_dp(Q, a, b, r);
+      const double step = f / (df - defl * f);
+      r -= step;
+      if (std::fabs(step) < 1e-17) break;
+    }
+    x[k] = r;
+  }
+  // sort ascending (Newton from ascending guesses normally keeps order)
+  for (int i = 1; i < Q; ++i)
+    for (int j = i; j > 0 && x[j] < x[j - 1]; --j) std::swap(x[j], x[j - 1]);
+  const double lc = (a + b + 1.0) * std::log(2.0) + std::lgamma(Q + a + 1.0) + std::lgamma(Q + b + 1.0) -
+                    std::lgamma(Q + a + b + 1.0) - std::lgamma(Q + 1.0);
+  const double C = std::exp(lc);
+  for (int i = 0; i < Q; ++i) {
+    const double d = jac_dp(Q, a, b, x[i]);
+    w[i] = C / ((1.0 - x[i] * x[i]) * d * d);
+  }
+}
+
+void gauss_lobatto(int Q, double* x, double* w) {
+  x[0] = -1.0;
+  x[Q - 1] = 1.0;
+  if (Q > 2) {
+    std::vector<double> xi(Q - 2), wi(Q - 2);
+    gauss_jacobi(Q - 2, 1.0, 1.0, xi.data(), wi.data());
+    for (int i = 0; i < Q - 2; ++i) x[i + 1] = xi[i];
+  }
+  for (int i = 0; i < Q; ++i) {
+    const double pl = jac_p(Q - 1, 0.0, 0.0, x[i]);
+    w[i] = 2.0 / (Q * (Q - 1.0) * pl * pl);
+  }
+}
+
+void rule_1d(int Q, int alpha, double* x, double* w) {
+  if (alpha == 0)
+    gauss_lobatto(Q, x, w);
+  else
+    gauss_jacobi(Q, (double)alpha, 0.0, x, w);
+}
+
+// modified basis in one direction
+static double fA(int p, double z) {
+  if (p == 0) return 0.5 * (1.0 - z);
+  if (p == 1) return 0.5 * (1.0 + z);
+  return 0.25 * (1.0 - z) * (1.0 + z) * jac_p(p - 2, 1.0, 1.0, z);
+}
+static double fdA(int p, double z) {
+  if (p == 0) return -0.5;
+  if (p == 1) return 0.5;
+  return -0.5 * z * jac_p(p - 2, 1.0, 1.0, z) + 0.25 * (1.0 - z) * (1.0 + z) * jac_dp(p - 2, 1.0, 1.0, z);
+}
+static double fC(int k, int r, double z) {
+  if (k == 0) return fA(r, z);
+  const double v0 = 0.5 * (1.0 - z);
+  const double v0k = std::pow(v0, k);
+  if (r == 0) return v0k;
+  return v0k * 0.5 * (1.0 + z) * jac_p(r - 1, 2.0 * k - 1.0, 1.0, z);
+}
+static double fdC(int k, int r, double z) {
+  if (k == 0) return fdA(r, z);
+  const double v0 = 0.5 * (1.0 - z), v1 = 0.5 * (1.0 + z);
+  const double v0km1 = std::pow(v0, k - 1);
+  if (r == 0) return -0.5 * k * v0km1;
+  const double J = jac_p(r - 1, 2.0 * k - 1.0, 1.0, z);
+  const double dJ = jac_dp(r - 1, 2.0 * k - 1.0, 1.0, z);
+  return -0.5 * k * v0km1 * v1 * J + v0km1 * v0 * (0.5 * J + v1 * dJ);
+}
+
+static void colloc_deriv(int Q, const double* x, double* D) {
+  std::vector<double> l(Q);
+  for (int j = 0; j < Q; ++j) {
+    double p = 1.0;
+    for (int k = 0; k < Q; ++k)
+      if (k != j) p *= (x[j] - x[k]);
+    l[j] = 1.0 / p;
+  }
+  for (int i = 0; i < Q; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < Q; ++j) {
+      if (j == i) continue;
+      const double v = (l[j] / l[i]) / (x[i] - x[j]);
+      D[i * Q + j] = v;
+      s += v;
+    }
+    D[i * Q + i] = -s;
+  }
+}
+
+void build_tables(int sh, int P, std::vector<double>& tab, std::vector<int>& itab) {
+  const TabLayout L = tab_layout(sh, P);
+  const int Q = L.Q, n = L.n;
+  tab.assign(L.total, 0.0);
+  double* z = tab.data() + L.z;
+  double* w = tab.data() + L.w;
+  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), z + d * Q, w + d * Q);
+  const double* z1 = z;
+  const double* z2 = z + Q;
+  const double* z3 = z + 2 * Q;
+  for (int p = 0; p < n; ++p)
+    for (int i = 0; i < Q; ++i) {
+      tab[L.A1 + p * Q + i] = fA(p, z1[i]);
+      tab[L.dA1 + p * Q + i] = fdA(p, z1[i]);
+    }
+  if (sh == TET) {
+    for (int p = 0; p <= P; ++p)
+      for (int q = 0; q <= P - p; ++q)
+        for (int j = 0; j < Q; ++j) {
+          tab[L.B2 + fam_index(P, p, q) * Q + j] = fC(p, q, z2[j]);
+          tab[L.dB2 + fam_index(P, p, q) * Q + j] = fdC(p, q, z2[j]);
+        }
+  } else {
+    for (int q = 0; q <= P; ++q)
+      for (int j = 0; j < Q; ++j) {
+        tab[L.B2 + q * Q + j] = fA(q, z2[j]);
+        tab[L.dB2 + q * Q + j] = fdA(q, z2[j]);
+      }
+  }
+  const int kmax = (sh == HEX) ? 0 : P;
+  for (int k = 0; k <= kmax; ++k)
+    for (int r = 0; r <= P - k; ++r)
+      for (int kk = 0; kk < Q; ++kk) {
+        tab[L.C3 + fam_index(P, k, r) * Q + kk] = fC(k, r, z3[kk]);
+        tab[L.dC3 + fam_index(P, k, r) * Q + kk] = fdC(k, r, z3[kk]);
+      }
+  for (int d = 0; d < 3; ++d) colloc_deriv(Q, z + d * Q, tab.data() + L.D + d * Q * Q);
+
+  // column table, p-major, q, with the running mode offset
+  const int NC = num_cols(sh, P);
+  itab.assign(NC * ICOL, 0);
+  int c = 0, off = 0;
+  for (int p = 0; p <= P; ++p)
+    for (int q = 0; q < nq_of(sh, P, p); ++q) {
+      int* ct = itab.data() + c * ICOL;
+      ct[0] = p;
+      ct[1] = q;
+      ct[2] = off;
+      ct[3] = col_len(sh, P, p, q);
+      ct[4] = fam_index(P, kappa3(sh, p, q), 0);
+      off += ct[3];
+      ++c;
+    }
+}
+
+void reference_points(int sh, int Q, double* xi, double* wout) {
+  std::vector<double> z(3 * Q), w(3 * Q);
+  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), z.data() + d * Q, w.data() + d * Q);
+  const int Q3 = Q * Q * Q;
+  for (int i = 0; i < Q; ++i)
+    for (int j = 0; j < Q; ++j)
+      for (int k = 0; k < Q; ++k) {
+        const int pt = (i * Q + j) * Q + k;
+        const double e1 = z[i], e2 = z[Q + j], e3 = z[2 * Q + k];
+        double x1 = e1, x2 = e2, x3 = e3;
+        if (sh == PRISM) {
+          x1 = 0.5 * (1.0 + e1) * (1.0 - e3) - 1.0;
+        } else if (sh == PYR) {
+          x1 = 0.5 * (1.0 + e1) * (1.0 - e3) - 1.0;
+          x2 = 0.5 * (1.0 + e2) * (1.0 - e3) - 1.0;
+        } else if (sh == TET) {
+          x1 = 0.25 * (1.0 + e1) * (1.0 - e2) * (1.0 - e3) - 1.0;
+          x2 = 0.5 * (1.0 + e2) * (1.0 - e3) - 1.0;
+        }
+        xi[0 * Q3 + pt] = x1;
+        xi[1 * Q3 + pt] = x2;
+        xi[2 * Q3 + pt] = x3;
+        if (wout) wout[pt] = w[i] * w[Q + j] * w[2 * Q + k];
+      }
+}
+
+}  // namespace shp

@@ -1,0 +1,196 @@
+"""Python binding of libshp (include/shp.h): argument marshalling only.
+
+Every operator runs in the HIP kernels of libshp.so; this module passes torch
+tensor device pointers and the current HIP stream through the C ABI.  There is
+no fallback: if the library or a GPU is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshp.so")
+
+SHAPES = {"hex": 0, "prism": 1, "pyr": 2, "tet": 3}
+GEOM = {"affine": 0, "curved": 1}
+OPS = {"bwd": 0, "iprod": 1, "physderiv": 2, "iprod_deriv": 3, "mass": 4, "laplacian": 5, "helmholtz": 6}
+STRATEGY = {"auto": 0, "sumfac": 1, "sumfac_coll": 2}
+ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "BAD_GEOMETRY", -4: "WORKSPACE",
+          -5: "STATE", -6: "DEVICE", -7: "NOT_CONVERGED"}
+
+# exported symbols with their argument types
+_SIGS = {
+    "shp_num_modes": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "shp_num_points": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "shp_quadrature": [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+    "shp_plan_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_int],
+    "shp_plan_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "shp_plan_bind_workspace": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "shp_plan_set_geometry": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+    "shp_block_offsets": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(ctypes.c_int64)],
+    "shp_apply": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_double, ctypes.c_void_p],
+    "shp_set_tiling": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+    "shp_get_tiling": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                       ctypes.POINTER(ctypes.c_int)],
+    "shp_plan_destroy": [ctypes.c_void_p],
+}
+
+_lib = None
+
+
+class ShpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _BlockDesc(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int), ("P", ctypes.c_int), ("Q", ctypes.c_int),
+                ("n_elem", ctypes.c_int64), ("geom", ctypes.c_int)]
+
+
+def lib() -> ctypes.CDLL:
+    """Load libshp.so (built in-tree by paper_2604_04644_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_04644_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.shp_last_error.argtypes = []
+        L.shp_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != 0:
+        raise ShpError(code, lib().shp_last_error().decode())
+
+
+def num_modes(shape: str, P: int) -> int:
+    n = ctypes.c_int()
+    _check(lib().shp_num_modes(SHAPES[shape], P, ctypes.byref(n)))
+    return n.value
+
+
+def num_points(shape: str, Q: int) -> int:
+    n = ctypes.c_int()
+    _check(lib().shp_num_points(SHAPES[shape], Q, ctypes.byref(n)))
+    return n.value
+
+
+def quadrature(shape: str, Q: int):
+    """Reference points xi [Q^3, 3] and weights [Q^3] (numpy, host)."""
+    import numpy as np
+    Q3 = Q ** 3
+    xi = np.empty((3, Q3))
+    w = np.empty(Q3)
+    _check(lib().shp_quadrature(SHAPES[shape], Q, xi.ctypes.data, w.ctypes.data))
+    return np.ascontiguousarray(xi.T), w
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A plan over blocks [(shape, P, n_elem, geom)], with its workspace held as
+    a torch uint8 tensor on the current device."""
+
+    def __init__(self, blocks: Sequence, device=None):
+        import torch
+        self._torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libshp needs a HIP device; none is visible")
+        self.blocks = [(b[0], int(b[1]), int(b[2]), b[3] if len(b) > 3 else "curved") for b in blocks]
+        arr = (_BlockDesc * len(self.blocks))()
+        for i, (sh, P, ne, geom) in enumerate(self.blocks):
+            arr[i] = _BlockDesc(SHAPES[sh], P, P + 2, ne, GEOM[geom])
+        h = ctypes.c_void_p()
+        _check(lib().shp_plan_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p), len(self.blocks)))
+        self._h = h
+        nb = ctypes.c_size_t()
+        _check(lib().shp_plan_workspace_bytes(self._h, ctypes.byref(nb)))
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        _check(lib().shp_plan_bind_workspace(self._h, ctypes.c_void_p(self._ws_ptr), nb.value, _stream(torch)))
+        self.n_modes = [num_modes(sh, P) for sh, P, _, _ in self.blocks]
+        self.n_points = [(P + 2) ** 3 for _, P, _, _ in self.blocks]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.shp_plan_destroy(h)
+            self._h = None
+
+    # ---------------------------------------------------------------
+    def set_geometry(self, blk: int, jac):
+        """jac: float64 device tensor [n][9][Q^3] (curved) or [n][9] (affine)."""
+        t = self._torch
+        sh, P, ne, geom = self.blocks[blk]
+        want = (ne, 9, (P + 2) ** 3) if geom == "curved" else (ne, 9)
+        if tuple(jac.shape) != want or jac.dtype != t.float64 or not jac.is_cuda or not jac.is_contiguous():
+            raise ValueError(f"jac must be a contiguous float64 device tensor of shape {want}")
+        _check(lib().shp_plan_set_geometry(self._h, blk, ctypes.c_void_p(jac.data_ptr()), _stream(t)))
+
+    def offsets(self, blk: int):
+        c, p = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().shp_block_offsets(self._h, blk, ctypes.byref(c), ctypes.byref(p)))
+        return c.value, p.value
+
+    def totals(self):
+        nc = sum(b[2] * m for b, m in zip(self.blocks, self.n_modes))
+        npnt = sum(b[2] * q for b, q in zip(self.blocks, self.n_points))
+        return nc, npnt
+
+    def _out_shape(self, blk: int, op: str):
+        if blk >= 0:
+            ne = self.blocks[blk][2]
+            nm, nq = self.n_modes[blk], self.n_points[blk]
+            return {"bwd": (ne, nq), "physderiv": (3, ne, nq)}.get(op, (ne, nm))
+        nc, npnt = self.totals()
+        return {"bwd": (npnt,), "physderiv": (3, npnt)}.get(op, (nc,))
+
+    def _in_numel(self, blk: int, op: str):
+        if blk >= 0:
+            ne = self.blocks[blk][2]
+            nm, nq = self.n_modes[blk], self.n_points[blk]
+        else:
+            nm, nq, ne = None, None, None
+            nc, npnt = self.totals()
+            return {"iprod": npnt, "physderiv": npnt, "iprod_deriv": 3 * npnt}.get(op, nc)
+        return {"iprod": ne * nq, "physderiv": ne * nq, "iprod_deriv": 3 * ne * nq}.get(op, ne * nm)
+
+    def apply(self, blk: int, op: str, x, out=None, lam: float = 1.0, strategy: str = "sumfac_coll"):
+        """y = op(x) for block blk (or the whole mesh, blk = -1)."""
+        t = self._torch
+        if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous float64 device tensor")
+        if x.numel() != self._in_numel(blk, op):
+            raise ValueError(f"x has {x.numel()} values, {op} on block {blk} takes {self._in_numel(blk, op)}")
+        if out is None:
+            out = t.empty(self._out_shape(blk, op), dtype=t.float64, device=x.device)
+        elif out.dtype != t.float64 or not out.is_contiguous() or out.numel() != int(
+                t.Size(self._out_shape(blk, op)).numel()):
+            raise ValueError("bad output tensor")
+        _check(lib().shp_apply(self._h, blk, OPS[op], STRATEGY[strategy], ctypes.c_void_p(x.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr()), float(lam), _stream(t)))
+        return out
+
+    def set_tiling(self, blk: int, op: str, E: int, NT: int, strategy: str = "sumfac_coll"):
+        _check(lib().shp_set_tiling(self._h, blk, OPS[op], STRATEGY[strategy], E, NT))
+
+    def get_tiling(self, blk: int, op: str, strategy: str = "sumfac_coll"):
+        E, NT = ctypes.c_int(), ctypes.c_int()
+        _check(lib().shp_get_tiling(self._h, blk, OPS[op], STRATEGY[strategy], ctypes.byref(E), ctypes.byref(NT)))
+        return E.value, NT.value

@@ -1,0 +1,117 @@
+"""CPU tests of the C ABI: the library loads, exports every declared symbol,
+and validates its arguments before any HIP call (so error paths run without a
+GPU).  Host-side reference data (quadrature points and weights) are compared
+with the oracle's independent construction."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import shp_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "shp.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2604_04644_amd import shp
+    if not os.path.exists(shp.LIB_PATH):
+        pytest.skip("libshp.so not built")
+    return shp.lib()
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(shp_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(L):
+    syms = declared_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_num_modes_and_points(L):
+    from paper_2604_04644_amd import shp
+    for shape in O.SHAPES:
+        for P in range(1, 11):
+            assert shp.num_modes(shape, P) == O.num_modes(shape, P)
+        assert shp.num_points(shape, 6) == 216
+
+
+@pytest.mark.parametrize("shape", O.SHAPES)
+@pytest.mark.parametrize("Q", [3, 4, 6, 8, 12])
+def test_quadrature_matches_oracle(L, shape, Q):
+    """Library rule (Newton on Jacobi polynomials) vs the oracle's Golub-Welsch."""
+    from paper_2604_04644_amd import shp
+    xi, w = shp.quadrature(shape, Q)
+    eta, wo, _ = O.quadrature(shape, Q)
+    assert np.abs(xi - O.collapse(shape, eta)).max() < 2e-15
+    assert np.abs(w - wo).max() < 1e-14 * max(1.0, np.abs(wo).max())
+
+
+def _code(L, f, *args):
+    return f(*args)
+
+
+def test_error_paths_without_device(L):
+    from paper_2604_04644_amd import shp
+    n = ctypes.c_int()
+    assert L.shp_num_modes(7, 3, ctypes.byref(n)) == -1          # bad shape
+    assert L.shp_num_modes(0, 11, ctypes.byref(n)) == -2         # P out of range
+    assert L.shp_num_modes(0, 0, ctypes.byref(n)) == -2
+    assert L.shp_num_modes(0, 3, None) == -1                     # null output
+    assert L.shp_quadrature(0, 6, None, None) == -1
+    assert "null" in L.shp_last_error().decode()
+
+    def plan(descs):
+        arr = (shp._BlockDesc * len(descs))(*[shp._BlockDesc(*d) for d in descs])
+        h = ctypes.c_void_p()
+        rc = L.shp_plan_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p), len(descs))
+        return rc, h
+
+    assert plan([(0, 4, 5, 10, 1)])[0] == -2                     # Q != P+2
+    assert plan([(0, 11, 13, 10, 1)])[0] == -2                   # P > 10
+    assert plan([(9, 4, 6, 10, 1)])[0] == -1                     # bad shape
+    assert plan([(0, 4, 6, -1, 1)])[0] == -1                     # negative count
+    assert plan([(0, 4, 6, 10, 5)])[0] == -1                     # bad geom
+    rc, h = plan([(0, 4, 6, 10, 1), (3, 4, 6, 7, 1)])
+    assert rc == 0
+    nb = ctypes.c_size_t()
+    assert L.shp_plan_workspace_bytes(h, ctypes.byref(nb)) == 0
+    # hex: 10 elements * 16 factors * 216 points * 8 bytes at least
+    assert nb.value >= (10 + 7) * 16 * 216 * 8
+    # apply / geometry before a workspace is bound
+    buf = (ctypes.c_double * 8)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.shp_apply(h, 0, 6, 2, p, p, 1.0, None) == -5
+    assert L.shp_plan_set_geometry(h, 0, p, None) == -5
+    # bad arguments
+    assert L.shp_apply(h, 5, 6, 2, p, p, 1.0, None) == -1        # block index
+    assert L.shp_apply(h, 0, 9, 2, p, p, 1.0, None) == -1        # operator
+    assert L.shp_apply(h, 0, 6, 7, p, p, 1.0, None) == -1        # strategy
+    assert L.shp_apply(h, 0, 6, 2, None, p, 1.0, None) == -1     # null input
+    assert L.shp_apply(h, 0, 6, 2, p, p, float("nan"), None) == -1
+    assert L.shp_apply(h, 0, 6, 1, p, p, 1.0, None) == -2        # non-collocated not built
+    # workspace validation (no device call is reached)
+    assert L.shp_plan_bind_workspace(h, None, nb.value, None) == -4
+    assert L.shp_plan_bind_workspace(h, ctypes.c_void_p(256 * 1000 + 8), nb.value, None) == -4
+    assert L.shp_plan_bind_workspace(h, ctypes.c_void_p(256 * 1000), nb.value - 1, None) == -4
+    # tiling validation
+    assert L.shp_set_tiling(h, 0, 6, 2, 0, 256) == -1
+    assert L.shp_set_tiling(h, 0, 6, 2, 4, 100) == -1
+    assert L.shp_set_tiling(h, 0, 6, 2, 64, 256) == -2           # LDS overflow at P=4
+    assert L.shp_set_tiling(h, 0, 6, 2, 4, 128) == 0
+    E, NT = ctypes.c_int(), ctypes.c_int()
+    assert L.shp_get_tiling(h, 0, 6, 2, ctypes.byref(E), ctypes.byref(NT)) == 0
+    assert (E.value, NT.value) == (4, 128)
+    assert L.shp_set_tiling(h, 0, 6, 2, 0, 0) == 0               # back to default
+    c, q = ctypes.c_int64(), ctypes.c_int64()
+    assert L.shp_block_offsets(h, 1, ctypes.byref(c), ctypes.byref(q)) == 0
+    assert (c.value, q.value) == (10 * 125, 10 * 216)
+    assert L.shp_plan_destroy(h) == 0
+    assert L.shp_plan_destroy(None) == -1

@@ -1,0 +1,255 @@
+"""GPU parity of libshp against the FP64 oracle, through the C ABI.
+
+Every case prints its name before touching the GPU.  The bar is the max-norm
+error relative to the max-norm of the oracle's result, <= 1e-12 in FP64 (the
+two differ only by summation order; the survey's scratch check measured
+<= 8e-14).  Inputs: the library's quadrature points feed the GPU geometry, the
+oracle's own points feed the oracle's geometry; coefficients and point data are
+U[-1,1] from seeded generators.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import shp_oracle as O
+from paper_2604_04644_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+OPS = ["bwd", "iprod", "physderiv", "iprod_deriv", "mass", "laplacian", "helmholtz"]
+
+
+@pytest.fixture(scope="module")
+def shp():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2604_04644_amd import shp as S
+    S.lib()
+    return S
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def op_input(op, ne, NP, NQ, seed):
+    if op in ("iprod", "physderiv"):
+        return W.point_values(ne, NQ, seed)
+    if op == "iprod_deriv":
+        return W.point_values(ne, NQ, seed, ncomp=3)
+    return W.coeffs(ne, NP, seed)
+
+
+def gpu_geometry(shp, maps, shape, P, curved):
+    xi, _ = shp.quadrature(shape, P + 2)
+    if curved:
+        jac = W.jacobian(maps, xi, curved=True)
+    else:
+        jac = W.affine_jacobian(maps)
+    return torch.from_numpy(np.ascontiguousarray(jac)).cuda()
+
+
+def oracle_geometry(maps, shape, P, curved):
+    if curved:
+        return W.jacobian(maps, O.reference_points(shape, P + 2), curved=True)
+    return W.affine_jacobian(maps)
+
+
+CASES = [(s, P) for s in O.SHAPES for P in (1, 2, 3, 4, 5, 6, 8, 10)]
+
+
+@pytest.mark.parametrize("shape,P", CASES)
+def test_block_ops_vs_oracle(shp, shape, P):
+    """All seven operators on a ragged batch of curved elements."""
+    ne = 37 if P <= 6 else (9 if P == 8 else 4)
+    say(f"[parity] block ops shape={shape} P={P} n_elem={ne}")
+    maps = W.shape_batch(shape, ne)
+    NP, NQ = O.num_modes(shape, P), (P + 2) ** 3
+    plan = shp.Plan([(shape, P, ne, "curved")])
+    plan.set_geometry(0, gpu_geometry(shp, maps, shape, P, True))
+    jo = oracle_geometry(maps, shape, P, True)
+    for k, op in enumerate(OPS):
+        x = op_input(op, ne, NP, NQ, 100 + k)
+        ref = O.apply_op(op, shape, P, P + 2, jo, x, lam=1.0, chunk=8)
+        y = plan.apply(0, op, torch.from_numpy(np.ascontiguousarray(x)).cuda(), lam=1.0)
+        torch.cuda.synchronize()
+        e = rel(y.cpu().numpy().reshape(ref.shape), ref)
+        say(f"    {op:12s} rel={e:.2e}")
+        assert e <= TOL, (shape, P, op, e)
+
+
+@pytest.mark.parametrize("shape", O.SHAPES)
+def test_affine_blocks_vs_oracle(shp, shape):
+    P, ne = 3, 21
+    say(f"[parity] affine shape={shape} P={P}")
+    maps = W.shape_batch(shape, ne)
+    NP, NQ = O.num_modes(shape, P), (P + 2) ** 3
+    plan = shp.Plan([(shape, P, ne, "affine")])
+    plan.set_geometry(0, gpu_geometry(shp, maps, shape, P, False))
+    jo = oracle_geometry(maps, shape, P, False)
+    for k, op in enumerate(OPS):
+        x = op_input(op, ne, NP, NQ, 200 + k)
+        ref = O.apply_op(op, shape, P, P + 2, jo, x, lam=2.5)
+        y = plan.apply(0, op, torch.from_numpy(np.ascontiguousarray(x)).cuda(), lam=2.5)
+        e = rel(y.cpu().numpy().reshape(ref.shape), ref)
+        assert e <= TOL, (shape, op, e)
+
+
+def test_config1_affine_hex_helmholtz(shp):
+    """64 affine hexes of side 1/4, P=2, Q=4, lambda=1, seed 0."""
+    say("[parity] config-1 affine hex grid")
+    maps = W.affine_hex_grid(4)
+    P = 2
+    x = W.coeffs(64, 27, W.SEED_CFG1)
+    plan = shp.Plan([("hex", P, 64, "affine")])
+    plan.set_geometry(0, torch.from_numpy(W.affine_jacobian(maps)).cuda())
+    y = plan.apply(0, "helmholtz", torch.from_numpy(x).cuda(), lam=1.0).cpu().numpy()
+    ref = O.apply_op("helmholtz", "hex", P, 4, W.affine_jacobian(maps), x, lam=1.0)
+    assert rel(y, ref) <= TOL
+
+
+def _mixed_plan(shp, ncell, P):
+    mesh = W.quadrant_mesh(ncell)
+    blocks = [(s, P, len(mesh[s]), "curved") for s in O.SHAPES]
+    plan = shp.Plan(blocks)
+    for b, s in enumerate(O.SHAPES):
+        plan.set_geometry(b, gpu_geometry(shp, mesh[s], s, P, True))
+    return mesh, plan
+
+
+@pytest.mark.parametrize("P", [1, 3, 4])
+def test_whole_mesh_launch(shp, P):
+    """One mixed-shape launch equals the per-block launches bitwise and the oracle
+    to the FP64 bar, for every operator."""
+    say(f"[parity] whole-mesh launch P={P}")
+    mesh, plan = _mixed_plan(shp, 4, P)
+    nc, npnt = plan.totals()
+    for k, op in enumerate(OPS):
+        if op in ("iprod", "physderiv"):
+            x = W.point_values(1, npnt, 300 + k)[0]
+        elif op == "iprod_deriv":
+            x = W.point_values(1, npnt, 300 + k, ncomp=3).reshape(3, npnt)
+        else:
+            x = W.coeffs(1, nc, 300 + k)[0]
+        xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        y = plan.apply(-1, op, xt, lam=1.0).cpu().numpy()
+        for b, s in enumerate(O.SHAPES):
+            co, po = plan.offsets(b)
+            ne = len(mesh[s])
+            NP, NQ = plan.n_modes[b], plan.n_points[b]
+            if op in ("iprod", "physderiv"):
+                xb = x[po:po + ne * NQ].reshape(ne, NQ)
+            elif op == "iprod_deriv":
+                xb = x[:, po:po + ne * NQ].reshape(3, ne, NQ)
+            else:
+                xb = x[co:co + ne * NP].reshape(ne, NP)
+            yb = plan.apply(b, op, torch.from_numpy(np.ascontiguousarray(xb)).cuda(), lam=1.0).cpu().numpy()
+            if op == "bwd":
+                ym = y[po:po + ne * NQ].reshape(yb.shape)
+            elif op == "physderiv":
+                ym = y.reshape(3, -1)[:, po:po + ne * NQ].reshape(yb.shape)
+            else:
+                ym = y[co:co + ne * NP].reshape(yb.shape)
+            assert np.array_equal(ym, yb), (op, s)
+            ref = O.apply_op(op, s, P, P + 2, oracle_geometry(mesh[s], s, P, True), xb, lam=1.0)
+            assert rel(yb.reshape(ref.shape), ref) <= TOL, (op, s)
+
+
+@pytest.mark.parametrize("shape", O.SHAPES)
+def test_tilings_agree_bitwise(shp, shape):
+    """Every launch shape computes each element with the same arithmetic."""
+    P, ne = 4, 53
+    say(f"[parity] tilings shape={shape}")
+    maps = W.shape_batch(shape, ne)
+    plan = shp.Plan([(shape, P, ne, "curved")])
+    plan.set_geometry(0, gpu_geometry(shp, maps, shape, P, True))
+    x = torch.from_numpy(W.coeffs(ne, plan.n_modes[0], 9)).cuda()
+    base = plan.apply(0, "helmholtz", x).cpu().numpy()
+    for E, NT in ((1, 64), (2, 128), (5, 256), (8, 512), (3, 192)):
+        plan.set_tiling(0, "helmholtz", E, NT)
+        y = plan.apply(0, "helmholtz", x).cpu().numpy()
+        assert np.array_equal(y, base), (E, NT)
+
+
+def test_bad_geometry_is_reported(shp):
+    say("[parity] bad geometry error path")
+    maps = W.shape_batch("tet", 6)
+    jac = gpu_geometry(shp, maps, "tet", 2, True)
+    jac[3, 0:3, :] *= -1.0         # reflect element 3 (negate row 0 of dx/dxi): det < 0
+    plan = shp.Plan([("tet", 2, 6, "curved")])
+    with pytest.raises(shp.ShpError) as ei:
+        plan.set_geometry(0, jac)
+    assert ei.value.code == -3
+    x = torch.zeros(6, plan.n_modes[0], dtype=torch.float64, device="cuda")
+    with pytest.raises(shp.ShpError):
+        plan.apply(0, "helmholtz", x)
+
+
+def test_empty_block(shp):
+    say("[parity] empty block")
+    plan = shp.Plan([("hex", 3, 0, "curved"), ("tet", 3, 5, "curved")])
+    maps = W.shape_batch("tet", 5)
+    plan.set_geometry(0, torch.zeros(0, 9, 125, dtype=torch.float64, device="cuda"))
+    plan.set_geometry(1, gpu_geometry(shp, maps, "tet", 3, True))
+    x = torch.from_numpy(W.coeffs(1, plan.totals()[0], 3)[0]).cuda()
+    y = plan.apply(-1, "helmholtz", x).cpu().numpy()
+    ref = O.apply_op("helmholtz", "tet", 3, 5, oracle_geometry(maps, "tet", 3, True),
+                     x.cpu().numpy().reshape(5, -1))
+    assert rel(y.reshape(ref.shape), ref) <= TOL
+
+
+def _sample(ne, k, rng):
+    idx = set([0, ne - 1]) | set(rng.choice(ne, size=min(k, ne), replace=False).tolist())
+    return np.array(sorted(idx))
+
+
+@pytest.fixture(scope="module")
+def cfg2(shp):
+    say("[parity] building the 32^3 mixed mesh at P=4")
+    return _mixed_plan(shp, 32, 4)
+
+
+@pytest.mark.parametrize("op", ["helmholtz", "bwd", "iprod", "physderiv"])
+def test_config2_full_mesh_sampled(shp, cfg2, op):
+    """The mixed P=4 mesh (32^3 cells, 122,880 curved elements) in one launch;
+    the oracle checks a sample of elements of every shape."""
+    say(f"[parity] config-2 full mesh op={op}")
+    P = 4
+    mesh, plan = cfg2
+    nc, npnt = plan.totals()
+    seeds = W.SEED_MIXED
+    if op in ("iprod", "physderiv"):
+        parts = [W.point_values(len(mesh[s]), (P + 2) ** 3, seeds[s]).ravel() for s in O.SHAPES]
+    else:
+        parts = [W.coeffs(len(mesh[s]), plan.n_modes[b], seeds[s]).ravel() for b, s in enumerate(O.SHAPES)]
+    x = np.concatenate(parts)
+    y = plan.apply(-1, op, torch.from_numpy(x).cuda(), lam=1.0).cpu().numpy()
+    rng = np.random.default_rng(77)
+    for b, s in enumerate(O.SHAPES):
+        co, po = plan.offsets(b)
+        ne = len(mesh[s])
+        NP, NQ = plan.n_modes[b], plan.n_points[b]
+        idx = _sample(ne, 40, rng)
+        sub = mesh[s].take(idx)
+        jo = oracle_geometry(sub, s, P, True)
+        if op in ("iprod", "physderiv"):
+            xb = x[po:po + ne * NQ].reshape(ne, NQ)[idx]
+        else:
+            xb = x[co:co + ne * NP].reshape(ne, NP)[idx]
+        ref = O.apply_op(op, s, P, P + 2, jo, xb, lam=1.0)
+        if op == "bwd":
+            yb = y[po:po + ne * NQ].reshape(ne, NQ)[idx]
+        elif op == "physderiv":
+            yb = y.reshape(3, -1)[:, po:po + ne * NQ].reshape(3, ne, NQ)[:, idx]
+        else:
+            yb = y[co:co + ne * NP].reshape(ne, NP)[idx]
+        e = rel(yb, ref)
+        say(f"    {s:5s} sampled {len(idx)} rel={e:.2e}")
+        assert e <= TOL, (s, e)
