@@ -140,13 +140,18 @@ int shp_block_offsets(shp_plan plan, int blk, int64_t* coeff_off /* host out */,
 int shp_apply(shp_plan plan, int blk, int op, int strategy, const double* in /* device */,
               double* out /* device */, double lambda, void* stream);
 
-/* Fix the launch shape used for (blk, op, strategy): elements per work-group
- * and threads per work-group (0, 0 restores the default).  Used by tuning. */
-int shp_set_tiling(shp_plan plan, int blk, int op, int strategy, int elems_per_wg, int threads);
+/* Fix the launch shape used for (blk, op, strategy), blk = -1 for the
+ * whole-mesh launch: elements per work-group (1..64, within the 160 KiB LDS of
+ * a work-group), threads per work-group (multiple of 64 in [64,512]) and, for
+ * the Laplacian and Helmholtz actions, persistent = 1 to run persistent
+ * work-groups that prefetch each tile's geometric factors into registers
+ * (used when elems_per_wg * Q^3 <= 8 * threads, else the one-tile-per-work-group
+ * kernel runs).  (0, 0, 0) restores the default.  Used by tuning. */
+int shp_set_tiling(shp_plan plan, int blk, int op, int strategy, int elems_per_wg, int threads, int persistent);
 
 /* Current launch shape for (blk, op, strategy). */
 int shp_get_tiling(shp_plan plan, int blk, int op, int strategy, int* elems_per_wg /* host out */,
-                   int* threads /* host out */);
+                   int* threads /* host out */, int* persistent /* host out */);
 
 /* Destroy a plan (host metadata only; the workspace stays the caller's). */
 int shp_plan_destroy(shp_plan plan);

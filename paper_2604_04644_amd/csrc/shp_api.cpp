@@ -40,6 +40,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Tiling {
   int E = 0;
   int NT = 0;
+  int persist = 1;  // Laplacian/Helmholtz: persistent work-groups with prefetched geometry
 };
 
 struct Block {
@@ -93,14 +94,17 @@ int opk_of(int op, int strategy, int* opk) {
 bool in_is_modes(int opk) { return opk == OPK_BWD || opk == OPK_MASS || opk == OPK_LAP || opk == OPK_HELM || opk == OPK_HELM_NC; }
 bool out_is_modes(int opk) { return !(opk == OPK_BWD || opk == OPK_DERIV); }
 
-// Default launch shape: as many elements per work-group as fit a 64 KiB LDS
-// budget (at most 16), 256 threads.
+// Default launch shape: as many elements per work-group as fit a 40 KiB LDS
+// budget (at most 16; several work-groups share a CU), 256 threads, persistent
+// work-groups for the Laplacian and Helmholtz actions when the metric stage's
+// points fit the register slots.
 Tiling default_tiling(int sh, int P, int opk) {
   Tiling t;
   t.NT = 256;
   int E = 1;
-  while (E < 16 && op_lds_bytes(sh, P, opk, E + 1) <= 64 * 1024) ++E;
+  while (E < 16 && op_lds_bytes(sh, P, opk, E + 1) <= 40 * 1024) ++E;
   t.E = E;
+  t.persist = points_per_thread((long long)E * (P + 2) * (P + 2) * (P + 2), t.NT) > 0 ? 1 : 0;
   return t;
 }
 
@@ -295,7 +299,7 @@ int shp_block_offsets(shp_plan p, int blk, int64_t* coeff_off, int64_t* phys_off
   return SHP_OK;
 }
 
-int shp_set_tiling(shp_plan p, int blk, int op, int strategy, int E, int NT) {
+int shp_set_tiling(shp_plan p, int blk, int op, int strategy, int E, int NT, int persistent) {
   if (int r = check_plan(p)) return r;
   int opk;
   if (int r = opk_of(op, strategy, &opk)) return r;
@@ -313,9 +317,11 @@ int shp_set_tiling(shp_plan p, int blk, int op, int strategy, int E, int NT) {
           return fail(SHP_ERR_UNSUPPORTED, "%d elements exceed the LDS of a work-group", E);
     }
   }
+  if (persistent != 0 && persistent != 1) return fail(SHP_ERR_INVALID_ARG, "persistent must be 0 or 1");
   Tiling t;
   t.E = E;
   t.NT = NT;
+  t.persist = persistent;
   if (blk >= 0)
     p->blocks[blk].tiling[opk] = t;
   else {
@@ -327,12 +333,12 @@ int shp_set_tiling(shp_plan p, int blk, int op, int strategy, int E, int NT) {
 
 static Tiling mixed_tiling(shp_plan p, int opk);
 
-int shp_get_tiling(shp_plan p, int blk, int op, int strategy, int* E, int* NT) {
+int shp_get_tiling(shp_plan p, int blk, int op, int strategy, int* E, int* NT, int* persistent) {
   if (int r = check_plan(p)) return r;
   int opk;
   if (int r = opk_of(op, strategy, &opk)) return r;
   if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
-  if (!E || !NT) return fail(SHP_ERR_INVALID_ARG, "null output");
+  if (!E || !NT || !persistent) return fail(SHP_ERR_INVALID_ARG, "null output");
   Tiling t;
   if (blk >= 0) {
     const Block& B = p->blocks[blk];
@@ -342,6 +348,7 @@ int shp_get_tiling(shp_plan p, int blk, int op, int strategy, int* E, int* NT) {
   }
   *E = t.E;
   *NT = t.NT;
+  *persistent = t.persist;
   return SHP_OK;
 }
 
@@ -350,11 +357,12 @@ int shp_get_tiling(shp_plan p, int blk, int op, int strategy, int* E, int* NT) {
 static Tiling mixed_tiling(shp_plan p, int opk) {
   Tiling t = p->mixed[opk];
   if (t.E > 0 && t.NT > 0) return t;
-  t = Tiling{64, 512};
+  t = Tiling{64, 512, 1};
   for (const auto& B : p->blocks) {
     const Tiling d = default_tiling(B.d.shape, B.d.P, opk);
     t.E = std::min(t.E, d.E);
     t.NT = std::min(t.NT, d.NT);
+    t.persist = std::min(t.persist, d.persist);
   }
   return t;
 }
@@ -419,7 +427,7 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
     a.out_cs = a.in_cs;
     a.lambda = lambda;
     a.E = t.E;
-    hipError_t e = launch_block(B.d.shape, B.d.P, opk, a, t.NT, s);
+    hipError_t e = launch_block(B.d.shape, B.d.P, opk, a, t.NT, t.persist, s);
     if (e != hipSuccess) return dev_fail(e, "operator launch");
     return SHP_OK;
   }
@@ -445,7 +453,7 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
       a.out_cs = p->total_phys;
       a.lambda = lambda;
       a.E = t.E;
-      hipError_t e = launch_block(B.d.shape, B.d.P, opk, a, t.NT, s);
+      hipError_t e = launch_block(B.d.shape, B.d.P, opk, a, t.NT, t.persist, s);
       if (e != hipSuccess) return dev_fail(e, "operator launch");
     }
     return SHP_OK;
@@ -458,7 +466,7 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
   for (const auto& B : p->blocks) lds = std::max(lds, op_lds_bytes(B.d.shape, B.d.P, opk, E));
   const Tile* tiles = reinterpret_cast<const Tile*>(p->ws + p->off_tiles) + (size_t)opk * p->max_tiles;
   hipError_t e = launch_mixed(p->blocks[0].d.P, opk, reinterpret_cast<const BlockStatic*>(p->ws + p->off_bstat), tiles,
-                              p->mixed_ntiles[opk], in, out, p->total_phys, p->total_phys, lambda, NT, lds, s);
+                              p->mixed_ntiles[opk], in, out, p->total_phys, p->total_phys, lambda, NT, lds, E, mt.persist, s);
   if (e != hipSuccess) return dev_fail(e, "mixed launch");
   return SHP_OK;
 }

@@ -36,11 +36,16 @@ void reference_points(int sh, int Q, double* xi, double* w);
 
 // launchers (shp_k_*.hip); return hipSuccess or the launch error
 size_t op_lds_bytes(int sh, int P, int opk, int E);
-hipError_t launch_block(int sh, int P, int opk, const OpArgs& a, int threads, hipStream_t s);
+hipError_t launch_block(int sh, int P, int opk, const OpArgs& a, int threads, int persist, hipStream_t s);
 hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
-                        double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds,
-                        hipStream_t s);
+                        double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds, int E,
+                        int persist, hipStream_t s);
+// persistent launches: CUs of the current device, grid = occupancy * CUs, and
+// the register slots per thread of the metric stage (2, 4, 8; 0 = too many)
+int num_cus();
+long long persistent_grid(const void* kernel, int threads, size_t lds);
+int points_per_thread(long long points, int threads);
 
 constexpr int MAX_P = 10;
 constexpr size_t LDS_LIMIT = 160 * 1024;

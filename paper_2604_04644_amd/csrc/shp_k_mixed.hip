@@ -1,13 +1,15 @@
 // Mixed-shape kernels (one launch over every block of a whole mesh) and the
 // dispatch from runtime (shape, P, operator) to the templated launchers.
+#include <algorithm>
+
 #include "shp_kernels.hpp"
 
 namespace shp {
 
-hipError_t launch_block_hex(int P, int opk, const OpArgs& a, int threads, hipStream_t s);
-hipError_t launch_block_prism(int P, int opk, const OpArgs& a, int threads, hipStream_t s);
-hipError_t launch_block_pyr(int P, int opk, const OpArgs& a, int threads, hipStream_t s);
-hipError_t launch_block_tet(int P, int opk, const OpArgs& a, int threads, hipStream_t s);
+hipError_t launch_block_hex(int P, int opk, const OpArgs& a, int threads, int persist, hipStream_t s);
+hipError_t launch_block_prism(int P, int opk, const OpArgs& a, int threads, int persist, hipStream_t s);
+hipError_t launch_block_pyr(int P, int opk, const OpArgs& a, int threads, int persist, hipStream_t s);
+hipError_t launch_block_tet(int P, int opk, const OpArgs& a, int threads, int persist, hipStream_t s);
 hipError_t launch_geometry_hex(int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_geometry_prism(int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_geometry_pyr(int P, const GeomArgs& g, hipStream_t s);
@@ -27,13 +29,36 @@ size_t op_lds_bytes(int sh, int P, int opk, int E) {
   }
 }
 
-hipError_t launch_block(int sh, int P, int opk, const OpArgs& a, int threads, hipStream_t s) {
+hipError_t launch_block(int sh, int P, int opk, const OpArgs& a, int threads, int persist, hipStream_t s) {
   switch (sh) {
-    case HEX: return launch_block_hex(P, opk, a, threads, s);
-    case PRISM: return launch_block_prism(P, opk, a, threads, s);
-    case PYR: return launch_block_pyr(P, opk, a, threads, s);
-    default: return launch_block_tet(P, opk, a, threads, s);
+    case HEX: return launch_block_hex(P, opk, a, threads, persist, s);
+    case PRISM: return launch_block_prism(P, opk, a, threads, persist, s);
+    case PYR: return launch_block_pyr(P, opk, a, threads, persist, s);
+    default: return launch_block_tet(P, opk, a, threads, persist, s);
   }
+}
+
+int num_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+    cus[dev] = n;
+  }
+  return cus[dev];
+}
+
+long long persistent_grid(const void* kernel, int threads, size_t lds) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, lds) != hipSuccess || occ < 1) occ = 1;
+  return (long long)occ * num_cus();
+}
+
+int points_per_thread(long long points, int threads) {
+  const long long need = (points + threads - 1) / threads;
+  return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 0;
 }
 
 hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s) {
@@ -45,11 +70,39 @@ hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s) {
   }
 }
 
+template <int P, int OP, int PPT>
+static hipError_t launch_mixed_hp(const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
+                                  double* out, double lambda, int threads, size_t lds, hipStream_t s) {
+  const long long grid =
+      std::min<long long>(ntiles, persistent_grid((const void*)k_helm_mixed_persist<P, OP, PPT>, threads, lds));
+  hipLaunchKernelGGL((k_helm_mixed_persist<P, OP, PPT>), dim3((unsigned)grid), dim3(threads), lds, s, blocks, tiles,
+                     ntiles, in, out, lambda);
+  return hipGetLastError();
+}
+
+template <int P, int OP>
+static hipError_t launch_mixed_ppt(int ppt, const BlockStatic* blocks, const Tile* tiles, int ntiles,
+                                   const double* in, double* out, double lambda, int threads, size_t lds,
+                                   hipStream_t s) {
+  switch (ppt) {
+    case 2: return launch_mixed_hp<P, OP, 2>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
+    case 4: return launch_mixed_hp<P, OP, 4>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
+    case 8: return launch_mixed_hp<P, OP, 8>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int P>
 static hipError_t launch_mixed_p(int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
                                  double* out, long long in_cs, long long out_cs, double lambda, int threads,
-                                 size_t lds, hipStream_t s) {
+                                 size_t lds, int E, int persist, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  if (persist && (opk == OPK_HELM || opk == OPK_LAP)) {
+    const int ppt = points_per_thread((long long)E * (P + 2) * (P + 2) * (P + 2), threads);
+    if (ppt > 0)
+      return opk == OPK_HELM ? launch_mixed_ppt<P, OPK_HELM>(ppt, blocks, tiles, ntiles, in, out, lambda, threads, lds, s)
+                             : launch_mixed_ppt<P, OPK_LAP>(ppt, blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
+  }
   const dim3 g((unsigned)ntiles), b((unsigned)threads);
   switch (opk) {
 #define K_(op) \
@@ -62,11 +115,13 @@ static hipError_t launch_mixed_p(int opk, const BlockStatic* blocks, const Tile*
 }
 
 hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
-                        double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds,
-                        hipStream_t s) {
+                        double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds, int E,
+                        int persist, hipStream_t s) {
   switch (P) {
-#define C_(p) \
-  case p: return launch_mixed_p<p>(opk, blocks, tiles, ntiles, in, out, in_cs, out_cs, lambda, threads, lds, s);
+#define C_(p)                                                                                                   \
+  case p:                                                                                                       \
+    return launch_mixed_p<p>(opk, blocks, tiles, ntiles, in, out, in_cs, out_cs, lambda, threads, lds, E, persist, \
+                             s);
     C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10)
 #undef C_
   }

@@ -643,6 +643,149 @@ __global__ void __launch_bounds__(512) k_mixed(const BlockStatic* __restrict__ b
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pipelined Laplacian / Helmholtz: persistent work-groups, geometry in registers
+// ---------------------------------------------------------------------------
+// Each work-group walks the tile list with a stride of the grid size.  The 7
+// geometric factors of the points a thread owns in the metric stage are loaded
+// into registers before they are needed: for the first tile at kernel start,
+// for every later tile right after the previous tile's metric stage, so the
+// HBM latency of the dominant byte stream overlaps the sum-factorisation stages.
+// PPT is the number of points a thread owns in the metric stage.
+
+template <int PPT>
+struct GeoRegs {
+  double v[PPT][NFAC];
+};
+
+template <int P, int PPT>
+__device__ __forceinline__ void prefetch_geo(const double* __restrict__ fac, long long e0, int ne, GeoRegs<PPT>& g) {
+  constexpr int Q3 = (P + 2) * (P + 2) * (P + 2);
+  const double* base = fac + e0 * (long long)(NFAC * Q3);
+#pragma unroll
+  for (int it = 0; it < PPT; ++it) {
+    const int t = tid() + it * nthr();
+    if (t < ne * Q3) {
+      const int e = t / Q3, pt = t - e * Q3;
+      const double* f = base + e * (NFAC * Q3) + pt;
+#pragma unroll
+      for (int c = 0; c < NFAC; ++c) g.v[it][c] = __builtin_nontemporal_load(f + c * Q3);
+    }
+  }
+}
+
+template <int SH, int P, int OP, int PPT, typename Next>
+__device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH, P>& T, GeoRegs<PPT>& g,
+                          bool tables, Next next) {
+  using D = Dims<SH, P>;
+  constexpr int Q3 = D::Q3;
+  if (tables) load_tables<SH, P>(a, T);
+  load_modes<SH, P>(T, a.in, e0, ne, 0);
+  __syncthreads();
+  bwd_chain<SH, P>(T, ne);
+  grad3<SH, P>(T, ne);
+  __syncthreads();
+  const double lam = (OP == OPK_HELM) ? a.lambda : 0.0;
+#pragma unroll
+  for (int it = 0; it < PPT; ++it) {
+    const int t = tid() + it * nthr();
+    if (t < ne * Q3) {
+      const int e = t / Q3, pt = t - e * Q3;
+      const int lp = lds_pt<SH, P>(pt);
+      const double* gg = g.v[it];
+      double* p0 = T.G(e, 0) + lp;
+      double* p1 = T.G(e, 1) + lp;
+      double* p2 = T.G(e, 2) + lp;
+      const double d0 = *p0, d1 = *p1, d2 = *p2;
+      *p0 = gg[1] * d0 + gg[2] * d1 + gg[3] * d2;
+      *p1 = gg[2] * d0 + gg[4] * d1 + gg[5] * d2;
+      *p2 = gg[3] * d0 + gg[5] * d1 + gg[6] * d2;
+      if (OP == OPK_HELM) {
+        double* u = T.U(e) + lp;
+        *u = lam * gg[0] * (*u);
+      }
+    }
+  }
+  next();  // registers of this tile's geometry are dead: start the next tile's loads
+  __syncthreads();
+  grad3T<SH, P>(T, ne);
+  __syncthreads();
+  ipr_chain<SH, P>(T, ne, (OP == OPK_HELM ? 1 : 0) | 2 | 4 | 8);
+  store_modes<SH, P>(T, a.out, e0, ne, 1);
+}
+
+template <int SH, int P, int OP, int PPT>
+__global__ void __launch_bounds__(512) k_helm_persist(OpArgs a, int ntiles) {
+  extern __shared__ double smem[];
+  int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  const Tile_<SH, P> T = make_tile<SH, P>(smem);
+  auto ne_of = [&](int i) {
+    const long long r = a.n_elem - (long long)i * a.E;
+    return (int)(r < a.E ? r : a.E);
+  };
+  GeoRegs<PPT> g;
+  prefetch_geo<P, PPT>(a.fac, (long long)ti * a.E, ne_of(ti), g);
+  bool first = true;
+  while (true) {
+    const int nx = ti + (int)gridDim.x;
+    __syncthreads();
+    helm_tile<SH, P, OP, PPT>(a, (long long)ti * a.E, ne_of(ti), T, g, first, [&]() {
+      if (nx < ntiles) prefetch_geo<P, PPT>(a.fac, (long long)nx * a.E, ne_of(nx), g);
+    });
+    first = false;
+    if (nx >= ntiles) break;
+    ti = nx;
+  }
+}
+
+template <int P, int OP, int PPT>
+__global__ void __launch_bounds__(512) k_helm_mixed_persist(const BlockStatic* __restrict__ blocks,
+                                                            const Tile* __restrict__ tiles, int ntiles,
+                                                            const double* in, double* out, double lambda) {
+  extern __shared__ double smem[];
+  int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  Tile tl = tiles[ti];
+  GeoRegs<PPT> g;
+  prefetch_geo<P, PPT>(blocks[tl.blk].fac, tl.e0, tl.ne, g);
+  int prev = -1;
+  while (true) {
+    const int nx = ti + (int)gridDim.x;
+    Tile tn = tl;
+    if (nx < ntiles) tn = tiles[nx];
+    const BlockStatic b = blocks[tl.blk];
+    OpArgs a;
+    a.tab = b.tab;
+    a.itab = b.itab;
+    a.fac = b.fac;
+    a.dxi = b.dxi;
+    a.n_elem = b.n_elem;
+    a.in = in + b.coeff_off;
+    a.out = out + b.coeff_off;
+    a.in_cs = 0;
+    a.out_cs = 0;
+    a.lambda = lambda;
+    a.E = 0;
+    a.pad_ = 0;
+    const bool tables = (tl.blk != prev);
+    auto next = [&]() {
+      if (nx < ntiles) prefetch_geo<P, PPT>(blocks[tn.blk].fac, tn.e0, tn.ne, g);
+    };
+    __syncthreads();
+    switch (b.shape) {
+      case HEX: helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem), g, tables, next); break;
+      case PRISM: helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem), g, tables, next); break;
+      case PYR: helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem), g, tables, next); break;
+      default: helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<TET, P>(smem), g, tables, next); break;
+    }
+    prev = tl.blk;
+    if (nx >= ntiles) break;
+    ti = nx;
+    tl = tn;
+  }
+}
+
 // LDS bytes of a tile of E elements
 template <int SH, int P>
 constexpr size_t lds_bytes(int E) {

@@ -33,9 +33,10 @@ _SIGS = {
                           ctypes.POINTER(ctypes.c_int64)],
     "shp_apply": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.c_double, ctypes.c_void_p],
-    "shp_set_tiling": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+    "shp_set_tiling": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                       ctypes.c_int],
     "shp_get_tiling": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
-                       ctypes.POINTER(ctypes.c_int)],
+                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
     "shp_plan_destroy": [ctypes.c_void_p],
 }
 
@@ -187,10 +188,11 @@ class Plan:
                                ctypes.c_void_p(out.data_ptr()), float(lam), _stream(t)))
         return out
 
-    def set_tiling(self, blk: int, op: str, E: int, NT: int, strategy: str = "sumfac_coll"):
-        _check(lib().shp_set_tiling(self._h, blk, OPS[op], STRATEGY[strategy], E, NT))
+    def set_tiling(self, blk: int, op: str, E: int, NT: int, persistent: int = 1, strategy: str = "sumfac_coll"):
+        _check(lib().shp_set_tiling(self._h, blk, OPS[op], STRATEGY[strategy], E, NT, persistent))
 
     def get_tiling(self, blk: int, op: str, strategy: str = "sumfac_coll"):
-        E, NT = ctypes.c_int(), ctypes.c_int()
-        _check(lib().shp_get_tiling(self._h, blk, OPS[op], STRATEGY[strategy], ctypes.byref(E), ctypes.byref(NT)))
-        return E.value, NT.value
+        E, NT, pe = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().shp_get_tiling(self._h, blk, OPS[op], STRATEGY[strategy], ctypes.byref(E), ctypes.byref(NT),
+                                    ctypes.byref(pe)))
+        return E.value, NT.value, pe.value

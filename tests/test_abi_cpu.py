@@ -102,14 +102,17 @@ def test_error_paths_without_device(L):
     assert L.shp_plan_bind_workspace(h, ctypes.c_void_p(256 * 1000 + 8), nb.value, None) == -4
     assert L.shp_plan_bind_workspace(h, ctypes.c_void_p(256 * 1000), nb.value - 1, None) == -4
     # tiling validation
-    assert L.shp_set_tiling(h, 0, 6, 2, 0, 256) == -1
-    assert L.shp_set_tiling(h, 0, 6, 2, 4, 100) == -1
-    assert L.shp_set_tiling(h, 0, 6, 2, 64, 256) == -2           # LDS overflow at P=4
-    assert L.shp_set_tiling(h, 0, 6, 2, 4, 128) == 0
-    E, NT = ctypes.c_int(), ctypes.c_int()
-    assert L.shp_get_tiling(h, 0, 6, 2, ctypes.byref(E), ctypes.byref(NT)) == 0
-    assert (E.value, NT.value) == (4, 128)
-    assert L.shp_set_tiling(h, 0, 6, 2, 0, 0) == 0               # back to default
+    assert L.shp_set_tiling(h, 0, 6, 2, 0, 256, 1) == -1
+    assert L.shp_set_tiling(h, 0, 6, 2, 4, 100, 1) == -1
+    assert L.shp_set_tiling(h, 0, 6, 2, 4, 128, 3) == -1
+    assert L.shp_set_tiling(h, 0, 6, 2, 64, 256, 1) == -2        # LDS overflow at P=4
+    assert L.shp_set_tiling(h, 0, 6, 2, 4, 128, 0) == 0
+    E, NT, pe = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert L.shp_get_tiling(h, 0, 6, 2, ctypes.byref(E), ctypes.byref(NT), ctypes.byref(pe)) == 0
+    assert (E.value, NT.value, pe.value) == (4, 128, 0)
+    assert L.shp_set_tiling(h, 0, 6, 2, 0, 0, 0) == 0            # back to default
+    assert L.shp_get_tiling(h, -1, 6, 2, ctypes.byref(E), ctypes.byref(NT), ctypes.byref(pe)) == 0
+    assert (E.value, NT.value, pe.value) == (4, 256, 1)          # 40 KiB LDS budget at P=4
     c, q = ctypes.c_int64(), ctypes.c_int64()
     assert L.shp_block_offsets(h, 1, ctypes.byref(c), ctypes.byref(q)) == 0
     assert (c.value, q.value) == (10 * 125, 10 * 216)

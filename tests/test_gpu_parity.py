@@ -172,10 +172,11 @@ def test_tilings_agree_bitwise(shp, shape):
     plan.set_geometry(0, gpu_geometry(shp, maps, shape, P, True))
     x = torch.from_numpy(W.coeffs(ne, plan.n_modes[0], 9)).cuda()
     base = plan.apply(0, "helmholtz", x).cpu().numpy()
-    for E, NT in ((1, 64), (2, 128), (5, 256), (8, 512), (3, 192)):
-        plan.set_tiling(0, "helmholtz", E, NT)
+    for E, NT, pe in ((1, 64, 0), (2, 128, 0), (5, 256, 0), (8, 512, 0), (3, 192, 0),
+                      (1, 64, 1), (2, 128, 1), (4, 256, 1), (8, 512, 1), (3, 192, 1), (6, 256, 1)):
+        plan.set_tiling(0, "helmholtz", E, NT, pe)
         y = plan.apply(0, "helmholtz", x).cpu().numpy()
-        assert np.array_equal(y, base), (E, NT)
+        assert np.array_equal(y, base), (E, NT, pe)
 
 
 def test_bad_geometry_is_reported(shp):
