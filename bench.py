@@ -38,6 +38,37 @@ def bytes_per_elem(n_modes: int, n_points: int) -> int:
     return 16 * n_modes + 56 * n_points
 
 
+def kernel_source_hash() -> str:
+    """sha256[:16] of the HIP/C++ sources of libshp (names and contents)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_04644_amd", "csrc", "*"))):
+        if f.endswith((".hpp", ".hip", ".inc", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(P: int, ncell: int):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, when it was taken on the current kernel sources; else None."""
+    import re
+    if (P, ncell) != (4, 32):
+        return None
+    path = os.path.join(ROOT, "profiles", "helmholtz_mixed_P4_hbm_traffic.md")
+    try:
+        txt = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*(\d+)", txt)
+    h = re.search(r"source_sha256_16:\s*([0-9a-f]+)", txt)
+    if not m or not h or h.group(1) != kernel_source_hash():
+        return None
+    return int(m.group(1))
+
+
 def build_mesh_plan(torch, shp, W, ncell: int, P: int):
     mesh = W.quadrant_mesh(ncell)
     blocks = [(s, P, len(mesh[s]), "curved") for s in SHAPES]
@@ -184,7 +215,7 @@ def main():
                    "elements": int(sum(len(mesh[s]) for s in SHAPES)), "dof": int(dof),
                    "elements_per_shape": {s: len(mesh[s]) for s in SHAPES}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(P, a.ncell),
                      "algorithmic_bytes": int(nbytes), "launch_ms": round(ev_mean_ms, 5)},
         "cpu_baseline": cpu,
         "mixed_vs_fp64": None,

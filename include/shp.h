@@ -143,15 +143,19 @@ int shp_apply(shp_plan plan, int blk, int op, int strategy, const double* in /* 
 /* Fix the launch shape used for (blk, op, strategy), blk = -1 for the
  * whole-mesh launch: elements per work-group (1..64, within the 160 KiB LDS of
  * a work-group), threads per work-group (multiple of 64 in [64,512]) and, for
- * the Laplacian and Helmholtz actions, persistent = 1 to run persistent
- * work-groups that prefetch each tile's geometric factors into registers
- * (used when elems_per_wg * Q^3 <= 8 * threads, else the one-tile-per-work-group
- * kernel runs).  (0, 0, 0) restores the default.  Used by tuning. */
-int shp_set_tiling(shp_plan plan, int blk, int op, int strategy, int elems_per_wg, int threads, int persistent);
+ * the Laplacian and Helmholtz actions, the launch variant:
+ *   0  one tile per work-group, geometric factors loaded in the metric stage;
+ *   1  persistent work-groups; each tile's factors are loaded into registers
+ *      during the previous tile;
+ *   2  one tile per work-group, the tile's factors loaded into registers at
+ *      the start of the tile.
+ * Variants 1 and 2 are used when elems_per_wg * Q^3 <= 8 * threads, else
+ * variant 0 runs.  (0, 0, 0) restores the default.  Used by tuning. */
+int shp_set_tiling(shp_plan plan, int blk, int op, int strategy, int elems_per_wg, int threads, int variant);
 
 /* Current launch shape for (blk, op, strategy). */
 int shp_get_tiling(shp_plan plan, int blk, int op, int strategy, int* elems_per_wg /* host out */,
-                   int* threads /* host out */, int* persistent /* host out */);
+                   int* threads /* host out */, int* variant /* host out */);
 
 /* Destroy a plan (host metadata only; the workspace stays the caller's). */
 int shp_plan_destroy(shp_plan plan);

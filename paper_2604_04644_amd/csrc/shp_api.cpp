@@ -40,7 +40,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Tiling {
   int E = 0;
   int NT = 0;
-  int persist = 1;  // Laplacian/Helmholtz: persistent work-groups with prefetched geometry
+  int persist = 2;  // Laplacian/Helmholtz launch variant: 0 plain, 1 persistent + prefetch, 2 prefetch per tile
 };
 
 struct Block {
@@ -102,9 +102,9 @@ Tiling default_tiling(int sh, int P, int opk) {
   Tiling t;
   t.NT = 256;
   int E = 1;
-  while (E < 16 && op_lds_bytes(sh, P, opk, E + 1) <= 40 * 1024) ++E;
+  while (E < 16 && op_lds_bytes(sh, P, opk, E + 1, 2) <= 40 * 1024) ++E;
   t.E = E;
-  t.persist = points_per_thread((long long)E * (P + 2) * (P + 2) * (P + 2), t.NT) > 0 ? 1 : 0;
+  t.persist = points_per_thread((long long)E * (P + 2) * (P + 2) * (P + 2), t.NT) > 0 ? 2 : 0;
   return t;
 }
 
@@ -309,15 +309,15 @@ int shp_set_tiling(shp_plan p, int blk, int op, int strategy, int E, int NT, int
     if (NT < 64 || NT > 512 || NT % 64) return fail(SHP_ERR_INVALID_ARG, "threads %d: multiple of 64 in [64,512]", NT);
     if (blk >= 0) {
       const Block& B = p->blocks[blk];
-      if (op_lds_bytes(B.d.shape, B.d.P, opk, E) > LDS_LIMIT)
+      if (op_lds_bytes(B.d.shape, B.d.P, opk, E, persistent) > LDS_LIMIT)
         return fail(SHP_ERR_UNSUPPORTED, "%d elements exceed the LDS of a work-group", E);
     } else {
       for (const auto& B : p->blocks)
-        if (op_lds_bytes(B.d.shape, B.d.P, opk, E) > LDS_LIMIT)
+        if (op_lds_bytes(B.d.shape, B.d.P, opk, E, persistent) > LDS_LIMIT)
           return fail(SHP_ERR_UNSUPPORTED, "%d elements exceed the LDS of a work-group", E);
     }
   }
-  if (persistent != 0 && persistent != 1) return fail(SHP_ERR_INVALID_ARG, "persistent must be 0 or 1");
+  if (persistent < 0 || persistent > 4) return fail(SHP_ERR_INVALID_ARG, "launch variant must be in [0,4]");
   Tiling t;
   t.E = E;
   t.NT = NT;
@@ -357,7 +357,7 @@ int shp_get_tiling(shp_plan p, int blk, int op, int strategy, int* E, int* NT, i
 static Tiling mixed_tiling(shp_plan p, int opk) {
   Tiling t = p->mixed[opk];
   if (t.E > 0 && t.NT > 0) return t;
-  t = Tiling{64, 512, 1};
+  t = Tiling{64, 512, 2};
   for (const auto& B : p->blocks) {
     const Tiling d = default_tiling(B.d.shape, B.d.P, opk);
     t.E = std::min(t.E, d.E);
@@ -463,7 +463,7 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
   const Tiling mt = mixed_tiling(p, opk);
   const int E = mt.E, NT = mt.NT;
   size_t lds = 0;
-  for (const auto& B : p->blocks) lds = std::max(lds, op_lds_bytes(B.d.shape, B.d.P, opk, E));
+  for (const auto& B : p->blocks) lds = std::max(lds, op_lds_bytes(B.d.shape, B.d.P, opk, E, mt.persist));
   const Tile* tiles = reinterpret_cast<const Tile*>(p->ws + p->off_tiles) + (size_t)opk * p->max_tiles;
   hipError_t e = launch_mixed(p->blocks[0].d.P, opk, reinterpret_cast<const BlockStatic*>(p->ws + p->off_bstat), tiles,
                               p->mixed_ntiles[opk], in, out, p->total_phys, p->total_phys, lambda, NT, lds, E, mt.persist, s);

@@ -35,7 +35,7 @@ void build_tables(int sh, int P, std::vector<double>& tab, std::vector<int>& ita
 void reference_points(int sh, int Q, double* xi, double* w);
 
 // launchers (shp_k_*.hip); return hipSuccess or the launch error
-size_t op_lds_bytes(int sh, int P, int opk, int E);
+size_t op_lds_bytes(int sh, int P, int opk, int E, int variant);
 hipError_t launch_block(int sh, int P, int opk, const OpArgs& a, int threads, int persist, hipStream_t s);
 hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,

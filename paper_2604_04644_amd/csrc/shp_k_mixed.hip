@@ -14,18 +14,18 @@ hipError_t launch_geometry_hex(int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_geometry_prism(int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_geometry_pyr(int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_geometry_tet(int P, const GeomArgs& g, hipStream_t s);
-size_t lds_bytes_hex(int P, int E);
-size_t lds_bytes_prism(int P, int E);
-size_t lds_bytes_pyr(int P, int E);
-size_t lds_bytes_tet(int P, int E);
+size_t lds_bytes_hex(int P, int E, int nbuf);
+size_t lds_bytes_prism(int P, int E, int nbuf);
+size_t lds_bytes_pyr(int P, int E, int nbuf);
+size_t lds_bytes_tet(int P, int E, int nbuf);
 
-size_t op_lds_bytes(int sh, int P, int opk, int E) {
-  (void)opk;
+size_t op_lds_bytes(int sh, int P, int opk, int E, int variant) {
+  const int nbuf = (variant >= 3 && (opk == OPK_HELM || opk == OPK_LAP)) ? 3 : 4;
   switch (sh) {
-    case HEX: return lds_bytes_hex(P, E);
-    case PRISM: return lds_bytes_prism(P, E);
-    case PYR: return lds_bytes_pyr(P, E);
-    default: return lds_bytes_tet(P, E);
+    case HEX: return lds_bytes_hex(P, E, nbuf);
+    case PRISM: return lds_bytes_prism(P, E, nbuf);
+    case PYR: return lds_bytes_pyr(P, E, nbuf);
+    default: return lds_bytes_tet(P, E, nbuf);
   }
 }
 
@@ -80,10 +80,26 @@ static hipError_t launch_mixed_hp(const BlockStatic* blocks, const Tile* tiles, 
   return hipGetLastError();
 }
 
+template <int P, int OP, int PPT>
+static hipError_t launch_mixed_pf(const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
+                                  double* out, double lambda, int threads, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k_helm_mixed_pf<P, OP, PPT>), dim3((unsigned)ntiles), dim3(threads), lds, s, blocks, tiles,
+                     ntiles, in, out, lambda);
+  return hipGetLastError();
+}
+
 template <int P, int OP>
-static hipError_t launch_mixed_ppt(int ppt, const BlockStatic* blocks, const Tile* tiles, int ntiles,
+static hipError_t launch_mixed_ppt(int variant, int ppt, const BlockStatic* blocks, const Tile* tiles, int ntiles,
                                    const double* in, double* out, double lambda, int threads, size_t lds,
                                    hipStream_t s) {
+  if (variant == 2) {
+    switch (ppt) {
+      case 2: return launch_mixed_pf<P, OP, 2>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
+      case 4: return launch_mixed_pf<P, OP, 4>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
+      case 8: return launch_mixed_pf<P, OP, 8>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (ppt) {
     case 2: return launch_mixed_hp<P, OP, 2>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
     case 4: return launch_mixed_hp<P, OP, 4>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
@@ -92,16 +108,33 @@ static hipError_t launch_mixed_ppt(int ppt, const BlockStatic* blocks, const Til
   return hipErrorInvalidValue;
 }
 
+template <int P, int OP>
+static hipError_t launch_mixed_fused(const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
+                                     double* out, double lambda, int threads, size_t lds, bool pf, hipStream_t s) {
+  const dim3 g((unsigned)ntiles), b((unsigned)threads);
+  if (pf)
+    hipLaunchKernelGGL((k_helm_fused_mixed<P, OP, true>), g, b, lds, s, blocks, tiles, ntiles, in, out, lambda);
+  else
+    hipLaunchKernelGGL((k_helm_fused_mixed<P, OP, false>), g, b, lds, s, blocks, tiles, ntiles, in, out, lambda);
+  return hipGetLastError();
+}
+
 template <int P>
 static hipError_t launch_mixed_p(int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
                                  double* out, long long in_cs, long long out_cs, double lambda, int threads,
                                  size_t lds, int E, int persist, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (persist && (opk == OPK_HELM || opk == OPK_LAP)) {
+  if (persist >= 3 && (opk == OPK_HELM || opk == OPK_LAP)) {
+    const bool pf = (persist == 4) && (E * (P + 2) * (P + 2) <= threads);
+    return opk == OPK_HELM ? launch_mixed_fused<P, OPK_HELM>(blocks, tiles, ntiles, in, out, lambda, threads, lds, pf, s)
+                           : launch_mixed_fused<P, OPK_LAP>(blocks, tiles, ntiles, in, out, lambda, threads, lds, pf, s);
+  }
+  if ((persist == 1 || persist == 2) && (opk == OPK_HELM || opk == OPK_LAP)) {
     const int ppt = points_per_thread((long long)E * (P + 2) * (P + 2) * (P + 2), threads);
     if (ppt > 0)
-      return opk == OPK_HELM ? launch_mixed_ppt<P, OPK_HELM>(ppt, blocks, tiles, ntiles, in, out, lambda, threads, lds, s)
-                             : launch_mixed_ppt<P, OPK_LAP>(ppt, blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
+      return opk == OPK_HELM
+                 ? launch_mixed_ppt<P, OPK_HELM>(persist, ppt, blocks, tiles, ntiles, in, out, lambda, threads, lds, s)
+                 : launch_mixed_ppt<P, OPK_LAP>(persist, ppt, blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
   }
   const dim3 g((unsigned)ntiles), b((unsigned)threads);
   switch (opk) {

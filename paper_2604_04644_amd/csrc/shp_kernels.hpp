@@ -84,15 +84,33 @@ struct Dims {
   __device__ __host__ static constexpr int pidx(int i, int j, int k) { return (i * Q + j) * QP + k; }
 };
 
+// Pointers for tables that every lane reads at the same index: loads through
+// the constant address space become scalar loads into SGPRs, which feed the
+// FP64 FMAs directly and take no LDS bandwidth.  Streamed data is read through
+// the global address space.
+typedef const __attribute__((address_space(4))) double* ctab_t;
+typedef const __attribute__((address_space(1))) double* gptr_t;
+__device__ __forceinline__ ctab_t as_const(const double* p) { return (ctab_t)(p); }
+// Re-derive a table pointer inside a loop so the scalar loads stay in the loop
+// body (hoisting every table value out of the loop spills SGPRs).
+__device__ __forceinline__ ctab_t launder(ctab_t p) {
+  unsigned long long v = (unsigned long long)p;
+  asm volatile("" : "+s"(v));
+  return (ctab_t)v;
+}
+__device__ __forceinline__ gptr_t as_global(const double* p) { return (gptr_t)(p); }
+
 // LDS view of one tile.
 template <int SH, int P>
 struct Tile_ {
   using D = Dims<SH, P>;
   double* tab;
   int* itab;
-  double* el;  // E * PER_ELEM
-  __device__ double* U(int e) const { return el + e * D::PER_ELEM; }
-  __device__ double* G(int e, int d) const { return el + e * D::PER_ELEM + (d + 1) * D::S3; }
+  ctab_t ct;   // the same tables in global memory, for lane-uniform reads
+  double* el;  // E * per
+  int per;     // doubles per element: 4 buffers (U, G0, G1, G2) or 3 in the fused kernels
+  __device__ double* U(int e) const { return el + e * per; }
+  __device__ double* G(int e, int d) const { return el + e * per + (d + 1) * D::S3; }
 };
 
 __device__ __forceinline__ int tid() { return threadIdx.x; }
@@ -109,11 +127,31 @@ __device__ void load_tables(const OpArgs& a, const Tile_<SH, P>& T) {
 // modes -> points
 // ---------------------------------------------------------------------------
 
-// stage r: X (modes of element e at xo(e)) -> F[c][k] at fo(e) + c*QP + k
+// stage r: X (modes of element e) -> F[c][k] at c*QP + k
 template <int SH, int P, bool DER>
 __device__ void bwd_r(const Tile_<SH, P>& T, int ne, int xbuf, int fbuf) {
   using D = Dims<SH, P>;
-  constexpr int Q = D::Q;
+  constexpr int Q = D::Q, n = D::n;
+  if (SH == HEX) {
+    // every column runs r over 0..P with the same table: lane-uniform reads
+    for (int t = tid(); t < ne * D::NC; t += nthr()) {
+      const ctab_t C3 = launder(T.ct) + (DER ? D::L.dC3 : D::L.C3);
+      const int e = t / D::NC, c = t - e * D::NC;
+      const double* x = (xbuf < 0 ? T.U(e) : T.G(e, xbuf)) + c * n;
+      double xr[n];
+#pragma unroll
+      for (int r = 0; r < n; ++r) xr[r] = x[r];
+      double* f = T.G(e, fbuf) + c * D::QP;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        double a = 0.0;
+#pragma unroll
+        for (int r = 0; r < n; ++r) a = fma(C3[r * Q + k], xr[r], a);
+        f[k] = a;
+      }
+    }
+    return;
+  }
   const double* C3 = T.tab + (DER ? D::L.dC3 : D::L.C3);
   const double* V1 = C3 + 1 * Q;  // family (0,1): v1 or its derivative 1/2
   for (int t = tid(); t < ne * D::NC; t += nthr()) {
@@ -155,9 +193,30 @@ template <int SH, int P, bool DER>
 __device__ void bwd_q(const Tile_<SH, P>& T, int ne, int fbuf, int gbuf) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  if (SH != TET) {
+    // eta2 functions A_q for every p: lane-uniform table
+    for (int t = tid(); t < ne * n * Q; t += nthr()) {
+      const ctab_t B2 = launder(T.ct) + (DER ? D::L.dB2 : D::L.B2);
+      const int e = t / (n * Q);
+      const int rem = t - e * (n * Q);
+      const int p = rem / Q, k = rem - p * Q;
+      const double* F = T.G(e, fbuf) + (p * n) * QP + k;
+      double fv[n];
+#pragma unroll
+      for (int q = 0; q < n; ++q) fv[q] = F[q * QP];
+      double* G = T.G(e, gbuf) + p * Q * QP + k;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < n; ++q) a = fma(B2[q * Q + j], fv[q], a);
+        G[j * QP] = a;
+      }
+    }
+    return;
+  }
   const double* B2 = T.tab + (DER ? D::L.dB2 : D::L.B2);
-  // v1 in eta2 (or its derivative) is the A_1 row of the eta2 table for the
-  // non-tet shapes; for the tet it is the family (0,1) row: index 1 either way
+  // v1 in eta2 (or its derivative) is the family (0,1) row of the tet's table
   const double* V1 = B2 + 1 * Q;
   for (int t = tid(); t < ne * n * Q; t += nthr()) {
     const int e = t / (n * Q);
@@ -165,7 +224,7 @@ __device__ void bwd_q(const Tile_<SH, P>& T, int ne, int fbuf, int gbuf) {
     const int p = rem / Q, k = rem - p * Q;
     const double* F = T.G(e, fbuf);
     const int nq = nq_of(SH, P, p), cb = col_base(SH, P, p);
-    const int bfam = (SH == TET) ? fam_index(P, p, 0) : 0;
+    const int bfam = fam_index(P, p, 0);
     double acc[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) acc[j] = 0.0;
@@ -175,7 +234,7 @@ __device__ void bwd_q(const Tile_<SH, P>& T, int ne, int fbuf, int gbuf) {
 #pragma unroll
       for (int j = 0; j < Q; ++j) acc[j] = fma(b[j], fv, acc[j]);
     }
-    if (SH == TET && p == 1) {
+    if (p == 1) {
       const double fv = F[1 * QP + k];  // column (0,1)
 #pragma unroll
       for (int j = 0; j < Q; ++j) acc[j] = fma(V1[j], fv, acc[j]);
@@ -191,8 +250,8 @@ template <int SH, int P, bool DER>
 __device__ void bwd_p(const Tile_<SH, P>& T, int ne, int gbuf, int ubuf) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, n = D::n, QP = D::QP;
-  const double* A1 = T.tab + (DER ? D::L.dA1 : D::L.A1);
   for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const ctab_t A1 = launder(T.ct) + (DER ? D::L.dA1 : D::L.A1);
     const int e = t / (Q * Q);
     const int rem = t - e * (Q * Q);
     const int j = rem / Q, k = rem - j * Q;
@@ -221,8 +280,8 @@ template <int SH, int P, bool DER>
 __device__ void ipr_p(const Tile_<SH, P>& T, int ne, int mask, int dst) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, n = D::n, QP = D::QP;
-  const double* A1 = T.tab + (DER ? D::L.dA1 : D::L.A1);
   for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const ctab_t A1 = launder(T.ct) + (DER ? D::L.dA1 : D::L.A1);
     const int e = t / (Q * Q);
     const int rem = t - e * (Q * Q);
     const int j = rem / Q, k = rem - j * Q;
@@ -259,6 +318,27 @@ template <int SH, int P, bool DER>
 __device__ void ipr_q(const Tile_<SH, P>& T, int ne, int gbuf, int fbuf) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  if (SH != TET) {
+    for (int t = tid(); t < ne * n * Q; t += nthr()) {
+      const ctab_t B2 = launder(T.ct) + (DER ? D::L.dB2 : D::L.B2);
+      const int e = t / (n * Q);
+      const int rem = t - e * (n * Q);
+      const int p = rem / Q, k = rem - p * Q;
+      const double* G = (gbuf < 0 ? T.U(e) : T.G(e, gbuf)) + p * Q * QP + k;
+      double g[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) g[j] = G[j * QP];
+      double* F = T.G(e, fbuf) + (p * n) * QP + k;
+#pragma unroll
+      for (int q = 0; q < n; ++q) {
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) a = fma(B2[q * Q + j], g[j], a);
+        F[q * QP] = a;
+      }
+    }
+    return;
+  }
   const double* B2 = T.tab + (DER ? D::L.dB2 : D::L.B2);
   const double* V1 = B2 + 1 * Q;
   for (int t = tid(); t < ne * n * Q; t += nthr()) {
@@ -270,14 +350,14 @@ __device__ void ipr_q(const Tile_<SH, P>& T, int ne, int gbuf, int fbuf) {
 #pragma unroll
     for (int j = 0; j < Q; ++j) g[j] = G[j * QP];
     const int nq = nq_of(SH, P, p), cb = col_base(SH, P, p);
-    const int bfam = (SH == TET) ? fam_index(P, p, 0) : 0;
+    const int bfam = fam_index(P, p, 0);
     double* F = T.G(e, fbuf);
     for (int q = 0; q < nq; ++q) {
       const double* b = B2 + (bfam + q) * Q;
       double a = 0.0;
 #pragma unroll
       for (int j = 0; j < Q; ++j) a = fma(b[j], g[j], a);
-      if (SH == TET && p == 0 && q == 1) {
+      if (p == 0 && q == 1) {
         // adjoint of the tet's extra eta2 term: column (0,1) also collects v1 * Gp[1]
         const double* G1 = G + 1 * Q * QP;
 #pragma unroll
@@ -292,7 +372,29 @@ __device__ void ipr_q(const Tile_<SH, P>& T, int ne, int gbuf, int fbuf) {
 template <int SH, int P, bool DER>
 __device__ void ipr_r(const Tile_<SH, P>& T, int ne, int fbuf, int ybuf, bool accumulate) {
   using D = Dims<SH, P>;
-  constexpr int Q = D::Q, QP = D::QP;
+  constexpr int Q = D::Q, QP = D::QP, n = D::n;
+  if (SH == HEX) {
+    for (int t = tid(); t < ne * D::NC; t += nthr()) {
+      const ctab_t C3u = launder(T.ct) + (DER ? D::L.dC3 : D::L.C3);
+      const int e = t / D::NC, c = t - e * D::NC;
+      const double* F = T.G(e, fbuf) + c * QP;
+      double f[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) f[k] = F[k];
+      double* y = (ybuf < 0 ? T.U(e) : T.G(e, ybuf)) + c * n;
+#pragma unroll
+      for (int r = 0; r < n; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) a = fma(C3u[r * Q + k], f[k], a);
+        if (accumulate)
+          y[r] += a;
+        else
+          y[r] = a;
+      }
+    }
+    return;
+  }
   const double* C3 = T.tab + (DER ? D::L.dC3 : D::L.C3);
   const double* V1 = C3 + 1 * Q;
   for (int t = tid(); t < ne * D::NC; t += nthr()) {
@@ -346,67 +448,47 @@ __device__ void ipr_r(const Tile_<SH, P>& T, int ne, int fbuf, int ybuf, bool ac
 // collocation derivatives
 // ---------------------------------------------------------------------------
 
-// G_d = D_d U for d = 0,1,2 (all three in one pass)
-template <int SH, int P>
-__device__ void grad3(const Tile_<SH, P>& T, int ne) {
+// one direction of the collocation derivative: lines along eta_{d+1}
+template <int SH, int P, int DIR, bool TRANS>
+__device__ __forceinline__ void grad_dir(const Tile_<SH, P>& T, int ne) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, QP = D::QP;
-  const int per = ne * Q * Q;
-  for (int t = tid(); t < 3 * per; t += nthr()) {
-    const int d = t / per;
-    const int r1 = t - d * per;
-    const int e = r1 / (Q * Q);
-    const int r2 = r1 - e * (Q * Q);
+  constexpr int stride = DIR == 0 ? Q * QP : DIR == 1 ? QP : 1;
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const ctab_t Dm = launder(T.ct) + D::L.D + DIR * Q * Q;
+    const int e = t / (Q * Q);
+    const int r2 = t - e * (Q * Q);
     const int a = r2 / Q, b = r2 - a * Q;
-    const double* Dm = T.tab + D::L.D + d * Q * Q;
-    int base, stride;
-    if (d == 0) { base = a * QP + b; stride = Q * QP; }          // line (j,k) along i
-    else if (d == 1) { base = a * Q * QP + b; stride = QP; }     // line (i,k) along j
-    else { base = (a * Q + b) * QP; stride = 1; }                 // line (i,j) along k
-    const double* u = T.U(e) + base;
+    const int base = DIR == 0 ? a * QP + b : DIR == 1 ? a * Q * QP + b : (a * Q + b) * QP;
+    const double* src = (TRANS ? T.G(e, DIR) : T.U(e)) + base;
     double v[Q];
 #pragma unroll
-    for (int l = 0; l < Q; ++l) v[l] = u[l * stride];
-    double* g = T.G(e, d) + base;
+    for (int l = 0; l < Q; ++l) v[l] = src[l * stride];
+    double* g = T.G(e, DIR) + base;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       double s = 0.0;
 #pragma unroll
-      for (int l = 0; l < Q; ++l) s = fma(Dm[i * Q + l], v[l], s);
+      for (int l = 0; l < Q; ++l) s = fma(TRANS ? Dm[l * Q + i] : Dm[i * Q + l], v[l], s);
       g[i * stride] = s;
     }
   }
 }
 
+// G_d = D_d U for d = 0,1,2
+template <int SH, int P>
+__device__ void grad3(const Tile_<SH, P>& T, int ne) {
+  grad_dir<SH, P, 0, false>(T, ne);
+  grad_dir<SH, P, 1, false>(T, ne);
+  grad_dir<SH, P, 2, false>(T, ne);
+}
+
 // G_d <- D_d^T G_d in place, d = 0,1,2
 template <int SH, int P>
 __device__ void grad3T(const Tile_<SH, P>& T, int ne) {
-  using D = Dims<SH, P>;
-  constexpr int Q = D::Q, QP = D::QP;
-  const int per = ne * Q * Q;
-  for (int t = tid(); t < 3 * per; t += nthr()) {
-    const int d = t / per;
-    const int r1 = t - d * per;
-    const int e = r1 / (Q * Q);
-    const int r2 = r1 - e * (Q * Q);
-    const int a = r2 / Q, b = r2 - a * Q;
-    const double* Dm = T.tab + D::L.D + d * Q * Q;
-    int base, stride;
-    if (d == 0) { base = a * QP + b; stride = Q * QP; }
-    else if (d == 1) { base = a * Q * QP + b; stride = QP; }
-    else { base = (a * Q + b) * QP; stride = 1; }
-    double* g = T.G(e, d) + base;
-    double v[Q];
-#pragma unroll
-    for (int l = 0; l < Q; ++l) v[l] = g[l * stride];
-#pragma unroll
-    for (int l = 0; l < Q; ++l) {
-      double s = 0.0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) s = fma(Dm[i * Q + l], v[i], s);
-      g[l * stride] = s;
-    }
-  }
+  grad_dir<SH, P, 0, true>(T, ne);
+  grad_dir<SH, P, 1, true>(T, ne);
+  grad_dir<SH, P, 2, true>(T, ne);
 }
 
 // ---------------------------------------------------------------------------
@@ -587,12 +669,21 @@ __device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH,
 }
 
 template <int SH, int P>
-__device__ Tile_<SH, P> make_tile(double* smem) {
+__device__ Tile_<SH, P> make_tile(double* smem, const double* gtab) {
   using D = Dims<SH, P>;
   Tile_<SH, P> T;
   T.tab = smem;
   T.itab = reinterpret_cast<int*>(smem + D::NTAB);
+  T.ct = as_const(gtab);
   T.el = smem + D::HEAD;
+  T.per = D::PER_ELEM;
+  return T;
+}
+
+template <int SH, int P>
+__device__ Tile_<SH, P> make_tile3(double* smem, const double* gtab) {
+  Tile_<SH, P> T = make_tile<SH, P>(smem, gtab);
+  T.per = 3 * Dims<SH, P>::S3;
   return T;
 }
 
@@ -604,7 +695,7 @@ __global__ void __launch_bounds__(512) k_block(OpArgs a) {
   const long long rem = a.n_elem - e0;
   const int ne = rem < a.E ? (int)rem : a.E;
   if (ne <= 0) return;
-  const Tile_<SH, P> T = make_tile<SH, P>(smem);
+  const Tile_<SH, P> T = make_tile<SH, P>(smem, a.tab);
   tile_body<SH, P, OP>(a, e0, ne, T);
 }
 
@@ -636,10 +727,10 @@ __global__ void __launch_bounds__(512) k_mixed(const BlockStatic* __restrict__ b
   a.E = b.E;
   a.pad_ = 0;
   switch (b.shape) {
-    case HEX: tile_body<HEX, P, OP>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem)); break;
-    case PRISM: tile_body<PRISM, P, OP>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem)); break;
-    case PYR: tile_body<PYR, P, OP>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem)); break;
-    default: tile_body<TET, P, OP>(a, tl.e0, tl.ne, make_tile<TET, P>(smem)); break;
+    case HEX: tile_body<HEX, P, OP>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem, a.tab)); break;
+    case PRISM: tile_body<PRISM, P, OP>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem, a.tab)); break;
+    case PYR: tile_body<PYR, P, OP>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem, a.tab)); break;
+    default: tile_body<TET, P, OP>(a, tl.e0, tl.ne, make_tile<TET, P>(smem, a.tab)); break;
   }
 }
 
@@ -661,13 +752,13 @@ struct GeoRegs {
 template <int P, int PPT>
 __device__ __forceinline__ void prefetch_geo(const double* __restrict__ fac, long long e0, int ne, GeoRegs<PPT>& g) {
   constexpr int Q3 = (P + 2) * (P + 2) * (P + 2);
-  const double* base = fac + e0 * (long long)(NFAC * Q3);
+  const gptr_t base = as_global(fac) + e0 * (long long)(NFAC * Q3);
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
     const int t = tid() + it * nthr();
     if (t < ne * Q3) {
       const int e = t / Q3, pt = t - e * Q3;
-      const double* f = base + e * (NFAC * Q3) + pt;
+      const gptr_t f = base + e * (NFAC * Q3) + pt;
 #pragma unroll
       for (int c = 0; c < NFAC; ++c) g.v[it][c] = __builtin_nontemporal_load(f + c * Q3);
     }
@@ -719,7 +810,7 @@ __global__ void __launch_bounds__(512) k_helm_persist(OpArgs a, int ntiles) {
   extern __shared__ double smem[];
   int ti = blockIdx.x;
   if (ti >= ntiles) return;
-  const Tile_<SH, P> T = make_tile<SH, P>(smem);
+  const Tile_<SH, P> T = make_tile<SH, P>(smem, a.tab);
   auto ne_of = [&](int i) {
     const long long r = a.n_elem - (long long)i * a.E;
     return (int)(r < a.E ? r : a.E);
@@ -774,16 +865,315 @@ __global__ void __launch_bounds__(512) k_helm_mixed_persist(const BlockStatic* _
     };
     __syncthreads();
     switch (b.shape) {
-      case HEX: helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem), g, tables, next); break;
-      case PRISM: helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem), g, tables, next); break;
-      case PYR: helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem), g, tables, next); break;
-      default: helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<TET, P>(smem), g, tables, next); break;
+      case HEX: helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem, a.tab), g, tables, next); break;
+      case PRISM: helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem, a.tab), g, tables, next); break;
+      case PYR: helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem, a.tab), g, tables, next); break;
+      default: helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<TET, P>(smem, a.tab), g, tables, next); break;
     }
     prev = tl.blk;
     if (nx >= ntiles) break;
     ti = nx;
     tl = tn;
   }
+}
+
+// One tile per work-group, with the tile's geometric factors loaded into
+// registers at kernel start (they arrive during the sum-factorisation stages).
+template <int SH, int P, int OP, int PPT>
+__global__ void __launch_bounds__(512) k_helm_block_pf(OpArgs a) {
+  extern __shared__ double smem[];
+  const long long e0 = (long long)blockIdx.x * a.E;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < a.E ? (int)rem : a.E;
+  if (ne <= 0) return;
+  GeoRegs<PPT> g;
+  prefetch_geo<P, PPT>(a.fac, e0, ne, g);
+  helm_tile<SH, P, OP, PPT>(a, e0, ne, make_tile<SH, P>(smem, a.tab), g, true, []() {});
+}
+
+template <int P, int OP, int PPT>
+__global__ void __launch_bounds__(512) k_helm_mixed_pf(const BlockStatic* __restrict__ blocks,
+                                                       const Tile* __restrict__ tiles, int ntiles, const double* in,
+                                                       double* out, double lambda) {
+  extern __shared__ double smem[];
+  const int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  const BlockStatic b = blocks[tl.blk];
+  GeoRegs<PPT> g;
+  prefetch_geo<P, PPT>(b.fac, tl.e0, tl.ne, g);
+  OpArgs a;
+  a.tab = b.tab;
+  a.itab = b.itab;
+  a.fac = b.fac;
+  a.dxi = b.dxi;
+  a.n_elem = b.n_elem;
+  a.in = in + b.coeff_off;
+  a.out = out + b.coeff_off;
+  a.in_cs = 0;
+  a.out_cs = 0;
+  a.lambda = lambda;
+  a.E = 0;
+  a.pad_ = 0;
+  auto none = []() {};
+  switch (b.shape) {
+    case HEX: helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem, a.tab), g, true, none); break;
+    case PRISM: helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem, a.tab), g, true, none); break;
+    case PYR: helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem, a.tab), g, true, none); break;
+    default: helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<TET, P>(smem, a.tab), g, true, none); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused collocated Laplacian / Helmholtz (three LDS buffers per element)
+// ---------------------------------------------------------------------------
+// The stages are grouped by line orientation so that each thread keeps a line
+// in registers across several operations:
+//   i-lines: stage p of B fused with D_1          (U <- u, G0 <- D_1 u)
+//   j-lines: D_2                                  (G1 <- D_2 u)
+//   k-lines: D_3, the metric, D_3^T and lambda jw u in registers
+//            (U <- D_3^T v_3 + lambda jw u, G0 <- v_1, G1 <- v_2)
+//   j-lines: D_2^T in place on G1
+//   i-lines: D_1^T fused with stage p of B^T      (U <- sum_i A_p(z_i) (...))
+// A k-line's 7 Q geometric factors are contiguous in HBM, so a thread reads
+// them with wide loads, either in the k-line stage or (PF) at the start of the
+// tile into registers.
+
+template <int Q>
+struct GeoLine {
+  double v[NFAC][Q];
+};
+
+template <int P>
+__device__ __forceinline__ void load_geo_line(gptr_t fac_tile, int e, int i, int j, GeoLine<P + 2>& g) {
+  constexpr int Q = P + 2, Q3 = Q * Q * Q;
+  const gptr_t f = fac_tile + e * (NFAC * Q3) + (i * Q + j) * Q;
+#pragma unroll
+  for (int c = 0; c < NFAC; ++c)
+#pragma unroll
+    for (int k = 0; k < Q; ++k) g.v[c][k] = __builtin_nontemporal_load(f + c * Q3 + k);
+}
+
+// i-lines: Gq (in U, p rows) -> U = u and G0 = D_1 u
+template <int SH, int P>
+__device__ void bwd_p_d1(const Tile_<SH, P>& T, int ne) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const ctab_t A1 = launder(T.ct) + D::L.A1;
+    const ctab_t D1 = launder(T.ct) + D::L.D;
+    const int e = t / (Q * Q);
+    const int rem = t - e * (Q * Q);
+    const int j = rem / Q, k = rem - j * Q;
+    double* U = T.U(e) + j * QP + k;
+    double* G0 = T.G(e, 0) + j * QP + k;
+    double g[n];
+#pragma unroll
+    for (int p = 0; p < n; ++p) g[p] = U[p * Q * QP];
+    double u[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int p = 0; p < n; ++p) s = fma(A1[p * Q + i], g[p], s);
+      u[i] = s;
+      U[i * Q * QP] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) s = fma(D1[i * Q + l], u[l], s);
+      G0[i * Q * QP] = s;
+    }
+  }
+}
+
+// j-lines: G1 = D_2 U (TRANS: G1 <- D_2^T G1)
+template <int SH, int P, bool TRANS>
+__device__ void d2_lines(const Tile_<SH, P>& T, int ne) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, QP = D::QP;
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const ctab_t Dm = launder(T.ct) + D::L.D + 1 * Q * Q;
+    const int e = t / (Q * Q);
+    const int rem = t - e * (Q * Q);
+    const int i = rem / Q, k = rem - i * Q;
+    const int base = i * Q * QP + k;
+    const double* src = (TRANS ? T.G(e, 1) : T.U(e)) + base;
+    double v[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) v[l] = src[l * QP];
+    double* g = T.G(e, 1) + base;
+#pragma unroll
+    for (int jj = 0; jj < Q; ++jj) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) s = fma(TRANS ? Dm[l * Q + jj] : Dm[jj * Q + l], v[l], s);
+      g[jj * QP] = s;
+    }
+  }
+}
+
+// k-lines: the metric stage with D_3 and D_3^T in registers
+template <int SH, int P, int OP, bool PF>
+__device__ void kline_metric(const Tile_<SH, P>& T, int ne, gptr_t fac_tile, double lam, GeoLine<P + 2>& gpf) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, QP = D::QP;
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const ctab_t D3 = launder(T.ct) + D::L.D + 2 * Q * Q;
+    const int e = t / (Q * Q);
+    const int rem = t - e * (Q * Q);
+    const int i = rem / Q, j = rem - i * Q;
+    GeoLine<Q> gl;
+    if (!PF) load_geo_line<P>(fac_tile, e, i, j, gl);
+    const GeoLine<Q>& g = PF ? gpf : gl;
+    const int base = (i * Q + j) * QP;
+    double* U = T.U(e) + base;
+    double* G0 = T.G(e, 0) + base;
+    double* G1 = T.G(e, 1) + base;
+    double u[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) u[k] = U[k];
+    double v2[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      double d2 = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) d2 = fma(D3[k * Q + l], u[l], d2);
+      const double d0 = G0[k], d1 = G1[k];
+      G0[k] = g.v[1][k] * d0 + g.v[2][k] * d1 + g.v[3][k] * d2;
+      G1[k] = g.v[2][k] * d0 + g.v[4][k] * d1 + g.v[5][k] * d2;
+      v2[k] = g.v[3][k] * d0 + g.v[5][k] * d1 + g.v[6][k] * d2;
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      double o = (OP == OPK_HELM) ? lam * g.v[0][k] * u[k] : 0.0;
+#pragma unroll
+      for (int m = 0; m < Q; ++m) o = fma(D3[m * Q + k], v2[m], o);
+      U[k] = o;
+    }
+  }
+}
+
+// i-lines: D_1^T on G0 plus U + G1, then stage p of B^T -> Gp in U
+template <int SH, int P>
+__device__ void ipr_p_d1t(const Tile_<SH, P>& T, int ne) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const ctab_t A1 = launder(T.ct) + D::L.A1;
+    const ctab_t D1 = launder(T.ct) + D::L.D;
+    const int e = t / (Q * Q);
+    const int rem = t - e * (Q * Q);
+    const int j = rem / Q, k = rem - j * Q;
+    const int o = j * QP + k;
+    const double* G0 = T.G(e, 0) + o;
+    const double* G1 = T.G(e, 1) + o;
+    double* U = T.U(e) + o;
+    double g0[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) g0[l] = G0[l * Q * QP];
+    double sv[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double s = U[i * Q * QP] + G1[i * Q * QP];
+#pragma unroll
+      for (int l = 0; l < Q; ++l) s = fma(D1[l * Q + i], g0[l], s);
+      sv[i] = s;
+    }
+#pragma unroll
+    for (int p = 0; p < n; ++p) {
+      double a = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) a = fma(A1[p * Q + i], sv[i], a);
+      U[p * Q * QP] = a;
+    }
+  }
+}
+
+template <int SH, int P, int OP, bool PF>
+__device__ void helm_fused_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH, P>& T, bool tables) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, Q3 = D::Q3;
+  const gptr_t fac_tile = as_global(a.fac) + e0 * (long long)(NFAC * Q3);
+  GeoLine<Q> gpf;
+  if (PF) {
+    const int t = tid();
+    if (t < ne * Q * Q) {
+      const int e = t / (Q * Q);
+      const int rem = t - e * (Q * Q);
+      load_geo_line<P>(fac_tile, e, rem / Q, rem - (rem / Q) * Q, gpf);
+    }
+  }
+  if (tables) load_tables<SH, P>(a, T);
+  load_modes<SH, P>(T, a.in, e0, ne, 0);
+  __syncthreads();
+  bwd_r<SH, P, false>(T, ne, 0, 1);  // modes in G0 -> F in G1
+  __syncthreads();
+  bwd_q<SH, P, false>(T, ne, 1, -1);  // F -> Gq in U
+  __syncthreads();
+  bwd_p_d1<SH, P>(T, ne);
+  __syncthreads();
+  d2_lines<SH, P, false>(T, ne);
+  __syncthreads();
+  kline_metric<SH, P, OP, PF>(T, ne, fac_tile, (OP == OPK_HELM) ? a.lambda : 0.0, gpf);
+  __syncthreads();
+  d2_lines<SH, P, true>(T, ne);
+  __syncthreads();
+  ipr_p_d1t<SH, P>(T, ne);
+  __syncthreads();
+  ipr_q<SH, P, false>(T, ne, -1, 0);  // Gp in U -> F in G0
+  __syncthreads();
+  ipr_r<SH, P, false>(T, ne, 0, 1, false);  // -> modes in G1
+  __syncthreads();
+  store_modes<SH, P>(T, a.out, e0, ne, 1);
+}
+
+template <int SH, int P, int OP, bool PF>
+__global__ void __launch_bounds__(512) k_helm_fused(OpArgs a) {
+  extern __shared__ double smem[];
+  const long long e0 = (long long)blockIdx.x * a.E;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < a.E ? (int)rem : a.E;
+  if (ne <= 0) return;
+  helm_fused_tile<SH, P, OP, PF>(a, e0, ne, make_tile3<SH, P>(smem, a.tab), true);
+}
+
+template <int P, int OP, bool PF>
+__global__ void __launch_bounds__(512) k_helm_fused_mixed(const BlockStatic* __restrict__ blocks,
+                                                          const Tile* __restrict__ tiles, int ntiles,
+                                                          const double* in, double* out, double lambda) {
+  extern __shared__ double smem[];
+  const int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  const BlockStatic b = blocks[tl.blk];
+  OpArgs a;
+  a.tab = b.tab;
+  a.itab = b.itab;
+  a.fac = b.fac;
+  a.dxi = b.dxi;
+  a.n_elem = b.n_elem;
+  a.in = in + b.coeff_off;
+  a.out = out + b.coeff_off;
+  a.in_cs = 0;
+  a.out_cs = 0;
+  a.lambda = lambda;
+  a.E = 0;
+  a.pad_ = 0;
+  switch (b.shape) {
+    case HEX: helm_fused_tile<HEX, P, OP, PF>(a, tl.e0, tl.ne, make_tile3<HEX, P>(smem, a.tab), true); break;
+    case PRISM: helm_fused_tile<PRISM, P, OP, PF>(a, tl.e0, tl.ne, make_tile3<PRISM, P>(smem, a.tab), true); break;
+    case PYR: helm_fused_tile<PYR, P, OP, PF>(a, tl.e0, tl.ne, make_tile3<PYR, P>(smem, a.tab), true); break;
+    default: helm_fused_tile<TET, P, OP, PF>(a, tl.e0, tl.ne, make_tile3<TET, P>(smem, a.tab), true); break;
+  }
+}
+
+template <int SH, int P>
+constexpr size_t lds_bytes3(int E) {
+  using D = Dims<SH, P>;
+  return sizeof(double) * (size_t)(D::HEAD + E * 3 * D::S3);
 }
 
 // LDS bytes of a tile of E elements

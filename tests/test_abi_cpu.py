@@ -104,7 +104,7 @@ def test_error_paths_without_device(L):
     # tiling validation
     assert L.shp_set_tiling(h, 0, 6, 2, 0, 256, 1) == -1
     assert L.shp_set_tiling(h, 0, 6, 2, 4, 100, 1) == -1
-    assert L.shp_set_tiling(h, 0, 6, 2, 4, 128, 3) == -1
+    assert L.shp_set_tiling(h, 0, 6, 2, 4, 128, 7) == -1
     assert L.shp_set_tiling(h, 0, 6, 2, 64, 256, 1) == -2        # LDS overflow at P=4
     assert L.shp_set_tiling(h, 0, 6, 2, 4, 128, 0) == 0
     E, NT, pe = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
@@ -112,7 +112,7 @@ def test_error_paths_without_device(L):
     assert (E.value, NT.value, pe.value) == (4, 128, 0)
     assert L.shp_set_tiling(h, 0, 6, 2, 0, 0, 0) == 0            # back to default
     assert L.shp_get_tiling(h, -1, 6, 2, ctypes.byref(E), ctypes.byref(NT), ctypes.byref(pe)) == 0
-    assert (E.value, NT.value, pe.value) == (4, 256, 1)          # 40 KiB LDS budget at P=4
+    assert (E.value, NT.value, pe.value) == (4, 256, 2)          # 40 KiB LDS budget at P=4
     c, q = ctypes.c_int64(), ctypes.c_int64()
     assert L.shp_block_offsets(h, 1, ctypes.byref(c), ctypes.byref(q)) == 0
     assert (c.value, q.value) == (10 * 125, 10 * 216)

@@ -115,6 +115,21 @@ def test_config1_affine_hex_helmholtz(shp):
     assert rel(y, ref) <= TOL
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+def test_whole_mesh_variants_agree(shp, variant):
+    """Every launch variant of the whole-mesh Helmholtz launch gives the same bits."""
+    say(f"[parity] whole-mesh variant={variant}")
+    mesh, plan = _mixed_plan(shp, 4, 4)
+    nc, _ = plan.totals()
+    x = torch.from_numpy(W.coeffs(1, nc, 21)[0]).cuda()
+    plan.set_tiling(-1, "helmholtz", 1, 64, 3 if variant >= 3 else 0)
+    base = plan.apply(-1, "helmholtz", x).cpu().numpy()
+    for E, NT in ((1, 64), (2, 128), (4, 256), (3, 192), (7, 256)):
+        plan.set_tiling(-1, "helmholtz", E, NT, variant)
+        y = plan.apply(-1, "helmholtz", x).cpu().numpy()
+        assert np.array_equal(y, base), (E, NT, variant)
+
+
 def _mixed_plan(shp, ncell, P):
     mesh = W.quadrant_mesh(ncell)
     blocks = [(s, P, len(mesh[s]), "curved") for s in O.SHAPES]
@@ -171,12 +186,23 @@ def test_tilings_agree_bitwise(shp, shape):
     plan = shp.Plan([(shape, P, ne, "curved")])
     plan.set_geometry(0, gpu_geometry(shp, maps, shape, P, True))
     x = torch.from_numpy(W.coeffs(ne, plan.n_modes[0], 9)).cuda()
-    base = plan.apply(0, "helmholtz", x).cpu().numpy()
+    base = {}
+    plan.set_tiling(0, "helmholtz", 1, 64, 0)
+    base[0] = plan.apply(0, "helmholtz", x).cpu().numpy()
+    plan.set_tiling(0, "helmholtz", 1, 64, 3)
+    base[3] = plan.apply(0, "helmholtz", x).cpu().numpy()
+    # the two families (separate stages; fused stages) differ by summation order only
+    assert rel(base[3], base[0]) < 1e-14
+    ref = O.apply_op("helmholtz", shape, P, P + 2, oracle_geometry(maps, shape, P, True), x.cpu().numpy())
+    assert rel(base[3], ref) <= TOL
     for E, NT, pe in ((1, 64, 0), (2, 128, 0), (5, 256, 0), (8, 512, 0), (3, 192, 0),
-                      (1, 64, 1), (2, 128, 1), (4, 256, 1), (8, 512, 1), (3, 192, 1), (6, 256, 1)):
+                      (1, 64, 1), (2, 128, 1), (4, 256, 1), (8, 512, 1), (3, 192, 1), (6, 256, 1),
+                      (1, 64, 2), (2, 128, 2), (4, 256, 2), (8, 512, 2), (3, 192, 2), (6, 256, 2),
+                      (1, 64, 3), (2, 128, 3), (4, 256, 3), (7, 512, 3), (3, 192, 3), (5, 320, 3),
+                      (1, 64, 4), (2, 128, 4), (4, 256, 4), (7, 256, 4), (3, 192, 4), (5, 320, 4)):
         plan.set_tiling(0, "helmholtz", E, NT, pe)
         y = plan.apply(0, "helmholtz", x).cpu().numpy()
-        assert np.array_equal(y, base), (E, NT, pe)
+        assert np.array_equal(y, base[3 if pe >= 3 else 0]), (E, NT, pe)
 
 
 def test_bad_geometry_is_reported(shp):
