@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--P", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--per-shape", action="store_true", help="also time each shape's block launch")
+    ap.add_argument("--strategies", action="store_true",
+                    help="also time collocated vs non-collocated Helmholtz per shape (block launches)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     a = ap.parse_args()
@@ -193,6 +195,21 @@ def main():
             per_shape[s] = {"GDOF/s": ne * plan.n_modes[b] / (m * 1e-3) / 1e9,
                             "hbm_frac": bb / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms": m}
             log(f"  {s}: {per_shape[s]}")
+    strategies = None
+    if a.strategies:
+        strategies = {}
+        for b, s in enumerate(SHAPES):
+            co, _ = plan.offsets(b)
+            ne = len(mesh[s])
+            xb = x[co:co + ne * plan.n_modes[b]].view(ne, -1)
+            yb = torch.empty_like(xb)
+            row = {}
+            for st in ("sumfac_coll", "sumfac"):
+                _, m, _ = time_launches(torch, lambda: plan.apply(b, "helmholtz", xb, out=yb, strategy=st), 20, 3)
+                row[st] = {"ms": round(m, 5), "GDOF/s": round(ne * plan.n_modes[b] / (m * 1e-3) / 1e9, 3)}
+            row["coll_speedup"] = round(row["sumfac"]["ms"] / row["sumfac_coll"]["ms"], 3)
+            strategies[s] = row
+            log(f"  {s}: {row}")
     cpu = None
     if not a.no_cpu:
         log("  cpu baseline (oracle, bounded sample)")
@@ -222,6 +239,8 @@ def main():
     }
     if per_shape is not None:
         out["per_shape"] = per_shape
+    if strategies is not None:
+        out["collocated_vs_noncollocated"] = strategies
     print(json.dumps(out), flush=True)
 
 

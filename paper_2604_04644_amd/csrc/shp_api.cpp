@@ -84,14 +84,18 @@ int opk_of(int op, int strategy, int* opk) {
     case SHP_OP_LAPLACIAN:
     case SHP_OP_HELMHOLTZ:
       if (strategy == SHP_SUMFAC)
-        return fail(SHP_ERR_UNSUPPORTED, "non-collocated Laplacian/Helmholtz is not built yet");
-      *opk = (op == SHP_OP_LAPLACIAN) ? OPK_LAP : OPK_HELM;
+        *opk = (op == SHP_OP_LAPLACIAN) ? OPK_LAP_NC : OPK_HELM_NC;
+      else
+        *opk = (op == SHP_OP_LAPLACIAN) ? OPK_LAP : OPK_HELM;
       return SHP_OK;
   }
   return fail(SHP_ERR_INVALID_ARG, "bad operator %d", op);
 }
 
-bool in_is_modes(int opk) { return opk == OPK_BWD || opk == OPK_MASS || opk == OPK_LAP || opk == OPK_HELM || opk == OPK_HELM_NC; }
+bool in_is_modes(int opk) {
+  return opk == OPK_BWD || opk == OPK_MASS || opk == OPK_LAP || opk == OPK_HELM || opk == OPK_HELM_NC ||
+         opk == OPK_LAP_NC;
+}
 bool out_is_modes(int opk) { return !(opk == OPK_BWD || opk == OPK_DERIV); }
 
 // Default launch shape: as many elements per work-group as fit a 40 KiB LDS

@@ -20,7 +20,8 @@ size_t lds_bytes_pyr(int P, int E, int nbuf);
 size_t lds_bytes_tet(int P, int E, int nbuf);
 
 size_t op_lds_bytes(int sh, int P, int opk, int E, int variant) {
-  const int nbuf = (variant >= 3 && (opk == OPK_HELM || opk == OPK_LAP)) ? 3 : 4;
+  const int nbuf = (opk == OPK_HELM_NC || opk == OPK_LAP_NC) ? 5
+                   : (variant >= 3 && (opk == OPK_HELM || opk == OPK_LAP)) ? 3 : 4;
   switch (sh) {
     case HEX: return lds_bytes_hex(P, E, nbuf);
     case PRISM: return lds_bytes_prism(P, E, nbuf);
@@ -124,6 +125,14 @@ static hipError_t launch_mixed_p(int opk, const BlockStatic* blocks, const Tile*
                                  double* out, long long in_cs, long long out_cs, double lambda, int threads,
                                  size_t lds, int E, int persist, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  if (opk == OPK_HELM_NC || opk == OPK_LAP_NC) {
+    const dim3 g((unsigned)ntiles), b((unsigned)threads);
+    if (opk == OPK_HELM_NC)
+      hipLaunchKernelGGL((k_helm_nc_mixed<P, OPK_HELM>), g, b, lds, s, blocks, tiles, ntiles, in, out, lambda);
+    else
+      hipLaunchKernelGGL((k_helm_nc_mixed<P, OPK_LAP>), g, b, lds, s, blocks, tiles, ntiles, in, out, lambda);
+    return hipGetLastError();
+  }
   if (persist >= 3 && (opk == OPK_HELM || opk == OPK_LAP)) {
     const bool pf = (persist == 4) && (E * (P + 2) * (P + 2) <= threads);
     return opk == OPK_HELM ? launch_mixed_fused<P, OPK_HELM>(blocks, tiles, ntiles, in, out, lambda, threads, lds, pf, s)

@@ -38,7 +38,8 @@ enum : int {
   OPK_LAP = 5,
   OPK_HELM = 6,
   OPK_HELM_NC = 7,  // non-collocated Helmholtz (Alg. 5)
-  OPK_COUNT = 8
+  OPK_LAP_NC = 8,   // non-collocated Laplacian
+  OPK_COUNT = 9
 };
 
 // Arguments of one block for one operator call.
@@ -711,7 +712,8 @@ __global__ void __launch_bounds__(512) k_mixed(const BlockStatic* __restrict__ b
   if (ti >= ntiles) return;
   const Tile tl = tiles[ti];
   const BlockStatic b = blocks[tl.blk];
-  constexpr bool in_modes = (OP == OPK_BWD || OP == OPK_MASS || OP == OPK_LAP || OP == OPK_HELM || OP == OPK_HELM_NC);
+  constexpr bool in_modes = (OP == OPK_BWD || OP == OPK_MASS || OP == OPK_LAP || OP == OPK_HELM || OP == OPK_HELM_NC ||
+                             OP == OPK_LAP_NC);
   constexpr bool out_modes = !(OP == OPK_BWD || OP == OPK_DERIV);
   OpArgs a;
   a.tab = b.tab;
@@ -1174,6 +1176,282 @@ template <int SH, int P>
 constexpr size_t lds_bytes3(int E) {
   using D = Dims<SH, P>;
   return sizeof(double) * (size_t)(D::HEAD + E * 3 * D::S3);
+}
+
+// ---------------------------------------------------------------------------
+// Non-collocated Laplacian / Helmholtz (Alg. 5): sum-factorised B and d_d B
+// ---------------------------------------------------------------------------
+// u = B x and v_d = (d_d B) x share a tree of 1D stages (tables A/dA in eta1,
+// B2/dB2 in eta2, C3/dC3 in eta3); after the metric the transposed tree sums
+// the table pairs:  y = C3^T[B2^T(A^T(lam W u) + dA^T v_1') + dB2^T A^T v_2']
+//                     + dC3^T B2^T A^T v_3'.
+// Five LDS buffers per element (U = B0, G(0..3) = B1..B4).
+
+template <int SH, int P>
+__device__ Tile_<SH, P> make_tile5(double* smem, const double* gtab) {
+  Tile_<SH, P> T = make_tile<SH, P>(smem, gtab);
+  T.per = 5 * Dims<SH, P>::S3;
+  return T;
+}
+
+__device__ __forceinline__ int bufidx(int b) { return b - 1; }  // B0 -> -1 (U), Bk -> G(k-1)
+
+// stage p of B: Gu (p rows, in buffer src) -> u in place and v_1 = dA rows into dst1
+template <int SH, int P>
+__device__ void nc_bwd_p_uv(const Tile_<SH, P>& T, int ne, int src, int dst1) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const ctab_t A1 = launder(T.ct) + D::L.A1;
+    const ctab_t dA1 = launder(T.ct) + D::L.dA1;
+    const int e = t / (Q * Q);
+    const int rem = t - e * (Q * Q);
+    const int j = rem / Q, k = rem - j * Q;
+    double* S = (src < 0 ? T.U(e) : T.G(e, src)) + j * QP + k;
+    double* V = T.G(e, dst1) + j * QP + k;
+    double g[n];
+#pragma unroll
+    for (int p = 0; p < n; ++p) g[p] = S[p * Q * QP];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int p = 0; p < n; ++p) {
+        a = fma(A1[p * Q + i], g[p], a);
+        b = fma(dA1[p * Q + i], g[p], b);
+      }
+      S[i * Q * QP] = a;
+      V[i * Q * QP] = b;
+    }
+  }
+}
+
+// stage p of B^T with two inputs: dst <- A^T(a) (+ dA^T(b) when b >= -1); in place over a
+template <int SH, int P, bool TWO>
+__device__ void nc_ipr_p(const Tile_<SH, P>& T, int ne, int a_buf, int b_buf) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const ctab_t A1 = launder(T.ct) + D::L.A1;
+    const ctab_t dA1 = launder(T.ct) + D::L.dA1;
+    const int e = t / (Q * Q);
+    const int rem = t - e * (Q * Q);
+    const int j = rem / Q, k = rem - j * Q;
+    double* Ab = (a_buf < 0 ? T.U(e) : T.G(e, a_buf)) + j * QP + k;
+    double sa[Q], sb[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) sa[i] = Ab[i * Q * QP];
+    if (TWO) {
+      const double* Bb = (b_buf < 0 ? T.U(e) : T.G(e, b_buf)) + j * QP + k;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) sb[i] = Bb[i * Q * QP];
+    }
+#pragma unroll
+    for (int p = 0; p < n; ++p) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        acc = fma(A1[p * Q + i], sa[i], acc);
+        if (TWO) acc = fma(dA1[p * Q + i], sb[i], acc);
+      }
+      Ab[p * Q * QP] = acc;
+    }
+  }
+}
+
+// stage q of B^T with up to two inputs: F (dst) <- B2^T(a) [+ dB2^T(b)]
+template <int SH, int P, bool TWO>
+__device__ void nc_ipr_q(const Tile_<SH, P>& T, int ne, int a_buf, int b_buf, int dst) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  for (int t = tid(); t < ne * n * Q; t += nthr()) {
+    const int e = t / (n * Q);
+    const int rem = t - e * (n * Q);
+    const int p = rem / Q, k = rem - p * Q;
+    const double* GA = (a_buf < 0 ? T.U(e) : T.G(e, a_buf)) + p * Q * QP + k;
+    const double* GB = (b_buf < 0 ? T.U(e) : T.G(e, b_buf)) + p * Q * QP + k;
+    double ga[Q], gb[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) ga[j] = GA[j * QP];
+    if (TWO) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) gb[j] = GB[j * QP];
+    }
+    double* F = T.G(e, dst);
+    const int nq = nq_of(SH, P, p), cb = col_base(SH, P, p);
+    const int bfam = (SH == TET) ? fam_index(P, p, 0) : 0;
+    const double* B2 = T.tab + D::L.B2;
+    const double* dB2 = T.tab + D::L.dB2;
+    for (int q = 0; q < nq; ++q) {
+      double acc = 0.0;
+      const double* b = B2 + (bfam + q) * Q;
+      const double* db = dB2 + (bfam + q) * Q;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        acc = fma(b[j], ga[j], acc);
+        if (TWO) acc = fma(db[j], gb[j], acc);
+      }
+      if (SH == TET && p == 0 && q == 1) {
+        // adjoints of the tet's extra eta2 term, one per (table, input) pair
+        const double* GA1 = GA + 1 * Q * QP;
+        const double* GB1 = GB + 1 * Q * QP;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          acc = fma(B2[1 * Q + j], GA1[j * QP], acc);
+          if (TWO) acc = fma(dB2[1 * Q + j], GB1[j * QP], acc);
+        }
+      }
+      F[(cb + q) * QP + k] = acc;
+    }
+  }
+}
+
+// stage r of B^T with two inputs: y (dst) <- C3^T(Fa) + dC3^T(Fb)
+template <int SH, int P>
+__device__ void nc_ipr_r(const Tile_<SH, P>& T, int ne, int fa, int fb_buf, int dst) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, QP = D::QP;
+  const double* C3 = T.tab + D::L.C3;
+  const double* dC3 = T.tab + D::L.dC3;
+  for (int t = tid(); t < ne * D::NC; t += nthr()) {
+    const int e = t / D::NC, c = t - e * D::NC;
+    const int* ct = T.itab + c * ICOL;
+    const int p = ct[0], q = ct[1], off = ct[2], R = ct[3], fam = ct[4];
+    const double* FA = T.G(e, fa);
+    const double* FB = T.G(e, fb_buf);
+    double f[Q], g[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      f[k] = FA[c * QP + k];
+      g[k] = FB[c * QP + k];
+    }
+    double* y = (dst < 0 ? T.U(e) : T.G(e, dst)) + off;
+    for (int r = 0; r < R; ++r) {
+      const double* cf = C3 + (fam + r) * Q;
+      const double* dcf = dC3 + (fam + r) * Q;
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) a = fma(cf[k], f[k], fma(dcf[k], g[k], a));
+      const bool vx = (r == 1) && ((SH == PRISM && p == 0) || ((SH == PYR || SH == TET) && p == 0 && q == 0));
+      if (vx) {
+        // the collapsed-vertex splits, adjoint per (table, input) pair
+        int cols[3];
+        int nc = 0;
+        if (SH == PRISM) {
+          cols[nc++] = (P + 1) + q;
+        } else if (SH == PYR) {
+          cols[nc++] = P + 1;
+          cols[nc++] = 1;
+          cols[nc++] = P + 2;
+        } else {
+          cols[nc++] = 1;
+          cols[nc++] = P + 1;
+        }
+        for (int u = 0; u < nc; ++u) {
+#pragma unroll
+          for (int k = 0; k < Q; ++k)
+            a = fma(C3[1 * Q + k], FA[cols[u] * QP + k], fma(dC3[1 * Q + k], FB[cols[u] * QP + k], a));
+        }
+      }
+      y[r] = a;
+    }
+  }
+}
+
+template <int SH, int P, int OP>
+__device__ void helm_nc_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH, P>& T) {
+  using D = Dims<SH, P>;
+  constexpr int Q3 = D::Q3;
+  load_tables<SH, P>(a, T);
+  load_modes<SH, P>(T, a.in, e0, ne, 3);  // x in B4
+  __syncthreads();
+  bwd_r<SH, P, false>(T, ne, 3, 0);  // F  (C3)  -> B1
+  bwd_r<SH, P, true>(T, ne, 3, 1);   // F' (dC3) -> B2
+  __syncthreads();
+  bwd_q<SH, P, false>(T, ne, 0, -1);  // Gu  = B2 F   -> B0
+  bwd_q<SH, P, true>(T, ne, 0, 2);    // G2' = dB2 F  -> B3
+  bwd_q<SH, P, false>(T, ne, 1, 3);   // G3' = B2 F'  -> B4
+  __syncthreads();
+  nc_bwd_p_uv<SH, P>(T, ne, -1, 0);   // u -> B0, v_1 -> B1
+  bwd_p<SH, P, false>(T, ne, 2, 2);   // v_2 -> B3 (in place)
+  bwd_p<SH, P, false>(T, ne, 3, 3);   // v_3 -> B4 (in place)
+  __syncthreads();
+  const gptr_t fac = as_global(a.fac) + e0 * (long long)(NFAC * Q3);
+  const double lam = (OP == OPK_HELM) ? a.lambda : 0.0;
+  for (int t = tid(); t < ne * Q3; t += nthr()) {
+    const int e = t / Q3, pt = t - e * Q3;
+    const int lp = lds_pt<SH, P>(pt);
+    const gptr_t g = fac + e * (NFAC * Q3) + pt;
+    double* u = T.U(e) + lp;
+    double* p1 = T.G(e, 0) + lp;
+    double* p2 = T.G(e, 2) + lp;
+    double* p3 = T.G(e, 3) + lp;
+    const double d0 = *p1, d1 = *p2, d2 = *p3;
+    const double jw = g[0];
+    const double g00 = g[1 * Q3], g01 = g[2 * Q3], g02 = g[3 * Q3];
+    const double g11 = g[4 * Q3], g12 = g[5 * Q3], g22 = g[6 * Q3];
+    *p1 = g00 * d0 + g01 * d1 + g02 * d2;
+    *p2 = g01 * d0 + g11 * d1 + g12 * d2;
+    *p3 = g02 * d0 + g12 * d1 + g22 * d2;
+    *u = lam * jw * (*u);
+  }
+  __syncthreads();
+  nc_ipr_p<SH, P, true>(T, ne, -1, 0);  // Hu = A^T(lam W u) + dA^T v_1' -> B0
+  nc_ipr_p<SH, P, false>(T, ne, 2, 0);  // H2 = A^T v_2' -> B3
+  nc_ipr_p<SH, P, false>(T, ne, 3, 0);  // H3 = A^T v_3' -> B4
+  __syncthreads();
+  nc_ipr_q<SH, P, true>(T, ne, -1, 2, 0);  // K  = B2^T Hu + dB2^T H2 -> B1
+  nc_ipr_q<SH, P, false>(T, ne, 3, 3, 1);  // K3 = B2^T H3           -> B2
+  __syncthreads();
+  nc_ipr_r<SH, P>(T, ne, 0, 1, -1);  // y = C3^T K + dC3^T K3 -> B0
+  __syncthreads();
+  store_modes<SH, P>(T, a.out, e0, ne, -1);
+}
+
+template <int SH, int P, int OP>
+__global__ void __launch_bounds__(512) k_helm_nc(OpArgs a) {
+  extern __shared__ double smem[];
+  const long long e0 = (long long)blockIdx.x * a.E;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < a.E ? (int)rem : a.E;
+  if (ne <= 0) return;
+  helm_nc_tile<SH, P, OP>(a, e0, ne, make_tile5<SH, P>(smem, a.tab));
+}
+
+template <int P, int OP>
+__global__ void __launch_bounds__(512) k_helm_nc_mixed(const BlockStatic* __restrict__ blocks,
+                                                       const Tile* __restrict__ tiles, int ntiles, const double* in,
+                                                       double* out, double lambda) {
+  extern __shared__ double smem[];
+  const int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  const BlockStatic b = blocks[tl.blk];
+  OpArgs a;
+  a.tab = b.tab;
+  a.itab = b.itab;
+  a.fac = b.fac;
+  a.dxi = b.dxi;
+  a.n_elem = b.n_elem;
+  a.in = in + b.coeff_off;
+  a.out = out + b.coeff_off;
+  a.in_cs = 0;
+  a.out_cs = 0;
+  a.lambda = lambda;
+  a.E = 0;
+  a.pad_ = 0;
+  switch (b.shape) {
+    case HEX: helm_nc_tile<HEX, P, OP>(a, tl.e0, tl.ne, make_tile5<HEX, P>(smem, a.tab)); break;
+    case PRISM: helm_nc_tile<PRISM, P, OP>(a, tl.e0, tl.ne, make_tile5<PRISM, P>(smem, a.tab)); break;
+    case PYR: helm_nc_tile<PYR, P, OP>(a, tl.e0, tl.ne, make_tile5<PYR, P>(smem, a.tab)); break;
+    default: helm_nc_tile<TET, P, OP>(a, tl.e0, tl.ne, make_tile5<TET, P>(smem, a.tab)); break;
+  }
+}
+
+template <int SH, int P>
+constexpr size_t lds_bytes5(int E) {
+  using D = Dims<SH, P>;
+  return sizeof(double) * (size_t)(D::HEAD + E * 5 * D::S3);
 }
 
 // LDS bytes of a tile of E elements

@@ -85,6 +85,44 @@ def test_block_ops_vs_oracle(shp, shape, P):
         assert e <= TOL, (shape, P, op, e)
 
 
+@pytest.mark.parametrize("shape,P", [(s, P) for s in O.SHAPES for P in (1, 2, 4, 6, 9)])
+def test_noncollocated_vs_oracle(shp, shape, P):
+    """Alg. 5 (sum-factorised B and d_d B, strategy 'sumfac') for the Laplacian and
+    Helmholtz actions, and its agreement with the collocated form (eq. helm1)."""
+    ne = 23 if P <= 6 else 4
+    say(f"[parity] non-collocated shape={shape} P={P}")
+    maps = W.shape_batch(shape, ne)
+    plan = shp.Plan([(shape, P, ne, "curved")])
+    plan.set_geometry(0, gpu_geometry(shp, maps, shape, P, True))
+    jo = oracle_geometry(maps, shape, P, True)
+    for k, op in enumerate(("laplacian", "helmholtz")):
+        x = W.coeffs(ne, plan.n_modes[0], 400 + k)
+        ref = O.apply_op(op, shape, P, P + 2, jo, x, lam=0.7, chunk=8)
+        xt = torch.from_numpy(x).cuda()
+        y = plan.apply(0, op, xt, lam=0.7, strategy="sumfac").cpu().numpy()
+        yc = plan.apply(0, op, xt, lam=0.7, strategy="sumfac_coll").cpu().numpy()
+        e = rel(y, ref)
+        say(f"    {op:12s} rel={e:.2e} vs collocated {rel(y, yc):.2e}")
+        assert e <= TOL, (shape, P, op, e)
+        assert rel(y, yc) <= TOL
+
+
+def test_noncollocated_whole_mesh(shp):
+    say("[parity] non-collocated whole mesh")
+    mesh, plan = _mixed_plan(shp, 4, 3)
+    nc, _ = plan.totals()
+    x = torch.from_numpy(W.coeffs(1, nc, 31)[0]).cuda()
+    y = plan.apply(-1, "helmholtz", x, strategy="sumfac").cpu().numpy()
+    for b, s in enumerate(O.SHAPES):
+        co, _ = plan.offsets(b)
+        ne, NP = len(mesh[s]), plan.n_modes[b]
+        xb = x.cpu().numpy()[co:co + ne * NP].reshape(ne, NP)
+        yb = plan.apply(b, "helmholtz", torch.from_numpy(xb).cuda(), strategy="sumfac").cpu().numpy()
+        assert np.array_equal(y[co:co + ne * NP].reshape(ne, NP), yb)
+        ref = O.apply_op("helmholtz", s, 3, 5, oracle_geometry(mesh[s], s, 3, True), xb)
+        assert rel(yb, ref) <= TOL
+
+
 @pytest.mark.parametrize("shape", O.SHAPES)
 def test_affine_blocks_vs_oracle(shp, shape):
     P, ne = 3, 21
