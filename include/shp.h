@@ -78,7 +78,10 @@ typedef enum {
 typedef enum {
   SHP_AUTO = 0,        /* tuned choice if one is cached, else SHP_SUMFAC_COLL     */
   SHP_SUMFAC = 1,      /* sum-factorisation, non-collocated derivatives (Alg. 5)  */
-  SHP_SUMFAC_COLL = 2  /* sum-factorisation, collocated derivatives (Alg. 6)      */
+  SHP_SUMFAC_COLL = 2, /* sum-factorisation, collocated derivatives (Alg. 6)      */
+  SHP_LOCALMAT = 3     /* reference matrices [B; d_d B] on FP64 MFMA (Alg. 1, the
+                          non-collocated form); mass, Laplacian and Helmholtz at
+                          P <= 4; other operators and orders: SHP_ERR_UNSUPPORTED */
 } shp_strategy;
 
 typedef struct {
@@ -156,6 +159,71 @@ int shp_set_tiling(shp_plan plan, int blk, int op, int strategy, int elems_per_w
 /* Current launch shape for (blk, op, strategy). */
 int shp_get_tiling(shp_plan plan, int blk, int op, int strategy, int* elems_per_wg /* host out */,
                    int* threads /* host out */, int* variant /* host out */);
+
+/* Result of tuning one (block, operator). */
+typedef struct {
+  int strategy;      /* fastest strategy */
+  int elems_per_wg;  /* its launch shape */
+  int threads;
+  int variant;
+  double ms;         /* median launch time of the choice */
+  int n_candidates;  /* candidates run */
+  int n_rejected;    /* candidates that failed the parity gate */
+} shp_tune_result;
+
+/* One timed candidate. ms < 0 when the candidate failed the parity gate. */
+typedef struct {
+  int strategy, elems_per_wg, threads, variant;
+  double ms;
+  int passed;
+} shp_tune_record;
+
+/* Exhaustive tuning of operator op on block blk (-1: the whole-mesh launch):
+ * "different implementation choices may be made per block" (Sec. 3.3).  Every
+ * strategy and launch shape that fits (quick = 1: a reduced set) runs on the
+ * caller's representative input in; its output must match the default
+ * collocated launch's output (written to ref) to 1e-12 in the max norm
+ * relative to max |ref| or it is rejected; accepted candidates are timed as the
+ * median of reps launches with HIP events on stream.  The fastest becomes the
+ * launch shape of its strategy and the choice SHP_AUTO makes for (blk, op).
+ * out and ref are caller device buffers of the operator's output size.
+ * records (host, may be NULL) receives up to max_records candidate timings.
+ * Synchronises stream.  Returns SHP_ERR_NOT_CONVERGED if no candidate passes. */
+int shp_tune(shp_plan plan, int blk, int op, const double* in /* device */, double* out /* device */,
+             double* ref /* device */, double lambda, int reps, int quick, shp_tune_result* result /* host out */,
+             shp_tune_record* records /* host out or NULL */, int max_records, int* n_records /* host out or NULL */,
+             void* stream);
+
+/* Fix the strategy SHP_AUTO uses for (blk, op) without tuning (used by a cost
+ * model that predicts the fastest strategy). */
+int shp_set_auto_strategy(shp_plan plan, int blk, int op, int strategy);
+
+/* Append the plan's tuned choices to a JSON-lines cache file, keyed by device,
+ * precision, operator, shape, P, Q, log2 of the block size and mapping type. */
+int shp_tune_cache_save(shp_plan plan, const char* path /* host */);
+
+/* Apply the entries of a cache file that match this plan's blocks (same keys)
+ * and device; malformed or out-of-range entries are skipped.  n_applied may be
+ * NULL. */
+int shp_tune_cache_load(shp_plan plan, const char* path /* host */, int* n_applied /* host out or NULL */);
+
+/* ---- MLP cost model (11 -> 64 -> 64 -> 1, ReLU, FP32), trained on the GPU ----
+ * Inputs per sample: shape one-hot (4), P/10, Q/12, log2(n_elem)/22, curved,
+ * strategy one-hot (local matrix, sum-factorisation, collocated); output: a
+ * standardised log launch time per DOF.  All pointers are device FP32 buffers
+ * owned by the caller; work holds per-sample activations (shp_mlp_work_floats).
+ * Parameters: W1 [64][11], b1 [64], W2 [64][64], b2 [64], W3 [1][64], b3 [1]. */
+int shp_mlp_num_params(int* n /* host out */);
+int shp_mlp_work_floats(int n_samples, long long* n /* host out */);
+/* y [n] = network(X [n][11]). */
+int shp_mlp_forward(const float* params, const float* X, int n, float* y, float* work, void* stream);
+/* Mean squared error of the network against target [n] (loss [1]) and its
+ * gradient with respect to the parameters (grad [num_params]). */
+int shp_mlp_loss_grad(const float* params, const float* X, const float* target, int n, float* grad, float* loss,
+                      float* work, void* stream);
+/* One Adam step (step counts from 1) on params with moments m, v. */
+int shp_mlp_adam(float* params, const float* grad, float* m, float* v, int step, float lr, float beta1, float beta2,
+                 float eps, void* stream);
 
 /* Destroy a plan (host metadata only; the workspace stays the caller's). */
 int shp_plan_destroy(shp_plan plan);

@@ -48,10 +48,17 @@ struct Block {
   int NP = 0, NQ = 0;
   std::vector<double> tab;
   std::vector<int> itab;
-  size_t off_tab = 0, off_itab = 0, off_fac = 0, off_dxi = 0;
+  size_t off_tab = 0, off_itab = 0, off_fac = 0, off_dxi = 0, off_lm = 0;
+  std::vector<double> lm;  // [B; d_d B] for the local-matrix strategy (P <= 4)
   long long coeff_off = 0, phys_off = 0;
   bool geom_ok = false;
   Tiling tiling[OPK_COUNT];
+  int auto_strategy[7] = {2, 2, 2, 2, 2, 2, 2};  // per public operator, used by SHP_AUTO
+  struct Tuned {
+    bool valid = false;
+    int strategy = 2, E = 0, NT = 0, variant = 0;
+    double ms = 0.0;
+  } tuned[7];
 };
 
 }  // namespace
@@ -67,6 +74,8 @@ struct shp_plan_s {
   int mixed_ntiles[OPK_COUNT] = {};
   bool mixed_dirty[OPK_COUNT] = {};
   bool uniform_P = true;
+  int auto_mixed[7] = {2, 2, 2, 2, 2, 2, 2};
+  Block::Tuned tuned_mixed[7];
 };
 
 namespace {
@@ -74,7 +83,16 @@ namespace {
 bool valid_shape(int s) { return s >= SHP_HEX && s <= SHP_TET; }
 
 int opk_of(int op, int strategy, int* opk) {
-  if (strategy < SHP_AUTO || strategy > SHP_SUMFAC_COLL) return fail(SHP_ERR_INVALID_ARG, "bad strategy %d", strategy);
+  if (strategy < SHP_AUTO || strategy > SHP_LOCALMAT) return fail(SHP_ERR_INVALID_ARG, "bad strategy %d", strategy);
+  if (strategy == SHP_LOCALMAT) {
+    switch (op) {
+      case SHP_OP_MASS: *opk = OPK_MASS_LM; return SHP_OK;
+      case SHP_OP_LAPLACIAN: *opk = OPK_LAP_LM; return SHP_OK;
+      case SHP_OP_HELMHOLTZ: *opk = OPK_HELM_LM; return SHP_OK;
+    }
+    if (op < 0 || op > SHP_OP_HELMHOLTZ) return fail(SHP_ERR_INVALID_ARG, "bad operator %d", op);
+    return fail(SHP_ERR_UNSUPPORTED, "the local-matrix strategy covers mass, Laplacian and Helmholtz");
+  }
   switch (op) {
     case SHP_OP_BWDTRANS: *opk = OPK_BWD; return SHP_OK;
     case SHP_OP_IPRODUCT: *opk = OPK_IPR; return SHP_OK;
@@ -94,8 +112,9 @@ int opk_of(int op, int strategy, int* opk) {
 
 bool in_is_modes(int opk) {
   return opk == OPK_BWD || opk == OPK_MASS || opk == OPK_LAP || opk == OPK_HELM || opk == OPK_HELM_NC ||
-         opk == OPK_LAP_NC;
+         opk == OPK_LAP_NC || opk >= OPK_MASS_LM;
 }
+bool is_localmat(int opk) { return opk >= OPK_MASS_LM; }
 bool out_is_modes(int opk) { return !(opk == OPK_BWD || opk == OPK_DERIV); }
 
 // Default launch shape: as many elements per work-group as fit a 40 KiB LDS
@@ -177,6 +196,10 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     B.NP = num_modes(B.d.shape, B.d.P);
     B.NQ = B.d.Q * B.d.Q * B.d.Q;
     build_tables(B.d.shape, B.d.P, B.tab, B.itab);
+    if (B.d.P <= LOCALMAT_MAX_P) {
+      int q3p, kp;
+      build_localmat(B.d.shape, B.d.P, B.lm, q3p, kp);
+    }
     B.coeff_off = cofs;
     B.phys_off = pofs;
     cofs += B.d.n_elem * B.NP;
@@ -194,6 +217,8 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     off = align_up(off + sizeof(double) * B.tab.size());
     B.off_itab = off;
     off = align_up(off + sizeof(int) * B.itab.size());
+    B.off_lm = off;
+    off = align_up(off + sizeof(double) * B.lm.size());
   }
   for (auto& B : p->blocks) {
     B.off_fac = off;
@@ -253,6 +278,8 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(p->ws + B.off_itab, B.itab.data(), sizeof(int) * B.itab.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !B.lm.empty())
+      e = hipMemcpyAsync(p->ws + B.off_lm, B.lm.data(), sizeof(double) * B.lm.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return dev_fail(e, "hipMemcpyAsync(tables)");
   }
   for (int k = 0; k < OPK_COUNT; ++k) p->mixed_dirty[k] = true;
@@ -407,6 +434,8 @@ static int build_tiles(shp_plan p, int opk, hipStream_t s) {
 
 int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, double* out, double lambda, void* stream) {
   if (int r = check_plan(p)) return r;
+  if (strategy == SHP_AUTO && op >= 0 && op <= SHP_OP_HELMHOLTZ && blk >= -1 && blk < (int)p->blocks.size())
+    strategy = blk >= 0 ? p->blocks[blk].auto_strategy[op] : p->auto_mixed[op];
   int opk;
   if (int r = opk_of(op, strategy, &opk)) return r;
   if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
@@ -415,6 +444,27 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
   const bool needs_geom = !(opk == OPK_BWD);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (is_localmat(opk)) {
+    const int b0 = blk >= 0 ? blk : 0, b1 = blk >= 0 ? blk + 1 : (int)p->blocks.size();
+    for (int b = b0; b < b1; ++b) {
+      const Block& B = p->blocks[b];
+      if (B.d.P > LOCALMAT_MAX_P) return fail(SHP_ERR_UNSUPPORTED, "local-matrix strategy needs P <= %d", LOCALMAT_MAX_P);
+      if (!B.geom_ok) return fail(SHP_ERR_STATE, "block %d: geometry not set", b);
+    }
+    for (int b = b0; b < b1; ++b) {
+      const Block& B = p->blocks[b];
+      LocalMatArgs la;
+      la.bcat = reinterpret_cast<const double*>(p->ws + B.off_lm);
+      la.fac = reinterpret_cast<const double*>(p->ws + B.off_fac);
+      la.in = in + (blk >= 0 ? 0 : B.coeff_off);
+      la.out = out + (blk >= 0 ? 0 : B.coeff_off);
+      la.n_elem = B.d.n_elem;
+      la.lambda = lambda;
+      hipError_t e = launch_localmat(B.d.shape, B.d.P, opk, la, s);
+      if (e != hipSuccess) return dev_fail(e, "local-matrix launch");
+    }
+    return SHP_OK;
+  }
   if (blk >= 0) {
     Block& B = p->blocks[blk];
     if (needs_geom && !B.geom_ok) return fail(SHP_ERR_STATE, "block %d: geometry not set", blk);
@@ -472,6 +522,330 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
   hipError_t e = launch_mixed(p->blocks[0].d.P, opk, reinterpret_cast<const BlockStatic*>(p->ws + p->off_bstat), tiles,
                               p->mixed_ntiles[opk], in, out, p->total_phys, p->total_phys, lambda, NT, lds, E, mt.persist, s);
   if (e != hipSuccess) return dev_fail(e, "mixed launch");
+  return SHP_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Autotuning
+// ---------------------------------------------------------------------------
+
+static long long out_count(shp_plan p, int blk, int op) {
+  long long modes = 0, pts = 0;
+  if (blk >= 0) {
+    const Block& B = p->blocks[blk];
+    modes = B.d.n_elem * B.NP;
+    pts = B.d.n_elem * B.NQ;
+  } else {
+    modes = p->total_coeff;
+    pts = p->total_phys;
+  }
+  if (op == SHP_OP_BWDTRANS) return pts;
+  if (op == SHP_OP_PHYSDERIV) return 3 * pts;
+  return modes;
+}
+
+static void set_tiling_raw(shp_plan p, int blk, int opk, const Tiling& t) {
+  if (blk >= 0)
+    p->blocks[blk].tiling[opk] = t;
+  else {
+    p->mixed[opk] = t;
+    p->mixed_dirty[opk] = true;
+  }
+}
+
+static Tiling get_tiling_raw(shp_plan p, int blk, int opk) {
+  return blk >= 0 ? p->blocks[blk].tiling[opk] : p->mixed[opk];
+}
+
+int shp_tune(shp_plan p, int blk, int op, const double* in, double* out, double* ref, double lambda, int reps,
+             int quick, shp_tune_result* res, shp_tune_record* records, int max_records, int* n_records,
+             void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
+  if (op < 0 || op > SHP_OP_HELMHOLTZ) return fail(SHP_ERR_INVALID_ARG, "bad operator %d", op);
+  if (!in || !out || !ref || !res) return fail(SHP_ERR_INVALID_ARG, "null argument");
+  if (reps < 1 || reps > 1000) return fail(SHP_ERR_INVALID_ARG, "reps=%d outside [1,1000]", reps);
+  if (max_records > 0 && !records) return fail(SHP_ERR_INVALID_ARG, "null records");
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool helm = (op == SHP_OP_HELMHOLTZ || op == SHP_OP_LAPLACIAN);
+  bool lm_ok = (helm || op == SHP_OP_MASS);
+  if (blk >= 0)
+    lm_ok = lm_ok && p->blocks[blk].d.P <= LOCALMAT_MAX_P;
+  else
+    for (const auto& B : p->blocks) lm_ok = lm_ok && B.d.P <= LOCALMAT_MAX_P;
+  int strategies[3] = {SHP_SUMFAC_COLL, SHP_SUMFAC, SHP_LOCALMAT};
+  int nstrat = helm ? 2 : 1;
+  if (lm_ok) strategies[nstrat++] = SHP_LOCALMAT;
+  int opks[3];
+  for (int i = 0; i < nstrat; ++i)
+    if (int r = opk_of(op, strategies[i], &opks[i])) return r;
+  // keep the caller's launch shapes to restore the loser's afterwards
+  Tiling saved[3];
+  for (int i = 0; i < nstrat; ++i) saved[i] = get_tiling_raw(p, blk, opks[i]);
+  const long long nout = out_count(p, blk, op);
+  unsigned long long* dd = reinterpret_cast<unsigned long long*>(p->ws + p->off_status + 64);
+  // reference: the default launch of the collocated strategy
+  set_tiling_raw(p, blk, opks[0], Tiling{0, 0, 2});
+  if (int r = shp_apply(p, blk, op, SHP_SUMFAC_COLL, in, ref, lambda, stream)) return r;
+  hipEvent_t ev[2 * 64];
+  const int nev = std::min(reps, 64);
+  for (int i = 0; i < 2 * nev; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) return dev_fail(hipGetLastError(), "hipEventCreate");
+  // smallest P of the blocks involved, for the launch-shape limits
+  int P = MAX_P;
+  if (blk >= 0)
+    P = p->blocks[blk].d.P;
+  else
+    for (const auto& B : p->blocks) P = std::min(P, B.d.P);
+  const int Q = P + 2;
+  std::vector<int> Es, NTs, Vs;
+  if (quick) {
+    Es = {1, 2, 4, 8};
+    NTs = {128, 256};
+  } else {
+    for (int E = 1; E <= 16; ++E) Es.push_back(E);
+    NTs = {64, 128, 192, 256, 320, 384, 512};
+  }
+  int ncand = 0, nrej = 0, nrec = 0;
+  Block::Tuned best;
+  best.ms = 1e300;
+  int rc = SHP_OK;
+  for (int si = 0; si < nstrat && rc == SHP_OK; ++si) {
+    const int st = strategies[si], opk = opks[si];
+    if (helm && st == SHP_SUMFAC_COLL)
+      Vs = quick ? std::vector<int>{0, 2, 3} : std::vector<int>{0, 1, 2, 3, 4};
+    else
+      Vs = {0};
+    const bool lm = (st == SHP_LOCALMAT);  // one launch shape: 16 elements, 4 waves
+    for (int E : (lm ? std::vector<int>{16} : Es))
+      for (int NT : (lm ? std::vector<int>{256} : NTs))
+        for (int V : Vs) {
+          if ((V == 1 || V == 2) && (long long)E * Q * Q * Q > 8LL * NT) continue;
+          if (V == 4 && E * Q * Q > NT) continue;
+          if (!lm && NT > 64 && NT > 2 * E * Q * Q * Q) continue;  // most threads would idle
+          bool fits = true;
+          if (blk >= 0)
+            fits = op_lds_bytes(p->blocks[blk].d.shape, p->blocks[blk].d.P, opk, E, V) <= 64 * 1024 * 2;
+          else
+            for (const auto& B : p->blocks) fits = fits && op_lds_bytes(B.d.shape, B.d.P, opk, E, V) <= 64 * 1024 * 2;
+          if (lm) fits = true;
+          if (!fits) continue;
+          set_tiling_raw(p, blk, opk, Tiling{E, NT, V});
+          if ((rc = shp_apply(p, blk, op, st, in, out, lambda, stream))) break;
+          hipError_t e = hipMemsetAsync(dd, 0, 2 * sizeof(unsigned long long), s);
+          if (e == hipSuccess) e = launch_maxdiff(out, ref, nout, dd, s);
+          unsigned long long h[2] = {0, 0};
+          if (e == hipSuccess) e = hipMemcpyAsync(h, dd, sizeof h, hipMemcpyDeviceToHost, s);
+          if (e == hipSuccess) e = hipStreamSynchronize(s);
+          if (e != hipSuccess) {
+            rc = dev_fail(e, "tuning parity check");
+            break;
+          }
+          double dmax, bmax;
+          std::memcpy(&dmax, &h[0], sizeof dmax);
+          std::memcpy(&bmax, &h[1], sizeof bmax);
+          const bool pass = std::isfinite(dmax) && dmax <= 1e-12 * std::max(bmax, 1e-300);
+          ++ncand;
+          double med = -1.0;
+          if (pass) {
+            for (int r = 0; r < nev && rc == SHP_OK; ++r) {
+              hipEventRecord(ev[2 * r], s);
+              rc = shp_apply(p, blk, op, st, in, out, lambda, stream);
+              hipEventRecord(ev[2 * r + 1], s);
+            }
+            if (rc) break;
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+              rc = dev_fail(e, "tuning timing");
+              break;
+            }
+            std::vector<float> t(nev);
+            for (int r = 0; r < nev; ++r) hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]);
+            std::sort(t.begin(), t.end());
+            med = t[nev / 2];
+            if (med < best.ms) {
+              best.valid = true;
+              best.ms = med;
+              best.strategy = st;
+              best.E = E;
+              best.NT = NT;
+              best.variant = V;
+            }
+          } else {
+            ++nrej;
+          }
+          if (records && nrec < max_records) {
+            shp_tune_record& R = records[nrec++];
+            R.strategy = st;
+            R.elems_per_wg = E;
+            R.threads = NT;
+            R.variant = V;
+            R.ms = med;
+            R.passed = pass ? 1 : 0;
+          }
+        }
+  }
+  for (int i = 0; i < 2 * nev; ++i) hipEventDestroy(ev[i]);
+  for (int i = 0; i < nstrat; ++i) set_tiling_raw(p, blk, opks[i], saved[i]);
+  if (rc) return rc;
+  if (n_records) *n_records = nrec;
+  if (!best.valid) return fail(SHP_ERR_NOT_CONVERGED, "no candidate passed the parity gate");
+  int bopk;
+  opk_of(op, best.strategy, &bopk);
+  set_tiling_raw(p, blk, bopk, Tiling{best.E, best.NT, best.variant});
+  if (blk >= 0) {
+    p->blocks[blk].auto_strategy[op] = best.strategy;
+    p->blocks[blk].tuned[op] = best;
+  } else {
+    p->auto_mixed[op] = best.strategy;
+    p->tuned_mixed[op] = best;
+  }
+  res->strategy = best.strategy;
+  res->elems_per_wg = best.E;
+  res->threads = best.NT;
+  res->variant = best.variant;
+  res->ms = best.ms;
+  res->n_candidates = ncand;
+  res->n_rejected = nrej;
+  return SHP_OK;
+}
+
+int shp_set_auto_strategy(shp_plan p, int blk, int op, int strategy) {
+  if (int r = check_plan(p)) return r;
+  if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
+  if (op < 0 || op > SHP_OP_HELMHOLTZ) return fail(SHP_ERR_INVALID_ARG, "bad operator %d", op);
+  if (strategy < SHP_SUMFAC || strategy > SHP_LOCALMAT) return fail(SHP_ERR_INVALID_ARG, "bad strategy");
+  if (blk >= 0)
+    p->blocks[blk].auto_strategy[op] = strategy;
+  else
+    p->auto_mixed[op] = strategy;
+  return SHP_OK;
+}
+
+// --- persisted tuning cache: one JSON object per line -----------------------
+
+static std::string device_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string n = prop.gcnArchName;
+  for (auto& c : n)
+    if (c == '"' || c == '\\') c = '_';
+  return n;
+}
+
+static int nbucket(long long n) {
+  int b = 0;
+  while (n > 1) {
+    n >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+static std::string mixed_signature(shp_plan p) {
+  std::string sig;
+  for (const auto& B : p->blocks) {
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%s%d:%d:%d:%d", sig.empty() ? "" : ",", B.d.shape, B.d.P, nbucket(B.d.n_elem),
+                  B.d.geom);
+    sig += buf;
+  }
+  return sig;
+}
+
+static bool json_int(const std::string& l, const char* key, long long* v) {
+  const std::string k = std::string("\"") + key + "\":";
+  const size_t i = l.find(k);
+  if (i == std::string::npos) return false;
+  *v = std::strtoll(l.c_str() + i + k.size(), nullptr, 10);
+  return true;
+}
+
+static bool json_str(const std::string& l, const char* key, std::string* v) {
+  const std::string k = std::string("\"") + key + "\":\"";
+  const size_t i = l.find(k);
+  if (i == std::string::npos) return false;
+  const size_t j = l.find('"', i + k.size());
+  if (j == std::string::npos) return false;
+  *v = l.substr(i + k.size(), j - i - k.size());
+  return true;
+}
+
+int shp_tune_cache_save(shp_plan p, const char* path) {
+  if (int r = check_plan(p)) return r;
+  if (!path) return fail(SHP_ERR_INVALID_ARG, "null path");
+  FILE* f = std::fopen(path, "a");
+  if (!f) return fail(SHP_ERR_INVALID_ARG, "cannot open %s", path);
+  const std::string dev = device_name();
+  for (const auto& B : p->blocks)
+    for (int op = 0; op < 7; ++op) {
+      const auto& t = B.tuned[op];
+      if (!t.valid) continue;
+      std::fprintf(f,
+                   "{\"kind\":\"block\",\"device\":\"%s\",\"prec\":\"fp64\",\"op\":%d,\"shape\":%d,\"P\":%d,\"Q\":%d,"
+                   "\"nbucket\":%d,\"geom\":%d,\"strategy\":%d,\"E\":%d,\"NT\":%d,\"variant\":%d,\"us\":%lld}\n",
+                   dev.c_str(), op, B.d.shape, B.d.P, B.d.Q, nbucket(B.d.n_elem), B.d.geom, t.strategy, t.E, t.NT,
+                   t.variant, (long long)(t.ms * 1e3));
+    }
+  for (int op = 0; op < 7; ++op) {
+    const auto& t = p->tuned_mixed[op];
+    if (!t.valid) continue;
+    std::fprintf(f,
+                 "{\"kind\":\"mixed\",\"device\":\"%s\",\"prec\":\"fp64\",\"op\":%d,\"blocks\":\"%s\",\"strategy\":%d,"
+                 "\"E\":%d,\"NT\":%d,\"variant\":%d,\"us\":%lld}\n",
+                 dev.c_str(), op, mixed_signature(p).c_str(), t.strategy, t.E, t.NT, t.variant, (long long)(t.ms * 1e3));
+  }
+  std::fclose(f);
+  return SHP_OK;
+}
+
+int shp_tune_cache_load(shp_plan p, const char* path, int* n_applied) {
+  if (int r = check_plan(p)) return r;
+  if (!path) return fail(SHP_ERR_INVALID_ARG, "null path");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(SHP_ERR_INVALID_ARG, "cannot open %s", path);
+  const std::string dev = device_name();
+  int applied = 0;
+  char line[1024];
+  while (std::fgets(line, sizeof line, f)) {
+    const std::string l(line);
+    std::string kind, d, prec;
+    long long op, st, E, NT, V;
+    if (!json_str(l, "kind", &kind) || !json_str(l, "device", &d) || !json_str(l, "prec", &prec)) continue;
+    if (d != dev || prec != "fp64") continue;
+    if (!json_int(l, "op", &op) || !json_int(l, "strategy", &st) || !json_int(l, "E", &E) || !json_int(l, "NT", &NT) ||
+        !json_int(l, "variant", &V))
+      continue;
+    if (op < 0 || op > 6 || st < SHP_SUMFAC || st > SHP_LOCALMAT || E < 1 || E > 64 || NT < 64 || NT > 512 ||
+        NT % 64 || V < 0 || V > 4)
+      continue;  // a corrupt entry is skipped
+    int opk;
+    if (opk_of((int)op, (int)st, &opk)) continue;
+    if (kind == "block") {
+      long long sh, P, Q, nb, geom;
+      if (!json_int(l, "shape", &sh) || !json_int(l, "P", &P) || !json_int(l, "Q", &Q) || !json_int(l, "nbucket", &nb) ||
+          !json_int(l, "geom", &geom))
+        continue;
+      for (auto& B : p->blocks) {
+        if (B.d.shape != sh || B.d.P != P || B.d.Q != Q || nbucket(B.d.n_elem) != nb || B.d.geom != geom) continue;
+        if (op_lds_bytes(B.d.shape, B.d.P, opk, (int)E, (int)V) > LDS_LIMIT) continue;
+        B.tiling[opk] = Tiling{(int)E, (int)NT, (int)V};
+        B.auto_strategy[op] = (int)st;
+        ++applied;
+      }
+    } else if (kind == "mixed") {
+      std::string sig;
+      if (!json_str(l, "blocks", &sig) || sig != mixed_signature(p)) continue;
+      p->mixed[opk] = Tiling{(int)E, (int)NT, (int)V};
+      p->mixed_dirty[opk] = true;
+      p->auto_mixed[op] = (int)st;
+      ++applied;
+    }
+  }
+  std::fclose(f);
+  if (n_applied) *n_applied = applied;
   return SHP_OK;
 }
 

@@ -13,6 +13,7 @@ namespace shp {
 struct OpArgs;
 struct Tile;
 struct GeomArgs;
+struct LocalMatArgs;
 
 // Static per-block data of a mixed launch (device copy in the workspace).
 struct BlockStatic {
@@ -33,11 +34,14 @@ void gauss_lobatto(int Q, double* x, double* w);
 void rule_1d(int Q, int alpha, double* x, double* w);
 void build_tables(int sh, int P, std::vector<double>& tab, std::vector<int>& itab);
 void reference_points(int sh, int Q, double* xi, double* w);
+void build_localmat(int sh, int P, std::vector<double>& bcat, int& Q3p, int& Kp);
+constexpr int LOCALMAT_MAX_P = 4;  // dense reference matrices only at low order
 
 // launchers (shp_k_*.hip); return hipSuccess or the launch error
 size_t op_lds_bytes(int sh, int P, int opk, int E, int variant);
 hipError_t launch_block(int sh, int P, int opk, const OpArgs& a, int threads, int persist, hipStream_t s);
 hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s);
+hipError_t launch_localmat(int sh, int P, int opk, const LocalMatArgs& a, hipStream_t s);
 hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
                         double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds, int E,
                         int persist, hipStream_t s);
@@ -46,6 +50,8 @@ hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* t
 int num_cus();
 long long persistent_grid(const void* kernel, int threads, size_t lds);
 int points_per_thread(long long points, int threads);
+// max |a-b| and max |b| into out[0], out[1] (bit patterns of non-negative doubles)
+hipError_t launch_maxdiff(const double* a, const double* b, long long n, unsigned long long* out, hipStream_t s);
 
 constexpr int MAX_P = 10;
 constexpr size_t LDS_LIMIT = 160 * 1024;

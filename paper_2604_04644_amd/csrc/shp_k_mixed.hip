@@ -14,6 +14,20 @@ hipError_t launch_geometry_hex(int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_geometry_prism(int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_geometry_pyr(int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_geometry_tet(int P, const GeomArgs& g, hipStream_t s);
+hipError_t launch_localmat_hex(int P, int opk, const LocalMatArgs& a, hipStream_t s);
+hipError_t launch_localmat_prism(int P, int opk, const LocalMatArgs& a, hipStream_t s);
+hipError_t launch_localmat_pyr(int P, int opk, const LocalMatArgs& a, hipStream_t s);
+hipError_t launch_localmat_tet(int P, int opk, const LocalMatArgs& a, hipStream_t s);
+
+hipError_t launch_localmat(int sh, int P, int opk, const LocalMatArgs& a, hipStream_t s) {
+  switch (sh) {
+    case HEX: return launch_localmat_hex(P, opk, a, s);
+    case PRISM: return launch_localmat_prism(P, opk, a, s);
+    case PYR: return launch_localmat_pyr(P, opk, a, s);
+    default: return launch_localmat_tet(P, opk, a, s);
+  }
+}
+
 size_t lds_bytes_hex(int P, int E, int nbuf);
 size_t lds_bytes_prism(int P, int E, int nbuf);
 size_t lds_bytes_pyr(int P, int E, int nbuf);
@@ -168,6 +182,40 @@ hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* t
 #undef C_
   }
   return hipErrorInvalidValue;
+}
+
+}  // namespace shp
+
+namespace shp {
+
+// max |a - b| and max |b| over n values, as the bit patterns of non-negative
+// doubles (which order like unsigned integers; a NaN difference orders above
+// every finite value).
+__global__ void __launch_bounds__(256) k_maxdiff(const double* __restrict__ a, const double* __restrict__ b,
+                                                 long long n, unsigned long long* out) {
+  double dm = 0.0, bm = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double d = fabs(a[i] - b[i]);
+    dm = (d > dm || d != d) ? d : dm;
+    bm = fmax(bm, fabs(b[i]));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double od = __shfl_down(dm, off);
+    const double ob = __shfl_down(bm, off);
+    dm = (od > dm || od != od) ? od : dm;
+    bm = fmax(bm, ob);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out + 0, (unsigned long long)__double_as_longlong(dm));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(bm));
+  }
+}
+
+hipError_t launch_maxdiff(const double* a, const double* b, long long n, unsigned long long* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long nb = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_maxdiff, dim3((unsigned)nb), dim3(256), 0, s, a, b, n, out);
+  return hipGetLastError();
 }
 
 }  // namespace shp

@@ -189,6 +189,64 @@ void build_tables(int sh, int P, std::vector<double>& tab, std::vector<int>& ita
     }
 }
 
+// Dense reference matrices [B; d_1 B; d_2 B; d_3 B] at the quadrature points
+// for the local-matrix strategy: row d*Q3p + q, column m; rows padded to a
+// multiple of 16, columns to a multiple of 16 (zeros).  Each mode is a product
+// of 1D functions of eta (the collapsed-vertex modes drop the factors of the
+// collapsed coordinates), differentiated factor by factor.
+void build_localmat(int sh, int P, std::vector<double>& bcat, int& Q3p, int& Kp) {
+  const int Q = P + 2, Q3 = Q * Q * Q, NP = num_modes(sh, P);
+  Q3p = (Q3 + 15) / 16 * 16;
+  Kp = (NP + 15) / 16 * 16;
+  bcat.assign((size_t)4 * Q3p * Kp, 0.0);
+  std::vector<double> z(3 * Q), w(3 * Q);
+  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), z.data() + d * Q, w.data() + d * Q);
+  // 1D factor kinds: 0 = constant 1, 1 = A_p, 2 = C_{k,r}, 3 = v1
+  struct F { int kind, a, b; };
+  auto fval = [](const F& f, double x, bool der) {
+    switch (f.kind) {
+      case 0: return der ? 0.0 : 1.0;
+      case 1: return der ? fdA(f.a, x) : fA(f.a, x);
+      case 2: return der ? fdC(f.a, f.b, x) : fC(f.a, f.b, x);
+      default: return der ? 0.5 : 0.5 * (1.0 + x);
+    }
+  };
+  int m = 0;
+  for (int p = 0; p <= P; ++p)
+    for (int q = 0; q < nq_of(sh, P, p); ++q)
+      for (int r = 0; r < col_len(sh, P, p, q); ++r, ++m) {
+        F f[3];
+        if (sh == HEX) {
+          f[0] = {1, p, 0}; f[1] = {1, q, 0}; f[2] = {1, r, 0};
+        } else if (sh == PRISM) {
+          if (p == 0 && r == 1) { f[0] = {0, 0, 0}; f[1] = {1, q, 0}; f[2] = {3, 0, 0}; }
+          else { f[0] = {1, p, 0}; f[1] = {1, q, 0}; f[2] = {2, p, r}; }
+        } else if (sh == PYR) {
+          if (p == 0 && q == 0 && r == 1) { f[0] = {0, 0, 0}; f[1] = {0, 0, 0}; f[2] = {3, 0, 0}; }
+          else { f[0] = {1, p, 0}; f[1] = {1, q, 0}; f[2] = {2, imax(p, q), r}; }
+        } else {
+          if (p == 0 && q == 0 && r == 1) { f[0] = {0, 0, 0}; f[1] = {0, 0, 0}; f[2] = {3, 0, 0}; }
+          else if (p == 0 && q == 1) { f[0] = {0, 0, 0}; f[1] = {3, 0, 0}; f[2] = {2, 1, r}; }
+          else { f[0] = {1, p, 0}; f[1] = {2, p, q}; f[2] = {2, p + q, r}; }
+        }
+        for (int i = 0; i < Q; ++i)
+          for (int j = 0; j < Q; ++j)
+            for (int k = 0; k < Q; ++k) {
+              const int pt = (i * Q + j) * Q + k;
+              const double x[3] = {z[i], z[Q + j], z[2 * Q + k]};
+              double v[3], dv[3];
+              for (int d = 0; d < 3; ++d) {
+                v[d] = fval(f[d], x[d], false);
+                dv[d] = fval(f[d], x[d], true);
+              }
+              bcat[(size_t)(0 * Q3p + pt) * Kp + m] = v[0] * v[1] * v[2];
+              bcat[(size_t)(1 * Q3p + pt) * Kp + m] = dv[0] * v[1] * v[2];
+              bcat[(size_t)(2 * Q3p + pt) * Kp + m] = v[0] * dv[1] * v[2];
+              bcat[(size_t)(3 * Q3p + pt) * Kp + m] = v[0] * v[1] * dv[2];
+            }
+      }
+}
+
 void reference_points(int sh, int Q, double* xi, double* wout) {
   std::vector<double> z(3 * Q), w(3 * Q);
   for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), z.data() + d * Q, w.data() + d * Q);

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libshp.so")
 SHAPES = {"hex": 0, "prism": 1, "pyr": 2, "tet": 3}
 GEOM = {"affine": 0, "curved": 1}
 OPS = {"bwd": 0, "iprod": 1, "physderiv": 2, "iprod_deriv": 3, "mass": 4, "laplacian": 5, "helmholtz": 6}
-STRATEGY = {"auto": 0, "sumfac": 1, "sumfac_coll": 2}
+STRATEGY = {"auto": 0, "sumfac": 1, "sumfac_coll": 2, "localmat": 3}
 ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "BAD_GEOMETRY", -4: "WORKSPACE",
           -5: "STATE", -6: "DEVICE", -7: "NOT_CONVERGED"}
 
@@ -38,9 +38,29 @@ _SIGS = {
     "shp_get_tiling": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
     "shp_plan_destroy": [ctypes.c_void_p],
+    "shp_tune": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                 ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                 ctypes.POINTER(ctypes.c_int), ctypes.c_void_p],
+    "shp_set_auto_strategy": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+    "shp_tune_cache_save": [ctypes.c_void_p, ctypes.c_char_p],
+    "shp_tune_cache_load": [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)],
 }
 
 _lib = None
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("strategy", ctypes.c_int), ("elems_per_wg", ctypes.c_int), ("threads", ctypes.c_int),
+                ("variant", ctypes.c_int), ("ms", ctypes.c_double), ("n_candidates", ctypes.c_int),
+                ("n_rejected", ctypes.c_int)]
+
+
+class TuneRecord(ctypes.Structure):
+    _fields_ = [("strategy", ctypes.c_int), ("elems_per_wg", ctypes.c_int), ("threads", ctypes.c_int),
+                ("variant", ctypes.c_int), ("ms", ctypes.c_double), ("passed", ctypes.c_int)]
+
+
+STRATEGY_NAME = {v: k for k, v in {"auto": 0, "sumfac": 1, "sumfac_coll": 2, "localmat": 3}.items()}
 
 
 class ShpError(RuntimeError):
@@ -196,3 +216,35 @@ class Plan:
         _check(lib().shp_get_tiling(self._h, blk, OPS[op], STRATEGY[strategy], ctypes.byref(E), ctypes.byref(NT),
                                     ctypes.byref(pe)))
         return E.value, NT.value, pe.value
+
+    # ---------------------------------------------------------------
+    def tune(self, blk: int, op: str, x, lam: float = 1.0, reps: int = 10, quick: bool = False,
+             max_records: int = 4096):
+        """Exhaustive tuning of (blk, op) on input x; returns (result dict, list of
+        candidate records).  SHP_AUTO then uses the choice."""
+        t = self._torch
+        out = t.empty(self._out_shape(blk, op), dtype=t.float64, device=x.device)
+        ref = t.empty_like(out)
+        res = TuneResult()
+        recs = (TuneRecord * max_records)()
+        nrec = ctypes.c_int()
+        _check(lib().shp_tune(self._h, blk, OPS[op], ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                              ctypes.c_void_p(ref.data_ptr()), float(lam), int(reps), int(quick), ctypes.byref(res),
+                              ctypes.cast(recs, ctypes.c_void_p), max_records, ctypes.byref(nrec), _stream(t)))
+        result = {"strategy": STRATEGY_NAME[res.strategy], "elems_per_wg": res.elems_per_wg,
+                  "threads": res.threads, "variant": res.variant, "ms": res.ms,
+                  "n_candidates": res.n_candidates, "n_rejected": res.n_rejected}
+        records = [{"strategy": STRATEGY_NAME[r.strategy], "elems_per_wg": r.elems_per_wg, "threads": r.threads,
+                    "variant": r.variant, "ms": r.ms, "passed": bool(r.passed)} for r in recs[:nrec.value]]
+        return result, records
+
+    def set_auto_strategy(self, blk: int, op: str, strategy: str):
+        _check(lib().shp_set_auto_strategy(self._h, blk, OPS[op], STRATEGY[strategy]))
+
+    def save_tuning(self, path: str):
+        _check(lib().shp_tune_cache_save(self._h, path.encode()))
+
+    def load_tuning(self, path: str) -> int:
+        n = ctypes.c_int()
+        _check(lib().shp_tune_cache_load(self._h, path.encode(), ctypes.byref(n)))
+        return n.value

@@ -200,6 +200,34 @@ def jacobian(maps: ElementMaps, xi: np.ndarray, curved: bool, amp: float = AMP,
     return out
 
 
+def jacobian_torch(maps: ElementMaps, xi: np.ndarray, curved: bool, device, amp: float = AMP, chunk: int = 65536):
+    """jacobian() evaluated with torch on a device (same formula), for large
+    batches: returns a float64 tensor [n_elem][9][n_pts]."""
+    import torch
+    xi_t = torch.as_tensor(np.asarray(xi, dtype=np.float64), device=device)
+    ne, npts = len(maps), xi_t.shape[0]
+    out = torch.empty((ne, 9, npts), dtype=torch.float64, device=device)
+    t = 0.5 * (1.0 + xi_t)                                              # [npts,3]
+    for e0 in range(0, ne, chunk):
+        e1 = min(ne, e0 + chunk)
+        A = torch.as_tensor(maps.A[e0:e1], device=device)
+        x0 = torch.as_tensor(maps.x0[e0:e1], device=device)
+        Ah = 0.5 * A
+        if not curved:
+            out[e0:e1] = Ah.reshape(e1 - e0, 9, 1).expand(e1 - e0, 9, npts)
+            continue
+        X = x0[:, None, :] + torch.einsum("eij,pj->epi", A, t)          # [ne,npts,3]
+        sn = torch.sin(2 * np.pi * X)
+        cs = torch.cos(2 * np.pi * X)
+        ds = torch.stack([2 * np.pi * cs[..., 0] * sn[..., 1] * sn[..., 2],
+                          2 * np.pi * sn[..., 0] * cs[..., 1] * sn[..., 2],
+                          2 * np.pi * sn[..., 0] * sn[..., 1] * cs[..., 2]], dim=-1)
+        g = torch.einsum("epk,ekj->epj", ds, Ah)
+        J = Ah[:, None, :, :] + amp * g[:, :, None, :]
+        out[e0:e1] = J.reshape(e1 - e0, npts, 9).permute(0, 2, 1)
+    return out
+
+
 def affine_jacobian(maps: ElementMaps) -> np.ndarray:
     """Constant d x_i / d xi_j of straight-sided elements, layout [n_elem][9]."""
     return np.ascontiguousarray((0.5 * maps.A).reshape(len(maps), 9))

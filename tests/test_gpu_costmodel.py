@@ -1,0 +1,88 @@
+"""GPU tests of the MLP cost model: forward values and gradients of the
+hand-written kernels against the FP64 oracle, training on the committed sweep
+timings, and regret on held-out (P, batch size) pairs against exhaustive
+tuning, with the gain over the fixed rule and over tuning time."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+from paper_2604_04644_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cm():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2604_04644_amd import costmodel
+    return costmodel
+
+
+def test_kernels_vs_oracle(cm):
+    print("[mlp] forward and gradient vs the FP64 oracle", flush=True)
+    model = cm.CostModel(seed=3)
+    rng = np.random.default_rng(1)
+    X = rng.normal(0, 1, (173, cm.NIN)).astype(np.float32)
+    t = rng.normal(0, 1, 173).astype(np.float32)
+    p = model.params.cpu().numpy().astype(np.float64)
+    y = model.forward_raw(X)
+    yo, _ = M.forward(p, X.astype(np.float64))
+    assert np.abs(y - yo).max() <= 1e-5 * max(1.0, np.abs(yo).max())
+    loss, g = model.loss_grad_raw(X, t)
+    lo, go = M.loss_grad(p, X.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - lo) <= 1e-5 * max(1.0, lo)
+    assert np.abs(g - go).max() <= 1e-4 * np.abs(go).max()
+
+
+def test_training_and_regret(cm):
+    print("[mlp] train on the sweep timings, evaluate held-out regret", flush=True)
+    rows = cm.load_rows()
+    train, test = cm.split_heldout(rows)
+    assert len(train) > 200 and len(test) > 200
+    model = cm.CostModel(seed=0)
+    hist = model.fit(train, epochs=3000, lr=3e-3)
+    assert hist[-1][1] < 0.1 * hist[0][1]
+    r = cm.regret(model, test)
+    mean_reg = float(np.mean([x["regret"] for x in r]))
+    max_reg = float(np.max([x["regret"] for x in r]))
+    fixed = float(np.mean([x["fixed_regret"] for x in r]))
+    print(f"    held-out configs {len(r)}: MLP regret mean {mean_reg:.4f} max {max_reg:.4f}; "
+          f"always-collocated regret mean {fixed:.4f}", flush=True)
+    assert mean_reg <= max(fixed, 0.01) + 0.02
+    assert max_reg <= 0.5
+
+
+def test_gain_over_tuning_time(cm):
+    """The model's choice costs one forward pass; exhaustive tuning of the same
+    block costs tens of launches per candidate."""
+    from paper_2604_04644_amd import shp
+    print("[mlp] gain over tuning time", flush=True)
+    rows = cm.load_rows()
+    model = cm.CostModel(seed=0)
+    model.fit(rows, epochs=1500, lr=3e-3)
+    shape, P, ne = "tet", 4, 20000
+    maps = W.shape_batch(shape, ne)
+    xi, _ = shp.quadrature(shape, P + 2)
+    plan = shp.Plan([(shape, P, ne, "curved")])
+    plan.set_geometry(0, W.jacobian_torch(maps, xi, True, "cuda"))
+    x = torch.from_numpy(W.coeffs(ne, plan.n_modes[0], 2)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, recs = plan.tune(0, "helmholtz", x, reps=5, quick=True)
+    t_tune = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pick = model.choose(shape, P, ne)
+    t_pick = time.perf_counter() - t0
+    best_of = {}
+    for r in recs:
+        if r["passed"]:
+            best_of[r["strategy"]] = min(best_of.get(r["strategy"], 1e9), r["ms"])
+    reg = best_of[pick] / min(best_of.values()) - 1.0
+    print(f"    tune {t_tune*1e3:.1f} ms ({len(recs)} candidates) vs model {t_pick*1e3:.2f} ms; "
+          f"pick {pick}, regret {reg:.4f}", flush=True)
+    assert t_pick < t_tune / 5
+    assert reg <= 0.25

@@ -107,6 +107,48 @@ def test_noncollocated_vs_oracle(shp, shape, P):
         assert rel(y, yc) <= TOL
 
 
+@pytest.mark.parametrize("shape,P", [(s, P) for s in O.SHAPES for P in (1, 2, 3, 4)])
+def test_localmat_vs_oracle(shp, shape, P):
+    """The local-matrix strategy on FP64 MFMA (mass, Laplacian, Helmholtz) on a
+    ragged batch (not a multiple of the 16-element tile)."""
+    ne = 37
+    say(f"[parity] local matrix shape={shape} P={P}")
+    maps = W.shape_batch(shape, ne)
+    plan = shp.Plan([(shape, P, ne, "curved")])
+    plan.set_geometry(0, gpu_geometry(shp, maps, shape, P, True))
+    jo = oracle_geometry(maps, shape, P, True)
+    for k, op in enumerate(("mass", "laplacian", "helmholtz")):
+        x = W.coeffs(ne, plan.n_modes[0], 500 + k)
+        ref = O.apply_op(op, shape, P, P + 2, jo, x, lam=1.7)
+        y = plan.apply(0, op, torch.from_numpy(x).cuda(), lam=1.7, strategy="localmat").cpu().numpy()
+        e = rel(y, ref)
+        say(f"    {op:12s} rel={e:.2e}")
+        assert e <= TOL, (shape, P, op, e)
+
+
+def test_localmat_whole_mesh_and_limits(shp):
+    say("[parity] local matrix whole mesh and limits")
+    mesh, plan = _mixed_plan(shp, 4, 2)
+    nc, _ = plan.totals()
+    x = W.coeffs(1, nc, 41)[0]
+    y = plan.apply(-1, "helmholtz", torch.from_numpy(x).cuda(), strategy="localmat").cpu().numpy()
+    for b, s in enumerate(O.SHAPES):
+        co, _ = plan.offsets(b)
+        ne, NP = len(mesh[s]), plan.n_modes[b]
+        ref = O.apply_op("helmholtz", s, 2, 4, oracle_geometry(mesh[s], s, 2, True), x[co:co + ne * NP].reshape(ne, NP))
+        assert rel(y[co:co + ne * NP].reshape(ne, NP), ref) <= TOL
+    with pytest.raises(shp.ShpError) as ei:      # BwdTrans has no local-matrix form here
+        plan.apply(-1, "bwd", torch.from_numpy(x).cuda(), strategy="localmat")
+    assert ei.value.code == -2
+    maps = W.shape_batch("hex", 3)
+    p5 = shp.Plan([("hex", 5, 3, "curved")])
+    p5.set_geometry(0, gpu_geometry(shp, maps, "hex", 5, True))
+    with pytest.raises(shp.ShpError) as ei:      # dense reference matrices only up to P = 4
+        p5.apply(0, "helmholtz", torch.zeros(3, p5.n_modes[0], dtype=torch.float64, device="cuda"),
+                 strategy="localmat")
+    assert ei.value.code == -2
+
+
 def test_noncollocated_whole_mesh(shp):
     say("[parity] non-collocated whole mesh")
     mesh, plan = _mixed_plan(shp, 4, 3)
