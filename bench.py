@@ -99,6 +99,68 @@ def time_launches(torch, fn, steps: int, warmup: int):
     return wall, float(np.mean(ev)), float(np.median(ev))
 
 
+def mixed_precision_leg(torch, shp, W, ncell: int = 32, P: int = 6, lam: float = 1.0):
+    """Mixed precision on the mixed mesh at P = 6: the Helmholtz action with FP32
+    contractions against FP64, and the Helmholtz solve with a manufactured
+    right-hand side (u = sin(pi x) sin(pi y) sin(pi z), b = IProduct((lambda +
+    3 pi^2) u)) by FP64 iterative refinement around an FP32 Jacobi-PCG against
+    a plain FP64 Jacobi-PCG, to the same FP64 relative residual."""
+    log(f"mixed precision: mesh ncell={ncell} P={P}")
+    mesh = W.quadrant_mesh(ncell)
+    dev = torch.device("cuda")
+    plan = shp.Plan([(s, P, len(mesh[s]), "curved") for s in SHAPES])
+    for b, s in enumerate(SHAPES):
+        plan.set_geometry(b, W.jacobian_torch(mesh[s], shp.quadrature(s, P + 2)[0], True, dev))
+    nc, _ = plan.totals()
+    x64 = torch.from_numpy(np.concatenate([W.coeffs(len(mesh[s]), plan.n_modes[b], W.SEED_MIXED[s]).ravel()
+                                           for b, s in enumerate(SHAPES)])).cuda()
+    x32 = x64.float()
+    y64, y32 = torch.empty_like(x64), torch.empty_like(x32)
+    _, t64, _ = time_launches(torch, lambda: plan.apply(-1, "helmholtz", x64, out=y64, lam=lam), 20, 3)
+    _, t32, _ = time_launches(torch, lambda: plan.apply_prec("helmholtz", x32, out=y32, lam=lam, prec="fp32"), 20, 3)
+    dev32 = float((y32.double() - y64).abs().max() / y64.abs().max())
+    action = {"fp64_ms": round(t64, 5), "fp32_ms": round(t32, 5), "fp64_GDOF/s": round(nc / t64 / 1e6, 3),
+              "fp32_GDOF/s": round(nc / t32 / 1e6, 3), "speedup": round(t64 / t32, 3),
+              "fp32_vs_fp64_maxrel": dev32}
+    log(f"  action: {action}")
+    del x32, y32, y64
+    f = torch.cat([W.manufactured_u_torch(mesh[s], shp.quadrature(s, P + 2)[0], dev).reshape(-1)
+                   for s in SHAPES]) * (lam + 3 * np.pi ** 2)
+    b = plan.apply(-1, "iprod", f)
+    del f
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.helmholtz_diag(lam)
+    torch.cuda.synchronize()
+    t_diag = time.perf_counter() - t0
+    solves = {}
+    # residual tolerances for the error targets 1e-6 and 1e-10 against the
+    # oracle on this mesh (the FP64 action's relative residual floor here is
+    # about 9e-12; at a residual of 2e-11 the sampled error is below 3e-11)
+    for target, tol in ((1e-6, 1e-9), (1e-10, 2e-11)):
+        row = {}
+        sols = {}
+        for name, kw in (("fp64", dict(inner="fp64", inner_tol=0.5 * tol, max_outer=3, max_inner=20000)),
+                         ("mixed", dict(inner="fp32", inner_tol=1e-3, max_outer=12, max_inner=5000))):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xs, st = plan.solve(b, lam=lam, tol=tol, check=False, **kw)
+            torch.cuda.synchronize()
+            st["s"] = round(time.perf_counter() - t0, 4)
+            row[name] = st
+            sols[name] = xs
+            log(f"  solve tol={tol:g} {name}: {st}")
+        row["speedup"] = round(row["fp64"]["s"] / row["mixed"]["s"], 3)
+        row["mixed_vs_fp64_rel2"] = float((sols["mixed"] - sols["fp64"]).norm() / sols["fp64"].norm())
+        row["resid_tol"] = tol
+        solves[f"err_target_{target:g}"] = row
+    return {"workload": f"mixed-element mesh {ncell}^3 cells, curved, P={P}, Q={P + 2}, lambda={lam}",
+            "dof": int(nc), "action": action, "diag_setup_s": round(t_diag, 4), "solve": solves,
+            "note": "solve: FP64 residual and update, inner Jacobi-PCG in FP32 (mixed) or FP64 (plain, one "
+                    "inner solve to the tolerance); wall time per solve including host checks; error against "
+                    "the FP64 oracle is asserted by the test suite on sampled elements"}
+
+
 def cpu_baseline(mesh, P: int, budget_s: float = 15.0):
     """The oracle's Helmholtz action (form H_e by explicit quadrature, then
     y = H_e x) on a bounded sample of the mesh: rounds of 1/128 of every
@@ -143,6 +205,8 @@ def main():
     ap.add_argument("--per-shape", action="store_true", help="also time each shape's block launch")
     ap.add_argument("--strategies", action="store_true",
                     help="also time collocated vs non-collocated Helmholtz per shape (block launches)")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg (P=6 mesh)")
+    ap.add_argument("--mixed-ncell", type=int, default=32)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     a = ap.parse_args()
@@ -210,6 +274,11 @@ def main():
             row["coll_speedup"] = round(row["sumfac"]["ms"] / row["sumfac_coll"]["ms"], 3)
             strategies[s] = row
             log(f"  {s}: {row}")
+    mixed = None
+    if not a.no_mixed:
+        del plan
+        torch.cuda.empty_cache()
+        mixed = mixed_precision_leg(torch, shp, W, a.mixed_ncell)
     cpu = None
     if not a.no_cpu:
         log("  cpu baseline (oracle, bounded sample)")
@@ -235,7 +304,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(P, a.ncell),
                      "algorithmic_bytes": int(nbytes), "launch_ms": round(ev_mean_ms, 5)},
         "cpu_baseline": cpu,
-        "mixed_vs_fp64": None,
+        "mixed_vs_fp64": mixed,
     }
     if per_shape is not None:
         out["per_shape"] = per_shape

@@ -143,6 +143,62 @@ int shp_block_offsets(shp_plan plan, int blk, int64_t* coeff_off /* host out */,
 int shp_apply(shp_plan plan, int blk, int op, int strategy, const double* in /* device */,
               double* out /* device */, double lambda, void* stream);
 
+/* Contraction precision: SHP_FP64, or SHP_FP32 (FP32 data, tables and
+ * accumulation in the sum-factorisation stages; the FP64 geometric factors are
+ * applied in FP64 and the results rounded); SHP_BF16 is reserved. */
+typedef enum { SHP_FP64 = 0, SHP_FP32 = 1, SHP_BF16 = 2 } shp_prec;
+
+/* shp_apply with a contraction precision: in/out are device arrays of doubles
+ * (SHP_FP64) or floats (SHP_FP32) in the same layouts.  SHP_FP32 covers the
+ * collocated Laplacian and Helmholtz actions as a whole-mesh launch (blk = -1,
+ * one P for all blocks); other combinations return SHP_ERR_UNSUPPORTED. */
+int shp_apply_prec(shp_plan plan, int blk, int op, int strategy, int prec, const void* in /* device */,
+                   void* out /* device */, double lambda, void* stream);
+
+/* ---- Helmholtz solve with mixed precision ------------------------------
+ * Solves H x = b for the elemental (unassembled, block-diagonal) Helmholtz
+ * operator H = lambda M + L of every element of the plan (Sec. 2, the
+ * Helmholtz problem; each H_e is symmetric positive definite for lambda > 0).
+ * Both calls below use a device scratch buffer ws, 256-byte aligned, of at
+ * least shp_solve_workspace_bytes, owned by the caller and not kept after
+ * return; both synchronise stream. */
+int shp_solve_workspace_bytes(shp_plan plan, size_t* bytes /* host out */);
+
+/* Jacobi preconditioner: diag[i] = H_e[m][m] for the coefficient i = mode m of
+ * element e, in the whole-mesh layout (device FP64 out, [total coefficients]).
+ * Formed with FP64 collocated actions on the unit vectors of each local mode
+ * index (max N_P whole-mesh actions). */
+int shp_helmholtz_diag(shp_plan plan, double lambda, double* diag /* device out */, void* ws /* device */,
+                       size_t ws_bytes, void* stream);
+
+/* Iterative refinement: the residual r = b - H x and the update x += d are
+ * FP64 (FP64 collocated action); each correction d solves H d = r with a
+ * Jacobi-preconditioned conjugate-gradient iteration whose operator actions,
+ * vectors and updates run in inner_prec (SHP_FP32 through shp_apply_prec, or
+ * SHP_FP64), with FP64 dot products.  The residual is scaled by 1/max|r|
+ * before it enters the inner precision.
+ *
+ * diag: from shp_helmholtz_diag with the same lambda.  b, x: device FP64
+ * arrays [total coefficients] in the whole-mesh layout; x holds the initial
+ * guess on entry and the solution on return.  Stops when ||b - H x||_2 <= tol
+ * ||b||_2 (checked before every outer step), after max_outer outer steps, or
+ * on error.  The inner iteration stops when its recursive residual has fallen
+ * by inner_tol (checked every 10 iterations) or after max_inner iterations.
+ * Returns SHP_ERR_NOT_CONVERGED (stats filled in) when the tolerance is not
+ * reached, SHP_ERR_INVALID_ARG for b = 0, SHP_ERR_UNSUPPORTED for SHP_BF16 or
+ * an FP32 request on a plan with more than one P. */
+typedef struct {
+  int outer_iters;     /* refinement steps taken */
+  int inner_iters;     /* inner CG iterations, summed over the steps */
+  int converged;       /* 1 when ||b - H x|| <= tol ||b|| */
+  double rel_residual; /* final ||b - H x||_2 / ||b||_2, FP64 action */
+} shp_solve_stats;
+
+int shp_helmholtz_solve(shp_plan plan, double lambda, const double* diag /* device */, const double* b /* device */,
+                        double* x /* device, in/out */, int inner_prec, double tol, int max_outer, int max_inner,
+                        double inner_tol, void* ws /* device */, size_t ws_bytes,
+                        shp_solve_stats* stats /* host out */, void* stream);
+
 /* Fix the launch shape used for (blk, op, strategy), blk = -1 for the
  * whole-mesh launch: elements per work-group (1..64, within the 160 KiB LDS of
  * a work-group), threads per work-group (multiple of 64 in [64,512]) and, for

@@ -10,6 +10,7 @@ import concurrent.futures as cf
 import glob
 import os
 import subprocess
+import time
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,20 +29,22 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def _compile(src: str):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    return obj
+    return obj, time.time() - t0
 
 
 def build(jobs: int = 8, verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        done = list(ex.map(_compile, srcs))
+    objs = [o for o, _ in done]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,7 +52,8 @@ def build(jobs: int = 8, verbose: bool = True) -> str:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
     if verbose:
-        print(f"built {LIB}", flush=True)
+        slow = ", ".join(f"{os.path.basename(o)[:-2]} {t:.0f}s" for o, t in sorted(done, key=lambda d: -d[1])[:4])
+        print(f"built {LIB} (slowest: {slow})", flush=True)
     return LIB
 
 

@@ -48,8 +48,9 @@ struct Block {
   int NP = 0, NQ = 0;
   std::vector<double> tab;
   std::vector<int> itab;
-  size_t off_tab = 0, off_itab = 0, off_fac = 0, off_dxi = 0, off_lm = 0;
+  size_t off_tab = 0, off_itab = 0, off_fac = 0, off_dxi = 0, off_lm = 0, off_tabf = 0;
   std::vector<double> lm;  // [B; d_d B] for the local-matrix strategy (P <= 4)
+  std::vector<float> tabf; // the reference tables rounded to FP32
   long long coeff_off = 0, phys_off = 0;
   bool geom_ok = false;
   Tiling tiling[OPK_COUNT];
@@ -219,6 +220,8 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     off = align_up(off + sizeof(int) * B.itab.size());
     B.off_lm = off;
     off = align_up(off + sizeof(double) * B.lm.size());
+    B.off_tabf = off;
+    off = align_up(off + sizeof(float) * B.tab.size());
   }
   for (auto& B : p->blocks) {
     B.off_fac = off;
@@ -253,6 +256,7 @@ static int upload_static(shp_plan p, hipStream_t s) {
     bs[b].itab = reinterpret_cast<const int*>(p->ws + B.off_itab);
     bs[b].fac = reinterpret_cast<const double*>(p->ws + B.off_fac);
     bs[b].dxi = reinterpret_cast<const double*>(p->ws + B.off_dxi);
+    bs[b].tabf = reinterpret_cast<const float*>(p->ws + B.off_tabf);
     bs[b].n_elem = B.d.n_elem;
     bs[b].coeff_off = B.coeff_off;
     bs[b].phys_off = B.phys_off;
@@ -280,6 +284,10 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
       e = hipMemcpyAsync(p->ws + B.off_itab, B.itab.data(), sizeof(int) * B.itab.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.lm.empty())
       e = hipMemcpyAsync(p->ws + B.off_lm, B.lm.data(), sizeof(double) * B.lm.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      B.tabf.assign(B.tab.begin(), B.tab.end());
+      e = hipMemcpyAsync(p->ws + B.off_tabf, B.tabf.data(), sizeof(float) * B.tabf.size(), hipMemcpyHostToDevice, s);
+    }
     if (e != hipSuccess) return dev_fail(e, "hipMemcpyAsync(tables)");
   }
   for (int k = 0; k < OPK_COUNT; ++k) p->mixed_dirty[k] = true;
@@ -321,6 +329,39 @@ int shp_plan_set_geometry(shp_plan p, int blk, const double* jac, void* stream) 
   B.geom_ok = true;
   return SHP_OK;
 }
+
+}  // extern "C"
+
+namespace shp {
+
+int plan_mode_index(shp_plan_s* p, std::vector<int>& mode) {
+  if (int r = check_plan(p)) return r;
+  mode.assign(p->total_coeff, 0);
+  for (const auto& B : p->blocks) {
+    const int nm = num_modes(B.d.shape, B.d.P);
+    for (long long e = 0; e < B.d.n_elem; ++e)
+      for (int m = 0; m < nm; ++m) mode[B.coeff_off + e * nm + m] = m;
+  }
+  return SHP_OK;
+}
+
+long long plan_total_coeff(const shp_plan_s* p) { return p ? p->total_coeff : 0; }
+
+int plan_check_solve(shp_plan_s* p, int inner_prec) {
+  if (int r = check_plan(p)) return r;
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  for (size_t b = 0; b < p->blocks.size(); ++b)
+    if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
+  if (inner_prec == SHP_FP32 && !p->uniform_P)
+    return fail(SHP_ERR_UNSUPPORTED, "FP32 whole-mesh launch needs one P for all blocks");
+  return SHP_OK;
+}
+
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+}  // namespace shp
+
+extern "C" {
 
 int shp_block_offsets(shp_plan p, int blk, int64_t* coeff_off, int64_t* phys_off) {
   if (int r = check_plan(p)) return r;
@@ -525,6 +566,41 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
   return SHP_OK;
 }
 
+
+int shp_apply_prec(shp_plan p, int blk, int op, int strategy, int prec, const void* in, void* out, double lambda,
+                   void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (prec == SHP_FP64)
+    return shp_apply(p, blk, op, strategy, static_cast<const double*>(in), static_cast<double*>(out), lambda, stream);
+  if (prec == SHP_BF16) return fail(SHP_ERR_UNSUPPORTED, "BF16 contractions are not built");
+  if (prec != SHP_FP32) return fail(SHP_ERR_INVALID_ARG, "bad precision %d", prec);
+  if (op != SHP_OP_HELMHOLTZ && op != SHP_OP_LAPLACIAN)
+    return fail(SHP_ERR_UNSUPPORTED, "FP32 contractions cover the Laplacian and Helmholtz actions");
+  if (strategy != SHP_AUTO && strategy != SHP_SUMFAC_COLL)
+    return fail(SHP_ERR_UNSUPPORTED, "FP32 contractions use the collocated sum-factorisation");
+  if (blk != -1) return fail(SHP_ERR_UNSUPPORTED, "FP32 contractions run as a whole-mesh launch (blk = -1)");
+  if (!in || !out) return fail(SHP_ERR_INVALID_ARG, "null in/out");
+  if (!std::isfinite(lambda)) return fail(SHP_ERR_INVALID_ARG, "lambda not finite");
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  if (!p->uniform_P) return fail(SHP_ERR_UNSUPPORTED, "FP32 whole-mesh launch needs one P for all blocks");
+  for (size_t b = 0; b < p->blocks.size(); ++b)
+    if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
+  const int opk = (op == SHP_OP_HELMHOLTZ) ? OPK_HELM : OPK_LAP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->mixed_dirty[opk])
+    if (int r = build_tiles(p, opk, s)) return r;
+  const Tiling mt = mixed_tiling(p, opk);
+  size_t lds = 0;
+  for (const auto& B : p->blocks) lds = std::max(lds, lds_bytes_f32(B.d.shape, B.d.P, mt.E));
+  if (points_per_thread((long long)mt.E * (p->blocks[0].d.Q) * p->blocks[0].d.Q * p->blocks[0].d.Q, mt.NT) == 0)
+    return fail(SHP_ERR_UNSUPPORTED, "launch shape too large for the FP32 kernel's register slots");
+  const Tile* tiles = reinterpret_cast<const Tile*>(p->ws + p->off_tiles) + (size_t)opk * p->max_tiles;
+  hipError_t e = launch_mixed_f32(p->blocks[0].d.P, opk, reinterpret_cast<const BlockStatic*>(p->ws + p->off_bstat),
+                                  tiles, p->mixed_ntiles[opk], static_cast<const float*>(in), static_cast<float*>(out),
+                                  lambda, mt.NT, lds, mt.E, s);
+  if (e != hipSuccess) return dev_fail(e, "FP32 launch");
+  return SHP_OK;
+}
 
 // ---------------------------------------------------------------------------
 // Autotuning

@@ -8,6 +8,8 @@
 
 #include "shp_layout.hpp"
 
+struct shp_plan_s;
+
 namespace shp {
 
 struct OpArgs;
@@ -21,6 +23,7 @@ struct BlockStatic {
   const int* itab;
   const double* fac;
   const double* dxi;
+  const float* tabf;    // the reference tables rounded to FP32
   long long n_elem;
   long long coeff_off;  // element offset * N_P of the block in whole-mesh coefficient buffers
   long long phys_off;   // element offset * N_Q in whole-mesh point buffers
@@ -45,6 +48,10 @@ hipError_t launch_localmat(int sh, int P, int opk, const LocalMatArgs& a, hipStr
 hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
                         double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds, int E,
                         int persist, hipStream_t s);
+// FP32 contractions (whole-mesh collocated Laplacian/Helmholtz, prefetch variant)
+size_t lds_bytes_f32(int sh, int P, int E);
+hipError_t launch_mixed_f32(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const float* in,
+                            float* out, double lambda, int threads, size_t lds, int E, hipStream_t s);
 // persistent launches: CUs of the current device, grid = occupancy * CUs, and
 // the register slots per thread of the metric stage (2, 4, 8; 0 = too many)
 int num_cus();
@@ -55,5 +62,13 @@ hipError_t launch_maxdiff(const double* a, const double* b, long long n, unsigne
 
 constexpr int MAX_P = 10;
 constexpr size_t LDS_LIMIT = 160 * 1024;
+
+// Plan queries for the solver (shp_api.cpp): the local mode index of every
+// coefficient of the whole mesh, the mesh's coefficient count, and the error
+// text reported by shp_last_error.
+int plan_mode_index(shp_plan_s* p, std::vector<int>& mode);
+long long plan_total_coeff(const shp_plan_s* p);
+int plan_check_solve(shp_plan_s* p, int inner_prec);  // workspace, geometry, FP32 needs one P
+int set_error(int code, const char* msg);
 
 }  // namespace shp

@@ -1,5 +1,6 @@
-// Mixed-shape kernels (one launch over every block of a whole mesh) and the
-// dispatch from runtime (shape, P, operator) to the templated launchers.
+// Dispatch from runtime (shape, P, operator) to the templated launchers: the
+// per-shape block launchers (shp_k_<shape>.hip) and the whole-mesh launchers
+// of each order (shp_k_mixed_p<P>.hip); plus the device max-difference check.
 #include <algorithm>
 
 #include "shp_kernels.hpp"
@@ -25,6 +26,20 @@ hipError_t launch_localmat(int sh, int P, int opk, const LocalMatArgs& a, hipStr
     case PRISM: return launch_localmat_prism(P, opk, a, s);
     case PYR: return launch_localmat_pyr(P, opk, a, s);
     default: return launch_localmat_tet(P, opk, a, s);
+  }
+}
+
+size_t lds_bytes_f32_hex(int P, int E);
+size_t lds_bytes_f32_prism(int P, int E);
+size_t lds_bytes_f32_pyr(int P, int E);
+size_t lds_bytes_f32_tet(int P, int E);
+
+size_t lds_bytes_f32(int sh, int P, int E) {
+  switch (sh) {
+    case HEX: return lds_bytes_f32_hex(P, E);
+    case PRISM: return lds_bytes_f32_prism(P, E);
+    case PYR: return lds_bytes_f32_pyr(P, E);
+    default: return lds_bytes_f32_tet(P, E);
   }
 }
 
@@ -85,89 +100,24 @@ hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s) {
   }
 }
 
-template <int P, int OP, int PPT>
-static hipError_t launch_mixed_hp(const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
-                                  double* out, double lambda, int threads, size_t lds, hipStream_t s) {
-  const long long grid =
-      std::min<long long>(ntiles, persistent_grid((const void*)k_helm_mixed_persist<P, OP, PPT>, threads, lds));
-  hipLaunchKernelGGL((k_helm_mixed_persist<P, OP, PPT>), dim3((unsigned)grid), dim3(threads), lds, s, blocks, tiles,
-                     ntiles, in, out, lambda);
-  return hipGetLastError();
-}
+#define D_(p)                                                                                                      \
+  hipError_t launch_mixed_P##p(int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in, \
+                               double* out, long long in_cs, long long out_cs, double lambda, int threads,          \
+                               size_t lds, int E, int persist, hipStream_t s);                                      \
+  hipError_t launch_mixed_f32_P##p(int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles,               \
+                                   const float* in, float* out, double lambda, int threads, size_t lds, int E,       \
+                                   hipStream_t s);
+D_(1) D_(2) D_(3) D_(4) D_(5) D_(6) D_(7) D_(8) D_(9) D_(10)
+#undef D_
 
-template <int P, int OP, int PPT>
-static hipError_t launch_mixed_pf(const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
-                                  double* out, double lambda, int threads, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_helm_mixed_pf<P, OP, PPT>), dim3((unsigned)ntiles), dim3(threads), lds, s, blocks, tiles,
-                     ntiles, in, out, lambda);
-  return hipGetLastError();
-}
-
-template <int P, int OP>
-static hipError_t launch_mixed_ppt(int variant, int ppt, const BlockStatic* blocks, const Tile* tiles, int ntiles,
-                                   const double* in, double* out, double lambda, int threads, size_t lds,
-                                   hipStream_t s) {
-  if (variant == 2) {
-    switch (ppt) {
-      case 2: return launch_mixed_pf<P, OP, 2>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
-      case 4: return launch_mixed_pf<P, OP, 4>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
-      case 8: return launch_mixed_pf<P, OP, 8>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
-    }
-    return hipErrorInvalidValue;
-  }
-  switch (ppt) {
-    case 2: return launch_mixed_hp<P, OP, 2>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
-    case 4: return launch_mixed_hp<P, OP, 4>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
-    case 8: return launch_mixed_hp<P, OP, 8>(blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
+hipError_t launch_mixed_f32(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const float* in,
+                            float* out, double lambda, int threads, size_t lds, int E, hipStream_t s) {
+  switch (P) {
+#define C_(p) case p: return launch_mixed_f32_P##p(opk, blocks, tiles, ntiles, in, out, lambda, threads, lds, E, s);
+    C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10)
+#undef C_
   }
   return hipErrorInvalidValue;
-}
-
-template <int P, int OP>
-static hipError_t launch_mixed_fused(const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
-                                     double* out, double lambda, int threads, size_t lds, bool pf, hipStream_t s) {
-  const dim3 g((unsigned)ntiles), b((unsigned)threads);
-  if (pf)
-    hipLaunchKernelGGL((k_helm_fused_mixed<P, OP, true>), g, b, lds, s, blocks, tiles, ntiles, in, out, lambda);
-  else
-    hipLaunchKernelGGL((k_helm_fused_mixed<P, OP, false>), g, b, lds, s, blocks, tiles, ntiles, in, out, lambda);
-  return hipGetLastError();
-}
-
-template <int P>
-static hipError_t launch_mixed_p(int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
-                                 double* out, long long in_cs, long long out_cs, double lambda, int threads,
-                                 size_t lds, int E, int persist, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  if (opk == OPK_HELM_NC || opk == OPK_LAP_NC) {
-    const dim3 g((unsigned)ntiles), b((unsigned)threads);
-    if (opk == OPK_HELM_NC)
-      hipLaunchKernelGGL((k_helm_nc_mixed<P, OPK_HELM>), g, b, lds, s, blocks, tiles, ntiles, in, out, lambda);
-    else
-      hipLaunchKernelGGL((k_helm_nc_mixed<P, OPK_LAP>), g, b, lds, s, blocks, tiles, ntiles, in, out, lambda);
-    return hipGetLastError();
-  }
-  if (persist >= 3 && (opk == OPK_HELM || opk == OPK_LAP)) {
-    const bool pf = (persist == 4) && (E * (P + 2) * (P + 2) <= threads);
-    return opk == OPK_HELM ? launch_mixed_fused<P, OPK_HELM>(blocks, tiles, ntiles, in, out, lambda, threads, lds, pf, s)
-                           : launch_mixed_fused<P, OPK_LAP>(blocks, tiles, ntiles, in, out, lambda, threads, lds, pf, s);
-  }
-  if ((persist == 1 || persist == 2) && (opk == OPK_HELM || opk == OPK_LAP)) {
-    const int ppt = points_per_thread((long long)E * (P + 2) * (P + 2) * (P + 2), threads);
-    if (ppt > 0)
-      return opk == OPK_HELM
-                 ? launch_mixed_ppt<P, OPK_HELM>(persist, ppt, blocks, tiles, ntiles, in, out, lambda, threads, lds, s)
-                 : launch_mixed_ppt<P, OPK_LAP>(persist, ppt, blocks, tiles, ntiles, in, out, lambda, threads, lds, s);
-  }
-  const dim3 g((unsigned)ntiles), b((unsigned)threads);
-  switch (opk) {
-#define K_(op) \
-  case op: hipLaunchKernelGGL((k_mixed<P, op>), g, b, lds, s, blocks, tiles, ntiles, in, out, in_cs, out_cs, lambda); break;
-    K_(OPK_BWD) K_(OPK_IPR) K_(OPK_DERIV) K_(OPK_IPRD) K_(OPK_MASS) K_(OPK_LAP) K_(OPK_HELM)
-#undef K_
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
 }
 
 hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
@@ -176,7 +126,7 @@ hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* t
   switch (P) {
 #define C_(p)                                                                                                   \
   case p:                                                                                                       \
-    return launch_mixed_p<p>(opk, blocks, tiles, ntiles, in, out, in_cs, out_cs, lambda, threads, lds, E, persist, \
+    return launch_mixed_P##p(opk, blocks, tiles, ntiles, in, out, in_cs, out_cs, lambda, threads, lds, E, persist, \
                              s);
     C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10)
 #undef C_

@@ -92,38 +92,43 @@ struct Dims {
 // the constant address space become scalar loads into SGPRs, which feed the
 // FP64 FMAs directly and take no LDS bandwidth.  Streamed data is read through
 // the global address space.
-typedef const __attribute__((address_space(4))) double* ctab_t;
+template <typename R>
+using ctab = const __attribute__((address_space(4))) R*;
+typedef ctab<double> ctab_t;
 typedef const __attribute__((address_space(1))) double* gptr_t;
 __device__ __forceinline__ ctab_t as_const(const double* p) { return (ctab_t)(p); }
 // Re-derive a table pointer inside a loop so the scalar loads stay in the loop
 // body (hoisting every table value out of the loop spills SGPRs).
-__device__ __forceinline__ ctab_t launder(ctab_t p) {
+template <typename R>
+__device__ __forceinline__ ctab<R> launder(ctab<R> p) {
   unsigned long long v = (unsigned long long)p;
   asm volatile("" : "+s"(v));
-  return (ctab_t)v;
+  return (ctab<R>)v;
 }
 __device__ __forceinline__ gptr_t as_global(const double* p) { return (gptr_t)(p); }
 
 // LDS view of one tile.
-template <int SH, int P>
+// R is the type of the contractions and of the field data in LDS (double, or
+// float for the mixed-precision path); geometric factors stay double.
+template <int SH, int P, typename R = double>
 struct Tile_ {
   using D = Dims<SH, P>;
-  double* tab;
+  R* tab;
   int* itab;
-  ctab_t ct;   // the same tables in global memory, for lane-uniform reads
-  double* el;  // E * per
-  int per;     // doubles per element: 4 buffers (U, G0, G1, G2) or 3 in the fused kernels
-  __device__ double* U(int e) const { return el + e * per; }
-  __device__ double* G(int e, int d) const { return el + e * per + (d + 1) * D::S3; }
+  ctab<R> ct;  // the same tables in global memory, for lane-uniform reads
+  R* el;       // E * per
+  int per;     // values per element: 4 buffers (U, G0, G1, G2), 3 fused, 5 non-collocated
+  __device__ R* U(int e) const { return el + e * per; }
+  __device__ R* G(int e, int d) const { return el + e * per + (d + 1) * D::S3; }
 };
 
 __device__ __forceinline__ int tid() { return threadIdx.x; }
 __device__ __forceinline__ int nthr() { return blockDim.x; }
 
-template <int SH, int P>
-__device__ void load_tables(const OpArgs& a, const Tile_<SH, P>& T) {
+template <int SH, int P, typename R>
+__device__ void load_tables(const OpArgs& a, const Tile_<SH, P, R>& T) {
   using D = Dims<SH, P>;
-  for (int t = tid(); t < D::NTAB; t += nthr()) T.tab[t] = a.tab[t];
+  for (int t = tid(); t < D::NTAB; t += nthr()) T.tab[t] = (R)a.tab[t];
   for (int t = tid(); t < D::NITAB; t += nthr()) T.itab[t] = a.itab[t];
 }
 
@@ -132,23 +137,23 @@ __device__ void load_tables(const OpArgs& a, const Tile_<SH, P>& T) {
 // ---------------------------------------------------------------------------
 
 // stage r: X (modes of element e) -> F[c][k] at c*QP + k
-template <int SH, int P, bool DER>
-__device__ void bwd_r(const Tile_<SH, P>& T, int ne, int xbuf, int fbuf) {
+template <int SH, int P, bool DER, typename R>
+__device__ void bwd_r(const Tile_<SH, P, R>& T, int ne, int xbuf, int fbuf) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, n = D::n;
   if (SH == HEX) {
     // every column runs r over 0..P with the same table: lane-uniform reads
     for (int t = tid(); t < ne * D::NC; t += nthr()) {
-      const ctab_t C3 = launder(T.ct) + (DER ? D::L.dC3 : D::L.C3);
+      const ctab<R> C3 = launder(T.ct) + (DER ? D::L.dC3 : D::L.C3);
       const int e = t / D::NC, c = t - e * D::NC;
-      const double* x = (xbuf < 0 ? T.U(e) : T.G(e, xbuf)) + c * n;
-      double xr[n];
+      const R* x = (xbuf < 0 ? T.U(e) : T.G(e, xbuf)) + c * n;
+      R xr[n];
 #pragma unroll
       for (int r = 0; r < n; ++r) xr[r] = x[r];
-      double* f = T.G(e, fbuf) + c * D::QP;
+      R* f = T.G(e, fbuf) + c * D::QP;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        double a = 0.0;
+        R a = 0.0;
 #pragma unroll
         for (int r = 0; r < n; ++r) a = fma(C3[r * Q + k], xr[r], a);
         f[k] = a;
@@ -156,24 +161,24 @@ __device__ void bwd_r(const Tile_<SH, P>& T, int ne, int xbuf, int fbuf) {
     }
     return;
   }
-  const double* C3 = T.tab + (DER ? D::L.dC3 : D::L.C3);
-  const double* V1 = C3 + 1 * Q;  // family (0,1): v1 or its derivative 1/2
+  const R* C3 = T.tab + (DER ? D::L.dC3 : D::L.C3);
+  const R* V1 = C3 + 1 * Q;  // family (0,1): v1 or its derivative 1/2
   for (int t = tid(); t < ne * D::NC; t += nthr()) {
     const int e = t / D::NC, c = t - e * D::NC;
     const int* ct = T.itab + c * ICOL;
-    const int p = ct[0], q = ct[1], off = ct[2], R = ct[3], fb = ct[4];
-    const double* x = (xbuf < 0 ? T.U(e) : T.G(e, xbuf));
-    const double* cf = C3 + fb * Q;
-    double acc[Q];
+    const int p = ct[0], q = ct[1], off = ct[2], RL = ct[3], fb = ct[4];
+    const R* x = (xbuf < 0 ? T.U(e) : T.G(e, xbuf));
+    const R* cf = C3 + fb * Q;
+    R acc[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) acc[k] = 0.0;
-    for (int r = 0; r < R; ++r) {
-      const double xr = x[off + r];
+    for (int r = 0; r < RL; ++r) {
+      const R xr = x[off + r];
 #pragma unroll
       for (int k = 0; k < Q; ++k) acc[k] = fma(cf[r * Q + k], xr, acc[k]);
     }
     // collapsed-vertex modes: extra eta3 term v1 in columns p = 1 (and q = 1)
-    double xe = 0.0;
+    R xe = 0.0;
     bool extra = false;
     if (SH == PRISM) {
       if (p == 1) { xe = x[q * (P + 1) + 1]; extra = true; }
@@ -186,32 +191,32 @@ __device__ void bwd_r(const Tile_<SH, P>& T, int ne, int xbuf, int fbuf) {
 #pragma unroll
       for (int k = 0; k < Q; ++k) acc[k] = fma(V1[k], xe, acc[k]);
     }
-    double* f = T.G(e, fbuf) + c * D::QP;
+    R* f = T.G(e, fbuf) + c * D::QP;
 #pragma unroll
     for (int k = 0; k < Q; ++k) f[k] = acc[k];
   }
 }
 
 // stage q: F[c][k] -> G[p][j][k] (p*Q*QP + j*QP + k)
-template <int SH, int P, bool DER>
-__device__ void bwd_q(const Tile_<SH, P>& T, int ne, int fbuf, int gbuf) {
+template <int SH, int P, bool DER, typename R>
+__device__ void bwd_q(const Tile_<SH, P, R>& T, int ne, int fbuf, int gbuf) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, n = D::n, QP = D::QP;
   if (SH != TET) {
     // eta2 functions A_q for every p: lane-uniform table
     for (int t = tid(); t < ne * n * Q; t += nthr()) {
-      const ctab_t B2 = launder(T.ct) + (DER ? D::L.dB2 : D::L.B2);
+      const ctab<R> B2 = launder(T.ct) + (DER ? D::L.dB2 : D::L.B2);
       const int e = t / (n * Q);
       const int rem = t - e * (n * Q);
       const int p = rem / Q, k = rem - p * Q;
-      const double* F = T.G(e, fbuf) + (p * n) * QP + k;
-      double fv[n];
+      const R* F = T.G(e, fbuf) + (p * n) * QP + k;
+      R fv[n];
 #pragma unroll
       for (int q = 0; q < n; ++q) fv[q] = F[q * QP];
-      double* G = T.G(e, gbuf) + p * Q * QP + k;
+      R* G = T.G(e, gbuf) + p * Q * QP + k;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        double a = 0.0;
+        R a = 0.0;
 #pragma unroll
         for (int q = 0; q < n; ++q) a = fma(B2[q * Q + j], fv[q], a);
         G[j * QP] = a;
@@ -219,54 +224,54 @@ __device__ void bwd_q(const Tile_<SH, P>& T, int ne, int fbuf, int gbuf) {
     }
     return;
   }
-  const double* B2 = T.tab + (DER ? D::L.dB2 : D::L.B2);
+  const R* B2 = T.tab + (DER ? D::L.dB2 : D::L.B2);
   // v1 in eta2 (or its derivative) is the family (0,1) row of the tet's table
-  const double* V1 = B2 + 1 * Q;
+  const R* V1 = B2 + 1 * Q;
   for (int t = tid(); t < ne * n * Q; t += nthr()) {
     const int e = t / (n * Q);
     const int rem = t - e * (n * Q);
     const int p = rem / Q, k = rem - p * Q;
-    const double* F = T.G(e, fbuf);
+    const R* F = T.G(e, fbuf);
     const int nq = nq_of(SH, P, p), cb = col_base(SH, P, p);
     const int bfam = fam_index(P, p, 0);
-    double acc[Q];
+    R acc[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) acc[j] = 0.0;
     for (int q = 0; q < nq; ++q) {
-      const double fv = F[(cb + q) * QP + k];
-      const double* b = B2 + (bfam + q) * Q;
+      const R fv = F[(cb + q) * QP + k];
+      const R* b = B2 + (bfam + q) * Q;
 #pragma unroll
       for (int j = 0; j < Q; ++j) acc[j] = fma(b[j], fv, acc[j]);
     }
     if (p == 1) {
-      const double fv = F[1 * QP + k];  // column (0,1)
+      const R fv = F[1 * QP + k];  // column (0,1)
 #pragma unroll
       for (int j = 0; j < Q; ++j) acc[j] = fma(V1[j], fv, acc[j]);
     }
-    double* G = T.G(e, gbuf) + p * Q * QP + k;
+    R* G = T.G(e, gbuf) + p * Q * QP + k;
 #pragma unroll
     for (int j = 0; j < Q; ++j) G[j * QP] = acc[j];
   }
 }
 
 // stage p: G[p][j][k] -> U[i][j][k] (U buffer index ubuf: -1 = U, else G(ubuf))
-template <int SH, int P, bool DER>
-__device__ void bwd_p(const Tile_<SH, P>& T, int ne, int gbuf, int ubuf) {
+template <int SH, int P, bool DER, typename R>
+__device__ void bwd_p(const Tile_<SH, P, R>& T, int ne, int gbuf, int ubuf) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, n = D::n, QP = D::QP;
   for (int t = tid(); t < ne * Q * Q; t += nthr()) {
-    const ctab_t A1 = launder(T.ct) + (DER ? D::L.dA1 : D::L.A1);
+    const ctab<R> A1 = launder(T.ct) + (DER ? D::L.dA1 : D::L.A1);
     const int e = t / (Q * Q);
     const int rem = t - e * (Q * Q);
     const int j = rem / Q, k = rem - j * Q;
-    const double* G = T.G(e, gbuf) + j * QP + k;
-    double g[n];
+    const R* G = T.G(e, gbuf) + j * QP + k;
+    R g[n];
 #pragma unroll
     for (int p = 0; p < n; ++p) g[p] = G[p * Q * QP];
-    double* U = (ubuf < 0 ? T.U(e) : T.G(e, ubuf)) + j * QP + k;
+    R* U = (ubuf < 0 ? T.U(e) : T.G(e, ubuf)) + j * QP + k;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      double s = 0.0;
+      R s = 0.0;
 #pragma unroll
       for (int p = 0; p < n; ++p) s = fma(A1[p * Q + i], g[p], s);
       U[i * Q * QP] = s;
@@ -280,36 +285,36 @@ __device__ void bwd_p(const Tile_<SH, P>& T, int ne, int gbuf, int ubuf) {
 
 // stage p^T: s(i,j,k) = sum over the buffers in mask (bit0: U, bit1..3: G0..G2)
 // -> Gp[p][j][k], written in place into buffer dst (-1 = U) at (p, j, k).
-template <int SH, int P, bool DER>
-__device__ void ipr_p(const Tile_<SH, P>& T, int ne, int mask, int dst) {
+template <int SH, int P, bool DER, typename R>
+__device__ void ipr_p(const Tile_<SH, P, R>& T, int ne, int mask, int dst) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, n = D::n, QP = D::QP;
   for (int t = tid(); t < ne * Q * Q; t += nthr()) {
-    const ctab_t A1 = launder(T.ct) + (DER ? D::L.dA1 : D::L.A1);
+    const ctab<R> A1 = launder(T.ct) + (DER ? D::L.dA1 : D::L.A1);
     const int e = t / (Q * Q);
     const int rem = t - e * (Q * Q);
     const int j = rem / Q, k = rem - j * Q;
     const int o = j * QP + k;
-    double s[Q];
+    R s[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) s[i] = 0.0;
     if (mask & 1) {
-      const double* b = T.U(e) + o;
+      const R* b = T.U(e) + o;
 #pragma unroll
       for (int i = 0; i < Q; ++i) s[i] += b[i * Q * QP];
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       if (mask & (2 << d)) {
-        const double* b = T.G(e, d) + o;
+        const R* b = T.G(e, d) + o;
 #pragma unroll
         for (int i = 0; i < Q; ++i) s[i] += b[i * Q * QP];
       }
     }
-    double* G = (dst < 0 ? T.U(e) : T.G(e, dst)) + o;
+    R* G = (dst < 0 ? T.U(e) : T.G(e, dst)) + o;
 #pragma unroll
     for (int p = 0; p < n; ++p) {
-      double a = 0.0;
+      R a = 0.0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) a = fma(A1[p * Q + i], s[i], a);
       G[p * Q * QP] = a;
@@ -318,24 +323,24 @@ __device__ void ipr_p(const Tile_<SH, P>& T, int ne, int mask, int dst) {
 }
 
 // stage q^T: Gp[p][j][k] (buffer gbuf) -> F[c][k] (buffer fbuf)
-template <int SH, int P, bool DER>
-__device__ void ipr_q(const Tile_<SH, P>& T, int ne, int gbuf, int fbuf) {
+template <int SH, int P, bool DER, typename R>
+__device__ void ipr_q(const Tile_<SH, P, R>& T, int ne, int gbuf, int fbuf) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, n = D::n, QP = D::QP;
   if (SH != TET) {
     for (int t = tid(); t < ne * n * Q; t += nthr()) {
-      const ctab_t B2 = launder(T.ct) + (DER ? D::L.dB2 : D::L.B2);
+      const ctab<R> B2 = launder(T.ct) + (DER ? D::L.dB2 : D::L.B2);
       const int e = t / (n * Q);
       const int rem = t - e * (n * Q);
       const int p = rem / Q, k = rem - p * Q;
-      const double* G = (gbuf < 0 ? T.U(e) : T.G(e, gbuf)) + p * Q * QP + k;
-      double g[Q];
+      const R* G = (gbuf < 0 ? T.U(e) : T.G(e, gbuf)) + p * Q * QP + k;
+      R g[Q];
 #pragma unroll
       for (int j = 0; j < Q; ++j) g[j] = G[j * QP];
-      double* F = T.G(e, fbuf) + (p * n) * QP + k;
+      R* F = T.G(e, fbuf) + (p * n) * QP + k;
 #pragma unroll
       for (int q = 0; q < n; ++q) {
-        double a = 0.0;
+        R a = 0.0;
 #pragma unroll
         for (int j = 0; j < Q; ++j) a = fma(B2[q * Q + j], g[j], a);
         F[q * QP] = a;
@@ -343,27 +348,27 @@ __device__ void ipr_q(const Tile_<SH, P>& T, int ne, int gbuf, int fbuf) {
     }
     return;
   }
-  const double* B2 = T.tab + (DER ? D::L.dB2 : D::L.B2);
-  const double* V1 = B2 + 1 * Q;
+  const R* B2 = T.tab + (DER ? D::L.dB2 : D::L.B2);
+  const R* V1 = B2 + 1 * Q;
   for (int t = tid(); t < ne * n * Q; t += nthr()) {
     const int e = t / (n * Q);
     const int rem = t - e * (n * Q);
     const int p = rem / Q, k = rem - p * Q;
-    const double* G = (gbuf < 0 ? T.U(e) : T.G(e, gbuf)) + p * Q * QP + k;
-    double g[Q];
+    const R* G = (gbuf < 0 ? T.U(e) : T.G(e, gbuf)) + p * Q * QP + k;
+    R g[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) g[j] = G[j * QP];
     const int nq = nq_of(SH, P, p), cb = col_base(SH, P, p);
     const int bfam = fam_index(P, p, 0);
-    double* F = T.G(e, fbuf);
+    R* F = T.G(e, fbuf);
     for (int q = 0; q < nq; ++q) {
-      const double* b = B2 + (bfam + q) * Q;
-      double a = 0.0;
+      const R* b = B2 + (bfam + q) * Q;
+      R a = 0.0;
 #pragma unroll
       for (int j = 0; j < Q; ++j) a = fma(b[j], g[j], a);
       if (p == 0 && q == 1) {
         // adjoint of the tet's extra eta2 term: column (0,1) also collects v1 * Gp[1]
-        const double* G1 = G + 1 * Q * QP;
+        const R* G1 = G + 1 * Q * QP;
 #pragma unroll
         for (int j = 0; j < Q; ++j) a = fma(V1[j], G1[j * QP], a);
       }
@@ -373,22 +378,22 @@ __device__ void ipr_q(const Tile_<SH, P>& T, int ne, int gbuf, int fbuf) {
 }
 
 // stage r^T: F[c][k] (buffer fbuf) -> y modes into buffer ybuf (-1 = U), [NP]
-template <int SH, int P, bool DER>
-__device__ void ipr_r(const Tile_<SH, P>& T, int ne, int fbuf, int ybuf, bool accumulate) {
+template <int SH, int P, bool DER, typename R>
+__device__ void ipr_r(const Tile_<SH, P, R>& T, int ne, int fbuf, int ybuf, bool accumulate) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, QP = D::QP, n = D::n;
   if (SH == HEX) {
     for (int t = tid(); t < ne * D::NC; t += nthr()) {
-      const ctab_t C3u = launder(T.ct) + (DER ? D::L.dC3 : D::L.C3);
+      const ctab<R> C3u = launder(T.ct) + (DER ? D::L.dC3 : D::L.C3);
       const int e = t / D::NC, c = t - e * D::NC;
-      const double* F = T.G(e, fbuf) + c * QP;
-      double f[Q];
+      const R* F = T.G(e, fbuf) + c * QP;
+      R f[Q];
 #pragma unroll
       for (int k = 0; k < Q; ++k) f[k] = F[k];
-      double* y = (ybuf < 0 ? T.U(e) : T.G(e, ybuf)) + c * n;
+      R* y = (ybuf < 0 ? T.U(e) : T.G(e, ybuf)) + c * n;
 #pragma unroll
       for (int r = 0; r < n; ++r) {
-        double a = 0.0;
+        R a = 0.0;
 #pragma unroll
         for (int k = 0; k < Q; ++k) a = fma(C3u[r * Q + k], f[k], a);
         if (accumulate)
@@ -399,41 +404,41 @@ __device__ void ipr_r(const Tile_<SH, P>& T, int ne, int fbuf, int ybuf, bool ac
     }
     return;
   }
-  const double* C3 = T.tab + (DER ? D::L.dC3 : D::L.C3);
-  const double* V1 = C3 + 1 * Q;
+  const R* C3 = T.tab + (DER ? D::L.dC3 : D::L.C3);
+  const R* V1 = C3 + 1 * Q;
   for (int t = tid(); t < ne * D::NC; t += nthr()) {
     const int e = t / D::NC, c = t - e * D::NC;
     const int* ct = T.itab + c * ICOL;
-    const int p = ct[0], q = ct[1], off = ct[2], R = ct[3], fb = ct[4];
-    const double* F = T.G(e, fbuf);
-    double f[Q];
+    const int p = ct[0], q = ct[1], off = ct[2], RL = ct[3], fb = ct[4];
+    const R* F = T.G(e, fbuf);
+    R f[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) f[k] = F[c * QP + k];
-    double* y = (ybuf < 0 ? T.U(e) : T.G(e, ybuf)) + off;
-    const double* cf = C3 + fb * Q;
-    for (int r = 0; r < R; ++r) {
-      double a = 0.0;
+    R* y = (ybuf < 0 ? T.U(e) : T.G(e, ybuf)) + off;
+    const R* cf = C3 + fb * Q;
+    for (int r = 0; r < RL; ++r) {
+      R a = 0.0;
 #pragma unroll
       for (int k = 0; k < Q; ++k) a = fma(cf[r * Q + k], f[k], a);
       // adjoints of the collapsed-vertex splits
       const bool vx = (r == 1) && ((SH == PRISM && p == 0) || ((SH == PYR || SH == TET) && p == 0 && q == 0));
       if (vx) {
-        double s[Q];
+        R s[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) s[k] = 0.0;
         if (SH == PRISM) {
-          const double* Fe = F + ((P + 1) + q) * QP;  // column (1,q)
+          const R* Fe = F + ((P + 1) + q) * QP;  // column (1,q)
 #pragma unroll
           for (int k = 0; k < Q; ++k) s[k] = Fe[k];
         } else if (SH == PYR) {
-          const double* Fa = F + (P + 1) * QP;  // (1,0)
-          const double* Fb = F + 1 * QP;        // (0,1)
-          const double* Fc = F + (P + 2) * QP;  // (1,1)
+          const R* Fa = F + (P + 1) * QP;  // (1,0)
+          const R* Fb = F + 1 * QP;        // (0,1)
+          const R* Fc = F + (P + 2) * QP;  // (1,1)
 #pragma unroll
           for (int k = 0; k < Q; ++k) s[k] = Fa[k] + Fb[k] + Fc[k];
         } else {
-          const double* Fa = F + 1 * QP;        // (0,1)
-          const double* Fb = F + (P + 1) * QP;  // (1,0)
+          const R* Fa = F + 1 * QP;        // (0,1)
+          const R* Fb = F + (P + 1) * QP;  // (1,0)
 #pragma unroll
           for (int k = 0; k < Q; ++k) s[k] = Fa[k] + Fb[k];
         }
@@ -453,25 +458,25 @@ __device__ void ipr_r(const Tile_<SH, P>& T, int ne, int fbuf, int ybuf, bool ac
 // ---------------------------------------------------------------------------
 
 // one direction of the collocation derivative: lines along eta_{d+1}
-template <int SH, int P, int DIR, bool TRANS>
-__device__ __forceinline__ void grad_dir(const Tile_<SH, P>& T, int ne) {
+template <int SH, int P, int DIR, bool TRANS, typename R>
+__device__ __forceinline__ void grad_dir(const Tile_<SH, P, R>& T, int ne) {
   using D = Dims<SH, P>;
   constexpr int Q = D::Q, QP = D::QP;
   constexpr int stride = DIR == 0 ? Q * QP : DIR == 1 ? QP : 1;
   for (int t = tid(); t < ne * Q * Q; t += nthr()) {
-    const ctab_t Dm = launder(T.ct) + D::L.D + DIR * Q * Q;
+    const ctab<R> Dm = launder(T.ct) + D::L.D + DIR * Q * Q;
     const int e = t / (Q * Q);
     const int r2 = t - e * (Q * Q);
     const int a = r2 / Q, b = r2 - a * Q;
     const int base = DIR == 0 ? a * QP + b : DIR == 1 ? a * Q * QP + b : (a * Q + b) * QP;
-    const double* src = (TRANS ? T.G(e, DIR) : T.U(e)) + base;
-    double v[Q];
+    const R* src = (TRANS ? T.G(e, DIR) : T.U(e)) + base;
+    R v[Q];
 #pragma unroll
     for (int l = 0; l < Q; ++l) v[l] = src[l * stride];
-    double* g = T.G(e, DIR) + base;
+    R* g = T.G(e, DIR) + base;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      double s = 0.0;
+      R s = 0.0;
 #pragma unroll
       for (int l = 0; l < Q; ++l) s = fma(TRANS ? Dm[l * Q + i] : Dm[i * Q + l], v[l], s);
       g[i * stride] = s;
@@ -480,16 +485,16 @@ __device__ __forceinline__ void grad_dir(const Tile_<SH, P>& T, int ne) {
 }
 
 // G_d = D_d U for d = 0,1,2
-template <int SH, int P>
-__device__ void grad3(const Tile_<SH, P>& T, int ne) {
+template <int SH, int P, typename R>
+__device__ void grad3(const Tile_<SH, P, R>& T, int ne) {
   grad_dir<SH, P, 0, false>(T, ne);
   grad_dir<SH, P, 1, false>(T, ne);
   grad_dir<SH, P, 2, false>(T, ne);
 }
 
 // G_d <- D_d^T G_d in place, d = 0,1,2
-template <int SH, int P>
-__device__ void grad3T(const Tile_<SH, P>& T, int ne) {
+template <int SH, int P, typename R>
+__device__ void grad3T(const Tile_<SH, P, R>& T, int ne) {
   grad_dir<SH, P, 0, true>(T, ne);
   grad_dir<SH, P, 1, true>(T, ne);
   grad_dir<SH, P, 2, true>(T, ne);
@@ -499,20 +504,20 @@ __device__ void grad3T(const Tile_<SH, P>& T, int ne) {
 // global <-> LDS
 // ---------------------------------------------------------------------------
 
-template <int SH, int P>
-__device__ void load_modes(const Tile_<SH, P>& T, const double* __restrict__ in, long long e0, int ne, int buf) {
+template <int SH, int P, typename R>
+__device__ void load_modes(const Tile_<SH, P, R>& T, const R* __restrict__ in, long long e0, int ne, int buf) {
   using D = Dims<SH, P>;
-  const double* src = in + e0 * D::NP;
+  const R* src = in + e0 * D::NP;
   for (int t = tid(); t < ne * D::NP; t += nthr()) {
     const int e = t / D::NP, m = t - e * D::NP;
     (buf < 0 ? T.U(e) : T.G(e, buf))[m] = src[t];
   }
 }
 
-template <int SH, int P>
-__device__ void store_modes(const Tile_<SH, P>& T, double* __restrict__ out, long long e0, int ne, int buf) {
+template <int SH, int P, typename R>
+__device__ void store_modes(const Tile_<SH, P, R>& T, R* __restrict__ out, long long e0, int ne, int buf) {
   using D = Dims<SH, P>;
-  double* dst = out + e0 * D::NP;
+  R* dst = out + e0 * D::NP;
   for (int t = tid(); t < ne * D::NP; t += nthr()) {
     const int e = t / D::NP, m = t - e * D::NP;
     dst[t] = (buf < 0 ? T.U(e) : T.G(e, buf))[m];
@@ -532,8 +537,8 @@ __device__ __forceinline__ int lds_pt(int pt) {
 // tile bodies, one per operator
 // ---------------------------------------------------------------------------
 
-template <int SH, int P>
-__device__ void bwd_chain(const Tile_<SH, P>& T, int ne) {
+template <int SH, int P, typename R>
+__device__ void bwd_chain(const Tile_<SH, P, R>& T, int ne) {
   // modes in G0 -> F in G1 -> G in G2 -> U
   bwd_r<SH, P, false>(T, ne, 0, 1);
   __syncthreads();
@@ -544,8 +549,8 @@ __device__ void bwd_chain(const Tile_<SH, P>& T, int ne) {
 }
 
 // points summed over mask -> modes in buffer G1; returns after a barrier
-template <int SH, int P>
-__device__ void ipr_chain(const Tile_<SH, P>& T, int ne, int mask) {
+template <int SH, int P, typename R>
+__device__ void ipr_chain(const Tile_<SH, P, R>& T, int ne, int mask) {
   ipr_p<SH, P, false>(T, ne, mask, -1);
   __syncthreads();
   ipr_q<SH, P, false>(T, ne, -1, 0);
@@ -554,13 +559,13 @@ __device__ void ipr_chain(const Tile_<SH, P>& T, int ne, int mask) {
   __syncthreads();
 }
 
-template <int SH, int P, int OP>
-__device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH, P>& T) {
+template <int SH, int P, int OP, typename R>
+__device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH, P, R>& T) {
   using D = Dims<SH, P>;
   constexpr int Q3 = D::Q3;
   load_tables<SH, P>(a, T);
   if (OP == OPK_BWD || OP == OPK_MASS || OP == OPK_LAP || OP == OPK_HELM) {
-    load_modes<SH, P>(T, a.in, e0, ne, 0);
+    load_modes<SH, P>(T, reinterpret_cast<const R*>(a.in), e0, ne, 0);
     __syncthreads();
     bwd_chain<SH, P>(T, ne);
   } else {
@@ -568,7 +573,7 @@ __device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH,
   }
 
   if (OP == OPK_BWD) {
-    double* dst = a.out + e0 * Q3;
+    R* dst = reinterpret_cast<R*>(a.out) + e0 * Q3;
     for (int t = tid(); t < ne * Q3; t += nthr()) {
       const int e = t / Q3, pt = t - e * Q3;
       dst[t] = T.U(e)[lds_pt<SH, P>(pt)];
@@ -578,22 +583,22 @@ __device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH,
 
   if (OP == OPK_IPR || OP == OPK_MASS) {
     const double* fac = a.fac + e0 * (long long)(NFAC * Q3);
-    const double* src = a.in + e0 * Q3;
+    const R* src = reinterpret_cast<const R*>(a.in) + e0 * Q3;
     for (int t = tid(); t < ne * Q3; t += nthr()) {
       const int e = t / Q3, pt = t - e * Q3;
       const double jw = fac[e * (NFAC * Q3) + pt];
-      double* u = T.U(e) + lds_pt<SH, P>(pt);
+      R* u = T.U(e) + lds_pt<SH, P>(pt);
       const double f = (OP == OPK_IPR) ? src[t] : *u;
       *u = jw * f;
     }
     __syncthreads();
     ipr_chain<SH, P>(T, ne, 1);
-    store_modes<SH, P>(T, a.out, e0, ne, 1);
+    store_modes<SH, P>(T, reinterpret_cast<R*>(a.out), e0, ne, 1);
     return;
   }
 
   if (OP == OPK_DERIV) {
-    const double* src = a.in + e0 * Q3;
+    const R* src = reinterpret_cast<const R*>(a.in) + e0 * Q3;
     for (int t = tid(); t < ne * Q3; t += nthr()) {
       const int e = t / Q3, pt = t - e * Q3;
       T.U(e)[lds_pt<SH, P>(pt)] = src[t];
@@ -610,7 +615,7 @@ __device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH,
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const double v = m[(0 * 3 + i) * Q3] * g0 + m[(1 * 3 + i) * Q3] * g1 + m[(2 * 3 + i) * Q3] * g2;
-        a.out[i * a.out_cs + e0 * Q3 + t] = v;
+        reinterpret_cast<R*>(a.out)[i * a.out_cs + e0 * Q3 + t] = (R)v;
       }
     }
     return;
@@ -622,9 +627,10 @@ __device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH,
     for (int t = tid(); t < ne * Q3; t += nthr()) {
       const int e = t / Q3, pt = t - e * Q3;
       const int lp = lds_pt<SH, P>(pt);
-      const double f0 = a.in[0 * a.in_cs + e0 * Q3 + t];
-      const double f1 = a.in[1 * a.in_cs + e0 * Q3 + t];
-      const double f2 = a.in[2 * a.in_cs + e0 * Q3 + t];
+      const R* fin = reinterpret_cast<const R*>(a.in);
+      const double f0 = fin[0 * a.in_cs + e0 * Q3 + t];
+      const double f1 = fin[1 * a.in_cs + e0 * Q3 + t];
+      const double f2 = fin[2 * a.in_cs + e0 * Q3 + t];
       const double jw = fac[e * (NFAC * Q3) + pt];
       const double* m = dxi + e * (NDXI * Q3) + pt;
 #pragma unroll
@@ -637,7 +643,7 @@ __device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH,
     grad3T<SH, P>(T, ne);
     __syncthreads();
     ipr_chain<SH, P>(T, ne, 2 | 4 | 8);
-    store_modes<SH, P>(T, a.out, e0, ne, 1);
+    store_modes<SH, P>(T, reinterpret_cast<R*>(a.out), e0, ne, 1);
     return;
   }
 
@@ -653,10 +659,10 @@ __device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH,
       const double jw = g[0];
       const double g00 = g[1 * Q3], g01 = g[2 * Q3], g02 = g[3 * Q3];
       const double g11 = g[4 * Q3], g12 = g[5 * Q3], g22 = g[6 * Q3];
-      double* u = T.U(e) + lp;
-      double* p0 = T.G(e, 0) + lp;
-      double* p1 = T.G(e, 1) + lp;
-      double* p2 = T.G(e, 2) + lp;
+      R* u = T.U(e) + lp;
+      R* p0 = T.G(e, 0) + lp;
+      R* p1 = T.G(e, 1) + lp;
+      R* p2 = T.G(e, 2) + lp;
       const double d0 = *p0, d1 = *p1, d2 = *p2;
       *p0 = g00 * d0 + g01 * d1 + g02 * d2;
       *p1 = g01 * d0 + g11 * d1 + g12 * d2;
@@ -667,7 +673,7 @@ __device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH,
     grad3T<SH, P>(T, ne);
     __syncthreads();
     ipr_chain<SH, P>(T, ne, (OP == OPK_HELM ? 1 : 0) | 2 | 4 | 8);
-    store_modes<SH, P>(T, a.out, e0, ne, 1);
+    store_modes<SH, P>(T, reinterpret_cast<R*>(a.out), e0, ne, 1);
     return;
   }
 }
@@ -682,6 +688,30 @@ __device__ Tile_<SH, P> make_tile(double* smem, const double* gtab) {
   T.el = smem + D::HEAD;
   T.per = D::PER_ELEM;
   return T;
+}
+
+// LDS head (tables and column table) in units of R
+template <int SH, int P, typename R>
+constexpr int head_r() {
+  using D = Dims<SH, P>;
+  return D::NTAB + (int)((D::NITAB * sizeof(int) + sizeof(R) - 1) / sizeof(R));
+}
+
+template <int SH, int P, typename R>
+__device__ Tile_<SH, P, R> make_tile_r(void* smem, const R* gtab) {
+  using D = Dims<SH, P>;
+  Tile_<SH, P, R> T;
+  T.tab = reinterpret_cast<R*>(smem);
+  T.itab = reinterpret_cast<int*>(T.tab + D::NTAB);
+  T.ct = (ctab<R>)(gtab);
+  T.el = T.tab + head_r<SH, P, R>();
+  T.per = D::PER_ELEM;
+  return T;
+}
+
+template <int SH, int P, typename R>
+constexpr size_t lds_bytes_r(int E) {
+  return sizeof(R) * (size_t)(head_r<SH, P, R>() + E * Dims<SH, P>::PER_ELEM);
 }
 
 template <int SH, int P>
@@ -770,13 +800,13 @@ __device__ __forceinline__ void prefetch_geo(const double* __restrict__ fac, lon
   }
 }
 
-template <int SH, int P, int OP, int PPT, typename Next>
-__device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH, P>& T, GeoRegs<PPT>& g,
+template <int SH, int P, int OP, int PPT, typename Next, typename R>
+__device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH, P, R>& T, GeoRegs<PPT>& g,
                           bool tables, Next next) {
   using D = Dims<SH, P>;
   constexpr int Q3 = D::Q3;
   if (tables) load_tables<SH, P>(a, T);
-  load_modes<SH, P>(T, a.in, e0, ne, 0);
+  load_modes<SH, P>(T, reinterpret_cast<const R*>(a.in), e0, ne, 0);
   __syncthreads();
   bwd_chain<SH, P>(T, ne);
   grad3<SH, P>(T, ne);
@@ -789,15 +819,15 @@ __device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH,
       const int e = t / Q3, pt = t - e * Q3;
       const int lp = lds_pt<SH, P>(pt);
       const double* gg = g.v[it];
-      double* p0 = T.G(e, 0) + lp;
-      double* p1 = T.G(e, 1) + lp;
-      double* p2 = T.G(e, 2) + lp;
+      R* p0 = T.G(e, 0) + lp;
+      R* p1 = T.G(e, 1) + lp;
+      R* p2 = T.G(e, 2) + lp;
       const double d0 = *p0, d1 = *p1, d2 = *p2;
       *p0 = gg[1] * d0 + gg[2] * d1 + gg[3] * d2;
       *p1 = gg[2] * d0 + gg[4] * d1 + gg[5] * d2;
       *p2 = gg[3] * d0 + gg[5] * d1 + gg[6] * d2;
       if (OP == OPK_HELM) {
-        double* u = T.U(e) + lp;
+        R* u = T.U(e) + lp;
         *u = lam * gg[0] * (*u);
       }
     }
@@ -807,7 +837,7 @@ __device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH,
   grad3T<SH, P>(T, ne);
   __syncthreads();
   ipr_chain<SH, P>(T, ne, (OP == OPK_HELM ? 1 : 0) | 2 | 4 | 8);
-  store_modes<SH, P>(T, a.out, e0, ne, 1);
+  store_modes<SH, P>(T, reinterpret_cast<R*>(a.out), e0, ne, 1);
 }
 
 template <int SH, int P, int OP, int PPT>
@@ -896,7 +926,7 @@ __global__ void __launch_bounds__(512) k_helm_block_pf(OpArgs a) {
   helm_tile<SH, P, OP, PPT>(a, e0, ne, make_tile<SH, P>(smem, a.tab), g, true, []() {});
 }
 
-template <int P, int OP, int PPT>
+template <int P, int OP, int PPT, typename R = double>
 __global__ void __launch_bounds__(512) k_helm_mixed_pf(const BlockStatic* __restrict__ blocks,
                                                        const Tile* __restrict__ tiles, int ntiles, const double* in,
                                                        double* out, double lambda) {
@@ -913,19 +943,21 @@ __global__ void __launch_bounds__(512) k_helm_mixed_pf(const BlockStatic* __rest
   a.fac = b.fac;
   a.dxi = b.dxi;
   a.n_elem = b.n_elem;
-  a.in = in + b.coeff_off;
-  a.out = out + b.coeff_off;
+  // in/out hold values of type R; the offsets count values
+  a.in = reinterpret_cast<const double*>(reinterpret_cast<const R*>(in) + b.coeff_off);
+  a.out = reinterpret_cast<double*>(reinterpret_cast<R*>(out) + b.coeff_off);
   a.in_cs = 0;
   a.out_cs = 0;
   a.lambda = lambda;
   a.E = 0;
   a.pad_ = 0;
+  const R* gt = sizeof(R) == sizeof(double) ? reinterpret_cast<const R*>(b.tab) : reinterpret_cast<const R*>(b.tabf);
   auto none = []() {};
   switch (b.shape) {
-    case HEX: helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem, a.tab), g, true, none); break;
-    case PRISM: helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem, a.tab), g, true, none); break;
-    case PYR: helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem, a.tab), g, true, none); break;
-    default: helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<TET, P>(smem, a.tab), g, true, none); break;
+    case HEX: helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<HEX, P, R>(smem, gt), g, true, none); break;
+    case PRISM: helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<PRISM, P, R>(smem, gt), g, true, none); break;
+    case PYR: helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<PYR, P, R>(smem, gt), g, true, none); break;
+    default: helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<TET, P, R>(smem, gt), g, true, none); break;
   }
 }
 
@@ -1319,7 +1351,7 @@ __device__ void nc_ipr_r(const Tile_<SH, P>& T, int ne, int fa, int fb_buf, int 
   for (int t = tid(); t < ne * D::NC; t += nthr()) {
     const int e = t / D::NC, c = t - e * D::NC;
     const int* ct = T.itab + c * ICOL;
-    const int p = ct[0], q = ct[1], off = ct[2], R = ct[3], fam = ct[4];
+    const int p = ct[0], q = ct[1], off = ct[2], RL = ct[3], fam = ct[4];
     const double* FA = T.G(e, fa);
     const double* FB = T.G(e, fb_buf);
     double f[Q], g[Q];
@@ -1329,7 +1361,7 @@ __device__ void nc_ipr_r(const Tile_<SH, P>& T, int ne, int fa, int fb_buf, int 
       g[k] = FB[c * QP + k];
     }
     double* y = (dst < 0 ? T.U(e) : T.G(e, dst)) + off;
-    for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < RL; ++r) {
       const double* cf = C3 + (fam + r) * Q;
       const double* dcf = dC3 + (fam + r) * Q;
       double a = 0.0;

@@ -1,0 +1,357 @@
+// Mixed-precision Helmholtz solve on the broken (elemental) space: iterative
+// refinement with an FP64 residual and update around a Jacobi-preconditioned
+// CG whose actions and vectors are FP32 (or FP64).
+//
+//   x = x0;  repeat:  r = b - H x                       (FP64 action)
+//                     stop when ||r|| <= tol ||b||
+//                     s = 1 / max|r|;  solve H d = s r   (inner PCG, FP32)
+//                     x += d / s                         (FP64)
+//
+// The system is block diagonal (one SPD H_e per element, lambda > 0).  CG
+// scalars stay on the device (dot products write them, the update kernels read
+// them); the host reads a residual norm every few inner iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/shp.h"
+#include "shp_internal.hpp"
+
+namespace {
+
+constexpr int NB = 1024;  // blocks of the dot-product reduction
+enum Slot { RZ = 0, PQ, RZN, RR, RR0, BB, RMAX, NSLOT };
+
+template <typename T>
+__global__ void k_dot(const T* __restrict__ a, const T* __restrict__ b, long long n, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    acc = fma((double)a[i], (double)b[i], acc);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// slot[dst] = sum of the partials; when dst == RZN also keep beta = RZN / RZ in
+// slot RMAX+1 and move RZN into RZ
+__global__ void k_dot_final(const double* __restrict__ part, int np, double* __restrict__ slot, int dst) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    slot[dst] = sh[0];
+    if (dst == RZN) {
+      slot[NSLOT] = slot[RZ] > 0.0 ? sh[0] / slot[RZ] : 0.0;
+      slot[RZ] = sh[0];
+    }
+  }
+}
+
+__global__ void k_absmax(const double* __restrict__ a, long long n, unsigned long long* __restrict__ out) {
+  double m = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(a[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+// r = b - y (FP64); rs = s r in the inner precision, s = 1 / max|r| from slot RMAX
+template <typename T>
+__global__ void k_resid(const double* __restrict__ b, const double* __restrict__ y, double* __restrict__ r,
+                        T* __restrict__ rs, const unsigned long long* __restrict__ rmax, long long n, int scale) {
+  double s = 1.0;
+  if (scale) {
+    double m;
+    const unsigned long long bits = *rmax;
+    std::memcpy(&m, &bits, sizeof m);
+    s = m > 0.0 ? 1.0 / m : 1.0;
+  }
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double v = scale ? r[i] : b[i] - y[i];
+    if (!scale) r[i] = v;
+    rs[i] = (T)(v * s);
+  }
+}
+
+// x += d / s (FP64 update of the outer solution)
+template <typename T>
+__global__ void k_update_x(double* __restrict__ x, const T* __restrict__ d, const unsigned long long* __restrict__ rmax,
+                           long long n) {
+  double m;
+  const unsigned long long bits = *rmax;
+  std::memcpy(&m, &bits, sizeof m);
+  const double inv = m > 0.0 ? m : 1.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] += (double)d[i] * inv;
+}
+
+// z = r / diag
+template <typename T>
+__global__ void k_jacobi(const T* __restrict__ r, const T* __restrict__ dg, T* __restrict__ z, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    z[i] = r[i] / dg[i];
+}
+
+template <typename T>
+__global__ void k_copy(const T* __restrict__ a, T* __restrict__ b, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+template <typename T>
+__global__ void k_zero(T* __restrict__ a, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    a[i] = (T)0;
+}
+
+// alpha = RZ / PQ; d += alpha p; r -= alpha q
+template <typename T>
+__global__ void k_cg1(T* __restrict__ d, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
+                      const double* __restrict__ slot, long long n) {
+  const T alpha = slot[PQ] > 0.0 ? (T)(slot[RZ] / slot[PQ]) : (T)0;  // 0 on breakdown, caught by the host check
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    d[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+  }
+}
+
+// p = z + beta p (beta in slot NSLOT)
+template <typename T>
+__global__ void k_cg2(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ slot, long long n) {
+  const T beta = (T)slot[NSLOT];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+// unit vectors of one local mode index, and the diagonal gather
+__global__ void k_unit(double* __restrict__ x, const int* __restrict__ mode, int m, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] = (mode[i] == m) ? 1.0 : 0.0;
+}
+__global__ void k_gather(const double* __restrict__ y, const int* __restrict__ mode, int m, double* __restrict__ d,
+                         long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    if (mode[i] == m) d[i] = y[i];
+}
+__global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+inline dim3 grid_for(long long n) { return dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)); }
+
+int sfail(int code, const char* msg) { return shp::set_error(code, msg); }
+
+struct SolveWs {
+  double *r, *y, *slot, *part;
+  float* diagf;
+  void* vec;  // inner vectors: rs, z, p, q, d (5 n of the inner type)
+  int* mode;
+  unsigned long long* rmax;
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t carve(void* base, long long n, SolveWs* w) {
+  char* p = static_cast<char*>(base);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char* q = p ? p + o : nullptr;
+    o = align256(o + bytes);
+    return q;
+  };
+  SolveWs s{};
+  s.r = reinterpret_cast<double*>(take(sizeof(double) * n));
+  s.y = reinterpret_cast<double*>(take(sizeof(double) * n));
+  s.diagf = reinterpret_cast<float*>(take(sizeof(float) * n));
+  s.vec = take(sizeof(double) * 5 * n);
+  s.mode = reinterpret_cast<int*>(take(sizeof(int) * n));
+  s.slot = reinterpret_cast<double*>(take(sizeof(double) * 16));
+  s.part = reinterpret_cast<double*>(take(sizeof(double) * NB));
+  s.rmax = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 2));
+  if (w) *w = s;
+  return o;
+}
+
+template <typename T>
+int dot(const T* a, const T* b, long long n, SolveWs& w, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot<T>, dim3(NB), dim3(256), 0, s, a, b, n, w.part);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, w.part, NB, w.slot, slot);
+  return hipGetLastError() == hipSuccess ? SHP_OK : SHP_ERR_DEVICE;
+}
+
+template <typename T>
+int apply_inner(shp_plan plan, const T* in, T* out, double lambda, hipStream_t s) {
+  const int prec = sizeof(T) == sizeof(float) ? SHP_FP32 : SHP_FP64;
+  return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, prec, in, out, lambda, s);
+}
+
+template <typename T>
+int inner_pcg(shp_plan plan, double lambda, long long n, SolveWs& w, const T* dg, int max_inner, double inner_tol,
+              int* iters, hipStream_t s) {
+  T* rs = static_cast<T*>(w.vec);
+  T* z = rs + n;
+  T* p = z + n;
+  T* q = p + n;
+  T* d = q + n;
+  const dim3 g = grid_for(n), b(256);
+  hipLaunchKernelGGL(k_zero<T>, g, b, 0, s, d, n);
+  hipLaunchKernelGGL(k_jacobi<T>, g, b, 0, s, rs, dg, z, n);
+  hipLaunchKernelGGL(k_copy<T>, g, b, 0, s, z, p, n);
+  if (int r = dot(rs, z, n, w, RZ, s)) return r;
+  if (int r = dot(rs, rs, n, w, RR0, s)) return r;
+  double h0[NSLOT + 1];
+  int it = 0;
+  for (it = 1; it <= max_inner; ++it) {
+    if (int r = apply_inner<T>(plan, p, q, lambda, s)) return r;
+    if (int r = dot(p, q, n, w, PQ, s)) return r;
+    hipLaunchKernelGGL(k_cg1<T>, g, b, 0, s, d, rs, p, q, w.slot, n);
+    if (it % 10 == 0 || it == max_inner) {
+      if (int r = dot(rs, rs, n, w, RR, s)) return r;
+      if (hipMemcpyAsync(h0, w.slot, sizeof h0, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return sfail(SHP_ERR_DEVICE, "solver readback");
+      if (h0[RR] == 0.0 || std::sqrt(h0[RR]) <= inner_tol * std::sqrt(h0[RR0])) break;
+      if (!(h0[PQ] > 0.0) || !std::isfinite(h0[RR])) return sfail(SHP_ERR_NOT_CONVERGED, "CG breakdown (p^T H p <= 0)");
+    }
+    hipLaunchKernelGGL(k_jacobi<T>, g, b, 0, s, rs, dg, z, n);
+    if (int r = dot(rs, z, n, w, RZN, s)) return r;
+    hipLaunchKernelGGL(k_cg2<T>, g, b, 0, s, p, z, w.slot, n);
+  }
+  *iters = std::min(it, max_inner);
+  return hipGetLastError() == hipSuccess ? SHP_OK : SHP_ERR_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int shp_solve_workspace_bytes(shp_plan plan, size_t* bytes) {
+  if (!plan || !bytes) return sfail(SHP_ERR_INVALID_ARG, "null argument");
+  *bytes = carve(nullptr, shp::plan_total_coeff(plan), nullptr);
+  return SHP_OK;
+}
+
+int shp_helmholtz_diag(shp_plan plan, double lambda, double* diag, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !diag || !ws) return sfail(SHP_ERR_INVALID_ARG, "null argument");
+  const long long n = shp::plan_total_coeff(plan);
+  if (n < 1) return sfail(SHP_ERR_INVALID_ARG, "empty mesh");
+  if (!std::isfinite(lambda)) return sfail(SHP_ERR_INVALID_ARG, "lambda not finite");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 || ws_bytes < carve(nullptr, n, nullptr))
+    return sfail(SHP_ERR_WORKSPACE, "solver workspace missing, misaligned or too small");
+  if (int r = shp::plan_check_solve(plan, SHP_FP64)) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SolveWs w;
+  carve(ws, n, &w);
+  const dim3 g = grid_for(n), bl(256);
+  int maxm = 0;
+  {
+    std::vector<int> hm;
+    if (int r = shp::plan_mode_index(plan, hm)) return r;
+    for (long long i = 0; i < n; ++i) maxm = std::max(maxm, hm[i] + 1);
+    if (hipMemcpyAsync(w.mode, hm.data(), sizeof(int) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return sfail(SHP_ERR_DEVICE, "mode index upload");
+  }
+  // every element's H_e applied to its m-th unit vector at once; entry m of
+  // the result is H_e[m][m]
+  for (int m = 0; m < maxm; ++m) {
+    hipLaunchKernelGGL(k_unit, g, bl, 0, s, w.r, w.mode, m, n);
+    if (int r = shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, w.r, w.y, lambda, s)) return r;
+    hipLaunchKernelGGL(k_gather, g, bl, 0, s, w.y, w.mode, m, diag, n);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return sfail(SHP_ERR_DEVICE, "diagonal");
+  return SHP_OK;
+}
+
+int shp_helmholtz_solve(shp_plan plan, double lambda, const double* diag, const double* b, double* x, int inner_prec,
+                        double tol, int max_outer, int max_inner, double inner_tol, void* ws, size_t ws_bytes,
+                        shp_solve_stats* st, void* stream) {
+  if (!plan || !diag || !b || !x || !ws || !st) return sfail(SHP_ERR_INVALID_ARG, "null argument");
+  const long long n_dof = shp::plan_total_coeff(plan);
+  if (n_dof < 1) return sfail(SHP_ERR_INVALID_ARG, "empty mesh");
+  if (!(lambda > 0.0) || !(tol > 0.0) || !(inner_tol > 0.0) || max_outer < 1 || max_inner < 1)
+    return sfail(SHP_ERR_INVALID_ARG, "lambda, tolerances and iteration limits must be positive");
+  if (inner_prec == SHP_BF16) return sfail(SHP_ERR_UNSUPPORTED, "BF16 contractions are not built");
+  if (inner_prec != SHP_FP64 && inner_prec != SHP_FP32) return sfail(SHP_ERR_INVALID_ARG, "bad inner precision");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 || ws_bytes < carve(nullptr, n_dof, nullptr))
+    return sfail(SHP_ERR_WORKSPACE, "solver workspace missing, misaligned or too small");
+  if (int r = shp::plan_check_solve(plan, inner_prec)) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SolveWs w;
+  carve(ws, n_dof, &w);
+  const long long n = n_dof;
+  const dim3 g = grid_for(n), bl(256);
+  std::memset(st, 0, sizeof *st);
+  if (inner_prec == SHP_FP32) hipLaunchKernelGGL(k_to_float, g, bl, 0, s, diag, w.diagf, n);
+  // ||b||
+  if (int r = dot(b, b, n, w, BB, s)) return r;
+  double hs[NSLOT + 1];
+  int total_inner = 0;
+  for (int outer = 1; outer <= max_outer; ++outer) {
+    if (int r = shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, x, w.y, lambda, s)) return r;
+    // r = b - y, then its norm and max|r|
+    if (inner_prec == SHP_FP32)
+      hipLaunchKernelGGL(k_resid<float>, g, bl, 0, s, b, w.y, w.r, static_cast<float*>(w.vec), w.rmax, n, 0);
+    else
+      hipLaunchKernelGGL(k_resid<double>, g, bl, 0, s, b, w.y, w.r, static_cast<double*>(w.vec), w.rmax, n, 0);
+    if (int r = dot(w.r, w.r, n, w, RR, s)) return r;
+    if (hipMemsetAsync(w.rmax, 0, sizeof(unsigned long long), s) != hipSuccess)
+      return sfail(SHP_ERR_DEVICE, "solver memset");
+    hipLaunchKernelGGL(k_absmax, g, bl, 0, s, w.r, n, w.rmax);
+    if (hipMemcpyAsync(hs, w.slot, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return sfail(SHP_ERR_DEVICE, "solver readback");
+    if (!(hs[BB] > 0.0) || !std::isfinite(hs[BB]))
+      return sfail(SHP_ERR_INVALID_ARG, "b is zero or not finite (relative residual undefined)");
+    st->rel_residual = std::sqrt(hs[RR] / hs[BB]);
+    st->outer_iters = outer - 1;
+    st->inner_iters = total_inner;
+    if (st->rel_residual <= tol) {
+      st->converged = 1;
+      return SHP_OK;
+    }
+    // scaled residual in the inner precision, inner PCG, FP64 update
+    int it = 0;
+    if (inner_prec == SHP_FP32) {
+      hipLaunchKernelGGL(k_resid<float>, g, bl, 0, s, b, w.y, w.r, static_cast<float*>(w.vec), w.rmax, n, 1);
+      if (int r = inner_pcg<float>(plan, lambda, n, w, w.diagf, max_inner, inner_tol, &it, s)) return r;
+      hipLaunchKernelGGL(k_update_x<float>, g, bl, 0, s, x, static_cast<float*>(w.vec) + 4 * n, w.rmax, n);
+    } else {
+      hipLaunchKernelGGL(k_resid<double>, g, bl, 0, s, b, w.y, w.r, static_cast<double*>(w.vec), w.rmax, n, 1);
+      if (int r = inner_pcg<double>(plan, lambda, n, w, diag, max_inner, inner_tol, &it, s)) return r;
+      hipLaunchKernelGGL(k_update_x<double>, g, bl, 0, s, x, static_cast<double*>(w.vec) + 4 * n, w.rmax, n);
+    }
+    total_inner += it;
+  }
+  // final residual
+  if (int r = shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, x, w.y, lambda, s)) return r;
+  hipLaunchKernelGGL(k_resid<double>, g, bl, 0, s, b, w.y, w.r, static_cast<double*>(w.vec), w.rmax, n, 0);
+  if (int r = dot(w.r, w.r, n, w, RR, s)) return r;
+  if (hipMemcpyAsync(hs, w.slot, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return sfail(SHP_ERR_DEVICE, "solver readback");
+  st->rel_residual = std::sqrt(hs[RR] / hs[BB]);
+  st->outer_iters = max_outer;
+  st->inner_iters = total_inner;
+  st->converged = st->rel_residual <= tol;
+  return st->converged ? SHP_OK : sfail(SHP_ERR_NOT_CONVERGED, "iterative refinement did not reach the tolerance");
+}
+
+}  // extern "C"

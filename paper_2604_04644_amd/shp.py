@@ -17,6 +17,7 @@ SHAPES = {"hex": 0, "prism": 1, "pyr": 2, "tet": 3}
 GEOM = {"affine": 0, "curved": 1}
 OPS = {"bwd": 0, "iprod": 1, "physderiv": 2, "iprod_deriv": 3, "mass": 4, "laplacian": 5, "helmholtz": 6}
 STRATEGY = {"auto": 0, "sumfac": 1, "sumfac_coll": 2, "localmat": 3}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "BAD_GEOMETRY", -4: "WORKSPACE",
           -5: "STATE", -6: "DEVICE", -7: "NOT_CONVERGED"}
 
@@ -44,6 +45,14 @@ _SIGS = {
     "shp_set_auto_strategy": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int],
     "shp_tune_cache_save": [ctypes.c_void_p, ctypes.c_char_p],
     "shp_tune_cache_load": [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)],
+    "shp_apply_prec": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                       ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p],
+    "shp_solve_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "shp_helmholtz_diag": [ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                           ctypes.c_void_p],
+    "shp_helmholtz_solve": [ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
 }
 
 _lib = None
@@ -61,6 +70,11 @@ class TuneRecord(ctypes.Structure):
 
 
 STRATEGY_NAME = {v: k for k, v in {"auto": 0, "sumfac": 1, "sumfac_coll": 2, "localmat": 3}.items()}
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("inner_iters", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_residual", ctypes.c_double)]
 
 
 class ShpError(RuntimeError):
@@ -158,6 +172,7 @@ class Plan:
     def set_geometry(self, blk: int, jac):
         """jac: float64 device tensor [n][9][Q^3] (curved) or [n][9] (affine)."""
         t = self._torch
+        self.__dict__.pop("_diag", None)
         sh, P, ne, geom = self.blocks[blk]
         want = (ne, 9, (P + 2) ** 3) if geom == "curved" else (ne, 9)
         if tuple(jac.shape) != want or jac.dtype != t.float64 or not jac.is_cuda or not jac.is_contiguous():
@@ -207,6 +222,72 @@ class Plan:
         _check(lib().shp_apply(self._h, blk, OPS[op], STRATEGY[strategy], ctypes.c_void_p(x.data_ptr()),
                                ctypes.c_void_p(out.data_ptr()), float(lam), _stream(t)))
         return out
+
+    def apply_prec(self, op: str, x, out=None, lam: float = 1.0, prec: str = "fp32"):
+        """Whole-mesh collocated Laplacian/Helmholtz action with contractions in
+        prec; x and out are float32 (fp32) or float64 (fp64) device tensors."""
+        t = self._torch
+        dt = {"fp64": t.float64, "fp32": t.float32}.get(prec)
+        if dt is None:
+            raise ShpError(-2, f"precision {prec} is not built")
+        if x.dtype != dt or not x.is_cuda or not x.is_contiguous():
+            raise ValueError(f"x must be a contiguous {dt} device tensor")
+        if x.numel() != self._in_numel(-1, op):
+            raise ValueError(f"x has {x.numel()} values, {op} takes {self._in_numel(-1, op)}")
+        if out is None:
+            out = t.empty(self._out_shape(-1, op), dtype=dt, device=x.device)
+        elif out.dtype != dt or not out.is_contiguous() or out.numel() != x.numel():
+            raise ValueError("bad output tensor")
+        _check(lib().shp_apply_prec(self._h, -1, OPS[op], STRATEGY["sumfac_coll"], PREC[prec],
+                                    ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), float(lam),
+                                    _stream(t)))
+        return out
+
+    def _solve_ws(self, device):
+        nb = ctypes.c_size_t()
+        _check(lib().shp_solve_workspace_bytes(self._h, ctypes.byref(nb)))
+        ws = getattr(self, "_sws", None)
+        if ws is None or ws.numel() < nb.value + 256:
+            ws = self._sws = self._torch.empty(nb.value + 256, dtype=self._torch.uint8, device=device)
+        return ctypes.c_void_p((ws.data_ptr() + 255) // 256 * 256), nb.value
+
+    def helmholtz_diag(self, lam: float = 1.0):
+        """diag(lam M + L) of every element in the whole-mesh layout (FP64,
+        device), cached per lam until the geometry changes."""
+        t = self._torch
+        cache = self.__dict__.setdefault("_diag", {})
+        if lam not in cache:
+            nc, _ = self.totals()
+            d = t.empty(nc, dtype=t.float64, device=self.device)
+            ws, nb = self._solve_ws(self.device)
+            _check(lib().shp_helmholtz_diag(self._h, float(lam), ctypes.c_void_p(d.data_ptr()), ws, nb, _stream(t)))
+            cache[lam] = d
+        return cache[lam]
+
+    def solve(self, b, x=None, lam: float = 1.0, inner: str = "fp32", tol: float = 1e-10, max_outer: int = 20,
+              max_inner: int = 500, inner_tol: float = 1e-3, check: bool = True):
+        """Solve (lam M + L) x = b on every element (FP64 iterative refinement
+        around an inner Jacobi-PCG in `inner` precision).  Returns (x, stats)."""
+        t = self._torch
+        nc, _ = self.totals()
+        if b.dtype != t.float64 or not b.is_cuda or not b.is_contiguous() or b.numel() != nc:
+            raise ValueError("b must be a contiguous float64 device tensor of all coefficients")
+        if x is None:
+            x = t.zeros_like(b)
+        elif x.dtype != t.float64 or not x.is_contiguous() or x.numel() != nc:
+            raise ValueError("bad initial guess")
+        diag = self.helmholtz_diag(lam)
+        ws, nb = self._solve_ws(b.device)
+        st = SolveStats()
+        code = lib().shp_helmholtz_solve(self._h, float(lam), ctypes.c_void_p(diag.data_ptr()),
+                                         ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), PREC[inner],
+                                         float(tol), int(max_outer), int(max_inner), float(inner_tol), ws, nb,
+                                         ctypes.byref(st), _stream(t))
+        stats = {"outer_iters": st.outer_iters, "inner_iters": st.inner_iters, "converged": bool(st.converged),
+                 "rel_residual": st.rel_residual}
+        if code != 0 and (check or code != -7):
+            _check(code)
+        return x, stats
 
     def set_tiling(self, blk: int, op: str, E: int, NT: int, persistent: int = 1, strategy: str = "sumfac_coll"):
         _check(lib().shp_set_tiling(self._h, blk, OPS[op], STRATEGY[strategy], E, NT, persistent))

@@ -228,6 +228,24 @@ def jacobian_torch(maps: ElementMaps, xi: np.ndarray, curved: bool, device, amp:
     return out
 
 
+def manufactured_u_torch(maps: ElementMaps, xi: np.ndarray, device, amp: float = AMP, chunk: int = 65536):
+    """manufactured_u at the curved coordinates x(xi), evaluated with torch on a
+    device: float64 tensor [n_elem][n_pts]."""
+    import torch
+    xi_t = torch.as_tensor(np.asarray(xi, dtype=np.float64), device=device)
+    ne, npts = len(maps), xi_t.shape[0]
+    out = torch.empty((ne, npts), dtype=torch.float64, device=device)
+    t = 0.5 * (1.0 + xi_t)
+    for e0 in range(0, ne, chunk):
+        e1 = min(ne, e0 + chunk)
+        A = torch.as_tensor(maps.A[e0:e1], device=device)
+        x0 = torch.as_tensor(maps.x0[e0:e1], device=device)
+        X = x0[:, None, :] + torch.einsum("eij,pj->epi", A, t)
+        X = X + amp * torch.prod(torch.sin(2 * np.pi * X), dim=-1, keepdim=True)
+        out[e0:e1] = torch.prod(torch.sin(np.pi * X), dim=-1)
+    return out
+
+
 def affine_jacobian(maps: ElementMaps) -> np.ndarray:
     """Constant d x_i / d xi_j of straight-sided elements, layout [n_elem][9]."""
     return np.ascontiguousarray((0.5 * maps.A).reshape(len(maps), 9))

@@ -115,5 +115,34 @@ def test_error_paths_without_device(L):
     c, q = ctypes.c_int64(), ctypes.c_int64()
     assert L.shp_block_offsets(h, 1, ctypes.byref(c), ctypes.byref(q)) == 0
     assert (c.value, q.value) == (10 * 125, 10 * 216)
+    # precision and solver validation (no device call is reached)
+    assert L.shp_apply_prec(h, -1, 6, 2, 2, p, p, 1.0, None) == -2    # BF16 not built
+    assert L.shp_apply_prec(h, -1, 6, 2, 5, p, p, 1.0, None) == -1    # bad precision
+    assert L.shp_apply_prec(h, -1, 4, 2, 1, p, p, 1.0, None) == -2    # FP32 mass
+    assert L.shp_apply_prec(h, 0, 6, 2, 1, p, p, 1.0, None) == -2     # FP32 per block
+    assert L.shp_apply_prec(h, -1, 6, 1, 1, p, p, 1.0, None) == -2    # FP32 non-collocated
+    assert L.shp_apply_prec(h, -1, 6, 2, 1, p, p, 1.0, None) == -5    # no workspace
+    sb = ctypes.c_size_t()
+    assert L.shp_solve_workspace_bytes(h, ctypes.byref(sb)) == 0
+    ncoef = 10 * 125 + 7 * 35
+    assert sb.value >= ncoef * (2 * 8 + 4 + 5 * 8 + 4)
+    st = shp.SolveStats()
+    ws = ctypes.c_void_p(256 * 1000)
+
+    def solve(lam=1.0, prec=1, tol=1e-10, mo=10, mi=100, itol=1e-3, w=ws, nbytes=sb.value):
+        return L.shp_helmholtz_solve(h, lam, p, p, p, prec, tol, mo, mi, itol, w, nbytes, ctypes.byref(st), None)
+    assert solve(prec=2) == -2                                    # BF16 not built
+    assert solve(prec=4) == -1
+    assert solve(lam=0.0) == -1                                   # H only semidefinite
+    assert solve(tol=0.0) == -1
+    assert solve(mo=0) == -1
+    assert solve(w=None) == -1
+    assert solve(w=ctypes.c_void_p(256 * 1000 + 64)) == -4        # misaligned
+    assert solve(nbytes=sb.value - 1) == -4
+    assert solve() == -5                                          # no workspace bound
+    assert L.shp_helmholtz_diag(h, 1.0, None, ws, sb.value, None) == -1
+    assert L.shp_helmholtz_diag(h, float("inf"), p, ws, sb.value, None) == -1
+    assert L.shp_helmholtz_diag(h, 1.0, p, ws, sb.value - 8, None) == -4
+    assert L.shp_helmholtz_diag(h, 1.0, p, ws, sb.value, None) == -5
     assert L.shp_plan_destroy(h) == 0
     assert L.shp_plan_destroy(None) == -1

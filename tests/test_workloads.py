@@ -21,3 +21,12 @@ def test_torch_jacobian_matches_numpy():
         a = W.jacobian(maps, xi, curved)
         b = W.jacobian_torch(maps, xi, curved, "cpu", chunk=10).numpy()
         assert np.abs(a - b).max() < 1e-14
+
+
+def test_torch_manufactured_u_matches_numpy():
+    torch = pytest.importorskip("torch")
+    maps = W.shape_batch("tet", 23)
+    xi = np.random.default_rng(1).uniform(-1, 1, size=(17, 3))
+    a = W.manufactured_u(W.coords(maps, xi, curved=True))
+    b = W.manufactured_u_torch(maps, xi, "cpu", chunk=7).numpy()
+    assert np.abs(a - b).max() < 1e-14
