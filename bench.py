@@ -8,9 +8,12 @@ whole-mesh action; roofline = algorithmic HBM bytes of the launch (16 N_P + 56
 N_Q bytes per element: x, y and 7 FP64 geometric factors per point) over the
 launch's mean duration from HIP events on the launch stream, against the 8 TB/s
 HBM3E peak; cpu_baseline = the FP64 oracle (dense elemental matrices) on a
-bounded sample of the same mesh.
+bounded sample of the same mesh; mixed_vs_fp64 = the mixed-precision leg on the
+same mesh at P = 6 (FP32 vs FP64 action, and the Helmholtz solve by FP64
+iterative refinement around FP32 PCG vs plain FP64 PCG at the residual
+tolerances of the 1e-6 and 1e-10 error targets).
 
-    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu] [--no-mixed]
 """
 from __future__ import annotations
 
@@ -38,16 +41,18 @@ def bytes_per_elem(n_modes: int, n_points: int) -> int:
     return 16 * n_modes + 56 * n_points
 
 
+KERNEL_SOURCES = ("shp_kernels.hpp", "shp_layout.hpp", "shp_k_mixed_p.inc", "shp_k_mixed_p4.hip")
+
+
 def kernel_source_hash() -> str:
-    """sha256[:16] of the HIP/C++ sources of libshp (names and contents)."""
-    import glob
+    """sha256[:16] of the sources that define the benchmarked whole-mesh
+    Helmholtz kernel at P = 4 (names and contents)."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_04644_amd", "csrc", "*"))):
-        if f.endswith((".hpp", ".hip", ".inc", ".cpp")):
-            h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2604_04644_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -63,12 +63,20 @@ __global__ void k_dot_final(const double* __restrict__ part, int np, double* __r
   }
 }
 
+// max |a| as the bit pattern of a non-negative double (ordered like an
+// unsigned integer): reduced within the work-group, one atomic per group
 __global__ void k_absmax(const double* __restrict__ a, long long n, unsigned long long* __restrict__ out) {
+  __shared__ double sh[256];
   double m = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     m = fmax(m, fabs(a[i]));
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sh[0]));
 }
 
 // r = b - y (FP64); rs = s r in the inner precision, s = 1 / max|r| from slot RMAX
@@ -314,7 +322,7 @@ int shp_helmholtz_solve(shp_plan plan, double lambda, const double* diag, const 
     if (int r = dot(w.r, w.r, n, w, RR, s)) return r;
     if (hipMemsetAsync(w.rmax, 0, sizeof(unsigned long long), s) != hipSuccess)
       return sfail(SHP_ERR_DEVICE, "solver memset");
-    hipLaunchKernelGGL(k_absmax, g, bl, 0, s, w.r, n, w.rmax);
+    hipLaunchKernelGGL(k_absmax, dim3(NB), bl, 0, s, w.r, n, w.rmax);
     if (hipMemcpyAsync(hs, w.slot, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return sfail(SHP_ERR_DEVICE, "solver readback");
