@@ -119,14 +119,16 @@ bool is_localmat(int opk) { return opk >= OPK_MASS_LM; }
 bool out_is_modes(int opk) { return !(opk == OPK_BWD || opk == OPK_DERIV); }
 
 // Default launch shape: as many elements per work-group as fit a 40 KiB LDS
-// budget (at most 16; several work-groups share a CU), 256 threads, persistent
-// work-groups for the Laplacian and Helmholtz actions when the metric stage's
-// points fit the register slots.
+// budget (at most 16; several work-groups share a CU), 256 threads, and for
+// the Laplacian and Helmholtz actions the geometry-prefetch launch with at most
+// 4 points per thread (8 register slots of 7 factors cost occupancy).
 Tiling default_tiling(int sh, int P, int opk) {
   Tiling t;
   t.NT = 256;
+  const bool helm = (opk == OPK_HELM || opk == OPK_LAP);
+  const long long Q3 = (long long)(P + 2) * (P + 2) * (P + 2);
   int E = 1;
-  while (E < 16 && op_lds_bytes(sh, P, opk, E + 1, 2) <= 40 * 1024) ++E;
+  while (E < 16 && op_lds_bytes(sh, P, opk, E + 1, 2) <= 40 * 1024 && (!helm || (E + 1) * Q3 <= 4LL * t.NT)) ++E;
   t.E = E;
   t.persist = points_per_thread((long long)E * (P + 2) * (P + 2) * (P + 2), t.NT) > 0 ? 2 : 0;
   return t;

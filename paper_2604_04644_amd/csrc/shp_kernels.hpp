@@ -501,6 +501,151 @@ __device__ void grad3T(const Tile_<SH, P, R>& T, int ne) {
 }
 
 // ---------------------------------------------------------------------------
+// merged and fused line stages of the Laplacian / Helmholtz tile
+// ---------------------------------------------------------------------------
+// The stages below do the same arithmetic per output as bwd_p, grad_dir and
+// ipr_p (same operands, same order), so their results are bitwise those of the
+// separate stages; they decompose each task index once and keep several lines
+// of LDS reads in flight.
+
+// bwd_p (G2 -> U) and, from the U line still in registers, the eta1
+// derivative G0 = D_0 U: one task per (e, j, k)
+template <int SH, int P, typename R>
+__device__ void bwd_p_grad0(const Tile_<SH, P, R>& T, int ne) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const ctab<R> A1 = launder(T.ct) + D::L.A1;
+    const int e = t / (Q * Q);
+    const int rem = t - e * (Q * Q);
+    const int j = rem / Q, k = rem - j * Q;
+    const int o = j * QP + k;
+    const R* G = T.G(e, 2) + o;
+    R g[n];
+#pragma unroll
+    for (int p = 0; p < n; ++p) g[p] = G[p * Q * QP];
+    R u[Q];
+    R* U = T.U(e) + o;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      R s = 0.0;
+#pragma unroll
+      for (int p = 0; p < n; ++p) s = fma(A1[p * Q + i], g[p], s);
+      u[i] = s;
+      U[i * Q * QP] = s;
+    }
+    const ctab<R> Dm = launder(T.ct) + D::L.D;
+    R* g0 = T.G(e, 0) + o;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      R s = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) s = fma(Dm[i * Q + l], u[l], s);
+      g0[i * Q * QP] = s;
+    }
+  }
+}
+
+// eta2 and eta3 collocation derivatives in one task loop: G_d = D_d U
+// (TRANS = false) or G_d <- D_d^T G_d in place (TRANS = true), d = 1, 2;
+// task (e, a, b) is the j-line at (i, k) = (a, b) and the k-line at
+// (i, j) = (a, b)
+template <int SH, int P, bool TRANS, typename R>
+__device__ void grad12(const Tile_<SH, P, R>& T, int ne) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, QP = D::QP;
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const int e = t / (Q * Q);
+    const int r2 = t - e * (Q * Q);
+    const int a = r2 / Q, b = r2 - a * Q;
+    const int o1 = a * Q * QP + b, o2 = (a * Q + b) * QP;
+    const R* s1 = (TRANS ? T.G(e, 1) : T.U(e)) + o1;
+    const R* s2 = (TRANS ? T.G(e, 2) : T.U(e)) + o2;
+    R v1[Q], v2[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      v1[l] = s1[l * QP];
+      v2[l] = s2[l];
+    }
+    {
+      const ctab<R> Dm = launder(T.ct) + D::L.D + 1 * Q * Q;
+      R* g = T.G(e, 1) + o1;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        R s = 0.0;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) s = fma(TRANS ? Dm[l * Q + i] : Dm[i * Q + l], v1[l], s);
+        g[i * QP] = s;
+      }
+    }
+    {
+      const ctab<R> Dm = launder(T.ct) + D::L.D + 2 * Q * Q;
+      R* g = T.G(e, 2) + o2;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        R s = 0.0;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) s = fma(TRANS ? Dm[l * Q + i] : Dm[i * Q + l], v2[l], s);
+        g[i] = s;
+      }
+    }
+  }
+}
+
+// the eta1 transposed derivative D_0^T G0 kept in registers and summed with
+// U (mask bit 0), G1 and G2 in ipr_p's order, then stage p^T into U
+template <int SH, int P, typename R>
+__device__ void grad0T_ipr_p(const Tile_<SH, P, R>& T, int ne, bool with_u) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, n = D::n, QP = D::QP;
+  for (int t = tid(); t < ne * Q * Q; t += nthr()) {
+    const int e = t / (Q * Q);
+    const int rem = t - e * (Q * Q);
+    const int j = rem / Q, k = rem - j * Q;
+    const int o = j * QP + k;
+    R v[Q], u[Q], w1[Q], w2[Q];
+    {
+      const R* g0 = T.G(e, 0) + o;
+      const R* pu = T.U(e) + o;
+      const R* g1 = T.G(e, 1) + o;
+      const R* g2 = T.G(e, 2) + o;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) {
+        v[l] = g0[l * Q * QP];
+        if (with_u) u[l] = pu[l * Q * QP];
+        w1[l] = g1[l * Q * QP];
+        w2[l] = g2[l * Q * QP];
+      }
+    }
+    R s[Q];
+    {
+      const ctab<R> Dm = launder(T.ct) + D::L.D;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        R d0 = 0.0;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) d0 = fma(Dm[l * Q + i], v[l], d0);
+        R a = 0.0;
+        if (with_u) a += u[i];
+        a += d0;
+        a += w1[i];
+        a += w2[i];
+        s[i] = a;
+      }
+    }
+    const ctab<R> A1 = launder(T.ct) + D::L.A1;
+    R* G = T.U(e) + o;
+#pragma unroll
+    for (int p = 0; p < n; ++p) {
+      R a = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) a = fma(A1[p * Q + i], s[i], a);
+      G[p * Q * QP] = a;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // global <-> LDS
 // ---------------------------------------------------------------------------
 
@@ -808,8 +953,14 @@ __device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH,
   if (tables) load_tables<SH, P>(a, T);
   load_modes<SH, P>(T, reinterpret_cast<const R*>(a.in), e0, ne, 0);
   __syncthreads();
-  bwd_chain<SH, P>(T, ne);
-  grad3<SH, P>(T, ne);
+  // modes in G0 -> F in G1 -> G in G2 -> U, with G0 = D_0 U from the same task
+  bwd_r<SH, P, false>(T, ne, 0, 1);
+  __syncthreads();
+  bwd_q<SH, P, false>(T, ne, 1, 2);
+  __syncthreads();
+  bwd_p_grad0<SH, P>(T, ne);
+  __syncthreads();
+  grad12<SH, P, false>(T, ne);
   __syncthreads();
   const double lam = (OP == OPK_HELM) ? a.lambda : 0.0;
 #pragma unroll
@@ -834,9 +985,15 @@ __device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH,
   }
   next();  // registers of this tile's geometry are dead: start the next tile's loads
   __syncthreads();
-  grad3T<SH, P>(T, ne);
+  grad12<SH, P, true>(T, ne);
   __syncthreads();
-  ipr_chain<SH, P>(T, ne, (OP == OPK_HELM ? 1 : 0) | 2 | 4 | 8);
+  // points -> modes: stage p^T (with D_0^T) into U, q^T into G0, r^T into G1
+  grad0T_ipr_p<SH, P>(T, ne, OP == OPK_HELM);
+  __syncthreads();
+  ipr_q<SH, P, false>(T, ne, -1, 0);
+  __syncthreads();
+  ipr_r<SH, P, false>(T, ne, 0, 1, false);
+  __syncthreads();
   store_modes<SH, P>(T, reinterpret_cast<R*>(a.out), e0, ne, 1);
 }
 

@@ -41,9 +41,13 @@ constexpr int kappa3(int sh, int p, int q) {
 constexpr int alpha_dir(int sh, int d) {
   return d == 0 ? 0 : d == 1 ? (sh == TET ? 1 : 0) : (sh == HEX ? 0 : sh == PRISM ? 1 : 2);
 }
-// padded innermost stride of point buffers in LDS (odd, avoids bank conflicts
-// of FP64 lanes that walk lines along eta3)
-constexpr int qpad(int Q) { return (Q % 2 == 0) ? Q + 1 : Q; }
+// innermost stride of point buffers in LDS.  FP64 LDS accesses are served 32
+// lanes at a time by 32 double-wide banks; the line stages walk i-, j- and
+// k-lines from consecutive task indices.  Over all stage patterns a model of
+// the bank conflicts favours padding to Q+1 only for Q = 4 and 8 (unpadded
+// strides of 4 and 8 put 4-8 k-line lanes on one bank); Q = 6, 10 and 12 do
+// better unpadded, and odd Q need no padding.
+constexpr int qpad(int Q) { return (Q == 4 || Q == 8) ? Q + 1 : Q; }
 
 // Reference tables of one (shape, P), Q = P + 2, laid out in one FP64 array:
 //   z[3][Q]          points per direction
