@@ -132,6 +132,21 @@ __device__ void load_tables(const OpArgs& a, const Tile_<SH, P, R>& T) {
   for (int t = tid(); t < D::NITAB; t += nthr()) T.itab[t] = a.itab[t];
 }
 
+// The part of the tables the collocated Laplacian / Helmholtz tile reads from
+// LDS: the collapsed shapes' eta3 table C3 and column table, and the tet's
+// eta2 table B2 (lane-uniform tables are read through the constant path).
+template <int SH, int P, typename R>
+__device__ void load_tables_helm(const OpArgs& a, const Tile_<SH, P, R>& T) {
+  using D = Dims<SH, P>;
+  if (SH == HEX) return;
+  constexpr int nc3 = D::L.nc3 * D::Q, nb2 = (SH == TET) ? D::L.nb2 * D::Q : 0;
+  for (int t = tid(); t < nc3 + nb2; t += nthr()) {
+    const int o = t < nc3 ? D::L.C3 + t : D::L.B2 + (t - nc3);
+    T.tab[o] = (R)a.tab[o];
+  }
+  for (int t = tid(); t < D::NITAB; t += nthr()) T.itab[t] = a.itab[t];
+}
+
 // ---------------------------------------------------------------------------
 // modes -> points
 // ---------------------------------------------------------------------------
@@ -172,10 +187,13 @@ __device__ void bwd_r(const Tile_<SH, P, R>& T, int ne, int xbuf, int fbuf) {
     R acc[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) acc[k] = 0.0;
-    for (int r = 0; r < RL; ++r) {
-      const R xr = x[off + r];
 #pragma unroll
-      for (int k = 0; k < Q; ++k) acc[k] = fma(cf[r * Q + k], xr, acc[k]);
+    for (int r = 0; r < n; ++r) {
+      if (r < RL) {
+        const R xr = x[off + r];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) acc[k] = fma(cf[r * Q + k], xr, acc[k]);
+      }
     }
     // collapsed-vertex modes: extra eta3 term v1 in columns p = 1 (and q = 1)
     R xe = 0.0;
@@ -237,11 +255,14 @@ __device__ void bwd_q(const Tile_<SH, P, R>& T, int ne, int fbuf, int gbuf) {
     R acc[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) acc[j] = 0.0;
-    for (int q = 0; q < nq; ++q) {
-      const R fv = F[(cb + q) * QP + k];
-      const R* b = B2 + (bfam + q) * Q;
 #pragma unroll
-      for (int j = 0; j < Q; ++j) acc[j] = fma(b[j], fv, acc[j]);
+    for (int q = 0; q < n; ++q) {
+      if (q < nq) {
+        const R fv = F[(cb + q) * QP + k];
+        const R* b = B2 + (bfam + q) * Q;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) acc[j] = fma(b[j], fv, acc[j]);
+      }
     }
     if (p == 1) {
       const R fv = F[1 * QP + k];  // column (0,1)
@@ -361,7 +382,9 @@ __device__ void ipr_q(const Tile_<SH, P, R>& T, int ne, int gbuf, int fbuf) {
     const int nq = nq_of(SH, P, p), cb = col_base(SH, P, p);
     const int bfam = fam_index(P, p, 0);
     R* F = T.G(e, fbuf);
-    for (int q = 0; q < nq; ++q) {
+#pragma unroll
+    for (int q = 0; q < n; ++q) {
+      if (q >= nq) continue;
       const R* b = B2 + (bfam + q) * Q;
       R a = 0.0;
 #pragma unroll
@@ -416,7 +439,9 @@ __device__ void ipr_r(const Tile_<SH, P, R>& T, int ne, int fbuf, int ybuf, bool
     for (int k = 0; k < Q; ++k) f[k] = F[c * QP + k];
     R* y = (ybuf < 0 ? T.U(e) : T.G(e, ybuf)) + off;
     const R* cf = C3 + fb * Q;
-    for (int r = 0; r < RL; ++r) {
+#pragma unroll
+    for (int r = 0; r < n; ++r) {
+      if (r >= RL) continue;
       R a = 0.0;
 #pragma unroll
       for (int k = 0; k < Q; ++k) a = fma(cf[r * Q + k], f[k], a);
@@ -950,7 +975,7 @@ __device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH,
                           bool tables, Next next) {
   using D = Dims<SH, P>;
   constexpr int Q3 = D::Q3;
-  if (tables) load_tables<SH, P>(a, T);
+  if (tables) load_tables_helm<SH, P>(a, T);
   load_modes<SH, P>(T, reinterpret_cast<const R*>(a.in), e0, ne, 0);
   __syncthreads();
   // modes in G0 -> F in G1 -> G in G2 -> U, with G0 = D_0 U from the same task
