@@ -108,8 +108,9 @@ def mixed_precision_leg(torch, shp, W, ncell: int = 32, P: int = 6, lam: float =
     """Mixed precision on the mixed mesh at P = 6: the Helmholtz action with FP32
     contractions against FP64, and the Helmholtz solve with a manufactured
     right-hand side (u = sin(pi x) sin(pi y) sin(pi z), b = IProduct((lambda +
-    3 pi^2) u)) by FP64 iterative refinement around an FP32 Jacobi-PCG against
-    a plain FP64 Jacobi-PCG, to the same FP64 relative residual."""
+    3 pi^2) u)) by an FP32 Jacobi-PCG with FP64 reliable updates (residual
+    replacement and solution update in FP64) against the same iteration run in
+    FP64, to the same FP64 relative residual."""
     log(f"mixed precision: mesh ncell={ncell} P={P}")
     mesh = W.quadrant_mesh(ncell)
     dev = torch.device("cuda")
@@ -145,8 +146,8 @@ def mixed_precision_leg(torch, shp, W, ncell: int = 32, P: int = 6, lam: float =
     for target, tol in ((1e-6, 1e-9), (1e-10, 2e-11)):
         row = {}
         sols = {}
-        for name, kw in (("fp64", dict(inner="fp64", inner_tol=0.5 * tol, max_outer=3, max_inner=20000)),
-                         ("mixed", dict(inner="fp32", inner_tol=1e-3, max_outer=12, max_inner=5000))):
+        for name, kw in (("fp64", dict(inner="fp64", max_outer=100, max_inner=30000)),
+                         ("mixed", dict(inner="fp32", max_outer=100, max_inner=30000))):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             xs, st = plan.solve(b, lam=lam, tol=tol, check=False, **kw)
@@ -161,9 +162,9 @@ def mixed_precision_leg(torch, shp, W, ncell: int = 32, P: int = 6, lam: float =
         solves[f"err_target_{target:g}"] = row
     return {"workload": f"mixed-element mesh {ncell}^3 cells, curved, P={P}, Q={P + 2}, lambda={lam}",
             "dof": int(nc), "action": action, "diag_setup_s": round(t_diag, 4), "solve": solves,
-            "note": "solve: FP64 residual and update, inner Jacobi-PCG in FP32 (mixed) or FP64 (plain, one "
-                    "inner solve to the tolerance); wall time per solve including host checks; error against "
-                    "the FP64 oracle is asserted by the test suite on sampled elements"}
+            "note": "solve: Jacobi-PCG in FP32 (mixed) or FP64 (plain), FP64 residual replacement and solution "
+                    "update every decade of residual reduction; wall time per solve including host checks; "
+                    "error against the FP64 oracle is asserted by the test suite on sampled elements"}
 
 
 def cpu_baseline(mesh, P: int, budget_s: float = 15.0):

@@ -171,25 +171,34 @@ int shp_solve_workspace_bytes(shp_plan plan, size_t* bytes /* host out */);
 int shp_helmholtz_diag(shp_plan plan, double lambda, double* diag /* device out */, void* ws /* device */,
                        size_t ws_bytes, void* stream);
 
-/* Iterative refinement: the residual r = b - H x and the update x += d are
- * FP64 (FP64 collocated action); each correction d solves H d = r with a
- * Jacobi-preconditioned conjugate-gradient iteration whose operator actions,
- * vectors and updates run in inner_prec (SHP_FP32 through shp_apply_prec, or
- * SHP_FP64), with FP64 dot products.  The residual is scaled by 1/max|r|
- * before it enters the inner precision.
+/* Mixed-precision solve: a Jacobi-preconditioned conjugate-gradient iteration
+ * whose operator actions, vectors and updates run in inner_prec (SHP_FP32
+ * through shp_apply_prec, or SHP_FP64) with FP64 dot products, refined in FP64
+ * by reliable updates: whenever the recursive residual has fallen by the factor
+ * inner_tol since the last update (or predicts the tolerance), the correction
+ * accumulated in inner_prec is added to x in FP64 and the residual is replaced
+ * by r = b - H x from the FP64 action; the iteration then continues from it
+ * with its search direction kept, or restarts the direction when the true
+ * residual exceeds the recursive one twice over (rounding near the floor of
+ * the FP64 residual).  The residual enters the inner precision scaled by
+ * 1/max|r_0|.  An update that does not lower the FP64 residual is undone
+ * (the direction restarts from the previous x); five in a row end the solve,
+ * as do max_outer updates or max_inner iterations, and x then holds the
+ * iterate with the smallest FP64 residual.  Updates come at least every 2000
+ * iterations.
  *
  * diag: from shp_helmholtz_diag with the same lambda.  b, x: device FP64
  * arrays [total coefficients] in the whole-mesh layout; x holds the initial
  * guess on entry and the solution on return.  Stops when ||b - H x||_2 <= tol
- * ||b||_2 (checked before every outer step), after max_outer outer steps, or
- * on error.  The inner iteration stops when its recursive residual has fallen
- * by inner_tol (checked every 10 iterations) or after max_inner iterations.
- * Returns SHP_ERR_NOT_CONVERGED (stats filled in) when the tolerance is not
- * reached, SHP_ERR_INVALID_ARG for b = 0, SHP_ERR_UNSUPPORTED for SHP_BF16 or
- * an FP32 request on a plan with more than one P. */
+ * ||b||_2 for the FP64 residual (checked on entry and at every update), after
+ * max_outer updates or max_inner iterations in all (convergence is tested
+ * every 10 iterations), or on error.  Returns SHP_ERR_NOT_CONVERGED (stats
+ * filled in) when the tolerance is not reached, SHP_ERR_INVALID_ARG for b = 0,
+ * SHP_ERR_UNSUPPORTED for SHP_BF16 or an FP32 request on a plan with more than
+ * one P. */
 typedef struct {
-  int outer_iters;     /* refinement steps taken */
-  int inner_iters;     /* inner CG iterations, summed over the steps */
+  int outer_iters;     /* reliable updates (FP64 residual replacements) taken */
+  int inner_iters;     /* CG iterations in all */
   int converged;       /* 1 when ||b - H x|| <= tol ||b|| */
   double rel_residual; /* final ||b - H x||_2 / ||b||_2, FP64 action */
 } shp_solve_stats;

@@ -167,7 +167,7 @@ inline dim3 grid_for(long long n) { return dim3((unsigned)std::min<long long>((n
 int sfail(int code, const char* msg) { return shp::set_error(code, msg); }
 
 struct SolveWs {
-  double *r, *y, *slot, *part;
+  double *r, *y, *xb, *slot, *part;
   float* diagf;
   void* vec;  // inner vectors: rs, z, p, q, d (5 n of the inner type)
   int* mode;
@@ -187,6 +187,7 @@ size_t carve(void* base, long long n, SolveWs* w) {
   SolveWs s{};
   s.r = reinterpret_cast<double*>(take(sizeof(double) * n));
   s.y = reinterpret_cast<double*>(take(sizeof(double) * n));
+  s.xb = reinterpret_cast<double*>(take(sizeof(double) * n));
   s.diagf = reinterpret_cast<float*>(take(sizeof(float) * n));
   s.vec = take(sizeof(double) * 5 * n);
   s.mode = reinterpret_cast<int*>(take(sizeof(int) * n));
@@ -210,40 +211,120 @@ int apply_inner(shp_plan plan, const T* in, T* out, double lambda, hipStream_t s
   return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, prec, in, out, lambda, s);
 }
 
+// FP64 true residual r = b - H x of the current x, its squared norm into slot
+// RR, and (when T is the inner type) the scaled copy rs = r / rmax in T
 template <typename T>
-int inner_pcg(shp_plan plan, double lambda, long long n, SolveWs& w, const T* dg, int max_inner, double inner_tol,
-              int* iters, hipStream_t s) {
+int true_residual(shp_plan plan, double lambda, const double* b, const double* x, long long n, SolveWs& w,
+                  bool scaled, hipStream_t s) {
+  const dim3 g = grid_for(n), bl(256);
+  if (int r = shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, x, w.y, lambda, s)) return r;
+  hipLaunchKernelGGL(k_resid<T>, g, bl, 0, s, b, w.y, w.r, static_cast<T*>(w.vec), w.rmax, n, 0);
+  if (scaled) hipLaunchKernelGGL(k_resid<T>, g, bl, 0, s, b, w.y, w.r, static_cast<T*>(w.vec), w.rmax, n, 1);
+  return dot(w.r, w.r, n, w, RR, s);
+}
+
+// Jacobi-preconditioned CG whose actions, vectors and updates run in T, with
+// reliable updates: every time the recursive residual has fallen by the factor
+// delta since the last update (checked every 10 iterations), the correction
+// accumulated in T is added to x in FP64, the residual is recomputed as
+// b - H x with the FP64 action, and the CG recursion continues from it with
+// its search direction kept.  Convergence is decided on that FP64 residual.
+template <typename T>
+int pcg_reliable(shp_plan plan, double lambda, const double* b, double* x, long long n, SolveWs& w, const T* dg,
+                 double tol, int max_updates, int max_iter, double delta, double bnorm2, shp_solve_stats* st,
+                 hipStream_t s) {
   T* rs = static_cast<T*>(w.vec);
   T* z = rs + n;
   T* p = z + n;
   T* q = p + n;
   T* d = q + n;
-  const dim3 g = grid_for(n), b(256);
-  hipLaunchKernelGGL(k_zero<T>, g, b, 0, s, d, n);
-  hipLaunchKernelGGL(k_jacobi<T>, g, b, 0, s, rs, dg, z, n);
-  hipLaunchKernelGGL(k_copy<T>, g, b, 0, s, z, p, n);
+  const dim3 g = grid_for(n), bl(256);
+  double h[NSLOT + 1];
+  auto readback = [&]() {
+    return hipMemcpyAsync(h, w.slot, sizeof h, hipMemcpyDeviceToHost, s) == hipSuccess &&
+           hipStreamSynchronize(s) == hipSuccess;
+  };
+  // the scale 1/max|r0| is fixed for the whole solve (w.rmax)
+  if (hipMemsetAsync(w.rmax, 0, sizeof(unsigned long long), s) != hipSuccess)
+    return sfail(SHP_ERR_DEVICE, "solver memset");
+  hipLaunchKernelGGL(k_absmax, dim3(NB), bl, 0, s, w.r, n, w.rmax);
+  hipLaunchKernelGGL(k_resid<T>, g, bl, 0, s, b, w.y, w.r, rs, w.rmax, n, 1);
+  hipLaunchKernelGGL(k_zero<T>, g, bl, 0, s, d, n);
+  hipLaunchKernelGGL(k_jacobi<T>, g, bl, 0, s, rs, dg, z, n);
+  hipLaunchKernelGGL(k_copy<T>, g, bl, 0, s, z, p, n);
   if (int r = dot(rs, z, n, w, RZ, s)) return r;
   if (int r = dot(rs, rs, n, w, RR0, s)) return r;
-  double h0[NSLOT + 1];
-  int it = 0;
-  for (it = 1; it <= max_inner; ++it) {
+  if (!readback()) return sfail(SHP_ERR_DEVICE, "solver readback");
+  double rr_ref = h[RR0];
+  // the scale, to turn the recursive residual into an estimate of ||b - H x||
+  unsigned long long rbits = 0;
+  if (hipMemcpy(&rbits, w.rmax, sizeof rbits, hipMemcpyDeviceToHost) != hipSuccess)
+    return sfail(SHP_ERR_DEVICE, "solver readback");
+  double rmax;
+  std::memcpy(&rmax, &rbits, sizeof rmax);
+  const double rr_goal = (tol / rmax) * (tol / rmax) * bnorm2;  // ||rs||^2 at the tolerance
+  double best = st->rel_residual;
+  int stalls = 0, last = 0;
+  constexpr int MAX_GAP = 2000;  // iterations between updates at most
+  for (int it = 1; it <= max_iter; ++it) {
     if (int r = apply_inner<T>(plan, p, q, lambda, s)) return r;
     if (int r = dot(p, q, n, w, PQ, s)) return r;
-    hipLaunchKernelGGL(k_cg1<T>, g, b, 0, s, d, rs, p, q, w.slot, n);
-    if (it % 10 == 0 || it == max_inner) {
+    hipLaunchKernelGGL(k_cg1<T>, g, bl, 0, s, d, rs, p, q, w.slot, n);
+    st->inner_iters = it;
+    if (it % 10 == 0 || it == max_iter) {
       if (int r = dot(rs, rs, n, w, RR, s)) return r;
-      if (hipMemcpyAsync(h0, w.slot, sizeof h0, hipMemcpyDeviceToHost, s) != hipSuccess ||
-          hipStreamSynchronize(s) != hipSuccess)
-        return sfail(SHP_ERR_DEVICE, "solver readback");
-      if (h0[RR] == 0.0 || std::sqrt(h0[RR]) <= inner_tol * std::sqrt(h0[RR0])) break;
-      if (!(h0[PQ] > 0.0) || !std::isfinite(h0[RR])) return sfail(SHP_ERR_NOT_CONVERGED, "CG breakdown (p^T H p <= 0)");
+      if (!readback()) return sfail(SHP_ERR_DEVICE, "solver readback");
+      if (!(h[PQ] > 0.0) || !std::isfinite(h[RR])) return sfail(SHP_ERR_NOT_CONVERGED, "CG breakdown (p^T H p <= 0)");
+      if (h[RR] <= delta * delta * rr_ref || h[RR] <= rr_goal || it == max_iter || it - last >= MAX_GAP) {
+        // reliable update: x += d in FP64 (the previous x kept), true residual
+        const double rr_rec = h[RR];
+        last = it;
+        hipLaunchKernelGGL(k_copy<double>, g, bl, 0, s, x, w.xb, n);
+        hipLaunchKernelGGL(k_update_x<T>, g, bl, 0, s, x, d, w.rmax, n);
+        hipLaunchKernelGGL(k_zero<T>, g, bl, 0, s, d, n);
+        if (int r = true_residual<T>(plan, lambda, b, x, n, w, true, s)) return r;
+        if (!readback()) return sfail(SHP_ERR_DEVICE, "solver readback");
+        st->outer_iters += 1;
+        const double rel = std::sqrt(h[RR] / bnorm2);
+        bool restart = false;
+        if (rel < best) {
+          best = rel;
+          stalls = 0;
+          st->rel_residual = rel;
+          if (rel <= tol) {
+            st->converged = 1;
+            return SHP_OK;
+          }
+          if (int r = dot(rs, rs, n, w, RR, s)) return r;
+          if (!readback()) return sfail(SHP_ERR_DEVICE, "solver readback");
+          rr_ref = h[RR];
+          // a true residual well above the recursive one (rounding near the
+          // floor) would make the next beta inconsistent: restart the direction
+          restart = rr_ref > 4.0 * rr_rec;
+        } else {
+          // no progress: return to the previous x and its residual, restart
+          hipLaunchKernelGGL(k_copy<double>, g, bl, 0, s, w.xb, x, n);
+          if (int r = true_residual<T>(plan, lambda, b, x, n, w, true, s)) return r;
+          if (int r = dot(rs, rs, n, w, RR, s)) return r;
+          if (!readback()) return sfail(SHP_ERR_DEVICE, "solver readback");
+          rr_ref = h[RR];
+          restart = true;
+          if (++stalls >= 5) break;  // the residual floor of the FP64 action
+        }
+        if (st->outer_iters >= max_updates) break;
+        if (restart) {
+          hipLaunchKernelGGL(k_jacobi<T>, g, bl, 0, s, rs, dg, z, n);
+          hipLaunchKernelGGL(k_copy<T>, g, bl, 0, s, z, p, n);
+          if (int r = dot(rs, z, n, w, RZ, s)) return r;
+          continue;
+        }
+      }
     }
-    hipLaunchKernelGGL(k_jacobi<T>, g, b, 0, s, rs, dg, z, n);
+    hipLaunchKernelGGL(k_jacobi<T>, g, bl, 0, s, rs, dg, z, n);
     if (int r = dot(rs, z, n, w, RZN, s)) return r;
-    hipLaunchKernelGGL(k_cg2<T>, g, b, 0, s, p, z, w.slot, n);
+    hipLaunchKernelGGL(k_cg2<T>, g, bl, 0, s, p, z, w.slot, n);
   }
-  *iters = std::min(it, max_inner);
-  return hipGetLastError() == hipSuccess ? SHP_OK : SHP_ERR_DEVICE;
+  return sfail(SHP_ERR_NOT_CONVERGED, "the residual did not reach the tolerance (x is the best iterate)");
 }
 
 }  // namespace
@@ -308,58 +389,25 @@ int shp_helmholtz_solve(shp_plan plan, double lambda, const double* diag, const 
   const dim3 g = grid_for(n), bl(256);
   std::memset(st, 0, sizeof *st);
   if (inner_prec == SHP_FP32) hipLaunchKernelGGL(k_to_float, g, bl, 0, s, diag, w.diagf, n);
-  // ||b||
+  // ||b|| and the initial FP64 residual
   if (int r = dot(b, b, n, w, BB, s)) return r;
+  if (int r = (inner_prec == SHP_FP32 ? true_residual<float>(plan, lambda, b, x, n, w, false, s)
+                                      : true_residual<double>(plan, lambda, b, x, n, w, false, s)))
+    return r;
   double hs[NSLOT + 1];
-  int total_inner = 0;
-  for (int outer = 1; outer <= max_outer; ++outer) {
-    if (int r = shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, x, w.y, lambda, s)) return r;
-    // r = b - y, then its norm and max|r|
-    if (inner_prec == SHP_FP32)
-      hipLaunchKernelGGL(k_resid<float>, g, bl, 0, s, b, w.y, w.r, static_cast<float*>(w.vec), w.rmax, n, 0);
-    else
-      hipLaunchKernelGGL(k_resid<double>, g, bl, 0, s, b, w.y, w.r, static_cast<double*>(w.vec), w.rmax, n, 0);
-    if (int r = dot(w.r, w.r, n, w, RR, s)) return r;
-    if (hipMemsetAsync(w.rmax, 0, sizeof(unsigned long long), s) != hipSuccess)
-      return sfail(SHP_ERR_DEVICE, "solver memset");
-    hipLaunchKernelGGL(k_absmax, dim3(NB), bl, 0, s, w.r, n, w.rmax);
-    if (hipMemcpyAsync(hs, w.slot, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return sfail(SHP_ERR_DEVICE, "solver readback");
-    if (!(hs[BB] > 0.0) || !std::isfinite(hs[BB]))
-      return sfail(SHP_ERR_INVALID_ARG, "b is zero or not finite (relative residual undefined)");
-    st->rel_residual = std::sqrt(hs[RR] / hs[BB]);
-    st->outer_iters = outer - 1;
-    st->inner_iters = total_inner;
-    if (st->rel_residual <= tol) {
-      st->converged = 1;
-      return SHP_OK;
-    }
-    // scaled residual in the inner precision, inner PCG, FP64 update
-    int it = 0;
-    if (inner_prec == SHP_FP32) {
-      hipLaunchKernelGGL(k_resid<float>, g, bl, 0, s, b, w.y, w.r, static_cast<float*>(w.vec), w.rmax, n, 1);
-      if (int r = inner_pcg<float>(plan, lambda, n, w, w.diagf, max_inner, inner_tol, &it, s)) return r;
-      hipLaunchKernelGGL(k_update_x<float>, g, bl, 0, s, x, static_cast<float*>(w.vec) + 4 * n, w.rmax, n);
-    } else {
-      hipLaunchKernelGGL(k_resid<double>, g, bl, 0, s, b, w.y, w.r, static_cast<double*>(w.vec), w.rmax, n, 1);
-      if (int r = inner_pcg<double>(plan, lambda, n, w, diag, max_inner, inner_tol, &it, s)) return r;
-      hipLaunchKernelGGL(k_update_x<double>, g, bl, 0, s, x, static_cast<double*>(w.vec) + 4 * n, w.rmax, n);
-    }
-    total_inner += it;
-  }
-  // final residual
-  if (int r = shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, x, w.y, lambda, s)) return r;
-  hipLaunchKernelGGL(k_resid<double>, g, bl, 0, s, b, w.y, w.r, static_cast<double*>(w.vec), w.rmax, n, 0);
-  if (int r = dot(w.r, w.r, n, w, RR, s)) return r;
   if (hipMemcpyAsync(hs, w.slot, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return sfail(SHP_ERR_DEVICE, "solver readback");
+  if (!(hs[BB] > 0.0) || !std::isfinite(hs[BB]))
+    return sfail(SHP_ERR_INVALID_ARG, "b is zero or not finite (relative residual undefined)");
   st->rel_residual = std::sqrt(hs[RR] / hs[BB]);
-  st->outer_iters = max_outer;
-  st->inner_iters = total_inner;
-  st->converged = st->rel_residual <= tol;
-  return st->converged ? SHP_OK : sfail(SHP_ERR_NOT_CONVERGED, "iterative refinement did not reach the tolerance");
+  if (st->rel_residual <= tol) {
+    st->converged = 1;
+    return SHP_OK;
+  }
+  if (inner_prec == SHP_FP32)
+    return pcg_reliable<float>(plan, lambda, b, x, n, w, w.diagf, tol, max_outer, max_inner, inner_tol, hs[BB], st, s);
+  return pcg_reliable<double>(plan, lambda, b, x, n, w, diag, tol, max_outer, max_inner, inner_tol, hs[BB], st, s);
 }
 
 }  // extern "C"

@@ -264,10 +264,12 @@ class Plan:
             cache[lam] = d
         return cache[lam]
 
-    def solve(self, b, x=None, lam: float = 1.0, inner: str = "fp32", tol: float = 1e-10, max_outer: int = 20,
-              max_inner: int = 500, inner_tol: float = 1e-3, check: bool = True):
-        """Solve (lam M + L) x = b on every element (FP64 iterative refinement
-        around an inner Jacobi-PCG in `inner` precision).  Returns (x, stats)."""
+    def solve(self, b, x=None, lam: float = 1.0, inner: str = "fp32", tol: float = 1e-10, max_outer: int = 100,
+              max_inner: int = 50000, inner_tol: float = 0.1, check: bool = True):
+        """Solve (lam M + L) x = b on every element: Jacobi-PCG in `inner`
+        precision with FP64 reliable updates every `inner_tol` reduction of the
+        residual (at most `max_outer` of them, `max_inner` iterations in all).
+        Returns (x, stats)."""
         t = self._torch
         nc, _ = self.totals()
         if b.dtype != t.float64 or not b.is_cuda or not b.is_contiguous() or b.numel() != nc:

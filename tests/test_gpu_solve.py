@@ -16,11 +16,14 @@ Jacobi scaling), and the forward error was 250-400 times the relative residual
 down to 1e-12.  The residual floor of the library's FP64 action there (the
 residual of the oracle's own solution) is 1.24e-13 (the oracle's dense FP64
 products give 3.7e-14), and the oracle's forward error is at most 2.1e-12
-(against an 80-bit refined solution).  So the residual tolerance is 1e-9 for
-the 1e-6 target and 3e-13, 2.4 times the floor, for the 1e-10 target (where
-the error measured 7.3e-12).
+(against an 80-bit refined solution).  Near the floor the error falls much
+faster than the residual (1.1e-10 at a residual of 3.0e-13), so the residual
+tolerance is 1e-9 for the 1e-6 target and 2e-13, 1.6 times the floor, for the
+1e-10 target.  Measured at 2e-13: 9.7e-11 (FP32 inner) and 9.0e-11 (FP64
+inner), a thin margin that is set by the floor itself: solving to the floor
+(residual 1.4-1.6e-13) gives 8.1-8.5e-11.
 """
-RESID_TOL = {1e-6: 1e-9, 1e-10: 3e-13}
+RESID_TOL = {1e-6: 1e-9, 1e-10: 2e-13}
 import numpy as np
 import pytest
 
@@ -145,12 +148,13 @@ def small_problem(shp):
 @pytest.mark.parametrize("inner", ["fp32", "fp64"])
 @pytest.mark.parametrize("target", [1e-6, 1e-10])
 def test_solve_vs_oracle(shp, small_problem, inner, target):
-    """Mixed-precision (and plain FP64) PCG/IR solve on the manufactured problem
-    against the oracle's Cholesky solution of every element."""
+    """Mixed-precision (and plain FP64) PCG with FP64 reliable updates on the
+    manufactured problem against the oracle's Cholesky solution of every
+    element."""
     mesh, plan, b, xref = small_problem
     say(f"[solve] inner={inner} target={target:g}")
     bt = torch.from_numpy(b).cuda()
-    x, st = plan.solve(bt, lam=LAM, inner=inner, tol=RESID_TOL[target], max_outer=30, max_inner=2000)
+    x, st = plan.solve(bt, lam=LAM, inner=inner, tol=RESID_TOL[target], max_outer=60, max_inner=20000)
     say(f"    {st}")
     assert st["converged"]
     xs = x.cpu().numpy()
@@ -225,7 +229,7 @@ def test_config4_full_mesh_sampled(shp):
     # tolerance for the 1e-10 target is 2e-11 here
     for target, tol in ((1e-6, 1e-9), (1e-10, 2e-11)):
         say(f"[solve] config-4 mesh P=6: solve fp32 inner, tol {tol:g}")
-        x, st = plan.solve(b, x=x, lam=LAM, inner="fp32", tol=tol, max_outer=12, max_inner=5000)
+        x, st = plan.solve(b, x=x, lam=LAM, inner="fp32", tol=tol, max_outer=60, max_inner=20000)
         say(f"    {st}")
         xs = x.cpu().numpy()
         for k, s in enumerate(O.SHAPES):
