@@ -167,6 +167,33 @@ def mixed_precision_leg(torch, shp, W, ncell: int = 32, P: int = 6, lam: float =
                     "error against the FP64 oracle is asserted by the test suite on sampled elements"}
 
 
+def affine_leg(torch, shp, W, dof: float = 4e6, Ps=(1, 2, 3, 4)):
+    """Affine single-shape blocks of about 4M DOF (config-3 style): the FP64
+    Helmholtz action with the local-matrix strategy (7 reference matrices on
+    FP64 MFMA, 7 coefficients per element) against the collocated
+    sum-factorisation (per-point factors), GDOF/s from the median of 20
+    launches."""
+    out = {}
+    for s in SHAPES:
+        for P in Ps:
+            nm = shp.num_modes(s, P)
+            ne = max(1, int(round(dof / nm)))
+            maps = W.shape_batch(s, ne)
+            plan = shp.Plan([(s, P, ne, "affine")])
+            plan.set_geometry(0, torch.from_numpy(W.affine_jacobian(maps)).cuda())
+            x = torch.from_numpy(W.coeffs(ne, nm, W.seed_sweep(P))).cuda()
+            y = torch.empty_like(x)
+            row = {"n_elem": ne}
+            for st in ("localmat", "sumfac_coll"):
+                _, _, med = time_launches(torch, lambda: plan.apply(0, "helmholtz", x, out=y, strategy=st), 20, 3)
+                row[st] = round(ne * nm / (med * 1e-3) / 1e9, 2)
+            row["localmat_speedup"] = round(row["localmat"] / row["sumfac_coll"], 3)
+            out[f"{s}_P{P}"] = row
+            log(f"  affine {s} P={P}: {row}")
+            del plan, x, y
+    return out
+
+
 def cpu_baseline(mesh, P: int, budget_s: float = 15.0):
     """The oracle's Helmholtz action (form H_e by explicit quadrature, then
     y = H_e x) on a bounded sample of the mesh: rounds of 1/128 of every
@@ -212,6 +239,8 @@ def main():
     ap.add_argument("--strategies", action="store_true",
                     help="also time collocated vs non-collocated Helmholtz per shape (block launches)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg (P=6 mesh)")
+    ap.add_argument("--affine", action="store_true",
+                    help="also time affine blocks per shape and P=1..4: local matrices on MFMA vs sum-factorisation")
     ap.add_argument("--mixed-ncell", type=int, default=32)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
@@ -280,6 +309,9 @@ def main():
             row["coll_speedup"] = round(row["sumfac"]["ms"] / row["sumfac_coll"]["ms"], 3)
             strategies[s] = row
             log(f"  {s}: {row}")
+    affine = None
+    if a.affine:
+        affine = affine_leg(torch, shp, W)
     mixed = None
     if not a.no_mixed:
         del plan
@@ -316,6 +348,8 @@ def main():
         out["per_shape"] = per_shape
     if strategies is not None:
         out["collocated_vs_noncollocated"] = strategies
+    if affine is not None:
+        out["affine_localmat_vs_sumfac"] = affine
     print(json.dumps(out), flush=True)
 
 

@@ -79,9 +79,14 @@ typedef enum {
   SHP_AUTO = 0,        /* tuned choice if one is cached, else SHP_SUMFAC_COLL     */
   SHP_SUMFAC = 1,      /* sum-factorisation, non-collocated derivatives (Alg. 5)  */
   SHP_SUMFAC_COLL = 2, /* sum-factorisation, collocated derivatives (Alg. 6)      */
-  SHP_LOCALMAT = 3     /* reference matrices [B; d_d B] on FP64 MFMA (Alg. 1, the
-                          non-collocated form); mass, Laplacian and Helmholtz at
-                          P <= 4; other operators and orders: SHP_ERR_UNSUPPORTED */
+  SHP_LOCALMAT = 3     /* local matrices on FP64 MFMA (Alg. 1, StdMat): curved
+                          blocks apply [B; d_d B] with the per-point metric (the
+                          non-collocated form); affine blocks apply
+                          H_e = lambda |J| A_0 + sum_k c_{e,k} A_k with 7 shared
+                          reference matrices (mass and the xi-space stiffness
+                          blocks) and 7 coefficients per element.  Mass,
+                          Laplacian and Helmholtz at P <= 4; other operators and
+                          orders: SHP_ERR_UNSUPPORTED */
 } shp_strategy;
 
 typedef struct {
@@ -123,7 +128,9 @@ int shp_plan_bind_workspace(shp_plan plan, void* ws, size_t ws_bytes, void* stre
  * chain rule of Sec. 2.1 and the collapse Jacobian of Sec. 2.3), computed in
  * FP64 on the device from jac = d x_i/d xi_j:
  *   SHP_CURVED: jac [n_elem][9][Q^3], component i*3+j, at shp_quadrature points;
- *   SHP_AFFINE: jac [n_elem][9], constant per element.
+ *   SHP_AFFINE: jac [n_elem][9], constant per element (also the 7 coefficients
+ *               |J| and |J| (J^-1 J^-T)_ab per element of the local-matrix
+ *               strategy, for P <= 4).
  * Synchronises stream to report SHP_ERR_BAD_GEOMETRY when det <= 0 or a value
  * is not finite.  Not safe to call concurrently with applies of the plan. */
 int shp_plan_set_geometry(shp_plan plan, int blk, const double* jac /* device */, void* stream);

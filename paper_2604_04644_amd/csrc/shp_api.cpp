@@ -50,6 +50,8 @@ struct Block {
   std::vector<int> itab;
   size_t off_tab = 0, off_itab = 0, off_fac = 0, off_dxi = 0, off_lm = 0, off_tabf = 0;
   std::vector<double> lm;  // [B; d_d B] for the local-matrix strategy (P <= 4)
+  std::vector<double> am;  // affine blocks: 7 reference matrices, MFMA fragment order
+  size_t off_am = 0, off_coef = 0;
   std::vector<float> tabf; // the reference tables rounded to FP32
   long long coeff_off = 0, phys_off = 0;
   bool geom_ok = false;
@@ -202,6 +204,7 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     if (B.d.P <= LOCALMAT_MAX_P) {
       int q3p, kp;
       build_localmat(B.d.shape, B.d.P, B.lm, q3p, kp);
+      if (B.d.geom == SHP_AFFINE) build_affine_mats(B.d.shape, B.d.P, B.am, kp);
     }
     B.coeff_off = cofs;
     B.phys_off = pofs;
@@ -224,12 +227,18 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     off = align_up(off + sizeof(double) * B.lm.size());
     B.off_tabf = off;
     off = align_up(off + sizeof(float) * B.tab.size());
+    B.off_am = off;
+    off = align_up(off + sizeof(double) * B.am.size());
   }
   for (auto& B : p->blocks) {
     B.off_fac = off;
     off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * NFAC * B.NQ);
     B.off_dxi = off;
     off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * NDXI * B.NQ);
+    if (!B.am.empty()) {
+      B.off_coef = off;
+      off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * NAFF);
+    }
   }
   p->ws_bytes = off;
   for (int k = 0; k < OPK_COUNT; ++k) p->mixed_dirty[k] = true;
@@ -286,6 +295,8 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
       e = hipMemcpyAsync(p->ws + B.off_itab, B.itab.data(), sizeof(int) * B.itab.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.lm.empty())
       e = hipMemcpyAsync(p->ws + B.off_lm, B.lm.data(), sizeof(double) * B.lm.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !B.am.empty())
+      e = hipMemcpyAsync(p->ws + B.off_am, B.am.data(), sizeof(double) * B.am.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
       B.tabf.assign(B.tab.begin(), B.tab.end());
       e = hipMemcpyAsync(p->ws + B.off_tabf, B.tabf.data(), sizeof(float) * B.tabf.size(), hipMemcpyHostToDevice, s);
@@ -320,6 +331,10 @@ int shp_plan_set_geometry(shp_plan p, int blk, const double* jac, void* stream) 
   g.affine = (B.d.geom == SHP_AFFINE);
   e = launch_geometry(B.d.shape, B.d.P, g, s);
   if (e != hipSuccess) return dev_fail(e, "geometry kernel launch");
+  if (!B.am.empty()) {
+    e = launch_affine_coef(jac, reinterpret_cast<double*>(p->ws + B.off_coef), B.d.n_elem, status, s);
+    if (e != hipSuccess) return dev_fail(e, "affine coefficient kernel launch");
+  }
   int h = 0;
   e = hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -496,6 +511,19 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
     }
     for (int b = b0; b < b1; ++b) {
       const Block& B = p->blocks[b];
+      if (!B.am.empty()) {
+        // affine block: 7 reference matrices and 7 coefficients per element
+        AffineMatArgs aa;
+        aa.afrag = reinterpret_cast<const double*>(p->ws + B.off_am);
+        aa.coef = reinterpret_cast<const double*>(p->ws + B.off_coef);
+        aa.in = in + (blk >= 0 ? 0 : B.coeff_off);
+        aa.out = out + (blk >= 0 ? 0 : B.coeff_off);
+        aa.n_elem = B.d.n_elem;
+        aa.lambda = lambda;
+        hipError_t e = launch_localmat_affine(B.d.shape, B.d.P, opk, aa, s);
+        if (e != hipSuccess) return dev_fail(e, "affine local-matrix launch");
+        continue;
+      }
       LocalMatArgs la;
       la.bcat = reinterpret_cast<const double*>(p->ws + B.off_lm);
       la.fac = reinterpret_cast<const double*>(p->ws + B.off_fac);

@@ -16,6 +16,7 @@ struct OpArgs;
 struct Tile;
 struct GeomArgs;
 struct LocalMatArgs;
+struct AffineMatArgs;
 
 // Static per-block data of a mixed launch (device copy in the workspace).
 struct BlockStatic {
@@ -39,12 +40,19 @@ void build_tables(int sh, int P, std::vector<double>& tab, std::vector<int>& ita
 void reference_points(int sh, int Q, double* xi, double* w);
 void build_localmat(int sh, int P, std::vector<double>& bcat, int& Q3p, int& Kp);
 constexpr int LOCALMAT_MAX_P = 4;  // dense reference matrices only at low order
+// affine blocks: the 7 reference matrices of H = sum_k c_{e,k} A_k in MFMA
+// fragment order (Kp = modes padded to 16, 7 Kp^2 values); coefficients per element
+// (|J|, |J| K00, |J| K01, |J| K02, |J| K11, |J| K12, |J| K22), K = J^-1 J^-T
+void build_affine_mats(int sh, int P, std::vector<double>& acat, int& Kp);
+constexpr int NAFF = 7;
 
 // launchers (shp_k_*.hip); return hipSuccess or the launch error
 size_t op_lds_bytes(int sh, int P, int opk, int E, int variant);
 hipError_t launch_block(int sh, int P, int opk, const OpArgs& a, int threads, int persist, hipStream_t s);
 hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_localmat(int sh, int P, int opk, const LocalMatArgs& a, hipStream_t s);
+hipError_t launch_localmat_affine(int sh, int P, int opk, const AffineMatArgs& a, hipStream_t s);
+hipError_t launch_affine_coef(const double* jac, double* coef, long long n, int* status, hipStream_t s);
 hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
                         double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds, int E,
                         int persist, hipStream_t s);

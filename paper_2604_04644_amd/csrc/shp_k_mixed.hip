@@ -20,6 +20,64 @@ hipError_t launch_localmat_prism(int P, int opk, const LocalMatArgs& a, hipStrea
 hipError_t launch_localmat_pyr(int P, int opk, const LocalMatArgs& a, hipStream_t s);
 hipError_t launch_localmat_tet(int P, int opk, const LocalMatArgs& a, hipStream_t s);
 
+hipError_t launch_localmat_affine_hex(int P, int opk, const AffineMatArgs& a, hipStream_t s);
+hipError_t launch_localmat_affine_prism(int P, int opk, const AffineMatArgs& a, hipStream_t s);
+hipError_t launch_localmat_affine_pyr(int P, int opk, const AffineMatArgs& a, hipStream_t s);
+hipError_t launch_localmat_affine_tet(int P, int opk, const AffineMatArgs& a, hipStream_t s);
+
+hipError_t launch_localmat_affine(int sh, int P, int opk, const AffineMatArgs& a, hipStream_t s) {
+  switch (sh) {
+    case HEX: return launch_localmat_affine_hex(P, opk, a, s);
+    case PRISM: return launch_localmat_affine_prism(P, opk, a, s);
+    case PYR: return launch_localmat_affine_pyr(P, opk, a, s);
+    case TET: return launch_localmat_affine_tet(P, opk, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// per-element coefficients of an affine element's local matrices from its
+// constant d x_i/d xi_j (jac [n][9], i*3+j): |J| and |J| (J^-1 J^-T)_ab
+__global__ void __launch_bounds__(256) k_affine_coef(const double* __restrict__ jac, double* __restrict__ coef,
+                                                     long long n, int* __restrict__ status) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double J[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) J[c] = jac[e * 9 + c];
+  const double c00 = J[4] * J[8] - J[5] * J[7];
+  const double c01 = J[5] * J[6] - J[3] * J[8];
+  const double c02 = J[3] * J[7] - J[4] * J[6];
+  const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+  const double id = 1.0 / det;
+  double X[9];  // d xi_a / d x_i at a*3+i
+  X[0] = c00 * id;
+  X[1] = (J[2] * J[7] - J[1] * J[8]) * id;
+  X[2] = (J[1] * J[5] - J[2] * J[4]) * id;
+  X[3] = c01 * id;
+  X[4] = (J[0] * J[8] - J[2] * J[6]) * id;
+  X[5] = (J[2] * J[3] - J[0] * J[5]) * id;
+  X[6] = c02 * id;
+  X[7] = (J[1] * J[6] - J[0] * J[7]) * id;
+  X[8] = (J[0] * J[4] - J[1] * J[3]) * id;
+  const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+  double* out = coef + e * NAFF;
+  out[0] = det;
+  bool bad = !(det > 0.0) || !isfinite(det);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const int ra = pa[c] * 3, rb = pb[c] * 3;
+    out[1 + c] = det * (X[ra] * X[rb] + X[ra + 1] * X[rb + 1] + X[ra + 2] * X[rb + 2]);
+    bad = bad || !isfinite(out[1 + c]);
+  }
+  if (bad) atomicOr(status, 1);
+}
+
+hipError_t launch_affine_coef(const double* jac, double* coef, long long n, int* status, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_affine_coef, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, jac, coef, n, status);
+  return hipGetLastError();
+}
+
 hipError_t launch_localmat(int sh, int P, int opk, const LocalMatArgs& a, hipStream_t s) {
   switch (sh) {
     case HEX: return launch_localmat_hex(P, opk, a, s);

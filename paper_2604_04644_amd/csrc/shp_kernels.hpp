@@ -1799,6 +1799,74 @@ __global__ void __launch_bounds__(256) k_localmat(LocalMatArgs a) {
   localmat_tile<SH, P, OP>(a, e0, ne, smem);
 }
 
+// ---------------------------------------------------------------------------
+// Local matrices of affine elements (FP64 MFMA)
+// ---------------------------------------------------------------------------
+// With constant d xi/d x the elemental operator is a combination of 7 shared
+// reference matrices, H_e = lambda |J| A_0 + sum_{k=1..6} c_{e,k} A_k (mass and
+// the xi-space stiffness blocks, built from the same quadrature), so
+//   Y = [A_0 ... A_6] [c_0 X; ...; c_6 X]
+// is one dense FP64 contraction with K = 7 N_P per 16-element tile.  Each
+// wave owns a tile: its B operand is the tile's coefficients scaled by the
+// element's c_k, and the A fragments stream from a fragment-ordered copy of
+// the matrices (64 consecutive doubles per fragment, one per lane):
+//   afrag[((kb * 7 + k) * MB + mb) * 64 + lane] = A_k[16 mb + lane%16][4 kb + lane/16].
+
+struct AffineMatArgs {
+  const double* afrag;  // fragment-ordered reference matrices
+  const double* coef;   // [n][7]
+  const double* in;     // [n][NP]
+  double* out;          // [n][NP]
+  long long n_elem;
+  double lambda;
+};
+
+template <int SH, int P, int OP>
+__global__ void __launch_bounds__(256) k_localmat_affine(AffineMatArgs a) {
+  constexpr int NP = num_modes(SH, P);
+  constexpr int Kp = (NP + 15) / 16 * 16;
+  constexpr int MB = Kp / 16;
+  constexpr int K0 = (OP == OPK_LAP) ? 1 : 0;     // the Laplacian has no mass term
+  constexpr int K1 = (OP == OPK_MASS) ? 1 : NAFF;  // the mass has only A_0
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const long long e0 = ((long long)blockIdx.x * (blockDim.x >> 6) + wave) * 16;
+  if (e0 >= a.n_elem) return;  // whole waves only: no barriers below
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < 16 ? (int)rem : 16;
+  const bool live = col < ne;
+  double c[NAFF];
+#pragma unroll
+  for (int k = 0; k < NAFF; ++k) c[k] = live ? a.coef[(e0 + col) * NAFF + k] : 0.0;
+  if (OP == OPK_HELM) c[0] *= a.lambda;
+  dbl4 acc[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) acc[mb] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const gptr_t Af = as_global(a.afrag) + lane;
+  const gptr_t X = as_global(a.in) + e0 * NP + (long long)col * NP;
+  for (int kb = 0; kb < Kp / 4; ++kb) {
+    const int n = 4 * kb + kq;
+    const double xb = (live && n < NP) ? X[n] : 0.0;
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+      const double b = xb * c[k];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const double av = Af[(long long)((kb * NAFF + k) * MB + mb) * 64];
+        acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[mb], 0, 0, 0);
+      }
+    }
+  }
+  double* Y = a.out + (e0 + col) * NP;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = mb * 16 + 4 * i + kq;
+      if (live && m < NP) Y[m] = acc[mb][i];
+    }
+}
+
 template <int SH, int P>
 constexpr size_t lds_bytes_localmat() {
   constexpr int Kp = (num_modes(SH, P) + 15) / 16 * 16;

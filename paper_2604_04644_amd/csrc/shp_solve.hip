@@ -258,7 +258,8 @@ int pcg_reliable(shp_plan plan, double lambda, const double* b, double* x, long 
   double rr_ref = h[RR0];
   // the scale, to turn the recursive residual into an estimate of ||b - H x||
   unsigned long long rbits = 0;
-  if (hipMemcpy(&rbits, w.rmax, sizeof rbits, hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipMemcpyAsync(&rbits, w.rmax, sizeof rbits, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
     return sfail(SHP_ERR_DEVICE, "solver readback");
   double rmax;
   std::memcpy(&rmax, &rbits, sizeof rmax);

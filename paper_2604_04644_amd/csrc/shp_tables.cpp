@@ -247,6 +247,91 @@ void build_localmat(int sh, int P, std::vector<double>& bcat, int& Q3p, int& Kp)
       }
 }
 
+// d eta / d xi of the collapse at (e1, e2, e3), rows eta_d, columns xi_a, and
+// the factor 2^{-sum alpha} that the Jacobi weights leave out (Sec. 2.3)
+static void collapse_deriv(int sh, double e1, double e2, double e3, double G[9], double* scale) {
+  for (int c = 0; c < 9; ++c) G[c] = (c % 4 == 0) ? 1.0 : 0.0;
+  *scale = 1.0;
+  if (sh == PRISM) {
+    G[0] = 2.0 / (1.0 - e3);
+    G[2] = (1.0 + e1) / (1.0 - e3);
+    *scale = 0.5;
+  } else if (sh == PYR) {
+    G[0] = 2.0 / (1.0 - e3);
+    G[2] = (1.0 + e1) / (1.0 - e3);
+    G[4] = 2.0 / (1.0 - e3);
+    G[5] = (1.0 + e2) / (1.0 - e3);
+    *scale = 0.25;
+  } else if (sh == TET) {
+    const double s = (1.0 - e2) * (1.0 - e3);
+    G[0] = 4.0 / s;
+    G[1] = 2.0 * (1.0 + e1) / s;
+    G[2] = 2.0 * (1.0 + e1) / s;
+    G[4] = 2.0 / (1.0 - e3);
+    G[5] = (1.0 + e2) / (1.0 - e3);
+    *scale = 0.125;
+  }
+}
+
+void build_affine_mats(int sh, int P, std::vector<double>& acat, int& Kp) {
+  std::vector<double> bcat;
+  int Q3p = 0;
+  build_localmat(sh, P, bcat, Q3p, Kp);
+  const int Q = P + 2, Q3 = Q * Q * Q, NP = num_modes(sh, P);
+  std::vector<double> z(3 * Q), w(3 * Q);
+  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), z.data() + d * Q, w.data() + d * Q);
+  // reference weights and xi-derivatives of the modes at the points
+  std::vector<double> wr(Q3), dx((size_t)3 * Q3 * NP);
+  for (int i = 0; i < Q; ++i)
+    for (int j = 0; j < Q; ++j)
+      for (int k = 0; k < Q; ++k) {
+        const int pt = (i * Q + j) * Q + k;
+        double G[9], scale;
+        collapse_deriv(sh, z[i], z[Q + j], z[2 * Q + k], G, &scale);
+        wr[pt] = w[i] * w[Q + j] * w[2 * Q + k] * scale;
+        for (int m = 0; m < NP; ++m)
+          for (int a = 0; a < 3; ++a) {
+            double v = 0.0;
+            for (int d = 0; d < 3; ++d) v += G[d * 3 + a] * bcat[(size_t)((1 + d) * Q3p + pt) * Kp + m];
+            dx[((size_t)a * Q3 + pt) * NP + m] = v;
+          }
+      }
+  // Acat[m][k Kp + n]: A_0 = B^T W B, then S_00, S_01 + S_10, S_02 + S_20,
+  // S_11, S_12 + S_21, S_22 with S_ab = (d_a B)^T W (d_b B) in xi
+  const int NK = 7, W7 = NK * Kp;
+  acat.assign((size_t)Kp * W7, 0.0);
+  const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+  for (int m = 0; m < NP; ++m)
+    for (int n = 0; n < NP; ++n) {
+      double mass = 0.0, S[3][3] = {};
+      for (int pt = 0; pt < Q3; ++pt) {
+        const double ww = wr[pt];
+        mass += ww * bcat[(size_t)pt * Kp + m] * bcat[(size_t)pt * Kp + n];
+        for (int a = 0; a < 3; ++a) {
+          const double da = ww * dx[((size_t)a * Q3 + pt) * NP + m];
+          for (int b = 0; b < 3; ++b) S[a][b] += da * dx[((size_t)b * Q3 + pt) * NP + n];
+        }
+      }
+      double* row = acat.data() + (size_t)m * W7;
+      row[0 * Kp + n] = mass;
+      for (int c = 0; c < 6; ++c) {
+        const int a = pa[c], b = pb[c];
+        row[(1 + c) * Kp + n] = (a == b) ? S[a][a] : S[a][b] + S[b][a];
+      }
+    }
+  // MFMA fragment order: A operand of v_mfma_f64_16x16x4f64, lane l holding
+  // row 16 mb + l%16 and column 4 kb + l/16 of A_k
+  const int MB = Kp / 16;
+  std::vector<double> frag(acat.size());
+  for (int kb = 0; kb < Kp / 4; ++kb)
+    for (int k = 0; k < NK; ++k)
+      for (int mb = 0; mb < MB; ++mb)
+        for (int l = 0; l < 64; ++l)
+          frag[(((size_t)kb * NK + k) * MB + mb) * 64 + l] =
+              acat[(size_t)(mb * 16 + l % 16) * W7 + k * Kp + 4 * kb + l / 16];
+  acat.swap(frag);
+}
+
 void reference_points(int sh, int Q, double* xi, double* wout) {
   std::vector<double> z(3 * Q), w(3 * Q);
   for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), z.data() + d * Q, w.data() + d * Q);

@@ -182,6 +182,51 @@ def test_affine_blocks_vs_oracle(shp, shape):
         assert e <= TOL, (shape, op, e)
 
 
+@pytest.mark.parametrize("shape,P", [(s, P) for s in O.SHAPES for P in (1, 2, 3, 4)])
+def test_affine_localmat_vs_oracle(shp, shape, P):
+    """Affine local matrices (7 reference matrices, 7 coefficients per element,
+    FP64 MFMA) for mass, Laplacian and Helmholtz on a ragged batch (the last
+    16-element tile and the last work-group partial) against the oracle, and
+    against the affine sum-factorisation of the same block."""
+    ne = 83
+    say(f"[parity] affine local matrices shape={shape} P={P} n_elem={ne}")
+    maps = W.shape_batch(shape, ne)
+    NP = O.num_modes(shape, P)
+    plan = shp.Plan([(shape, P, ne, "affine")])
+    plan.set_geometry(0, gpu_geometry(shp, maps, shape, P, False))
+    jo = oracle_geometry(maps, shape, P, False)
+    for k, op in enumerate(("mass", "laplacian", "helmholtz")):
+        x = W.coeffs(ne, NP, 700 + k)
+        xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        ref = O.apply_op(op, shape, P, P + 2, jo, x, lam=2.5)
+        y = plan.apply(0, op, xt, lam=2.5, strategy="localmat").cpu().numpy()
+        e = rel(y.reshape(ref.shape), ref)
+        assert e <= TOL, (shape, op, e)
+        ys = plan.apply(0, op, xt, lam=2.5, strategy="sumfac_coll").cpu().numpy()
+        assert rel(y, ys) <= TOL, (shape, op)
+
+
+def test_affine_localmat_whole_mesh(shp):
+    """Whole-mesh local matrices over affine blocks of every shape equal the
+    per-block launches bitwise (the same kernel per block)."""
+    say("[parity] affine local matrices, whole mesh")
+    P = 2
+    blocks = [(s, P, n, "affine") for s, n in zip(O.SHAPES, (5, 17, 33, 40))]
+    plan = shp.Plan(blocks)
+    maps = {}
+    for b, (s, _, n, _) in enumerate(blocks):
+        maps[s] = W.shape_batch(s, n)
+        plan.set_geometry(b, gpu_geometry(shp, maps[s], s, P, False))
+    nc, _ = plan.totals()
+    x = torch.from_numpy(W.coeffs(1, nc, 710)[0]).cuda()
+    y = plan.apply(-1, "helmholtz", x, strategy="localmat").cpu().numpy()
+    for b, (s, _, n, _) in enumerate(blocks):
+        co, _ = plan.offsets(b)
+        NP = plan.n_modes[b]
+        yb = plan.apply(b, "helmholtz", x[co:co + n * NP].view(n, NP).contiguous(), strategy="localmat")
+        assert np.array_equal(y[co:co + n * NP], yb.cpu().numpy().ravel()), s
+
+
 def test_config1_affine_hex_helmholtz(shp):
     """64 affine hexes of side 1/4, P=2, Q=4, lambda=1, seed 0."""
     say("[parity] config-1 affine hex grid")
