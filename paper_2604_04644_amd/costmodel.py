@@ -163,7 +163,7 @@ def regret(model: CostModel, rows):
         best = min(r["ms"] for r in byst.values())
         pick = model.choose(shape, P, ne, curved, strategies=tuple(byst))
         fixed = byst.get("sumfac_coll", min(byst.values(), key=lambda r: r["ms"]))
-        out.append({"shape": shape, "P": P, "n_elem": ne, "pick": pick,
+        out.append({"shape": shape, "P": P, "n_elem": ne, "curved": curved, "pick": pick, "best_ms": best,
                     "regret": byst[pick]["ms"] / best - 1.0, "fixed_regret": fixed["ms"] / best - 1.0})
     return out
 
