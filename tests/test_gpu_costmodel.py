@@ -93,3 +93,31 @@ def test_gain_over_tuning_time(cm):
           f"pick {pick}, regret {reg:.4f}", flush=True)
     assert t_pick < t_tune / 5
     assert reg <= 0.25
+
+
+def test_config2_mesh_per_block(cm):
+    """The selector on the blocks of the mixed mesh (32^3 cells, P = 4, curved):
+    its pick for each shape's block against the quick exhaustive tuning of that
+    block (the mesh is not in the training data; its batch sizes are)."""
+    from paper_2604_04644_amd import shp
+    print("[mlp] config-2 mesh, per block", flush=True)
+    model = cm.CostModel(seed=0)
+    model.fit(cm.load_rows(), epochs=1500, lr=3e-3)
+    P = 4
+    mesh = W.quadrant_mesh(32)
+    shapes = ("hex", "prism", "pyr", "tet")
+    plan = shp.Plan([(s, P, len(mesh[s]), "curved") for s in shapes])
+    regs = []
+    for b, s in enumerate(shapes):
+        plan.set_geometry(b, W.jacobian_torch(mesh[s], shp.quadrature(s, P + 2)[0], True, "cuda"))
+        x = torch.from_numpy(W.coeffs(len(mesh[s]), plan.n_modes[b], W.SEED_MIXED[s])).cuda()
+        _, recs = plan.tune(b, "helmholtz", x, reps=5, quick=True)
+        best_of = {}
+        for r in recs:
+            if r["passed"]:
+                best_of[r["strategy"]] = min(best_of.get(r["strategy"], 1e9), r["ms"])
+        pick = model.choose(s, P, len(mesh[s]), strategies=tuple(best_of))
+        reg = best_of[pick] / min(best_of.values()) - 1.0
+        regs.append(reg)
+        print(f"    {s}: pick {pick}, times {best_of}, regret {reg:.4f}", flush=True)
+    assert max(regs) <= 0.1
