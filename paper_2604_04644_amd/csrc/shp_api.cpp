@@ -13,6 +13,8 @@
 
 #include "../../include/shp.h"
 #include "shp_kernels.hpp"
+#include "shp_kernels_geom.hpp"
+#include "shp_kernels_lm.hpp"
 
 using namespace shp;
 

@@ -1,0 +1,211 @@
+// HIP kernels of libshp for gfx950: the local-matrix strategy on FP64 MFMA,
+// curved blocks ([B; d_d B] with the per-point metric) and affine blocks (7
+// reference matrices, 7 coefficients per element).
+#pragma once
+#include "shp_kernels.hpp"
+
+namespace shp {
+
+// ---------------------------------------------------------------------------
+// Local-matrix strategy on FP64 MFMA (Sec. 3.3.1 StdMat, Alg. 1; the
+// non-collocated form the paper prescribes for it, Sec. 3.3.4)
+// ---------------------------------------------------------------------------
+// A work-group of 4 waves takes 16 elements (the N = 16 columns of the MFMA
+// tiles).  Bcat = [B; d_1 B; d_2 B; d_3 B] (rows: points, padded to 16;
+// columns: modes, padded to 16) is shared by all elements.  Each wave walks
+// blocks of 16 points:
+//   U_d = Bcat_d[block] X        (v_mfma_f64_16x16x4f64, K = modes)
+//   metric on U_d in registers   (lane l, register i: point 4i + l/16, element l%16)
+//   Y  += Bcat_d[block]^T U'_d   (the accumulator registers are the B operand)
+// and the waves' partial Y are summed in LDS in a fixed order.
+// MFMA operand layouts: A lane l = A[l%16][l/16]; B lane l = B[l/16][l%16];
+// D lane l register i = D[4i + l/16][l%16].
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+struct LocalMatArgs {
+  const double* bcat;  // [4*Q3p][Kp]
+  const double* fac;   // [n][NFAC][Q3]
+  const double* in;    // [n][NP]
+  double* out;         // [n][NP]
+  long long n_elem;
+  double lambda;
+};
+
+template <int SH, int P, int OP>
+__device__ void localmat_tile(const LocalMatArgs& a, long long e0, int ne, double* smem) {
+  constexpr int Q = P + 2, Q3 = Q * Q * Q;
+  constexpr int Q3p = (Q3 + 15) / 16 * 16;
+  constexpr int NP = num_modes(SH, P);
+  constexpr int Kp = (NP + 15) / 16 * 16;
+  constexpr int MB = Kp / 16;               // 16-row blocks of Y
+  constexpr int ND = (OP == OPK_MASS) ? 1 : 4;
+  constexpr int D0 = (OP == OPK_LAP) ? 1 : 0;  // the Laplacian has no mass term
+  double* X = smem;            // [Kp][16]
+  double* R = smem + Kp * 16;  // [Kp][16] reduction
+  const int tidx = threadIdx.x, lane = tidx & 63, wave = tidx >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  // x tile transposed into LDS, zero padded
+  for (int t = tidx; t < Kp * 16; t += blockDim.x) {
+    const int m = t / 16, e = t - m * 16;
+    X[t] = (m < NP && e < ne) ? a.in[(e0 + e) * NP + m] : 0.0;
+  }
+  __syncthreads();
+  const gptr_t B = as_global(a.bcat);
+  const gptr_t G = as_global(a.fac) + e0 * (long long)(NFAC * Q3);
+  const bool live = col < ne;
+  dbl4 y[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) y[mb] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int qb = wave; qb < Q3p / 16; qb += (int)(blockDim.x >> 6)) {
+    dbl4 u[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) u[d] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // U_d = Bcat_d[qb] X
+    for (int kb = 0; kb < Kp / 4; ++kb) {
+      const double b = X[(4 * kb + kq) * 16 + col];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        const double av = B[(long long)(d * Q3p + qb * 16 + col) * Kp + 4 * kb + kq];
+        u[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, u[d], 0, 0, 0);
+      }
+    }
+    // metric at the lane's 4 points of this element
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int pt = qb * 16 + 4 * i + kq;
+      if (live && pt < Q3) {
+        const gptr_t g = G + col * (NFAC * Q3) + pt;
+        const double jw = g[0];
+        if (OP == OPK_MASS) {
+          u[0][i] = jw * u[0][i];
+        } else {
+          const double g00 = g[1 * Q3], g01 = g[2 * Q3], g02 = g[3 * Q3];
+          const double g11 = g[4 * Q3], g12 = g[5 * Q3], g22 = g[6 * Q3];
+          const double d0 = u[1][i], d1 = u[2][i], d2 = u[3][i];
+          u[1][i] = g00 * d0 + g01 * d1 + g02 * d2;
+          u[2][i] = g01 * d0 + g11 * d1 + g12 * d2;
+          u[3][i] = g02 * d0 + g12 * d1 + g22 * d2;
+          u[0][i] = (OP == OPK_HELM) ? a.lambda * jw * u[0][i] : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) u[d][i] = 0.0;
+      }
+    }
+    // Y += Bcat_d[qb]^T U'_d; the K-slab kb of this block is register kb
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int d = D0; d < ND; ++d)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          const double av = B[(long long)(d * Q3p + qb * 16 + 4 * kb + kq) * Kp + mb * 16 + col];
+          y[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, u[d][kb], y[mb], 0, 0, 0);
+        }
+  }
+  // sum the waves' partial results in a fixed order
+  const int nw = (int)(blockDim.x >> 6);
+  for (int w = 0; w < nw; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = mb * 16 + 4 * i + kq;
+          R[m * 16 + col] = (w == 0 ? 0.0 : R[m * 16 + col]) + y[mb][i];
+        }
+    }
+    __syncthreads();
+  }
+  for (int t = tidx; t < ne * NP; t += blockDim.x) {
+    const int e = t / NP, m = t - e * NP;
+    a.out[(e0 + e) * NP + m] = R[m * 16 + e];
+  }
+}
+
+template <int SH, int P, int OP>
+__global__ void __launch_bounds__(256) k_localmat(LocalMatArgs a) {
+  extern __shared__ double smem[];
+  const long long e0 = (long long)blockIdx.x * 16;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < 16 ? (int)rem : 16;
+  if (ne <= 0) return;
+  localmat_tile<SH, P, OP>(a, e0, ne, smem);
+}
+
+// ---------------------------------------------------------------------------
+// Local matrices of affine elements (FP64 MFMA)
+// ---------------------------------------------------------------------------
+// With constant d xi/d x the elemental operator is a combination of 7 shared
+// reference matrices, H_e = lambda |J| A_0 + sum_{k=1..6} c_{e,k} A_k (mass and
+// the xi-space stiffness blocks, built from the same quadrature), so
+//   Y = [A_0 ... A_6] [c_0 X; ...; c_6 X]
+// is one dense FP64 contraction with K = 7 N_P per 16-element tile.  Each
+// wave owns a tile: its B operand is the tile's coefficients scaled by the
+// element's c_k, and the A fragments stream from a fragment-ordered copy of
+// the matrices (64 consecutive doubles per fragment, one per lane):
+//   afrag[((kb * 7 + k) * MB + mb) * 64 + lane] = A_k[16 mb + lane%16][4 kb + lane/16].
+
+struct AffineMatArgs {
+  const double* afrag;  // fragment-ordered reference matrices
+  const double* coef;   // [n][7]
+  const double* in;     // [n][NP]
+  double* out;          // [n][NP]
+  long long n_elem;
+  double lambda;
+};
+
+template <int SH, int P, int OP>
+__global__ void __launch_bounds__(256) k_localmat_affine(AffineMatArgs a) {
+  constexpr int NP = num_modes(SH, P);
+  constexpr int Kp = (NP + 15) / 16 * 16;
+  constexpr int MB = Kp / 16;
+  constexpr int K0 = (OP == OPK_LAP) ? 1 : 0;     // the Laplacian has no mass term
+  constexpr int K1 = (OP == OPK_MASS) ? 1 : NAFF;  // the mass has only A_0
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const long long e0 = ((long long)blockIdx.x * (blockDim.x >> 6) + wave) * 16;
+  if (e0 >= a.n_elem) return;  // whole waves only: no barriers below
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < 16 ? (int)rem : 16;
+  const bool live = col < ne;
+  double c[NAFF];
+#pragma unroll
+  for (int k = 0; k < NAFF; ++k) c[k] = live ? a.coef[(e0 + col) * NAFF + k] : 0.0;
+  if (OP == OPK_HELM) c[0] *= a.lambda;
+  dbl4 acc[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) acc[mb] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const gptr_t Af = as_global(a.afrag) + lane;
+  const gptr_t X = as_global(a.in) + e0 * NP + (long long)col * NP;
+  for (int kb = 0; kb < Kp / 4; ++kb) {
+    const int n = 4 * kb + kq;
+    const double xb = (live && n < NP) ? X[n] : 0.0;
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+      const double b = xb * c[k];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const double av = Af[(long long)((kb * NAFF + k) * MB + mb) * 64];
+        acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[mb], 0, 0, 0);
+      }
+    }
+  }
+  double* Y = a.out + (e0 + col) * NP;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = mb * 16 + 4 * i + kq;
+      if (live && m < NP) Y[m] = acc[mb][i];
+    }
+}
+
+template <int SH, int P>
+constexpr size_t lds_bytes_localmat() {
+  constexpr int Kp = (num_modes(SH, P) + 15) / 16 * 16;
+  return sizeof(double) * 2 * Kp * 16;
+}
+
+}  // namespace shp
