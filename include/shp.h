@@ -279,6 +279,55 @@ int shp_tune_cache_save(shp_plan plan, const char* path /* host */);
  * NULL. */
 int shp_tune_cache_load(shp_plan plan, const char* path /* host */, int* n_applied /* host out or NULL */);
 
+/* ---- C0 assembly on a structured hexahedral grid ------------------------
+ * The elemental systems joined into the global Helmholtz problem of Sec. 2.1
+ * (H^e assembled by a local-to-global map A: the global operator is A^T H A)
+ * on a grid of n0 x n1 x n2 hexahedra, element e = (i0 n1 + i1) n2 + i2,
+ * whose reference axes xi_1, xi_2, xi_3 follow the grid directions: a face or
+ * edge shared by several elements then carries the same modified-basis
+ * functions in each, so the map needs no sign changes.  Homogeneous Dirichlet
+ * data on the grid boundary: the boundary DOFs are dropped.  Per direction the
+ * interior DOFs are the n P - 1 interior vertices and cell bubbles in line
+ * order (vertex v at v P - 1, bubble b of cell c at c P + b); a global index is
+ * (g0 m1 + g1) m2 + g2 with m_d = n_d P - 1.
+ *
+ * The plan must hold these elements as its only block (shape SHP_HEX, order
+ * P, affine or curved, element order as above); coefficients in the plan's
+ * [n_elem][N_P] layout are the local vectors.  Geometry continuous across
+ * faces (a global mesh map) is the caller's responsibility. */
+int shp_c0_hex_sizes(int n0, int n1, int n2, int P, int64_t* n_global /* host out */,
+                     int64_t* n_local /* host out: n_elem N_P */, int64_t* n_entries /* host out */);
+/* l2g: host [n_local], global index of each local coefficient or -1 on the
+ * Dirichlet boundary; row_ptr: host [n_global + 1] and col: host [n_entries],
+ * the local copies of each global DOF in ascending local order (CSR). */
+int shp_c0_hex_map(int n0, int n1, int n2, int P, int64_t* l2g, int64_t* row_ptr, int64_t* col);
+
+/* Assembled FP64 Helmholtz action yg = A^T H A xg (gather, whole-mesh
+ * collocated action, scatter-sum in the fixed CSR order).  l2g, row_ptr, col,
+ * xg, yg: device; work: device FP64 scratch of 2 n_local values. */
+int shp_c0_apply(shp_plan plan, const int64_t* l2g, const int64_t* row_ptr, const int64_t* col, int64_t n_global,
+                 const double* xg /* device */, double* yg /* device */, double lambda, double* work /* device */,
+                 void* stream);
+
+/* Assembled vector vg = A^T vl (each global DOF the sum of its local copies
+ * in the fixed CSR order), e.g. a right-hand side from shp_apply's inner
+ * products.  All arrays device; vl [n_local], vg [n_global]. */
+int shp_c0_assemble(const int64_t* row_ptr, const int64_t* col, int64_t n_global, const double* vl /* device */,
+                    double* vg /* device */, void* stream);
+
+/* Solve A^T H A x = b with the mixed-precision PCG of shp_helmholtz_solve
+ * (inner_prec, tol, max_outer, max_inner, inner_tol and the stats as there);
+ * the Jacobi diagonal is the elemental diagonals summed per global DOF,
+ * formed inside the call.  b, x: device FP64 [n_global].  ws: device,
+ * 256-byte aligned, at least shp_c0_solve_workspace_bytes.  Synchronises
+ * stream. */
+int shp_c0_solve_workspace_bytes(shp_plan plan, int64_t n_global, size_t* bytes /* host out */);
+int shp_c0_helmholtz_solve(shp_plan plan, const int64_t* l2g, const int64_t* row_ptr, const int64_t* col,
+                           int64_t n_global, double lambda, const double* b /* device */, double* x /* device */,
+                           int inner_prec, double tol, int max_outer, int max_inner, double inner_tol,
+                           void* ws /* device */, size_t ws_bytes, shp_solve_stats* stats /* host out */,
+                           void* stream);
+
 /* ---- MLP cost model (11 -> 64 -> 64 -> 1, ReLU, FP32), trained on the GPU ----
  * Inputs per sample: shape one-hot (4), P/10, Q/12, log2(n_elem)/22, curved,
  * strategy one-hot (local matrix, sum-factorisation, collocated); output: a

@@ -162,6 +162,28 @@ __global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, 
     b[i] = (float)a[i];
 }
 
+// assembled (C0) operator: local copies of global values and the sum of the
+// local copies of each global DOF in a fixed (ascending local) order
+template <typename T>
+__global__ void k_c0_gather(const int64_t* __restrict__ l2g, long long n_local, const T* __restrict__ xg,
+                            T* __restrict__ xl) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_local;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int64_t g = l2g[i];
+    xl[i] = g >= 0 ? xg[g] : (T)0;
+  }
+}
+template <typename T>
+__global__ void k_c0_scatter(const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ col, long long n_global,
+                             const T* __restrict__ yl, T* __restrict__ yg) {
+  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n_global;
+       g += (long long)gridDim.x * blockDim.x) {
+    T acc = 0;
+    for (int64_t j = row_ptr[g]; j < row_ptr[g + 1]; ++j) acc += yl[col[j]];
+    yg[g] = acc;
+  }
+}
+
 inline dim3 grid_for(long long n) { return dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)); }
 
 int sfail(int code, const char* msg) { return shp::set_error(code, msg); }
@@ -211,13 +233,53 @@ int apply_inner(shp_plan plan, const T* in, T* out, double lambda, hipStream_t s
   return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, prec, in, out, lambda, s);
 }
 
+// The operators of the solve: the FP64 action apply64 and the action in the
+// inner type.  ElemOp is the block-diagonal elemental H; C0Op the assembled
+// operator A^T H A of a local-to-global map A (gather, elemental action,
+// scatter-sum).
+struct ElemOp {
+  shp_plan plan;
+  double lambda;
+  int apply64(const double* x, double* y, hipStream_t s) const {
+    return shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, x, y, lambda, s);
+  }
+  template <typename T>
+  int apply(const T* x, T* y, hipStream_t s) const {
+    return apply_inner<T>(plan, x, y, lambda, s);
+  }
+};
+
+struct C0Op {
+  shp_plan plan;
+  double lambda;
+  const int64_t *l2g, *row_ptr, *col;
+  long long n_local, n_global;
+  double *xl, *yl;
+  float *xlf, *ylf;
+  template <typename T>
+  int run(const T* x, T* y, T* xl_, T* yl_, hipStream_t s) const {
+    hipLaunchKernelGGL(k_c0_gather<T>, grid_for(n_local), dim3(256), 0, s, l2g, n_local, x, xl_);
+    if (int r = apply_inner<T>(plan, xl_, yl_, lambda, s)) return r;
+    hipLaunchKernelGGL(k_c0_scatter<T>, grid_for(n_global), dim3(256), 0, s, row_ptr, col, n_global, yl_, y);
+    return hipGetLastError() == hipSuccess ? SHP_OK : SHP_ERR_DEVICE;
+  }
+  int apply64(const double* x, double* y, hipStream_t s) const { return run<double>(x, y, xl, yl, s); }
+  template <typename T>
+  int apply(const T* x, T* y, hipStream_t s) const {
+    if constexpr (sizeof(T) == sizeof(float))
+      return run<float>(x, y, xlf, ylf, s);
+    else
+      return run<double>(x, y, xl, yl, s);
+  }
+};
+
 // FP64 true residual r = b - H x of the current x, its squared norm into slot
 // RR, and (when T is the inner type) the scaled copy rs = r / rmax in T
-template <typename T>
-int true_residual(shp_plan plan, double lambda, const double* b, const double* x, long long n, SolveWs& w,
-                  bool scaled, hipStream_t s) {
+template <typename T, typename Op>
+int true_residual(const Op& op, const double* b, const double* x, long long n, SolveWs& w, bool scaled,
+                  hipStream_t s) {
   const dim3 g = grid_for(n), bl(256);
-  if (int r = shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, x, w.y, lambda, s)) return r;
+  if (int r = op.apply64(x, w.y, s)) return r;
   hipLaunchKernelGGL(k_resid<T>, g, bl, 0, s, b, w.y, w.r, static_cast<T*>(w.vec), w.rmax, n, 0);
   if (scaled) hipLaunchKernelGGL(k_resid<T>, g, bl, 0, s, b, w.y, w.r, static_cast<T*>(w.vec), w.rmax, n, 1);
   return dot(w.r, w.r, n, w, RR, s);
@@ -229,10 +291,9 @@ int true_residual(shp_plan plan, double lambda, const double* b, const double* x
 // accumulated in T is added to x in FP64, the residual is recomputed as
 // b - H x with the FP64 action, and the CG recursion continues from it with
 // its search direction kept.  Convergence is decided on that FP64 residual.
-template <typename T>
-int pcg_reliable(shp_plan plan, double lambda, const double* b, double* x, long long n, SolveWs& w, const T* dg,
-                 double tol, int max_updates, int max_iter, double delta, double bnorm2, shp_solve_stats* st,
-                 hipStream_t s) {
+template <typename T, typename Op>
+int pcg_reliable(const Op& op, const double* b, double* x, long long n, SolveWs& w, const T* dg, double tol,
+                 int max_updates, int max_iter, double delta, double bnorm2, shp_solve_stats* st, hipStream_t s) {
   T* rs = static_cast<T*>(w.vec);
   T* z = rs + n;
   T* p = z + n;
@@ -268,7 +329,7 @@ int pcg_reliable(shp_plan plan, double lambda, const double* b, double* x, long 
   int stalls = 0, last = 0;
   constexpr int MAX_GAP = 2000;  // iterations between updates at most
   for (int it = 1; it <= max_iter; ++it) {
-    if (int r = apply_inner<T>(plan, p, q, lambda, s)) return r;
+    if (int r = op.template apply<T>(p, q, s)) return r;
     if (int r = dot(p, q, n, w, PQ, s)) return r;
     hipLaunchKernelGGL(k_cg1<T>, g, bl, 0, s, d, rs, p, q, w.slot, n);
     st->inner_iters = it;
@@ -283,7 +344,7 @@ int pcg_reliable(shp_plan plan, double lambda, const double* b, double* x, long 
         hipLaunchKernelGGL(k_copy<double>, g, bl, 0, s, x, w.xb, n);
         hipLaunchKernelGGL(k_update_x<T>, g, bl, 0, s, x, d, w.rmax, n);
         hipLaunchKernelGGL(k_zero<T>, g, bl, 0, s, d, n);
-        if (int r = true_residual<T>(plan, lambda, b, x, n, w, true, s)) return r;
+        if (int r = true_residual<T>(op, b, x, n, w, true, s)) return r;
         if (!readback()) return sfail(SHP_ERR_DEVICE, "solver readback");
         st->outer_iters += 1;
         const double rel = std::sqrt(h[RR] / bnorm2);
@@ -305,7 +366,7 @@ int pcg_reliable(shp_plan plan, double lambda, const double* b, double* x, long 
         } else {
           // no progress: return to the previous x and its residual, restart
           hipLaunchKernelGGL(k_copy<double>, g, bl, 0, s, w.xb, x, n);
-          if (int r = true_residual<T>(plan, lambda, b, x, n, w, true, s)) return r;
+          if (int r = true_residual<T>(op, b, x, n, w, true, s)) return r;
           if (int r = dot(rs, rs, n, w, RR, s)) return r;
           if (!readback()) return sfail(SHP_ERR_DEVICE, "solver readback");
           rr_ref = h[RR];
@@ -326,6 +387,79 @@ int pcg_reliable(shp_plan plan, double lambda, const double* b, double* x, long 
     hipLaunchKernelGGL(k_cg2<T>, g, bl, 0, s, p, z, w.slot, n);
   }
   return sfail(SHP_ERR_NOT_CONVERGED, "the residual did not reach the tolerance (x is the best iterate)");
+}
+
+int check_solve_args(double lambda, double tol, double inner_tol, int max_outer, int max_inner, int inner_prec) {
+  if (!(lambda > 0.0) || !(tol > 0.0) || !(inner_tol > 0.0) || max_outer < 1 || max_inner < 1)
+    return sfail(SHP_ERR_INVALID_ARG, "lambda, tolerances and iteration limits must be positive");
+  if (inner_prec == SHP_BF16) return sfail(SHP_ERR_UNSUPPORTED, "BF16 contractions are not built");
+  if (inner_prec != SHP_FP64 && inner_prec != SHP_FP32) return sfail(SHP_ERR_INVALID_ARG, "bad inner precision");
+  return SHP_OK;
+}
+
+// the solve of op x = b (n unknowns, Jacobi diagonal diag in FP64) on the
+// carved workspace w
+template <typename Op>
+int solve_with(const Op& op, long long n, SolveWs& w, const double* diag, const double* b, double* x, int inner_prec,
+               double tol, int max_outer, int max_inner, double inner_tol, shp_solve_stats* st, hipStream_t s) {
+  const dim3 g = grid_for(n), bl(256);
+  std::memset(st, 0, sizeof *st);
+  if (inner_prec == SHP_FP32) hipLaunchKernelGGL(k_to_float, g, bl, 0, s, diag, w.diagf, n);
+  // ||b|| and the initial FP64 residual
+  if (int r = dot(b, b, n, w, BB, s)) return r;
+  if (int r = (inner_prec == SHP_FP32 ? true_residual<float>(op, b, x, n, w, false, s)
+                                      : true_residual<double>(op, b, x, n, w, false, s)))
+    return r;
+  double hs[NSLOT + 1];
+  if (hipMemcpyAsync(hs, w.slot, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return sfail(SHP_ERR_DEVICE, "solver readback");
+  if (!(hs[BB] > 0.0) || !std::isfinite(hs[BB]))
+    return sfail(SHP_ERR_INVALID_ARG, "b is zero or not finite (relative residual undefined)");
+  st->rel_residual = std::sqrt(hs[RR] / hs[BB]);
+  if (st->rel_residual <= tol) {
+    st->converged = 1;
+    return SHP_OK;
+  }
+  if (inner_prec == SHP_FP32)
+    return pcg_reliable<float>(op, b, x, n, w, w.diagf, tol, max_outer, max_inner, inner_tol, hs[BB], st, s);
+  return pcg_reliable<double>(op, b, x, n, w, diag, tol, max_outer, max_inner, inner_tol, hs[BB], st, s);
+}
+
+// workspace of the assembled solve: the PCG on n_global unknowns, the
+// elemental diagonal's scratch, local copies (FP64 and FP32) and the global
+// diagonal
+struct C0Ws {
+  SolveWs w;
+  void* elem_ws;
+  size_t elem_bytes;
+  double *xl, *yl, *diag;
+  float *xlf, *ylf;
+};
+
+size_t c0_carve(void* base, long long n_local, long long n_global, C0Ws* c) {
+  char* p = static_cast<char*>(base);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char* q = p ? p + o : nullptr;
+    o = align256(o + bytes);
+    return q;
+  };
+  C0Ws t{};
+  const size_t pcg = carve(nullptr, n_global, nullptr);
+  char* pc = take(pcg);
+  t.elem_bytes = carve(nullptr, n_local, nullptr);
+  t.elem_ws = take(t.elem_bytes);
+  t.xl = reinterpret_cast<double*>(take(sizeof(double) * n_local));
+  t.yl = reinterpret_cast<double*>(take(sizeof(double) * n_local));
+  t.xlf = reinterpret_cast<float*>(take(sizeof(float) * n_local));
+  t.ylf = reinterpret_cast<float*>(take(sizeof(float) * n_local));
+  t.diag = reinterpret_cast<double*>(take(sizeof(double) * n_global));
+  if (c) {
+    carve(pc, n_global, &t.w);
+    *c = t;
+  }
+  return o;
 }
 
 }  // namespace
@@ -376,39 +510,65 @@ int shp_helmholtz_solve(shp_plan plan, double lambda, const double* diag, const 
   if (!plan || !diag || !b || !x || !ws || !st) return sfail(SHP_ERR_INVALID_ARG, "null argument");
   const long long n_dof = shp::plan_total_coeff(plan);
   if (n_dof < 1) return sfail(SHP_ERR_INVALID_ARG, "empty mesh");
-  if (!(lambda > 0.0) || !(tol > 0.0) || !(inner_tol > 0.0) || max_outer < 1 || max_inner < 1)
-    return sfail(SHP_ERR_INVALID_ARG, "lambda, tolerances and iteration limits must be positive");
-  if (inner_prec == SHP_BF16) return sfail(SHP_ERR_UNSUPPORTED, "BF16 contractions are not built");
-  if (inner_prec != SHP_FP64 && inner_prec != SHP_FP32) return sfail(SHP_ERR_INVALID_ARG, "bad inner precision");
+  if (int r = check_solve_args(lambda, tol, inner_tol, max_outer, max_inner, inner_prec)) return r;
   if (reinterpret_cast<uintptr_t>(ws) % 256 || ws_bytes < carve(nullptr, n_dof, nullptr))
     return sfail(SHP_ERR_WORKSPACE, "solver workspace missing, misaligned or too small");
   if (int r = shp::plan_check_solve(plan, inner_prec)) return r;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   SolveWs w;
   carve(ws, n_dof, &w);
-  const long long n = n_dof;
-  const dim3 g = grid_for(n), bl(256);
-  std::memset(st, 0, sizeof *st);
-  if (inner_prec == SHP_FP32) hipLaunchKernelGGL(k_to_float, g, bl, 0, s, diag, w.diagf, n);
-  // ||b|| and the initial FP64 residual
-  if (int r = dot(b, b, n, w, BB, s)) return r;
-  if (int r = (inner_prec == SHP_FP32 ? true_residual<float>(plan, lambda, b, x, n, w, false, s)
-                                      : true_residual<double>(plan, lambda, b, x, n, w, false, s)))
-    return r;
-  double hs[NSLOT + 1];
-  if (hipMemcpyAsync(hs, w.slot, sizeof hs, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return sfail(SHP_ERR_DEVICE, "solver readback");
-  if (!(hs[BB] > 0.0) || !std::isfinite(hs[BB]))
-    return sfail(SHP_ERR_INVALID_ARG, "b is zero or not finite (relative residual undefined)");
-  st->rel_residual = std::sqrt(hs[RR] / hs[BB]);
-  if (st->rel_residual <= tol) {
-    st->converged = 1;
-    return SHP_OK;
-  }
-  if (inner_prec == SHP_FP32)
-    return pcg_reliable<float>(plan, lambda, b, x, n, w, w.diagf, tol, max_outer, max_inner, inner_tol, hs[BB], st, s);
-  return pcg_reliable<double>(plan, lambda, b, x, n, w, diag, tol, max_outer, max_inner, inner_tol, hs[BB], st, s);
+  return solve_with(ElemOp{plan, lambda}, n_dof, w, diag, b, x, inner_prec, tol, max_outer, max_inner, inner_tol, st,
+                    static_cast<hipStream_t>(stream));
+}
+
+// ---- C0 (assembled) operator -------------------------------------------
+
+int shp_c0_apply(shp_plan plan, const int64_t* l2g, const int64_t* row_ptr, const int64_t* col, int64_t n_global,
+                 const double* xg, double* yg, double lambda, double* work, void* stream) {
+  if (!plan || !l2g || !row_ptr || !col || !xg || !yg || !work || n_global < 1)
+    return sfail(SHP_ERR_INVALID_ARG, "null argument");
+  const long long n_local = shp::plan_total_coeff(plan);
+  if (n_local < 1) return sfail(SHP_ERR_INVALID_ARG, "empty mesh");
+  if (int r = shp::plan_check_solve(plan, SHP_FP64)) return r;
+  C0Op op{plan, lambda, l2g, row_ptr, col, n_local, n_global, work, work + n_local, nullptr, nullptr};
+  return op.apply64(xg, yg, static_cast<hipStream_t>(stream));
+}
+
+int shp_c0_assemble(const int64_t* row_ptr, const int64_t* col, int64_t n_global, const double* vl, double* vg,
+                    void* stream) {
+  if (!row_ptr || !col || !vl || !vg || n_global < 1) return sfail(SHP_ERR_INVALID_ARG, "null argument");
+  hipLaunchKernelGGL(k_c0_scatter<double>, grid_for(n_global), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     row_ptr, col, (long long)n_global, vl, vg);
+  return hipGetLastError() == hipSuccess ? SHP_OK : sfail(SHP_ERR_DEVICE, "assembly launch");
+}
+
+int shp_c0_solve_workspace_bytes(shp_plan plan, int64_t n_global, size_t* bytes) {
+  if (!plan || !bytes || n_global < 1) return sfail(SHP_ERR_INVALID_ARG, "null argument");
+  *bytes = c0_carve(nullptr, shp::plan_total_coeff(plan), n_global, nullptr);
+  return SHP_OK;
+}
+
+int shp_c0_helmholtz_solve(shp_plan plan, const int64_t* l2g, const int64_t* row_ptr, const int64_t* col,
+                           int64_t n_global, double lambda, const double* b, double* x, int inner_prec, double tol,
+                           int max_outer, int max_inner, double inner_tol, void* ws, size_t ws_bytes,
+                           shp_solve_stats* st, void* stream) {
+  if (!plan || !l2g || !row_ptr || !col || !b || !x || !ws || !st || n_global < 1)
+    return sfail(SHP_ERR_INVALID_ARG, "null argument");
+  const long long n_local = shp::plan_total_coeff(plan);
+  if (n_local < 1) return sfail(SHP_ERR_INVALID_ARG, "empty mesh");
+  if (int r = check_solve_args(lambda, tol, inner_tol, max_outer, max_inner, inner_prec)) return r;
+  if (reinterpret_cast<uintptr_t>(ws) % 256 || ws_bytes < c0_carve(nullptr, n_local, n_global, nullptr))
+    return sfail(SHP_ERR_WORKSPACE, "solver workspace missing, misaligned or too small");
+  if (int r = shp::plan_check_solve(plan, inner_prec)) return r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  C0Ws c;
+  c0_carve(ws, n_local, n_global, &c);
+  // Jacobi diagonal of A^T H A: the elemental diagonals summed over the local
+  // copies of each global DOF
+  if (int r = shp_helmholtz_diag(plan, lambda, c.xl, c.elem_ws, c.elem_bytes, s)) return r;
+  hipLaunchKernelGGL(k_c0_scatter<double>, grid_for(n_global), dim3(256), 0, s, row_ptr, col, (long long)n_global,
+                     c.xl, c.diag);
+  C0Op op{plan, lambda, l2g, row_ptr, col, n_local, n_global, c.xl, c.yl, c.xlf, c.ylf};
+  return solve_with(op, n_global, c.w, c.diag, b, x, inner_prec, tol, max_outer, max_inner, inner_tol, st, s);
 }
 
 }  // extern "C"

@@ -48,6 +48,19 @@ _SIGS = {
     "shp_apply_prec": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                        ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p],
     "shp_solve_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "shp_c0_hex_sizes": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+    "shp_c0_hex_map": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_void_p],
+    "shp_c0_apply": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p],
+    "shp_c0_assemble": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                        ctypes.c_void_p],
+    "shp_c0_solve_workspace_bytes": [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
+    "shp_c0_helmholtz_solve": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                               ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                               ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t,
+                               ctypes.c_void_p, ctypes.c_void_p],
     "shp_helmholtz_diag": [ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                            ctypes.c_void_p],
     "shp_helmholtz_solve": [ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -285,6 +298,73 @@ class Plan:
                                          ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), PREC[inner],
                                          float(tol), int(max_outer), int(max_inner), float(inner_tol), ws, nb,
                                          ctypes.byref(st), _stream(t))
+        stats = {"outer_iters": st.outer_iters, "inner_iters": st.inner_iters, "converged": bool(st.converged),
+                 "rel_residual": st.rel_residual}
+        if code != 0 and (check or code != -7):
+            _check(code)
+        return x, stats
+
+    # ---------------------------------------------------------------
+    def c0_hex_grid(self, n0: int, n1: int, n2: int):
+        """Local-to-global map of the plan's single hex block as an n0 x n1 x n2
+        grid (homogeneous Dirichlet data); returns a C0 handle dict with the
+        device arrays l2g, row_ptr, col and the global size."""
+        import numpy as np
+        t = self._torch
+        (sh, P, ne, _), = self.blocks
+        if sh != "hex" or ne != n0 * n1 * n2:
+            raise ValueError("the plan must hold the grid's hexahedra as its only block")
+        ng, nl, nent = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().shp_c0_hex_sizes(n0, n1, n2, P, ctypes.byref(ng), ctypes.byref(nl), ctypes.byref(nent)))
+        l2g = np.empty(nl.value, dtype=np.int64)
+        rp = np.empty(ng.value + 1, dtype=np.int64)
+        col = np.empty(max(nent.value, 1), dtype=np.int64)
+        _check(lib().shp_c0_hex_map(n0, n1, n2, P, l2g.ctypes.data, rp.ctypes.data, col.ctypes.data))
+        dev = self.device
+        return {"n_global": ng.value, "l2g": t.from_numpy(l2g).to(dev), "row_ptr": t.from_numpy(rp).to(dev),
+                "col": t.from_numpy(col).to(dev)}
+
+    def c0_assemble(self, c0, vl):
+        """A^T vl for a local vector (all coefficients of the block)."""
+        t = self._torch
+        out = t.empty(c0["n_global"], dtype=t.float64, device=vl.device)
+        _check(lib().shp_c0_assemble(ctypes.c_void_p(c0["row_ptr"].data_ptr()), ctypes.c_void_p(c0["col"].data_ptr()),
+                                     c0["n_global"], ctypes.c_void_p(vl.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                     _stream(t)))
+        return out
+
+    def c0_apply(self, c0, xg, lam: float = 1.0, out=None):
+        """Assembled FP64 Helmholtz action A^T H A xg."""
+        t = self._torch
+        nc, _ = self.totals()
+        if out is None:
+            out = t.empty(c0["n_global"], dtype=t.float64, device=xg.device)
+        work = t.empty(2 * nc, dtype=t.float64, device=xg.device)
+        _check(lib().shp_c0_apply(self._h, ctypes.c_void_p(c0["l2g"].data_ptr()),
+                                  ctypes.c_void_p(c0["row_ptr"].data_ptr()), ctypes.c_void_p(c0["col"].data_ptr()),
+                                  c0["n_global"], ctypes.c_void_p(xg.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  float(lam), ctypes.c_void_p(work.data_ptr()), _stream(t)))
+        return out
+
+    def c0_solve(self, c0, b, x=None, lam: float = 1.0, inner: str = "fp32", tol: float = 1e-10,
+                 max_outer: int = 100, max_inner: int = 50000, inner_tol: float = 0.1, check: bool = True):
+        """Solve A^T H A x = b (assembled, Dirichlet DOFs dropped) with the
+        mixed-precision PCG.  Returns (x, stats)."""
+        t = self._torch
+        ng = c0["n_global"]
+        if b.dtype != t.float64 or not b.is_cuda or b.numel() != ng:
+            raise ValueError("b must be a float64 device tensor of the global DOFs")
+        if x is None:
+            x = t.zeros_like(b)
+        nb = ctypes.c_size_t()
+        _check(lib().shp_c0_solve_workspace_bytes(self._h, ng, ctypes.byref(nb)))
+        ws = t.empty(nb.value + 256, dtype=t.uint8, device=b.device)
+        st = SolveStats()
+        code = lib().shp_c0_helmholtz_solve(
+            self._h, ctypes.c_void_p(c0["l2g"].data_ptr()), ctypes.c_void_p(c0["row_ptr"].data_ptr()),
+            ctypes.c_void_p(c0["col"].data_ptr()), ng, float(lam), ctypes.c_void_p(b.data_ptr()),
+            ctypes.c_void_p(x.data_ptr()), PREC[inner], float(tol), int(max_outer), int(max_inner), float(inner_tol),
+            ctypes.c_void_p((ws.data_ptr() + 255) // 256 * 256), nb.value, ctypes.byref(st), _stream(t))
         stats = {"outer_iters": st.outer_iters, "inner_iters": st.inner_iters, "converged": bool(st.converged),
                  "rel_residual": st.rel_residual}
         if code != 0 and (check or code != -7):
