@@ -146,3 +146,26 @@ def test_error_paths_without_device(L):
     assert L.shp_helmholtz_diag(h, 1.0, p, ws, sb.value, None) == -5
     assert L.shp_plan_destroy(h) == 0
     assert L.shp_plan_destroy(None) == -1
+
+
+def test_no_fallback_without_library_or_device(tmp_path):
+    """The binding raises when libshp.so is missing, and a plan needs a HIP
+    device: there is no CPU path."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2604_04644_amd import shp\n"
+        "shp.LIB_PATH = %r\n"
+        "try:\n"
+        "    shp.lib()\n"
+        "except RuntimeError as e:\n"
+        "    print('raised', 'missing' in str(e))\n"
+    ) % (ROOT, str(tmp_path / "absent.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.stdout.strip() == "raised True", r.stdout + r.stderr
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        from paper_2604_04644_amd import shp
+        with pytest.raises(RuntimeError):
+            shp.Plan([("hex", 2, 4, "curved")])
