@@ -81,7 +81,7 @@ struct Dims {
   static constexpr int NC = num_cols(SH, P);
   static constexpr TabLayout L = tab_layout(SH, P);
   static constexpr int NTAB = L.total;
-  static constexpr int NITAB = NC * ICOL;
+  static constexpr int NITAB = NC * ICOL + (P + 2) + NC;  // columns, family starts, family order
   // LDS words (doubles) before the per-element region
   static constexpr int HEAD = NTAB + (NITAB + 1) / 2;
   static constexpr int PER_ELEM = 4 * S3;
@@ -133,23 +133,74 @@ __device__ void load_tables(const OpArgs& a, const Tile_<SH, P, R>& T) {
 }
 
 // The part of the tables the collocated Laplacian / Helmholtz tile reads from
-// LDS: the collapsed shapes' eta3 table C3 and column table, and the tet's
-// eta2 table B2 (lane-uniform tables are read through the constant path).
+// LDS: the collapsed shapes' column table and the tet's eta2 table B2 (tables
+// read at wave-uniform indices go through the constant path).
 template <int SH, int P, typename R>
 __device__ void load_tables_helm(const OpArgs& a, const Tile_<SH, P, R>& T) {
   using D = Dims<SH, P>;
   if (SH == HEX) return;
-  constexpr int nc3 = D::L.nc3 * D::Q, nb2 = (SH == TET) ? D::L.nb2 * D::Q : 0;
-  for (int t = tid(); t < nc3 + nb2; t += nthr()) {
-    const int o = t < nc3 ? D::L.C3 + t : D::L.B2 + (t - nc3);
-    T.tab[o] = (R)a.tab[o];
-  }
+  if (SH == TET)
+    for (int t = tid(); t < D::L.nb2 * D::Q; t += nthr()) T.tab[D::L.B2 + t] = (R)a.tab[D::L.B2 + t];
   for (int t = tid(); t < D::NITAB; t += nthr()) T.itab[t] = a.itab[t];
 }
 
 // ---------------------------------------------------------------------------
 // modes -> points
 // ---------------------------------------------------------------------------
+
+// one eta3 family of a collapsed shape's stage r (see bwd_r), lanes ln of a wave
+template <int SH, int P, bool DER, typename R, int KAP>
+__device__ __forceinline__ void bwd_r_fam(const Tile_<SH, P, R>& T, int ne, int xbuf, int fbuf, int ln) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, RL = P + 1 - KAP;
+  constexpr int ncol = fam_ncols(SH, P, KAP), c0 = fam_start(SH, P, KAP);
+  const int* perm = T.itab + D::NC * ICOL + (P + 2);
+  for (int t = ln; t < ne * ncol; t += 64) {
+    const ctab<R> C3 = launder(T.ct) + (DER ? D::L.dC3 : D::L.C3);
+    const ctab<R> cf = C3 + fam_index(P, KAP, 0) * Q;
+    const ctab<R> V1 = C3 + 1 * Q;  // family (0,1): v1 or its derivative 1/2
+    const int e = t / ncol;
+    const int c = perm[c0 + t - e * ncol];
+    const int* ct = T.itab + c * ICOL;
+    const int p = ct[0], q = ct[1], off = ct[2];
+    const R* x = (xbuf < 0 ? T.U(e) : T.G(e, xbuf));
+    R acc[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const R xr = x[off + r];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) acc[k] = fma(cf[r * Q + k], xr, acc[k]);
+    }
+    // collapsed-vertex modes: extra eta3 term v1 in columns p = 1 (and q = 1)
+    R xe = 0.0;
+    bool extra = false;
+    if (SH == PRISM) {
+      if (p == 1) { xe = x[q * (P + 1) + 1]; extra = true; }
+    } else if (SH == PYR) {
+      if ((p == 1 && q <= 1) || (p == 0 && q == 1)) { xe = x[1]; extra = true; }
+    } else if (SH == TET) {
+      if ((p == 1 && q == 0) || (p == 0 && q == 1)) { xe = x[1]; extra = true; }
+    }
+    if (extra) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) acc[k] = fma(V1[k], xe, acc[k]);
+    }
+    R* f = T.G(e, fbuf) + c * D::QP;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f[k] = acc[k];
+  }
+}
+
+template <int SH, int P, bool DER, typename R, int KAP>
+__device__ __forceinline__ void bwd_r_fams(const Tile_<SH, P, R>& T, int ne, int xbuf, int fbuf, int wv, int nw,
+                                           int ln) {
+  if constexpr (KAP <= P) {
+    if (KAP % nw == wv) bwd_r_fam<SH, P, DER, R, KAP>(T, ne, xbuf, fbuf, ln);
+    bwd_r_fams<SH, P, DER, R, KAP + 1>(T, ne, xbuf, fbuf, wv, nw, ln);
+  }
+}
 
 // stage r: X (modes of element e) -> F[c][k] at c*QP + k
 template <int SH, int P, bool DER, typename R>
@@ -176,43 +227,14 @@ __device__ void bwd_r(const Tile_<SH, P, R>& T, int ne, int xbuf, int fbuf) {
     }
     return;
   }
-  const R* C3 = T.tab + (DER ? D::L.dC3 : D::L.C3);
-  const R* V1 = C3 + 1 * Q;  // family (0,1): v1 or its derivative 1/2
-  for (int t = tid(); t < ne * D::NC; t += nthr()) {
-    const int e = t / D::NC, c = t - e * D::NC;
-    const int* ct = T.itab + c * ICOL;
-    const int p = ct[0], q = ct[1], off = ct[2], RL = ct[3], fb = ct[4];
-    const R* x = (xbuf < 0 ? T.U(e) : T.G(e, xbuf));
-    const R* cf = C3 + fb * Q;
-    R acc[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) acc[k] = 0.0;
-#pragma unroll
-    for (int r = 0; r < n; ++r) {
-      if (r < RL) {
-        const R xr = x[off + r];
-#pragma unroll
-        for (int k = 0; k < Q; ++k) acc[k] = fma(cf[r * Q + k], xr, acc[k]);
-      }
-    }
-    // collapsed-vertex modes: extra eta3 term v1 in columns p = 1 (and q = 1)
-    R xe = 0.0;
-    bool extra = false;
-    if (SH == PRISM) {
-      if (p == 1) { xe = x[q * (P + 1) + 1]; extra = true; }
-    } else if (SH == PYR) {
-      if ((p == 1 && q <= 1) || (p == 0 && q == 1)) { xe = x[1]; extra = true; }
-    } else if (SH == TET) {
-      if ((p == 1 && q == 0) || (p == 0 && q == 1)) { xe = x[1]; extra = true; }
-    }
-    if (extra) {
-#pragma unroll
-      for (int k = 0; k < Q; ++k) acc[k] = fma(V1[k], xe, acc[k]);
-    }
-    R* f = T.G(e, fbuf) + c * D::QP;
-#pragma unroll
-    for (int k = 0; k < Q; ++k) f[k] = acc[k];
-  }
+  // collapsed shapes: the columns grouped by eta3 family kappa share their
+  // table rows and their run length P+1-kappa.  Each wave takes whole
+  // families (kappa = wave, wave + waves, ...; a wave-uniform branch per
+  // family), so the table rows are read through uniform pointers (scalar
+  // loads) and the run length, column count and offsets are constants.
+  const int nw = nthr() >> 6, ln = tid() & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid() >> 6);
+  bwd_r_fams<SH, P, DER, R, 0>(T, ne, xbuf, fbuf, wv, nw, ln);
 }
 
 // stage q: F[c][k] -> G[p][j][k] (p*Q*QP + j*QP + k)
@@ -400,48 +422,29 @@ __device__ void ipr_q(const Tile_<SH, P, R>& T, int ne, int gbuf, int fbuf) {
   }
 }
 
-// stage r^T: F[c][k] (buffer fbuf) -> y modes into buffer ybuf (-1 = U), [NP]
-template <int SH, int P, bool DER, typename R>
-__device__ void ipr_r(const Tile_<SH, P, R>& T, int ne, int fbuf, int ybuf, bool accumulate) {
+// one eta3 family of a collapsed shape's stage r^T (see ipr_r), lanes ln of a wave
+template <int SH, int P, bool DER, typename R, int KAP>
+__device__ __forceinline__ void ipr_r_fam(const Tile_<SH, P, R>& T, int ne, int fbuf, int ybuf, bool accumulate,
+                                          int ln) {
   using D = Dims<SH, P>;
-  constexpr int Q = D::Q, QP = D::QP, n = D::n;
-  if (SH == HEX) {
-    for (int t = tid(); t < ne * D::NC; t += nthr()) {
-      const ctab<R> C3u = launder(T.ct) + (DER ? D::L.dC3 : D::L.C3);
-      const int e = t / D::NC, c = t - e * D::NC;
-      const R* F = T.G(e, fbuf) + c * QP;
-      R f[Q];
-#pragma unroll
-      for (int k = 0; k < Q; ++k) f[k] = F[k];
-      R* y = (ybuf < 0 ? T.U(e) : T.G(e, ybuf)) + c * n;
-#pragma unroll
-      for (int r = 0; r < n; ++r) {
-        R a = 0.0;
-#pragma unroll
-        for (int k = 0; k < Q; ++k) a = fma(C3u[r * Q + k], f[k], a);
-        if (accumulate)
-          y[r] += a;
-        else
-          y[r] = a;
-      }
-    }
-    return;
-  }
-  const R* C3 = T.tab + (DER ? D::L.dC3 : D::L.C3);
-  const R* V1 = C3 + 1 * Q;
-  for (int t = tid(); t < ne * D::NC; t += nthr()) {
-    const int e = t / D::NC, c = t - e * D::NC;
+  constexpr int Q = D::Q, QP = D::QP, RL = P + 1 - KAP;
+  constexpr int ncol = fam_ncols(SH, P, KAP), c0 = fam_start(SH, P, KAP);
+  const int* perm = T.itab + D::NC * ICOL + (P + 2);
+  for (int t = ln; t < ne * ncol; t += 64) {
+    const ctab<R> C3 = launder(T.ct) + (DER ? D::L.dC3 : D::L.C3);
+    const ctab<R> cf = C3 + fam_index(P, KAP, 0) * Q;
+    const ctab<R> V1 = C3 + 1 * Q;
+    const int e = t / ncol;
+    const int c = perm[c0 + t - e * ncol];
     const int* ct = T.itab + c * ICOL;
-    const int p = ct[0], q = ct[1], off = ct[2], RL = ct[3], fb = ct[4];
+    const int p = ct[0], q = ct[1], off = ct[2];
     const R* F = T.G(e, fbuf);
     R f[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) f[k] = F[c * QP + k];
     R* y = (ybuf < 0 ? T.U(e) : T.G(e, ybuf)) + off;
-    const R* cf = C3 + fb * Q;
 #pragma unroll
-    for (int r = 0; r < n; ++r) {
-      if (r >= RL) continue;
+    for (int r = 0; r < RL; ++r) {
       R a = 0.0;
 #pragma unroll
       for (int k = 0; k < Q; ++k) a = fma(cf[r * Q + k], f[k], a);
@@ -476,6 +479,48 @@ __device__ void ipr_r(const Tile_<SH, P, R>& T, int ne, int fbuf, int ybuf, bool
         y[r] = a;
     }
   }
+}
+
+template <int SH, int P, bool DER, typename R, int KAP>
+__device__ __forceinline__ void ipr_r_fams(const Tile_<SH, P, R>& T, int ne, int fbuf, int ybuf, bool accumulate,
+                                           int wv, int nw, int ln) {
+  if constexpr (KAP <= P) {
+    if (KAP % nw == wv) ipr_r_fam<SH, P, DER, R, KAP>(T, ne, fbuf, ybuf, accumulate, ln);
+    ipr_r_fams<SH, P, DER, R, KAP + 1>(T, ne, fbuf, ybuf, accumulate, wv, nw, ln);
+  }
+}
+
+// stage r^T: F[c][k] (buffer fbuf) -> y modes into buffer ybuf (-1 = U), [NP]
+template <int SH, int P, bool DER, typename R>
+__device__ void ipr_r(const Tile_<SH, P, R>& T, int ne, int fbuf, int ybuf, bool accumulate) {
+  using D = Dims<SH, P>;
+  constexpr int Q = D::Q, QP = D::QP, n = D::n;
+  if (SH == HEX) {
+    for (int t = tid(); t < ne * D::NC; t += nthr()) {
+      const ctab<R> C3u = launder(T.ct) + (DER ? D::L.dC3 : D::L.C3);
+      const int e = t / D::NC, c = t - e * D::NC;
+      const R* F = T.G(e, fbuf) + c * QP;
+      R f[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) f[k] = F[k];
+      R* y = (ybuf < 0 ? T.U(e) : T.G(e, ybuf)) + c * n;
+#pragma unroll
+      for (int r = 0; r < n; ++r) {
+        R a = 0.0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) a = fma(C3u[r * Q + k], f[k], a);
+        if (accumulate)
+          y[r] += a;
+        else
+          y[r] = a;
+      }
+    }
+    return;
+  }
+  // columns grouped by eta3 family, whole families per wave (as in bwd_r)
+  const int nw = nthr() >> 6, ln = tid() & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid() >> 6);
+  ipr_r_fams<SH, P, DER, R, 0>(T, ne, fbuf, ybuf, accumulate, wv, nw, ln);
 }
 
 // ---------------------------------------------------------------------------

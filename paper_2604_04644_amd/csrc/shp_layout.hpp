@@ -37,6 +37,16 @@ constexpr int col_base(int sh, int P, int p) {
 constexpr int kappa3(int sh, int p, int q) {
   return sh == HEX ? 0 : sh == PRISM ? p : sh == PYR ? imax(p, q) : p + q;
 }
+// columns (p, q) of the eta3 family kappa, and the first of them in the
+// family-major column order (prism: kappa = p; pyramid: max(p, q); tet: p + q)
+constexpr int fam_ncols(int sh, int P, int kappa) {
+  return sh == PRISM ? P + 1 : sh == PYR ? 2 * kappa + 1 : sh == TET ? kappa + 1 : (P + 1) * (P + 1);
+}
+constexpr int fam_start(int sh, int P, int kappa) {
+  int s = 0;
+  for (int k = 0; k < kappa; ++k) s += fam_ncols(sh, P, k);
+  return s;
+}
 // Jacobi exponent of the rule in direction d (0: GLL)
 constexpr int alpha_dir(int sh, int d) {
   return d == 0 ? 0 : d == 1 ? (sh == TET ? 1 : 0) : (sh == HEX ? 0 : sh == PRISM ? 1 : 2);

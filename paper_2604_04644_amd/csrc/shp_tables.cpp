@@ -172,9 +172,10 @@ void build_tables(int sh, int P, std::vector<double>& tab, std::vector<int>& ita
       }
   for (int d = 0; d < 3; ++d) colloc_deriv(Q, z + d * Q, tab.data() + L.D + d * Q * Q);
 
-  // column table, p-major, q, with the running mode offset
+  // column table, p-major, q, with the running mode offset; then the columns
+  // grouped by eta3 family kappa: family starts [P + 2] and the column order [NC]
   const int NC = num_cols(sh, P);
-  itab.assign(NC * ICOL, 0);
+  itab.assign(NC * ICOL + (P + 2) + NC, 0);
   int c = 0, off = 0;
   for (int p = 0; p <= P; ++p)
     for (int q = 0; q < nq_of(sh, P, p); ++q) {
@@ -187,6 +188,17 @@ void build_tables(int sh, int P, std::vector<double>& tab, std::vector<int>& ita
       off += ct[3];
       ++c;
     }
+  int* fst = itab.data() + NC * ICOL;
+  int* perm = fst + (P + 2);
+  int k = 0;
+  for (int kap = 0; kap <= P; ++kap) {
+    fst[kap] = k;
+    for (int cc = 0; cc < NC; ++cc) {
+      const int* ct = itab.data() + cc * ICOL;
+      if (kappa3(sh, ct[0], ct[1]) == kap) perm[k++] = cc;
+    }
+  }
+  fst[P + 1] = k;
 }
 
 // Dense reference matrices [B; d_1 B; d_2 B; d_3 B] at the quadrature points
