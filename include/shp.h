@@ -35,8 +35,11 @@
  *   with the collapsed-vertex modes prism (0,q,1), pyramid (0,0,1), tet (0,0,1)
  *   and (0,1,r) independent of the collapsed coordinate(s).
  * - Quadrature: Q points per direction; Gauss-Lobatto-Legendre in directions
- *   that are not collapsed, Gauss-Jacobi(alpha,0) in a direction collapsed
- *   alpha times (prism eta3: 1, pyramid eta3: 2, tet eta2: 1, eta3: 2).
+ *   that are not collapsed, and in a direction collapsed alpha times (prism
+ *   eta3: 1, pyramid eta3: 2, tet eta2: 1, eta3: 2) Gauss-Jacobi(alpha,0)
+ *   (SHP_PTS_GJ, the default) or Gauss-Radau-Jacobi(alpha,0) with the node
+ *   eta = -1 (SHP_PTS_RADAU).  Hexahedra have no collapsed direction, so the
+ *   choice does not change them.
  *   This build supports 1 <= P <= 10 and Q = P + 2 (Sec. 2.1: at least P+2
  *   points per direction).
  *
@@ -66,6 +69,7 @@ extern "C" {
 
 typedef enum { SHP_HEX = 0, SHP_PRISM = 1, SHP_PYR = 2, SHP_TET = 3 } shp_shape;
 typedef enum { SHP_AFFINE = 0, SHP_CURVED = 1 } shp_geom;
+typedef enum { SHP_PTS_GJ = 0, SHP_PTS_RADAU = 1 } shp_points;
 typedef enum {
   SHP_OP_BWDTRANS = 0,       /* [n][N_P] -> [n][N_Q]   u = B x                      */
   SHP_OP_IPRODUCT = 1,       /* [n][N_Q] -> [n][N_P]   y = B^T W f                  */
@@ -95,6 +99,7 @@ typedef struct {
   int Q;           /* points per direction, P + 2 */
   int64_t n_elem;  /* elements in the block, >= 0 */
   int geom;        /* shp_geom: SHP_CURVED takes d x/d xi per point, SHP_AFFINE per element */
+  int pts;         /* shp_points of the collapsed directions; 0 (SHP_PTS_GJ) by default */
 } shp_block_desc;
 
 typedef struct shp_plan_s* shp_plan;
@@ -106,10 +111,11 @@ int shp_num_modes(int shape, int P, int* n_modes /* host out */);
 int shp_num_points(int shape, int Q, int* n_points /* host out */);
 
 /* The block's quadrature points in reference coordinates and their weights
- * (Sec. 2.1 tensor quadrature; Sec. 2.3 collapse).  xi: host [3][Q^3], component
- * slowest; w: host [Q^3] = product of the three 1D weights, may be NULL.
- * The mesh's Jacobian d x/d xi is expected at exactly these points. */
-int shp_quadrature(int shape, int Q, double* xi /* host out */, double* w /* host out or NULL */);
+ * (Sec. 2.1 tensor quadrature; Sec. 2.3 collapse) for point set pts
+ * (shp_points).  xi: host [3][Q^3], component slowest; w: host [Q^3] = product
+ * of the three 1D weights, may be NULL.  The mesh's Jacobian d x/d xi is
+ * expected at exactly these points. */
+int shp_quadrature(int shape, int Q, int pts, double* xi /* host out */, double* w /* host out or NULL */);
 
 /* Create a plan for nblk blocks (host metadata only; copies blk). */
 int shp_plan_create(shp_plan* plan /* host out */, const shp_block_desc* blk /* host [nblk] */,
@@ -145,8 +151,11 @@ int shp_block_offsets(shp_plan plan, int blk, int64_t* coeff_off /* host out */,
  * launch over all blocks when they share P and Q; tiles of all blocks are
  * ordered longest first).  in/out are FP64 device buffers in the layouts
  * above; in and out must not overlap.  lambda is used by SHP_OP_HELMHOLTZ.
- * Read-only on the workspace: applies on different streams may run
- * concurrently. */
+ * The first whole-mesh apply of an operator after the workspace is bound (and
+ * the first after its tiling changes) writes that operator's tile list into the
+ * workspace and synchronises the stream; otherwise the call is read-only on
+ * the workspace and applies on different streams may run concurrently.  Make
+ * one whole-mesh apply of each operator first before applying concurrently. */
 int shp_apply(shp_plan plan, int blk, int op, int strategy, const double* in /* device */,
               double* out /* device */, double lambda, void* stream);
 

@@ -37,7 +37,8 @@ the design notes):
                                               (0,1,r) -> v1(eta2) C_{1,r}(eta3)
 * quadrature, Q points per direction: Gauss-Lobatto-Legendre in the directions
   that are not collapsed, Gauss-Jacobi (alpha,0) in a direction collapsed alpha
-  times (prism eta3: 1; pyramid eta3: 2; tet eta2: 1, eta3: 2); the Jacobi weight
+  times (prism eta3: 1; pyramid eta3: 2; tet eta2: 1, eta3: 2), or on request
+  Gauss-Radau-Jacobi (alpha,0) there, which includes eta = -1; the Jacobi weight
   (1-eta)^alpha is divided back out of the integrand;
 * point index (i*Q + j)*Q + k with k (eta3) fastest.
 
@@ -107,6 +108,37 @@ def gauss_jacobi(Q: int, a: float, b: float):
     return x, w
 
 
+def gauss_radau_jacobi(Q: int, a: float, b: float):
+    """Q-point Gauss-Radau rule for the weight (1-x)^a (1+x)^b with the node
+    x = -1 fixed (Golub's modification of Golub-Welsch): the last diagonal entry
+    of the Jacobi matrix is replaced so that the monic degree-Q polynomial of
+    the modified recurrence vanishes at -1, i.e.
+    alpha'_{Q-1} = -1 - beta_{Q-1} p_{Q-2}(-1) / p_{Q-1}(-1) with p_k the monic
+    orthogonal polynomials; nodes and weights then follow as in gauss_jacobi."""
+    if Q == 1:
+        mu0 = 2.0 ** (a + b + 1.0) * math.gamma(a + 1.0) * math.gamma(b + 1.0) / math.gamma(a + b + 2.0)
+        return np.array([-1.0]), np.array([mu0])
+    k = np.arange(Q, dtype=np.float64)
+    alpha = np.empty(Q)
+    alpha[0] = (b - a) / (a + b + 2.0)
+    c = 2.0 * k[1:] + a + b
+    alpha[1:] = (b * b - a * a) / (c * (c + 2.0))
+    kb = np.arange(1, Q, dtype=np.float64)
+    c = 2.0 * kb + a + b
+    beta = 4.0 * kb * (kb + a) * (kb + b) * (kb + a + b) / (c * c * (c + 1.0) * (c - 1.0))
+    # monic p_0 .. p_{Q-1} at x = -1 by the three-term recurrence
+    pm, pk = 0.0, 1.0
+    for j in range(Q - 1):
+        pm, pk = pk, (-1.0 - alpha[j]) * pk - (beta[j - 1] * pm if j > 0 else 0.0)
+    alpha_mod = alpha.copy()
+    alpha_mod[Q - 1] = -1.0 - beta[Q - 2] * pm / pk
+    T = np.diag(alpha_mod) + np.diag(np.sqrt(beta), 1) + np.diag(np.sqrt(beta), -1)
+    x, V = np.linalg.eigh(T)
+    mu0 = 2.0 ** (a + b + 1.0) * math.gamma(a + 1.0) * math.gamma(b + 1.0) / math.gamma(a + b + 2.0)
+    w = mu0 * V[0, :] ** 2
+    return x, w
+
+
 def gauss_lobatto_legendre(Q: int):
     """Q-point Gauss-Lobatto-Legendre rule: the end points and the zeros of
     P'_{Q-1} (the Gauss-Jacobi(1,1) nodes), weights 2 / (Q (Q-1) P_{Q-1}(x)^2)."""
@@ -128,9 +160,19 @@ ALPHA = {"hex": (0, 0, 0), "prism": (0, 0, 1), "pyr": (0, 0, 2), "tet": (0, 1, 2
 VOLUME = {"hex": 8.0, "prism": 4.0, "pyr": 8.0 / 3.0, "tet": 4.0 / 3.0}
 
 
-def rule_1d(Q: int, alpha: int):
+POINTS = ("gj", "radau")
+
+
+def rule_1d(Q: int, alpha: int, pts: str = "gj"):
+    """GLL in a direction that is not collapsed; in a direction collapsed alpha
+    times, Gauss-Jacobi(alpha,0) ("gj") or Gauss-Radau-Jacobi(alpha,0) with the
+    node -1 ("radau")."""
+    if pts not in POINTS:
+        raise ValueError(pts)
     if alpha == 0:
         return gauss_lobatto_legendre(Q)
+    if pts == "radau":
+        return gauss_radau_jacobi(Q, float(alpha), 0.0)
     return gauss_jacobi(Q, float(alpha), 0.0)
 
 
@@ -176,16 +218,16 @@ def dxi_deta(shape: str, eta: np.ndarray) -> np.ndarray:
     return M
 
 
-def points_1d(shape: str, Q: int):
+def points_1d(shape: str, Q: int, pts: str = "gj"):
     """The three 1D rules (nodes, weights) of a shape."""
-    return [rule_1d(Q, a) for a in ALPHA[shape]]
+    return [rule_1d(Q, a, pts) for a in ALPHA[shape]]
 
 
-def quadrature(shape: str, Q: int):
+def quadrature(shape: str, Q: int, pts: str = "gj"):
     """Tensor points in eta [Q^3, 3] (k fastest), the products of the 1D weights
     [Q^3], and the divisor prod (1 - eta_d)^alpha_d [Q^3] that removes the Jacobi
     weight functions from the rule."""
-    r = points_1d(shape, Q)
+    r = points_1d(shape, Q, pts)
     z1, z2, z3 = (r[d][0] for d in range(3))
     w1, w2, w3 = (r[d][1] for d in range(3))
     E1, E2, E3 = np.meshgrid(z1, z2, z3, indexing="ij")
@@ -196,15 +238,15 @@ def quadrature(shape: str, Q: int):
     return eta, w, div
 
 
-def reference_points(shape: str, Q: int) -> np.ndarray:
+def reference_points(shape: str, Q: int, pts: str = "gj") -> np.ndarray:
     """Quadrature points in reference coordinates xi, [Q^3, 3]."""
-    eta, _, _ = quadrature(shape, Q)
+    eta, _, _ = quadrature(shape, Q, pts)
     return collapse(shape, eta)
 
 
-def integrate_reference(shape: str, Q: int, f) -> float:
+def integrate_reference(shape: str, Q: int, f, pts: str = "gj") -> float:
     """Quadrature of f(xi) over the reference element."""
-    eta, w, div = quadrature(shape, Q)
+    eta, w, div = quadrature(shape, Q, pts)
     xi = collapse(shape, eta)
     det = np.linalg.det(dxi_deta(shape, eta))
     return float(np.sum(w * det / div * f(xi)))
@@ -367,12 +409,12 @@ def _jac_xi(jac: np.ndarray, npts: int) -> np.ndarray:
     return np.transpose(jac, (0, 2, 1)).reshape(jac.shape[0], npts, 3, 3)
 
 
-def geometry(shape: str, Q: int, jac: np.ndarray):
+def geometry(shape: str, Q: int, jac: np.ndarray, pts: str = "gj"):
     """Per-point weights jw = w |det d x/d eta| / prod (1-eta)^alpha and the
     inverse Jacobian d eta_d / d x_i, computed by numerically inverting
     d x/d eta = (d x/d xi)(d xi/d eta).  Returns jw [n_elem, n_pts] and
     deta_dx [n_elem, n_pts, 3(d), 3(i)]."""
-    eta, w, div = quadrature(shape, Q)
+    eta, w, div = quadrature(shape, Q, pts)
     npts = eta.shape[0]
     Jxi = _jac_xi(jac, npts)
     Jeta = np.einsum("epia,pab->epib", Jxi, dxi_deta(shape, eta))
@@ -384,10 +426,10 @@ def geometry(shape: str, Q: int, jac: np.ndarray):
     return jw, deta_dx
 
 
-def geometric_factors(shape: str, Q: int, jac: np.ndarray):
+def geometric_factors(shape: str, Q: int, jac: np.ndarray, pts: str = "gj"):
     """jw, the symmetric metric g_de = jw sum_i (d eta_d/d x_i)(d eta_e/d x_i)
     [n_elem, n_pts, 3, 3] and d eta/d x."""
-    jw, G = geometry(shape, Q, jac)
+    jw, G = geometry(shape, Q, jac, pts)
     g = jw[..., None, None] * np.einsum("epdi,epei->epde", G, G)
     return jw, g, G
 
@@ -406,10 +448,10 @@ def lagrange_deriv_1d(z: np.ndarray) -> np.ndarray:
     return np.linalg.solve(V.T, Vd.T).T
 
 
-def deriv_matrices(shape: str, Q: int):
+def deriv_matrices(shape: str, Q: int, pts: str = "gj"):
     """Collocation derivatives in eta_1, eta_2, eta_3 on the tensor points,
     three [Q^3, Q^3] matrices."""
-    r = points_1d(shape, Q)
+    r = points_1d(shape, Q, pts)
     I = np.eye(Q)
     D = [lagrange_deriv_1d(r[d][0]) for d in range(3)]
     return [np.kron(np.kron(D[0], I), I), np.kron(np.kron(I, D[1]), I), np.kron(np.kron(I, I), D[2])]
@@ -422,14 +464,14 @@ def deriv_matrices(shape: str, Q: int):
 class Element:
     """Dense operators of a batch of elements of one shape.
 
-    jac: d x_i/d xi_j at the oracle's quadrature points, [n_elem][9][Q^3], or
-    constant per element [n_elem][9]."""
+    jac: d x_i/d xi_j at the oracle's quadrature points of point set pts,
+    [n_elem][9][Q^3], or constant per element [n_elem][9]."""
 
-    def __init__(self, shape: str, P: int, Q: int, jac: np.ndarray):
-        self.shape, self.P, self.Q = shape, P, Q
-        eta, _, _ = quadrature(shape, Q)
+    def __init__(self, shape: str, P: int, Q: int, jac: np.ndarray, pts: str = "gj"):
+        self.shape, self.P, self.Q, self.pts = shape, P, Q, pts
+        eta, _, _ = quadrature(shape, Q, pts)
         self.B, self.dB = basis(shape, P, eta)                # [nq,np], [3,nq,np]
-        self.jw, self.G = geometry(shape, Q, jac)             # [ne,nq], [ne,nq,d,i]
+        self.jw, self.G = geometry(shape, Q, jac, pts)        # [ne,nq], [ne,nq,d,i]
         # d phi / d x_i at the points: sum_d (d eta_d/d x_i) d phi/d eta_d
         self.dBx = np.einsum("eqdi,dqm->eiqm", self.G, self.dB)
 
@@ -467,7 +509,7 @@ class Element:
 
     def phys_deriv(self, u):
         """d u/d x_i at the points of the Lagrange interpolant of u, [3, n_elem, N_Q]."""
-        D = deriv_matrices(self.shape, self.Q)
+        D = deriv_matrices(self.shape, self.Q, self.pts)
         du = np.stack([u @ Dd.T for Dd in D], axis=0)       # [3(d), ne, nq]
         return np.einsum("eqdi,deq->ieq", self.G, du)
 
@@ -481,7 +523,7 @@ class Element:
         return np.einsum("emn,en->em", self.helmholtz(lam), x)
 
 
-def apply_op(op: str, shape: str, P: int, Q: int, jac, x, lam: float = 1.0, chunk: int = 512):
+def apply_op(op: str, shape: str, P: int, Q: int, jac, x, lam: float = 1.0, chunk: int = 512, pts: str = "gj"):
     """One operator over a batch, processed in chunks of elements.
     op in {bwd, iprod, physderiv, iprod_deriv, mass, laplacian, helmholtz}."""
     x = np.asarray(x, dtype=np.float64)
@@ -490,7 +532,7 @@ def apply_op(op: str, shape: str, P: int, Q: int, jac, x, lam: float = 1.0, chun
     outs = []
     for e0 in range(0, ne, chunk):
         e1 = min(ne, e0 + chunk)
-        el = Element(shape, P, Q, jac[e0:e1])
+        el = Element(shape, P, Q, jac[e0:e1], pts)
         if op == "bwd":
             outs.append(el.bwd_trans(x[e0:e1]))
         elif op == "iprod":
@@ -511,7 +553,7 @@ def apply_op(op: str, shape: str, P: int, Q: int, jac, x, lam: float = 1.0, chun
     return np.concatenate(outs, axis=axis)
 
 
-def helmholtz_solve(shape: str, P: int, Q: int, jac, b, lam: float = 1.0, chunk: int = 512):
+def helmholtz_solve(shape: str, P: int, Q: int, jac, b, lam: float = 1.0, chunk: int = 512, pts: str = "gj"):
     """x with H_e x_e = b_e for every element, by dense Cholesky (H_e is SPD for
     lambda > 0)."""
     b = np.asarray(b, dtype=np.float64)
@@ -519,7 +561,7 @@ def helmholtz_solve(shape: str, P: int, Q: int, jac, b, lam: float = 1.0, chunk:
     out = []
     for e0 in range(0, jac.shape[0], chunk):
         e1 = min(jac.shape[0], e0 + chunk)
-        H = Element(shape, P, Q, jac[e0:e1]).helmholtz(lam)
+        H = Element(shape, P, Q, jac[e0:e1], pts).helmholtz(lam)
         Lc = np.linalg.cholesky(H)
         y = np.linalg.solve(Lc, b[e0:e1][..., None])
         out.append(np.linalg.solve(np.transpose(Lc, (0, 2, 1)), y)[..., 0])

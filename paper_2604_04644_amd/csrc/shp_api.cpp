@@ -169,11 +169,12 @@ int shp_num_points(int shape, int Q, int* n) {
   return SHP_OK;
 }
 
-int shp_quadrature(int shape, int Q, double* xi, double* w) {
+int shp_quadrature(int shape, int Q, int pts, double* xi, double* w) {
   if (!xi) return fail(SHP_ERR_INVALID_ARG, "null xi");
   if (!valid_shape(shape)) return fail(SHP_ERR_INVALID_ARG, "bad shape %d", shape);
+  if (pts != SHP_PTS_GJ && pts != SHP_PTS_RADAU) return fail(SHP_ERR_INVALID_ARG, "bad point set %d", pts);
   if (Q < 3 || Q > MAX_P + 2) return fail(SHP_ERR_UNSUPPORTED, "Q=%d outside [3,%d]", Q, MAX_P + 2);
-  reference_points(shape, Q, xi, w);
+  reference_points(shape, Q, pts, xi, w);
   return SHP_OK;
 }
 
@@ -187,6 +188,7 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     if (d.Q != d.P + 2) return fail(SHP_ERR_UNSUPPORTED, "block %d: Q=%d, only Q=P+2 is built", b, d.Q);
     if (d.n_elem < 0 || d.n_elem > (1LL << 31)) return fail(SHP_ERR_INVALID_ARG, "block %d: n_elem=%lld", b, (long long)d.n_elem);
     if (d.geom != SHP_AFFINE && d.geom != SHP_CURVED) return fail(SHP_ERR_INVALID_ARG, "block %d: bad geom %d", b, d.geom);
+    if (d.pts != SHP_PTS_GJ && d.pts != SHP_PTS_RADAU) return fail(SHP_ERR_INVALID_ARG, "block %d: bad point set %d", b, d.pts);
   }
   shp_plan p = new (std::nothrow) shp_plan_s;
   if (!p) return fail(SHP_ERR_INVALID_ARG, "out of host memory");
@@ -202,11 +204,11 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     B.d = blk[b];
     B.NP = num_modes(B.d.shape, B.d.P);
     B.NQ = B.d.Q * B.d.Q * B.d.Q;
-    build_tables(B.d.shape, B.d.P, B.tab, B.itab);
+    build_tables(B.d.shape, B.d.P, B.d.pts, B.tab, B.itab);
     if (B.d.P <= LOCALMAT_MAX_P) {
       int q3p, kp;
-      build_localmat(B.d.shape, B.d.P, B.lm, q3p, kp);
-      if (B.d.geom == SHP_AFFINE) build_affine_mats(B.d.shape, B.d.P, B.am, kp);
+      build_localmat(B.d.shape, B.d.P, B.d.pts, B.lm, q3p, kp);
+      if (B.d.geom == SHP_AFFINE) build_affine_mats(B.d.shape, B.d.P, B.d.pts, B.am, kp);
     }
     B.coeff_off = cofs;
     B.phys_off = pofs;

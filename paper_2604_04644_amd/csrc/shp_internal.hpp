@@ -35,15 +35,16 @@ struct BlockStatic {
 // host tables (shp_tables.cpp)
 void gauss_jacobi(int Q, double a, double b, double* x, double* w);
 void gauss_lobatto(int Q, double* x, double* w);
-void rule_1d(int Q, int alpha, double* x, double* w);
-void build_tables(int sh, int P, std::vector<double>& tab, std::vector<int>& itab);
-void reference_points(int sh, int Q, double* xi, double* w);
-void build_localmat(int sh, int P, std::vector<double>& bcat, int& Q3p, int& Kp);
+void gauss_radau_jacobi(int Q, double a, double b, double* x, double* w);
+void rule_1d(int Q, int alpha, int pts, double* x, double* w);
+void build_tables(int sh, int P, int pts, std::vector<double>& tab, std::vector<int>& itab);
+void reference_points(int sh, int Q, int pts, double* xi, double* w);
+void build_localmat(int sh, int P, int pts, std::vector<double>& bcat, int& Q3p, int& Kp);
 constexpr int LOCALMAT_MAX_P = 4;  // dense reference matrices only at low order
 // affine blocks: the 7 reference matrices of H = sum_k c_{e,k} A_k in MFMA
 // fragment order (Kp = modes padded to 16, 7 Kp^2 values); coefficients per element
 // (|J|, |J| K00, |J| K01, |J| K02, |J| K11, |J| K12, |J| K22), K = J^-1 J^-T
-void build_affine_mats(int sh, int P, std::vector<double>& acat, int& Kp);
+void build_affine_mats(int sh, int P, int pts, std::vector<double>& acat, int& Kp);
 constexpr int NAFF = 7;
 
 // launchers (shp_k_*.hip); return hipSuccess or the launch error

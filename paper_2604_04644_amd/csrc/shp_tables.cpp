@@ -5,13 +5,15 @@
 // Quadrature (Sec. 2.1): Gauss-Jacobi zeros by Newton iteration on the Jacobi
 // polynomial with deflation of the zeros already found, weights from the
 // Christoffel closed form; Gauss-Lobatto-Legendre as the end points plus the
-// Gauss-Jacobi(1,1) zeros, weights 2 / (Q (Q-1) P_{Q-1}(x)^2).
+// Gauss-Jacobi(1,1) zeros, weights 2 / (Q (Q-1) P_{Q-1}(x)^2); Gauss-Radau-
+// Jacobi as -1 plus the Gauss-Jacobi(a, b+1) zeros.
 // Collocation derivative (Sec. 2.2, eq. dphitodh): barycentric form of the
 // derivative of the Lagrange interpolant, D_ij = (l_j / l_i) / (x_i - x_j),
 // D_ii = -sum_{j != i} D_ij.
 #include <cmath>
 #include <vector>
 
+#include "../../include/shp.h"
 #include "shp_internal.hpp"
 
 namespace shp {
@@ -79,9 +81,27 @@ void gauss_lobatto(int Q, double* x, double* w) {
   }
 }
 
-void rule_1d(int Q, int alpha, double* x, double* w) {
+// Gauss-Radau-Jacobi with the node -1: for f of degree <= 2Q-2 write
+// f(x) = f(-1) + (1 + x) g(x); g is integrated exactly under the weight
+// (1-x)^a (1+x)^(b+1) by the (Q-1)-point Gauss-Jacobi(a, b+1) rule, so the other
+// nodes are its zeros with weights w_i / (1 + x_i), and the weight of -1 is the
+// closed form 2^(a+b+1) (b+1) G(b+1)^2 G(Q) G(Q+a) / (G(Q+b+1) G(Q+a+b+1)).
+void gauss_radau_jacobi(int Q, double a, double b, double* x, double* w) {
+  x[0] = -1.0;
+  const double l0 = (a + b + 1.0) * std::log(2.0) + std::log(b + 1.0) + 2.0 * std::lgamma(b + 1.0) +
+                    std::lgamma((double)Q) + std::lgamma(Q + a) - std::lgamma(Q + b + 1.0) - std::lgamma(Q + a + b + 1.0);
+  w[0] = std::exp(l0);
+  if (Q > 1) {
+    gauss_jacobi(Q - 1, a, b + 1.0, x + 1, w + 1);
+    for (int i = 1; i < Q; ++i) w[i] /= (1.0 + x[i]);
+  }
+}
+
+void rule_1d(int Q, int alpha, int pts, double* x, double* w) {
   if (alpha == 0)
     gauss_lobatto(Q, x, w);
+  else if (pts == SHP_PTS_RADAU)
+    gauss_radau_jacobi(Q, (double)alpha, 0.0, x, w);
   else
     gauss_jacobi(Q, (double)alpha, 0.0, x, w);
 }
@@ -134,13 +154,13 @@ static void colloc_deriv(int Q, const double* x, double* D) {
   }
 }
 
-void build_tables(int sh, int P, std::vector<double>& tab, std::vector<int>& itab) {
+void build_tables(int sh, int P, int pts, std::vector<double>& tab, std::vector<int>& itab) {
   const TabLayout L = tab_layout(sh, P);
   const int Q = L.Q, n = L.n;
   tab.assign(L.total, 0.0);
   double* z = tab.data() + L.z;
   double* w = tab.data() + L.w;
-  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), z + d * Q, w + d * Q);
+  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), pts, z + d * Q, w + d * Q);
   const double* z1 = z;
   const double* z2 = z + Q;
   const double* z3 = z + 2 * Q;
@@ -206,13 +226,13 @@ void build_tables(int sh, int P, std::vector<double>& tab, std::vector<int>& ita
 // multiple of 16, columns to a multiple of 16 (zeros).  Each mode is a product
 // of 1D functions of eta (the collapsed-vertex modes drop the factors of the
 // collapsed coordinates), differentiated factor by factor.
-void build_localmat(int sh, int P, std::vector<double>& bcat, int& Q3p, int& Kp) {
+void build_localmat(int sh, int P, int pts, std::vector<double>& bcat, int& Q3p, int& Kp) {
   const int Q = P + 2, Q3 = Q * Q * Q, NP = num_modes(sh, P);
   Q3p = (Q3 + 15) / 16 * 16;
   Kp = (NP + 15) / 16 * 16;
   bcat.assign((size_t)4 * Q3p * Kp, 0.0);
   std::vector<double> z(3 * Q), w(3 * Q);
-  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), z.data() + d * Q, w.data() + d * Q);
+  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), pts, z.data() + d * Q, w.data() + d * Q);
   // 1D factor kinds: 0 = constant 1, 1 = A_p, 2 = C_{k,r}, 3 = v1
   struct F { int kind, a, b; };
   auto fval = [](const F& f, double x, bool der) {
@@ -285,13 +305,13 @@ static void collapse_deriv(int sh, double e1, double e2, double e3, double G[9],
   }
 }
 
-void build_affine_mats(int sh, int P, std::vector<double>& acat, int& Kp) {
+void build_affine_mats(int sh, int P, int pts, std::vector<double>& acat, int& Kp) {
   std::vector<double> bcat;
   int Q3p = 0;
-  build_localmat(sh, P, bcat, Q3p, Kp);
+  build_localmat(sh, P, pts, bcat, Q3p, Kp);
   const int Q = P + 2, Q3 = Q * Q * Q, NP = num_modes(sh, P);
   std::vector<double> z(3 * Q), w(3 * Q);
-  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), z.data() + d * Q, w.data() + d * Q);
+  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), pts, z.data() + d * Q, w.data() + d * Q);
   // reference weights and xi-derivatives of the modes at the points
   std::vector<double> wr(Q3), dx((size_t)3 * Q3 * NP);
   for (int i = 0; i < Q; ++i)
@@ -344,9 +364,9 @@ void build_affine_mats(int sh, int P, std::vector<double>& acat, int& Kp) {
   acat.swap(frag);
 }
 
-void reference_points(int sh, int Q, double* xi, double* wout) {
+void reference_points(int sh, int Q, int pts, double* xi, double* wout) {
   std::vector<double> z(3 * Q), w(3 * Q);
-  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), z.data() + d * Q, w.data() + d * Q);
+  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), pts, z.data() + d * Q, w.data() + d * Q);
   const int Q3 = Q * Q * Q;
   for (int i = 0; i < Q; ++i)
     for (int j = 0; j < Q; ++j)

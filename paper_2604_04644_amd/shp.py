@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libshp.so")
 
 SHAPES = {"hex": 0, "prism": 1, "pyr": 2, "tet": 3}
 GEOM = {"affine": 0, "curved": 1}
+POINTS = {"gj": 0, "radau": 1}
 OPS = {"bwd": 0, "iprod": 1, "physderiv": 2, "iprod_deriv": 3, "mass": 4, "laplacian": 5, "helmholtz": 6}
 STRATEGY = {"auto": 0, "sumfac": 1, "sumfac_coll": 2, "localmat": 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
@@ -25,7 +26,7 @@ ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "BAD_GEOMETRY", -4:
 _SIGS = {
     "shp_num_modes": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "shp_num_points": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
-    "shp_quadrature": [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
+    "shp_quadrature": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
     "shp_plan_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_int],
     "shp_plan_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
     "shp_plan_bind_workspace": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
@@ -98,7 +99,7 @@ class ShpError(RuntimeError):
 
 class _BlockDesc(ctypes.Structure):
     _fields_ = [("shape", ctypes.c_int), ("P", ctypes.c_int), ("Q", ctypes.c_int),
-                ("n_elem", ctypes.c_int64), ("geom", ctypes.c_int)]
+                ("n_elem", ctypes.c_int64), ("geom", ctypes.c_int), ("pts", ctypes.c_int)]
 
 
 def lib() -> ctypes.CDLL:
@@ -135,13 +136,14 @@ def num_points(shape: str, Q: int) -> int:
     return n.value
 
 
-def quadrature(shape: str, Q: int):
-    """Reference points xi [Q^3, 3] and weights [Q^3] (numpy, host)."""
+def quadrature(shape: str, Q: int, pts: str = "gj"):
+    """Reference points xi [Q^3, 3] and weights [Q^3] (numpy, host) of point set
+    pts ("gj" or "radau" in the collapsed directions)."""
     import numpy as np
     Q3 = Q ** 3
     xi = np.empty((3, Q3))
     w = np.empty(Q3)
-    _check(lib().shp_quadrature(SHAPES[shape], Q, xi.ctypes.data, w.ctypes.data))
+    _check(lib().shp_quadrature(SHAPES[shape], Q, POINTS[pts], xi.ctypes.data, w.ctypes.data))
     return np.ascontiguousarray(xi.T), w
 
 
@@ -150,8 +152,9 @@ def _stream(torch):
 
 
 class Plan:
-    """A plan over blocks [(shape, P, n_elem, geom)], with its workspace held as
-    a torch uint8 tensor on the current device."""
+    """A plan over blocks [(shape, P, n_elem, geom[, pts])], with its workspace
+    held as a torch uint8 tensor on the current device.  geom defaults to
+    "curved", pts (the collapsed directions' points) to "gj"."""
 
     def __init__(self, blocks: Sequence, device=None):
         import torch
@@ -159,9 +162,10 @@ class Plan:
         if not torch.cuda.is_available():
             raise RuntimeError("libshp needs a HIP device; none is visible")
         self.blocks = [(b[0], int(b[1]), int(b[2]), b[3] if len(b) > 3 else "curved") for b in blocks]
+        self.points = [b[4] if len(b) > 4 else "gj" for b in blocks]
         arr = (_BlockDesc * len(self.blocks))()
         for i, (sh, P, ne, geom) in enumerate(self.blocks):
-            arr[i] = _BlockDesc(SHAPES[sh], P, P + 2, ne, GEOM[geom])
+            arr[i] = _BlockDesc(SHAPES[sh], P, P + 2, ne, GEOM[geom], POINTS[self.points[i]])
         h = ctypes.c_void_p()
         _check(lib().shp_plan_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p), len(self.blocks)))
         self._h = h

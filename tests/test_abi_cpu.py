@@ -43,13 +43,16 @@ def test_num_modes_and_points(L):
         assert shp.num_points(shape, 6) == 216
 
 
+@pytest.mark.parametrize("pts", ["gj", "radau"])
 @pytest.mark.parametrize("shape", O.SHAPES)
 @pytest.mark.parametrize("Q", [3, 4, 6, 8, 12])
-def test_quadrature_matches_oracle(L, shape, Q):
-    """Library rule (Newton on Jacobi polynomials) vs the oracle's Golub-Welsch."""
+def test_quadrature_matches_oracle(L, shape, Q, pts):
+    """Library rule (Newton on Jacobi polynomials; Radau: -1 plus the shifted
+    Gauss-Jacobi zeros and the closed-form end weight) vs the oracle's
+    Golub-Welsch (Radau: Golub's modified Jacobi matrix)."""
     from paper_2604_04644_amd import shp
-    xi, w = shp.quadrature(shape, Q)
-    eta, wo, _ = O.quadrature(shape, Q)
+    xi, w = shp.quadrature(shape, Q, pts)
+    eta, wo, _ = O.quadrature(shape, Q, pts)
     assert np.abs(xi - O.collapse(shape, eta)).max() < 2e-15
     assert np.abs(w - wo).max() < 1e-14 * max(1.0, np.abs(wo).max())
 
@@ -65,8 +68,11 @@ def test_error_paths_without_device(L):
     assert L.shp_num_modes(0, 11, ctypes.byref(n)) == -2         # P out of range
     assert L.shp_num_modes(0, 0, ctypes.byref(n)) == -2
     assert L.shp_num_modes(0, 3, None) == -1                     # null output
-    assert L.shp_quadrature(0, 6, None, None) == -1
+    assert L.shp_quadrature(0, 6, 0, None, None) == -1
     assert "null" in L.shp_last_error().decode()
+    buf9 = (ctypes.c_double * 648)()
+    assert L.shp_quadrature(3, 6, 2, ctypes.cast(buf9, ctypes.c_void_p), None) == -1  # bad point set
+    assert "point set" in L.shp_last_error().decode()
 
     def plan(descs):
         arr = (shp._BlockDesc * len(descs))(*[shp._BlockDesc(*d) for d in descs])
@@ -79,6 +85,7 @@ def test_error_paths_without_device(L):
     assert plan([(9, 4, 6, 10, 1)])[0] == -1                     # bad shape
     assert plan([(0, 4, 6, -1, 1)])[0] == -1                     # negative count
     assert plan([(0, 4, 6, 10, 5)])[0] == -1                     # bad geom
+    assert plan([(3, 4, 6, 10, 1, 2)])[0] == -1                  # bad point set
     rc, h = plan([(0, 4, 6, 10, 1), (3, 4, 6, 7, 1)])
     assert rc == 0
     nb = ctypes.c_size_t()

@@ -63,6 +63,42 @@ def test_gauss_jacobi_vs_50_digits(Q, ab):
         assert abs(float(wex[i]) - w[i]) < 1e-14 * max(1.0, abs(float(wex[i])))
 
 
+@pytest.mark.parametrize("Q", [3, 4, 6, 8, 12])
+@pytest.mark.parametrize("ab", [(1, 0), (2, 0), (0, 0)])
+def test_gauss_radau_jacobi_vs_50_digits(Q, ab):
+    """Radau rule with the node -1: the other Q-1 nodes are the zeros of
+    P_{Q-1}^(a,b+1) (the polynomial that (1+x) times it must be orthogonal
+    to everything of degree Q-2 under the weight), the weights solve the moment
+    equations on the nodes, and the rule is exact up to degree 2Q-2 but not 2Q-1."""
+    mp.mp.dps = 50
+    a, b = ab
+    x, w = O.gauss_radau_jacobi(Q, float(a), float(b))
+    assert abs(x[0] + 1.0) < 1e-15
+    X = [mp.mpf(-1)] + [mp.findroot(lambda t: _mp_jacobi(Q - 1, a, b + 1, t), mp.mpf(float(xi))) for xi in x[1:]]
+    for i in range(Q):
+        assert abs(float(X[i]) - x[i]) < 2e-15
+    V = mp.matrix([[X[i] ** k for i in range(Q)] for k in range(Q)])
+    wex = mp.lu_solve(V, mp.matrix(_mp_moments(Q, a, b)))
+    for i in range(Q):
+        assert abs(float(wex[i]) - w[i]) < 1e-14 * max(1.0, abs(float(wex[i])))
+    mom = _mp_moments(2 * Q, a, b)
+    got = [float(np.sum(w * x ** k)) for k in range(2 * Q)]
+    for k in range(2 * Q - 1):
+        assert abs(got[k] - float(mom[k])) < 1e-13 * max(1.0, abs(float(mom[k])))
+    assert abs(got[2 * Q - 1] - float(mom[2 * Q - 1])) > 1e-8
+
+
+def test_gauss_radau_jacobi_two_points_by_hand():
+    """Q = 2 solved by hand from the moment equations: weight 1 - x, nodes -1
+    and 0 (the zero of P_1^(1,1)), weights 2/3 and 4/3; weight (1-x)^2, nodes -1
+    and -1/5 (the zero of P_1^(2,1) = 1/2 + 5x/2), weights 1 and 5/3; weight 1,
+    nodes -1 and 1/3, weights 1/2 and 3/2."""
+    for a, xs, ws in ((1, (-1.0, 0.0), (2 / 3, 4 / 3)), (2, (-1.0, -0.2), (1.0, 5 / 3)),
+                      (0, (-1.0, 1 / 3), (0.5, 1.5))):
+        x, w = O.gauss_radau_jacobi(2, float(a), 0.0)
+        assert np.allclose(x, xs, rtol=0, atol=1e-15) and np.allclose(w, ws, rtol=0, atol=1e-15)
+
+
 @pytest.mark.parametrize("Q", [3, 4, 5, 6, 8, 12])
 def test_gll_vs_50_digits(Q):
     mp.mp.dps = 50
@@ -97,15 +133,17 @@ def _exact_monomial(shape, a, b, c):
     raise ValueError(shape)
 
 
+@pytest.mark.parametrize("pts", O.POINTS)
 @pytest.mark.parametrize("shape", O.SHAPES)
 @pytest.mark.parametrize("Q", [3, 4, 6, 8])
-def test_reference_quadrature_monomials(shape, Q):
+def test_reference_quadrature_monomials(shape, Q, pts):
     deg = 2 * Q - 3
     for a, b, c in itertools.product(range(deg + 1), repeat=3):
         if a + b + c > deg:
             continue
         got = O.integrate_reference(
-            shape, Q, lambda xi: ((1 + xi[:, 0]) / 2) ** a * ((1 + xi[:, 1]) / 2) ** b * ((1 + xi[:, 2]) / 2) ** c)
+            shape, Q, lambda xi: ((1 + xi[:, 0]) / 2) ** a * ((1 + xi[:, 1]) / 2) ** b * ((1 + xi[:, 2]) / 2) ** c,
+            pts)
         ex = _exact_monomial(shape, a, b, c)
         assert abs(got - ex) <= 1e-13 * max(1.0, ex), (a, b, c, got, ex)
 
@@ -271,16 +309,19 @@ _AFF = [[1.5, 0.2, 0.0], [-0.25, 1.0, 1.0 / 3.0], [1.0 / 7.0, 0.0, 0.8]]
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
+@pytest.mark.parametrize("pts", O.POINTS)
 @pytest.mark.parametrize("shape", O.SHAPES)
 @pytest.mark.parametrize("P", [1, 2])
-def test_element_matrices_exact_rational(shape, P):
+def test_element_matrices_exact_rational(shape, P, pts):
     """Oracle M, L of an affine element against exact symbolic integrals
-    (tests/golden/make_exact_matrices.py)."""
+    (tests/golden/make_exact_matrices.py).  The integrands are polynomials that
+    both point sets integrate exactly at Q = P + 2, so the Radau rule must give
+    the same matrices."""
     Mx = np.loadtxt(os.path.join(GOLDEN, f"exact_M_{shape}_P{P}.txt"))
     Lx = np.loadtxt(os.path.join(GOLDEN, f"exact_L_{shape}_P{P}.txt"))
     Q = P + 2
     jac = np.array([[v for row in _AFF for v in row]])
-    el = O.Element(shape, P, Q, jac)
+    el = O.Element(shape, P, Q, jac, pts)
     M, L = el.mass()[0], el.laplacian()[0]
     assert np.abs(M - Mx).max() < 1e-14 * np.abs(Mx).max() * 10
     assert np.abs(L - Lx).max() < 1e-13 * np.abs(Lx).max()
@@ -338,15 +379,15 @@ def test_affine_hex_kronecker(P):
         assert np.abs(H[e] - Href).max() < 1e-13 * np.abs(Href).max()
 
 
-@pytest.mark.parametrize("shape", O.SHAPES)
-@pytest.mark.parametrize("P", [1, 3, 4])
-def test_curved_invariants(shape, P):
+@pytest.mark.parametrize("shape,P,pts", [(s, P, "gj") for s in O.SHAPES for P in (1, 3, 4)] +
+                         [(s, 3, "radau") for s in O.SHAPES])
+def test_curved_invariants(shape, P, pts):
     """M, L symmetric; M positive definite; L positive semidefinite with the
     constants as its one-dimensional kernel; L 1 = 0."""
     Q = P + 2
     maps = W.shape_batch(shape, 24)
-    jac = W.jacobian(maps, O.reference_points(shape, Q), curved=True)
-    el = O.Element(shape, P, Q, jac)
+    jac = W.jacobian(maps, O.reference_points(shape, Q, pts), curved=True)
+    el = O.Element(shape, P, Q, jac, pts)
     M, L = el.mass(), el.laplacian()
     c1 = O.vertex_indicator(shape, P)
     assert np.abs(M - np.transpose(M, (0, 2, 1))).max() < 1e-17 + 1e-14 * np.abs(M).max()
@@ -378,13 +419,14 @@ def test_mixed_mesh_volume(P):
         assert abs(total - 1.0) < 4 * tol
 
 
+@pytest.mark.parametrize("pts", O.POINTS)
 @pytest.mark.parametrize("shape", O.SHAPES)
-def test_collocation_derivative_exact_on_polynomials(shape):
+def test_collocation_derivative_exact_on_polynomials(shape, pts):
     """The Vandermonde collocation derivative differentiates polynomials of
     degree <= Q-1 per direction exactly."""
     Q = 5
-    eta, _, _ = O.quadrature(shape, Q)
-    D = O.deriv_matrices(shape, Q)
+    eta, _, _ = O.quadrature(shape, Q, pts)
+    D = O.deriv_matrices(shape, Q, pts)
     u = eta[:, 0] ** 4 * eta[:, 1] ** 3 - 2 * eta[:, 2] ** 4 * eta[:, 0] + eta[:, 1] * eta[:, 2] ** 2
     du = [4 * eta[:, 0] ** 3 * eta[:, 1] ** 3 - 2 * eta[:, 2] ** 4,
           3 * eta[:, 0] ** 4 * eta[:, 1] ** 2 + eta[:, 2] ** 2,
@@ -393,15 +435,16 @@ def test_collocation_derivative_exact_on_polynomials(shape):
         assert np.abs(D[d] @ u - du[d]).max() < 1e-12
 
 
+@pytest.mark.parametrize("pts", O.POINTS)
 @pytest.mark.parametrize("shape", O.SHAPES)
 @pytest.mark.parametrize("P", [1, 3])
-def test_cross_operator_identities(shape, P):
+def test_cross_operator_identities(shape, P, pts):
     """PhysDeriv(BwdTrans x) = sum x_m grad phi_m (analytic); the weak Laplacian
     equals IProductDeriv(PhysDeriv(BwdTrans x)); mass = IProduct(BwdTrans x)."""
     Q = P + 2
     maps = W.shape_batch(shape, 9)
-    jac = W.jacobian(maps, O.reference_points(shape, Q), curved=True)
-    el = O.Element(shape, P, Q, jac)
+    jac = W.jacobian(maps, O.reference_points(shape, Q, pts), curved=True)
+    el = O.Element(shape, P, Q, jac, pts)
     x = W.coeffs(9, O.num_modes(shape, P), 5)
     u = el.bwd_trans(x)
     g = el.phys_deriv(u)
