@@ -122,17 +122,21 @@ bool in_is_modes(int opk) {
 bool is_localmat(int opk) { return opk >= OPK_MASS_LM; }
 bool out_is_modes(int opk) { return !(opk == OPK_BWD || opk == OPK_DERIV); }
 
-// Default launch shape: as many elements per work-group as fit a 40 KiB LDS
-// budget (at most 16; several work-groups share a CU), 256 threads, and for
-// the Laplacian and Helmholtz actions the geometry-prefetch launch with at most
-// 4 points per thread (8 register slots of 7 factors cost occupancy).
-Tiling default_tiling(int sh, int P, int opk) {
+// Default launch shape: as many elements per work-group as fit an LDS budget
+// (at most 16; several work-groups share a CU), 256 threads, and for the
+// Laplacian and Helmholtz actions the geometry-prefetch launch with at most 4
+// points per thread (8 register slots of 7 factors cost occupancy).  The
+// budget is 40 KiB; the whole-mesh Laplacian and Helmholtz launch raises it to
+// 64 KiB where 40 KiB leaves at most 2 points per thread, which happens at
+// P = 6 (8^3 points): two elements per work-group there take 0.95 ms per FP64
+// action on the 32^3-cell mixed mesh against 1.21 ms for one.
+Tiling default_tiling(int sh, int P, int opk, size_t lds_budget = 40 * 1024) {
   Tiling t;
   t.NT = 256;
   const bool helm = (opk == OPK_HELM || opk == OPK_LAP);
   const long long Q3 = (long long)(P + 2) * (P + 2) * (P + 2);
   int E = 1;
-  while (E < 16 && op_lds_bytes(sh, P, opk, E + 1, 2) <= 40 * 1024 && (!helm || (E + 1) * Q3 <= 4LL * t.NT)) ++E;
+  while (E < 16 && op_lds_bytes(sh, P, opk, E + 1, 2) <= lds_budget && (!helm || (E + 1) * Q3 <= 4LL * t.NT)) ++E;
   t.E = E;
   t.persist = points_per_thread((long long)E * (P + 2) * (P + 2) * (P + 2), t.NT) > 0 ? 2 : 0;
   return t;
@@ -452,7 +456,10 @@ static Tiling mixed_tiling(shp_plan p, int opk) {
   if (t.E > 0 && t.NT > 0) return t;
   t = Tiling{64, 512, 2};
   for (const auto& B : p->blocks) {
-    const Tiling d = default_tiling(B.d.shape, B.d.P, opk);
+    Tiling d = default_tiling(B.d.shape, B.d.P, opk);
+    const long long Q3 = (long long)B.d.Q * B.d.Q * B.d.Q;
+    if ((opk == OPK_HELM || opk == OPK_LAP) && d.E * Q3 <= 2LL * d.NT)
+      d = default_tiling(B.d.shape, B.d.P, opk, 64 * 1024);
     t.E = std::min(t.E, d.E);
     t.NT = std::min(t.NT, d.NT);
     t.persist = std::min(t.persist, d.persist);

@@ -179,7 +179,9 @@ __global__ void __launch_bounds__(256) k_localmat_affine(AffineMatArgs a) {
   for (int mb = 0; mb < MB; ++mb) acc[mb] = dbl4{0.0, 0.0, 0.0, 0.0};
   const gptr_t Af = as_global(a.afrag) + lane;
   const gptr_t X = as_global(a.in) + e0 * NP + (long long)col * NP;
-  for (int kb = 0; kb < Kp / 4; ++kb) {
+  // K steps of 4 up to N_P only: the columns of A_k past N_P are zero padding
+  // (at N_P = 4 that is one step of the four a 16-wide padding would take)
+  for (int kb = 0; kb < (NP + 3) / 4; ++kb) {
     const int n = 4 * kb + kq;
     const double xb = (live && n < NP) ? X[n] : 0.0;
 #pragma unroll

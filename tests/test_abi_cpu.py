@@ -119,6 +119,13 @@ def test_error_paths_without_device(L):
     assert L.shp_set_tiling(h, 0, 6, 2, 0, 0, 0) == 0            # back to default
     assert L.shp_get_tiling(h, -1, 6, 2, ctypes.byref(E), ctypes.byref(NT), ctypes.byref(pe)) == 0
     assert (E.value, NT.value, pe.value) == (4, 256, 2)          # 40 KiB LDS budget at P=4
+    rc6, h6 = plan([(0, 6, 8, 10, 1), (3, 6, 8, 7, 1)])
+    assert rc6 == 0
+    assert L.shp_get_tiling(h6, 1, 6, 2, ctypes.byref(E), ctypes.byref(NT), ctypes.byref(pe)) == 0
+    assert (E.value, NT.value, pe.value) == (1, 256, 2)          # tet block at P=6: 40 KiB holds one
+    assert L.shp_get_tiling(h6, -1, 6, 2, ctypes.byref(E), ctypes.byref(NT), ctypes.byref(pe)) == 0
+    assert (E.value, NT.value, pe.value) == (2, 256, 2)          # whole mesh: 64 KiB, two elements
+    assert L.shp_plan_destroy(h6) == 0
     c, q = ctypes.c_int64(), ctypes.c_int64()
     assert L.shp_block_offsets(h, 1, ctypes.byref(c), ctypes.byref(q)) == 0
     assert (c.value, q.value) == (10 * 125, 10 * 216)
