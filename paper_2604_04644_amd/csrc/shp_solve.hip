@@ -128,23 +128,41 @@ __global__ void k_zero(T* __restrict__ a, long long n) {
     a[i] = (T)0;
 }
 
-// alpha = RZ / PQ; d += alpha p; r -= alpha q
+// One pass for the vector work of a CG step: alpha = RZ / PQ, d += alpha p,
+// r -= alpha q, and the per-block partials of r^T z with z = r / diag (not
+// stored).  Launched on NB blocks of 256 threads, so element i goes to the same
+// thread, in the same order, as in k_dot: the partials equal k_dot's on (r, z).
 template <typename T>
-__global__ void k_cg1(T* __restrict__ d, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
-                      const double* __restrict__ slot, long long n) {
+__global__ void k_cg1_rz(T* __restrict__ d, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
+                         const T* __restrict__ dg, const double* __restrict__ slot, long long n,
+                         double* __restrict__ part) {
+  __shared__ double sh[256];
   const T alpha = slot[PQ] > 0.0 ? (T)(slot[RZ] / slot[PQ]) : (T)0;  // 0 on breakdown, caught by the host check
+  double acc = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     d[i] += alpha * p[i];
-    r[i] -= alpha * q[i];
+    const T ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    const T zi = ri / dg[i];
+    acc = fma((double)ri, (double)zi, acc);
   }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// p = z + beta p (beta in slot NSLOT)
+// p = z + beta p (beta in slot NSLOT) with z = r / diag recomputed, rounded as
+// in k_jacobi
 template <typename T>
-__global__ void k_cg2(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ slot, long long n) {
+__global__ void k_cg2_r(T* __restrict__ p, const T* __restrict__ r, const T* __restrict__ dg,
+                        const double* __restrict__ slot, long long n) {
   const T beta = (T)slot[NSLOT];
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
+    p[i] = r[i] / dg[i] + beta * p[i];
 }
 
 // unit vectors of one local mode index, and the diagonal gather
@@ -189,7 +207,7 @@ inline dim3 grid_for(long long n) { return dim3((unsigned)std::min<long long>((n
 int sfail(int code, const char* msg) { return shp::set_error(code, msg); }
 
 struct SolveWs {
-  double *r, *y, *xb, *slot, *part;
+  double *r, *y, *xb, *slot, *part, *part_rz;  // part_rz: r^T z partials of k_cg1_rz
   float* diagf;
   void* vec;  // inner vectors: rs, z, p, q, d (5 n of the inner type)
   int* mode;
@@ -215,6 +233,7 @@ size_t carve(void* base, long long n, SolveWs* w) {
   s.mode = reinterpret_cast<int*>(take(sizeof(int) * n));
   s.slot = reinterpret_cast<double*>(take(sizeof(double) * 16));
   s.part = reinterpret_cast<double*>(take(sizeof(double) * NB));
+  s.part_rz = reinterpret_cast<double*>(take(sizeof(double) * NB));
   s.rmax = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * 2));
   if (w) *w = s;
   return o;
@@ -331,8 +350,9 @@ int pcg_reliable(const Op& op, const double* b, double* x, long long n, SolveWs&
   for (int it = 1; it <= max_iter; ++it) {
     if (int r = op.template apply<T>(p, q, s)) return r;
     if (int r = dot(p, q, n, w, PQ, s)) return r;
-    hipLaunchKernelGGL(k_cg1<T>, g, bl, 0, s, d, rs, p, q, w.slot, n);
+    hipLaunchKernelGGL(k_cg1_rz<T>, dim3(NB), bl, 0, s, d, rs, p, q, dg, w.slot, n, w.part_rz);
     st->inner_iters = it;
+    bool fresh_rz = true;  // part_rz holds r^T z of the current rs
     if (it % 10 == 0 || it == max_iter) {
       if (int r = dot(rs, rs, n, w, RR, s)) return r;
       if (!readback()) return sfail(SHP_ERR_DEVICE, "solver readback");
@@ -341,6 +361,7 @@ int pcg_reliable(const Op& op, const double* b, double* x, long long n, SolveWs&
         // reliable update: x += d in FP64 (the previous x kept), true residual
         const double rr_rec = h[RR];
         last = it;
+        fresh_rz = false;
         hipLaunchKernelGGL(k_copy<double>, g, bl, 0, s, x, w.xb, n);
         hipLaunchKernelGGL(k_update_x<T>, g, bl, 0, s, x, d, w.rmax, n);
         hipLaunchKernelGGL(k_zero<T>, g, bl, 0, s, d, n);
@@ -382,9 +403,13 @@ int pcg_reliable(const Op& op, const double* b, double* x, long long n, SolveWs&
         }
       }
     }
-    hipLaunchKernelGGL(k_jacobi<T>, g, bl, 0, s, rs, dg, z, n);
-    if (int r = dot(rs, z, n, w, RZN, s)) return r;
-    hipLaunchKernelGGL(k_cg2<T>, g, bl, 0, s, p, z, w.slot, n);
+    if (fresh_rz) {
+      hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, w.part_rz, NB, w.slot, (int)RZN);
+    } else {
+      hipLaunchKernelGGL(k_jacobi<T>, g, bl, 0, s, rs, dg, z, n);
+      if (int r = dot(rs, z, n, w, RZN, s)) return r;
+    }
+    hipLaunchKernelGGL(k_cg2_r<T>, g, bl, 0, s, p, rs, dg, w.slot, n);
   }
   return sfail(SHP_ERR_NOT_CONVERGED, "the residual did not reach the tolerance (x is the best iterate)");
 }
