@@ -194,6 +194,29 @@ def affine_leg(torch, shp, W, dof: float = 4e6, Ps=(1, 2, 3, 4)):
     return out
 
 
+def adr_leg(torch, plan, mesh, x, y, helm_ms: float, steps: int = 20):
+    """The advection-diffusion-reaction action (Helmholtz plus b . grad u tested
+    with the basis) on the same mesh, velocity U[-1,1] at every point: launch
+    time, GDOF/s and HBM rate of its algorithmic bytes (16 N_P + 80 Q^3 per
+    element: x, y, 7 factors and 3 advection factors per point)."""
+    nc, npnt = plan.totals()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(17)
+    vel = torch.rand(3 * npnt, generator=gen, dtype=torch.float64, device="cuda") * 2.0 - 1.0
+    adv = plan.advection_factors(vel)
+    del vel
+    _, m, _ = time_launches(torch, lambda: plan.apply_adr(x, adv, out=y, lam=1.0), steps, 3)
+    nbytes = sum(len(mesh[s]) * (16 * plan.n_modes[b] + 80 * plan.n_points[b]) for b, s in enumerate(SHAPES))
+    gbs = nbytes / (m * 1e-3) / 1e9
+    row = {"workload": "advection-diffusion-reaction action, same mesh, velocity U[-1,1] per point, lambda=1",
+           "launch_ms": round(m, 5), "GDOF/s": round(nc / (m * 1e-3) / 1e9, 3), "achieved_GB/s": round(gbs, 1),
+           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(nbytes),
+           "vs_helmholtz_launch": round(m / helm_ms, 3)}
+    log(f"  adr: {row}")
+    del adv
+    return row
+
+
 def c0_leg(torch, shp, W, n: int = 32, P: int = 4, lam: float = 1.0):
     """The C0-assembled problem on an n^3 grid of hexahedra curved by the mesh
     map, homogeneous Dirichlet data: the assembled action (gather, elemental
@@ -285,6 +308,7 @@ def main():
     ap.add_argument("--strategies", action="store_true",
                     help="also time collocated vs non-collocated Helmholtz per shape (block launches)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg (P=6 mesh)")
+    ap.add_argument("--no-adr", action="store_true", help="skip the advection-diffusion-reaction action")
     ap.add_argument("--c0", action="store_true",
                     help="also run the C0-assembled Helmholtz problem on a 32^3 curved hexahedral grid, P=4")
     ap.add_argument("--affine", action="store_true",
@@ -329,6 +353,7 @@ def main():
     achieved = nbytes / (ev_mean_ms * 1e-3) / 1e9
     log(f"  {ms:.3f} ms/step, launch {ev_mean_ms:.3f} ms (median {ev_med_ms:.3f}), {value:.2f} GDOF/s, "
         f"{achieved:.0f} GB/s")
+    adr = None if a.no_adr else adr_leg(torch, plan, mesh, x, y, ev_mean_ms)
     per_shape = None
     if a.per_shape:
         per_shape = {}
@@ -403,6 +428,8 @@ def main():
         out["affine_localmat_vs_sumfac"] = affine
     if c0 is not None:
         out["c0_assembled"] = c0
+    if adr is not None:
+        out["adr_action"] = adr
     print(json.dumps(out), flush=True)
 
 

@@ -171,6 +171,31 @@ typedef enum { SHP_FP64 = 0, SHP_FP32 = 1, SHP_BF16 = 2 } shp_prec;
 int shp_apply_prec(shp_plan plan, int blk, int op, int strategy, int prec, const void* in /* device */,
                    void* out /* device */, double lambda, void* stream);
 
+/* ---- Advection-diffusion-reaction action --------------------------------
+ * The collocated form of the Helmholtz action carries over to any operator
+ * tested against the basis or its derivatives (Sec. 2.2.1, after eq. helm1);
+ * here the linear advection-diffusion-reaction operator
+ *   y_m = sum_e integral phi_m (lambda u + b . grad u) + grad phi_m . grad u,
+ * u = sum_n x_n phi_n, with a velocity field b given at the quadrature points.
+ * At the points the advection term adds sum_d a_d D_d u to the reaction term
+ * lambda jw u before the restriction B^T, with the advection factors
+ * a_d = jw sum_i b_i d eta_d / d x_i (FP64, three per point). */
+
+/* Advection factors of every block from the velocity b at the points.
+ * vel: device FP64 [3][total points] (component slowest, blocks concatenated
+ * as in shp_block_offsets); adv: device FP64 [3 * total points], block b's
+ * factors from 3 * (its point offset), [n_elem][3][N_Q] within the block.
+ * Needs every block's geometry.  Enqueued on stream. */
+int shp_advection_factors(shp_plan plan, const double* vel /* device */, double* adv /* device */, void* stream);
+
+/* Whole-mesh advection-diffusion-reaction action in FP64 with the collocated
+ * sum-factorisation (one launch; every block of one P): in/out are whole-mesh
+ * coefficient buffers, adv the factors from shp_advection_factors.  With adv
+ * all zero the result equals the Helmholtz action.  The first call writes the
+ * operator's tile list into the workspace as shp_apply does. */
+int shp_apply_adr(shp_plan plan, const double* adv /* device */, const double* in /* device */,
+                  double* out /* device */, double lambda, void* stream);
+
 /* ---- Helmholtz solve with mixed precision ------------------------------
  * Solves H x = b for the elemental (unassembled, block-diagonal) Helmholtz
  * operator H = lambda M + L of every element of the plan (Sec. 2, the

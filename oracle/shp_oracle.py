@@ -21,7 +21,11 @@ What it computes, with the paper's passages:
   quadrature on [-1,1]^3 in eta (Sec. 2.3);
 * the physical derivative: the derivative of the tensor Lagrange interpolant
   through the quadrature points, chained with d eta/d x (Sec. 2.2, collocation
-  differentiation, eq. dphitodh).
+  differentiation, eq. dphitodh);
+* the advection-diffusion-reaction operator lambda M + L + C with
+  C[m,n] = integral phi_m b . grad phi_n for a velocity b given at the points,
+  the operator the collocated reading of the Helmholtz action extends to
+  (Sec. 2.2.1).
 
 Readings of what the paper leaves to its textbook reference (each also listed in
 the design notes):
@@ -494,6 +498,19 @@ class Element:
     def helmholtz(self, lam: float) -> np.ndarray:
         return lam * self.mass() + self.laplacian()
 
+    def advection(self, vel) -> np.ndarray:
+        """C[m,n] = sum_q jw_q phi_m(eta_q) sum_i b_i(q) (d phi_n/d x_i)(eta_q):
+        the advection term b . grad u tested with the basis, by explicit
+        quadrature (the collocated reading of Sec. 2.2.1 extends the Helmholtz
+        operator to advection-diffusion-reaction).  vel: [3, n_elem, N_Q]."""
+        vel = np.asarray(vel, dtype=np.float64)
+        bgrad = np.einsum("ieq,eiqn->eqn", vel, self.dBx)          # b . grad phi_n at the points
+        return np.matmul(self.B.T[None, :, :], self.jw[:, :, None] * bgrad)
+
+    def adr(self, lam: float, vel) -> np.ndarray:
+        """lambda M + L + C (advection-diffusion-reaction)."""
+        return self.helmholtz(lam) + self.advection(vel)
+
     # --- actions as dense matrix-vector products --------------------------
     def bwd_trans(self, x):
         """u_q = sum_m phi_m(eta_q) x_m, [n_elem, N_Q]."""
@@ -523,9 +540,11 @@ class Element:
         return np.einsum("emn,en->em", self.helmholtz(lam), x)
 
 
-def apply_op(op: str, shape: str, P: int, Q: int, jac, x, lam: float = 1.0, chunk: int = 512, pts: str = "gj"):
+def apply_op(op: str, shape: str, P: int, Q: int, jac, x, lam: float = 1.0, chunk: int = 512, pts: str = "gj",
+             vel=None):
     """One operator over a batch, processed in chunks of elements.
-    op in {bwd, iprod, physderiv, iprod_deriv, mass, laplacian, helmholtz}."""
+    op in {bwd, iprod, physderiv, iprod_deriv, mass, laplacian, helmholtz, adr};
+    adr takes the velocity vel [3, n_elem, N_Q] at the points."""
     x = np.asarray(x, dtype=np.float64)
     jac = np.asarray(jac, dtype=np.float64)
     ne = jac.shape[0]
@@ -547,6 +566,8 @@ def apply_op(op: str, shape: str, P: int, Q: int, jac, x, lam: float = 1.0, chun
             outs.append(el.laplacian_action(x[e0:e1]))
         elif op == "helmholtz":
             outs.append(el.helmholtz_action(x[e0:e1], lam))
+        elif op == "adr":
+            outs.append(np.einsum("emn,en->em", el.adr(lam, np.asarray(vel)[:, e0:e1]), x[e0:e1]))
         else:
             raise ValueError(op)
     axis = 1 if op == "physderiv" else 0

@@ -133,7 +133,7 @@ bool out_is_modes(int opk) { return !(opk == OPK_BWD || opk == OPK_DERIV); }
 Tiling default_tiling(int sh, int P, int opk, size_t lds_budget = 40 * 1024) {
   Tiling t;
   t.NT = 256;
-  const bool helm = (opk == OPK_HELM || opk == OPK_LAP);
+  const bool helm = (opk == OPK_HELM || opk == OPK_LAP || opk == OPK_ADR);
   const long long Q3 = (long long)(P + 2) * (P + 2) * (P + 2);
   int E = 1;
   while (E < 16 && op_lds_bytes(sh, P, opk, E + 1, 2) <= lds_budget && (!helm || (E + 1) * Q3 <= 4LL * t.NT)) ++E;
@@ -458,7 +458,7 @@ static Tiling mixed_tiling(shp_plan p, int opk) {
   for (const auto& B : p->blocks) {
     Tiling d = default_tiling(B.d.shape, B.d.P, opk);
     const long long Q3 = (long long)B.d.Q * B.d.Q * B.d.Q;
-    if ((opk == OPK_HELM || opk == OPK_LAP) && d.E * Q3 <= 2LL * d.NT)
+    if ((opk == OPK_HELM || opk == OPK_LAP || opk == OPK_ADR) && d.E * Q3 <= 2LL * d.NT)
       d = default_tiling(B.d.shape, B.d.P, opk, 64 * 1024);
     t.E = std::min(t.E, d.E);
     t.NT = std::min(t.NT, d.NT);
@@ -640,6 +640,46 @@ int shp_apply_prec(shp_plan p, int blk, int op, int strategy, int prec, const vo
                                   tiles, p->mixed_ntiles[opk], static_cast<const float*>(in), static_cast<float*>(out),
                                   lambda, mt.NT, lds, mt.E, s);
   if (e != hipSuccess) return dev_fail(e, "FP32 launch");
+  return SHP_OK;
+}
+
+int shp_advection_factors(shp_plan p, const double* vel, double* adv, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!vel || !adv) return fail(SHP_ERR_INVALID_ARG, "null vel/adv");
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  for (size_t b = 0; b < p->blocks.size(); ++b)
+    if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (const Block& B : p->blocks) {
+    const hipError_t e = launch_adv_factors(reinterpret_cast<const double*>(p->ws + B.off_fac),
+                                            reinterpret_cast<const double*>(p->ws + B.off_dxi), vel + B.phys_off,
+                                            p->total_phys, adv + 3 * B.phys_off, B.d.n_elem, B.NQ, s);
+    if (e != hipSuccess) return dev_fail(e, "advection factors");
+  }
+  return SHP_OK;
+}
+
+int shp_apply_adr(shp_plan p, const double* adv, const double* in, double* out, double lambda, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!adv || !in || !out) return fail(SHP_ERR_INVALID_ARG, "null adv/in/out");
+  if (!std::isfinite(lambda)) return fail(SHP_ERR_INVALID_ARG, "lambda not finite");
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  if (!p->uniform_P) return fail(SHP_ERR_UNSUPPORTED, "the whole-mesh launch needs one P for all blocks");
+  for (size_t b = 0; b < p->blocks.size(); ++b)
+    if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->mixed_dirty[OPK_ADR])
+    if (int r = build_tiles(p, OPK_ADR, s)) return r;
+  const Tiling mt = mixed_tiling(p, OPK_ADR);
+  const int Q = p->blocks[0].d.Q;
+  if (points_per_thread((long long)mt.E * Q * Q * Q, mt.NT) == 0)
+    return fail(SHP_ERR_UNSUPPORTED, "launch shape too large for the advection-diffusion-reaction kernel");
+  size_t lds = 0;
+  for (const auto& B : p->blocks) lds = std::max(lds, op_lds_bytes(B.d.shape, B.d.P, OPK_ADR, mt.E, 2));
+  const Tile* tiles = reinterpret_cast<const Tile*>(p->ws + p->off_tiles) + (size_t)OPK_ADR * p->max_tiles;
+  const hipError_t e = launch_adr(p->blocks[0].d.P, reinterpret_cast<const BlockStatic*>(p->ws + p->off_bstat), tiles,
+                                  p->mixed_ntiles[OPK_ADR], in, out, adv, lambda, mt.NT, lds, mt.E, s);
+  if (e != hipSuccess) return dev_fail(e, "advection-diffusion-reaction launch");
   return SHP_OK;
 }
 

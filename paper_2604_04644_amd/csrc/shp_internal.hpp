@@ -54,6 +54,12 @@ hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_localmat(int sh, int P, int opk, const LocalMatArgs& a, hipStream_t s);
 hipError_t launch_localmat_affine(int sh, int P, int opk, const AffineMatArgs& a, hipStream_t s);
 hipError_t launch_affine_coef(const double* jac, double* coef, long long n, int* status, hipStream_t s);
+// whole-mesh advection-diffusion-reaction action (FP64, geometry-prefetch launch)
+// and the advection factors of one block
+hipError_t launch_adr(int P, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in, double* out,
+                      const double* adv, double lambda, int threads, size_t lds, int E, hipStream_t s);
+hipError_t launch_adv_factors(const double* fac, const double* dxi, const double* vel, long long vstride, double* adv,
+                              long long n_elem, int Q3, hipStream_t s);
 hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
                         double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds, int E,
                         int persist, hipStream_t s);

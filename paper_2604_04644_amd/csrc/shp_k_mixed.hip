@@ -164,7 +164,10 @@ hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s) {
                                size_t lds, int E, int persist, hipStream_t s);                                      \
   hipError_t launch_mixed_f32_P##p(int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles,               \
                                    const float* in, float* out, double lambda, int threads, size_t lds, int E,       \
-                                   hipStream_t s);
+                                   hipStream_t s);                                                                   \
+  hipError_t launch_adr_P##p(const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,            \
+                             double* out, const double* adv, double lambda, int threads, size_t lds, int E,          \
+                             hipStream_t s);
 D_(1) D_(2) D_(3) D_(4) D_(5) D_(6) D_(7) D_(8) D_(9) D_(10)
 #undef D_
 
@@ -176,6 +179,46 @@ hipError_t launch_mixed_f32(int P, int opk, const BlockStatic* blocks, const Til
 #undef C_
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_adr(int P, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in, double* out,
+                      const double* adv, double lambda, int threads, size_t lds, int E, hipStream_t s) {
+  switch (P) {
+#define C_(p) \
+  case p: return launch_adr_P##p(blocks, tiles, ntiles, in, out, adv, lambda, threads, lds, E, s);
+    C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10)
+#undef C_
+  }
+  return hipErrorInvalidValue;
+}
+
+// Advection factors of one block: a_d = jw sum_i b_i d eta_d / d x_i at every
+// point, from the block's factors (jw first of NFAC per point) and d eta/d x
+// (NDXI = 9 per point, row eta_d, column x_i); vel is [3][vstride] with the
+// block's points first, adv [n][3][Q^3].
+__global__ void __launch_bounds__(256) k_adv_factors(const double* __restrict__ fac, const double* __restrict__ dxi,
+                                                     const double* __restrict__ vel, long long vstride,
+                                                     double* __restrict__ adv, long long n_elem, int Q3) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_elem * Q3) return;
+  const long long e = t / Q3;
+  const int pt = (int)(t - e * Q3);
+  const double jw = fac[e * (NFAC * (long long)Q3) + pt];
+  const double* m = dxi + e * (NDXI * (long long)Q3) + pt;
+  const double b0 = vel[t], b1 = vel[vstride + t], b2 = vel[2 * vstride + t];
+  double* o = adv + e * (3LL * Q3) + pt;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    o[d * Q3] = jw * (b0 * m[(d * 3 + 0) * Q3] + b1 * m[(d * 3 + 1) * Q3] + b2 * m[(d * 3 + 2) * Q3]);
+}
+
+hipError_t launch_adv_factors(const double* fac, const double* dxi, const double* vel, long long vstride, double* adv,
+                              long long n_elem, int Q3, hipStream_t s) {
+  const long long n = n_elem * Q3;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adv_factors, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, fac, dxi, vel, vstride, adv,
+                     n_elem, Q3);
+  return hipGetLastError();
 }
 
 hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,

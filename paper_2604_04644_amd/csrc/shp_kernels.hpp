@@ -42,7 +42,8 @@ enum : int {
   OPK_MASS_LM = 9,  // local-matrix strategy (FP64 MFMA): mass
   OPK_LAP_LM = 10,  //   Laplacian
   OPK_HELM_LM = 11, //   Helmholtz
-  OPK_COUNT = 12
+  OPK_ADR = 12,     // advection-diffusion-reaction: Helmholtz plus b . grad u tested with the basis
+  OPK_COUNT = 13
 };
 
 // Arguments of one block for one operator call.
@@ -1015,9 +1016,12 @@ __device__ __forceinline__ void prefetch_geo(const double* __restrict__ fac, lon
   }
 }
 
+// OP = OPK_ADR adds the advection term sum_d a_d D_d u at the points to the
+// reaction term, with a_d = jw sum_i b_i d eta_d / d x_i read from adv
+// ([n_elem][3][Q^3] of the tile's block).
 template <int SH, int P, int OP, int PPT, typename Next, typename R>
 __device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH, P, R>& T, GeoRegs<PPT>& g,
-                          bool tables, Next next) {
+                          bool tables, Next next, const double* __restrict__ adv = nullptr) {
   using D = Dims<SH, P>;
   constexpr int Q3 = D::Q3;
   if (tables) load_tables_helm<SH, P>(a, T);
@@ -1032,7 +1036,7 @@ __device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH,
   __syncthreads();
   grad12<SH, P, false>(T, ne);
   __syncthreads();
-  const double lam = (OP == OPK_HELM) ? a.lambda : 0.0;
+  const double lam = (OP == OPK_HELM || OP == OPK_ADR) ? a.lambda : 0.0;
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
     const int t = tid() + it * nthr();
@@ -1051,6 +1055,11 @@ __device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH,
         R* u = T.U(e) + lp;
         *u = lam * gg[0] * (*u);
       }
+      if constexpr (OP == OPK_ADR) {
+        const gptr_t av = as_global(adv) + (e0 + e) * (3LL * Q3) + pt;
+        R* u = T.U(e) + lp;
+        *u = lam * gg[0] * (*u) + (av[0] * d0 + av[Q3] * d1 + av[2 * Q3] * d2);
+      }
     }
   }
   next();  // registers of this tile's geometry are dead: start the next tile's loads
@@ -1058,7 +1067,7 @@ __device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH,
   grad12<SH, P, true>(T, ne);
   __syncthreads();
   // points -> modes: stage p^T (with D_0^T) into U, q^T into G0, r^T into G1
-  grad0T_ipr_p<SH, P>(T, ne, OP == OPK_HELM);
+  grad0T_ipr_p<SH, P>(T, ne, OP == OPK_HELM || OP == OPK_ADR);
   __syncthreads();
   ipr_q<SH, P, false>(T, ne, -1, 0);
   __syncthreads();
@@ -1185,6 +1194,45 @@ __global__ void __launch_bounds__(512) k_helm_mixed_pf(const BlockStatic* __rest
     case PRISM: helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<PRISM, P, R>(smem, gt), g, true, none); break;
     case PYR: helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<PYR, P, R>(smem, gt), g, true, none); break;
     default: helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<TET, P, R>(smem, gt), g, true, none); break;
+  }
+}
+
+// Whole-mesh advection-diffusion-reaction action (FP64): k_helm_mixed_pf with
+// the advection factors adv ([3][Q^3] per element, blocks concatenated like the
+// point buffers).
+template <int P, int PPT>
+__global__ void __launch_bounds__(512) k_adr_mixed_pf(const BlockStatic* __restrict__ blocks,
+                                                      const Tile* __restrict__ tiles, int ntiles, const double* in,
+                                                      double* out, double lambda, const double* __restrict__ adv) {
+  extern __shared__ double smem[];
+  const int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  const BlockStatic b = blocks[tl.blk];
+  GeoRegs<PPT> g;
+  prefetch_geo<P, PPT>(b.fac, tl.e0, tl.ne, g);
+  OpArgs a;
+  a.tab = b.tab;
+  a.itab = b.itab;
+  a.fac = b.fac;
+  a.dxi = b.dxi;
+  a.n_elem = b.n_elem;
+  a.in = in + b.coeff_off;
+  a.out = out + b.coeff_off;
+  a.in_cs = 0;
+  a.out_cs = 0;
+  a.lambda = lambda;
+  a.E = 0;
+  a.pad_ = 0;
+  const double* ab = adv + 3 * b.phys_off;
+  auto none = []() {};
+  switch (b.shape) {
+    case HEX: helm_tile<HEX, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem, b.tab), g, true, none, ab); break;
+    case PRISM:
+      helm_tile<PRISM, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem, b.tab), g, true, none, ab);
+      break;
+    case PYR: helm_tile<PYR, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem, b.tab), g, true, none, ab); break;
+    default: helm_tile<TET, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<TET, P>(smem, b.tab), g, true, none, ab); break;
   }
 }
 

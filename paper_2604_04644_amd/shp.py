@@ -49,6 +49,9 @@ _SIGS = {
     "shp_apply_prec": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                        ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p],
     "shp_solve_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "shp_advection_factors": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "shp_apply_adr": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                      ctypes.c_void_p],
     "shp_c0_hex_sizes": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "shp_c0_hex_map": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
@@ -258,6 +261,34 @@ class Plan:
         _check(lib().shp_apply_prec(self._h, -1, OPS[op], STRATEGY["sumfac_coll"], PREC[prec],
                                     ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), float(lam),
                                     _stream(t)))
+        return out
+
+    def advection_factors(self, vel):
+        """Advection factors [3 * total points] (float64, device) from the
+        velocity at the points, vel [3][total points] float64 on the device."""
+        t = self._torch
+        _, npnt = self.totals()
+        if vel.dtype != t.float64 or not vel.is_cuda or not vel.is_contiguous() or vel.numel() != 3 * npnt:
+            raise ValueError(f"vel must be a contiguous float64 device tensor of {3 * npnt} values")
+        adv = t.empty(3 * npnt, dtype=t.float64, device=vel.device)
+        _check(lib().shp_advection_factors(self._h, ctypes.c_void_p(vel.data_ptr()), ctypes.c_void_p(adv.data_ptr()),
+                                           _stream(t)))
+        return adv
+
+    def apply_adr(self, x, adv, out=None, lam: float = 1.0):
+        """Whole-mesh advection-diffusion-reaction action (FP64)."""
+        t = self._torch
+        nc, npnt = self.totals()
+        if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != nc:
+            raise ValueError(f"x must be a contiguous float64 device tensor of {nc} values")
+        if adv.dtype != t.float64 or not adv.is_contiguous() or adv.numel() != 3 * npnt:
+            raise ValueError("bad advection factors")
+        if out is None:
+            out = t.empty_like(x)
+        elif out.dtype != t.float64 or not out.is_contiguous() or out.numel() != nc:
+            raise ValueError("bad output tensor")
+        _check(lib().shp_apply_adr(self._h, ctypes.c_void_p(adv.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), float(lam), _stream(t)))
         return out
 
     def _solve_ws(self, device):

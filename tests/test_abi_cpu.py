@@ -103,6 +103,11 @@ def test_error_paths_without_device(L):
     assert L.shp_apply(h, 0, 6, 7, p, p, 1.0, None) == -1        # strategy
     assert L.shp_apply(h, 0, 6, 2, None, p, 1.0, None) == -1     # null input
     assert L.shp_apply(h, 0, 6, 2, p, p, float("nan"), None) == -1
+    assert L.shp_apply_adr(h, None, p, p, 1.0, None) == -1        # null advection factors
+    assert L.shp_apply_adr(h, p, p, p, float("inf"), None) == -1
+    assert L.shp_apply_adr(h, p, p, p, 1.0, None) == -5           # no workspace yet
+    assert L.shp_advection_factors(h, None, p, None) == -1
+    assert L.shp_advection_factors(h, p, p, None) == -5
     # workspace validation (no device call is reached)
     assert L.shp_plan_bind_workspace(h, None, nb.value, None) == -4
     assert L.shp_plan_bind_workspace(h, ctypes.c_void_p(256 * 1000 + 8), nb.value, None) == -4

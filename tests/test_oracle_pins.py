@@ -479,3 +479,31 @@ def test_helmholtz_solve_round_trip(shape):
     b = O.apply_op("helmholtz", shape, P, Q, jac, x, lam=1.0)
     xs = O.helmholtz_solve(shape, P, Q, jac, b, lam=1.0)
     assert np.abs(xs - x).max() < 1e-8
+
+
+@pytest.mark.parametrize("shape", O.SHAPES)
+@pytest.mark.parametrize("P", [1, 3])
+def test_advection_of_linear_fields(shape, P):
+    """Advection term of the advection-diffusion-reaction operator on affine
+    elements with a constant velocity b: b . grad f of a linear field f = a.x + c
+    is the constant b.a, so C x_f = (b.a) M 1 (M 1 the mass matrix applied to the
+    constant's coefficients); constants are not advected (C 1 = 0).  The
+    transposed operator fails this, and so does a wrong sign or component."""
+    Q = P + 2
+    maps = W.shape_batch(shape, 4)
+    xi = O.reference_points(shape, Q)
+    X = W.coords(maps, xi, curved=False)                     # [ne, 3, nq]
+    el = O.Element(shape, P, Q, W.affine_jacobian(maps))
+    b = np.array([0.7, -1.3, 0.4])
+    a = np.array([0.3, -1.2, 2.5])
+    vel = np.broadcast_to(b[:, None, None], (3, len(maps), Q ** 3))
+    C, M = el.advection(vel), el.mass()
+    c1 = O.vertex_indicator(shape, P)
+    for e in range(len(maps)):
+        f = a @ X[e] + 0.4
+        xf = np.linalg.lstsq(el.B, f, rcond=None)[0]           # exact: f lies in the span
+        assert np.abs(el.B @ xf - f).max() < 1e-12
+        lhs, rhs = C[e] @ xf, (b @ a) * (M[e] @ c1)
+        assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
+        assert np.abs(C[e] @ c1).max() < 1e-13 * np.abs(C[e]).max()
+        assert np.abs(C[e].T @ xf - rhs).max() > 1e-3 * np.abs(rhs).max()
