@@ -84,3 +84,36 @@ def test_adr_rejects_mixed_orders(shp):
     with pytest.raises(shp.ShpError) as ei:
         plan.apply_adr(torch.zeros(nc, dtype=torch.float64, device="cuda"), adv)
     assert ei.value.code == -2
+
+
+def test_adr_affine_and_radau_blocks(shp):
+    """Affine blocks (per-point factors from a constant Jacobian) and blocks on
+    Gauss-Radau-Jacobi points in one whole-mesh launch."""
+    say("[adr] affine and Radau blocks")
+    P = 3
+    blocks = [("hex", P, 7, "affine", "gj"), ("prism", P, 9, "curved", "radau"), ("pyr", P, 11, "affine", "radau"),
+              ("tet", P, 13, "curved", "gj")]
+    plan = shp.Plan(blocks)
+    maps, jos = {}, {}
+    for b, (s, _, n, geom, pts) in enumerate(blocks):
+        maps[s] = W.shape_batch(s, n)
+        if geom == "affine":
+            jac = W.affine_jacobian(maps[s])
+            jos[s] = jac
+        else:
+            jac = W.jacobian(maps[s], shp.quadrature(s, P + 2, pts)[0], curved=True)
+            jos[s] = W.jacobian(maps[s], O.reference_points(s, P + 2, pts), curved=True)
+        plan.set_geometry(b, torch.from_numpy(np.ascontiguousarray(jac)).cuda())
+    nc, npnt = plan.totals()
+    x = W.coeffs(1, nc, 830)[0]
+    vel = W.point_values(1, npnt, 831, ncomp=3).reshape(3, npnt)
+    adv = plan.advection_factors(torch.from_numpy(np.ascontiguousarray(vel)).cuda())
+    y = plan.apply_adr(torch.from_numpy(x).cuda(), adv, lam=0.6).cpu().numpy()
+    for b, (s, _, ne, geom, pts) in enumerate(blocks):
+        co, po = plan.offsets(b)
+        NP, NQ = plan.n_modes[b], plan.n_points[b]
+        ref = O.apply_op("adr", s, P, P + 2, jos[s], x[co:co + ne * NP].reshape(ne, NP), lam=0.6, pts=pts,
+                         vel=vel[:, po:po + ne * NQ].reshape(3, ne, NQ))
+        e = rel(y[co:co + ne * NP].reshape(ne, NP), ref)
+        say(f"    {s:6s} {geom:6s} {pts:5s} rel={e:.2e}")
+        assert e <= TOL, (s, e)
