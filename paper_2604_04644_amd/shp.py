@@ -236,7 +236,7 @@ class Plan:
             raise ValueError(f"x has {x.numel()} values, {op} on block {blk} takes {self._in_numel(blk, op)}")
         if out is None:
             out = t.empty(self._out_shape(blk, op), dtype=t.float64, device=x.device)
-        elif out.dtype != t.float64 or not out.is_contiguous() or out.numel() != int(
+        elif out.dtype != t.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() != int(
                 t.Size(self._out_shape(blk, op)).numel()):
             raise ValueError("bad output tensor")
         _check(lib().shp_apply(self._h, blk, OPS[op], STRATEGY[strategy], ctypes.c_void_p(x.data_ptr()),
@@ -256,7 +256,7 @@ class Plan:
             raise ValueError(f"x has {x.numel()} values, {op} takes {self._in_numel(-1, op)}")
         if out is None:
             out = t.empty(self._out_shape(-1, op), dtype=dt, device=x.device)
-        elif out.dtype != dt or not out.is_contiguous() or out.numel() != x.numel():
+        elif out.dtype != dt or not out.is_cuda or not out.is_contiguous() or out.numel() != x.numel():
             raise ValueError("bad output tensor")
         _check(lib().shp_apply_prec(self._h, -1, OPS[op], STRATEGY["sumfac_coll"], PREC[prec],
                                     ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), float(lam),
@@ -281,11 +281,11 @@ class Plan:
         nc, npnt = self.totals()
         if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != nc:
             raise ValueError(f"x must be a contiguous float64 device tensor of {nc} values")
-        if adv.dtype != t.float64 or not adv.is_contiguous() or adv.numel() != 3 * npnt:
+        if adv.dtype != t.float64 or not adv.is_cuda or not adv.is_contiguous() or adv.numel() != 3 * npnt:
             raise ValueError("bad advection factors")
         if out is None:
             out = t.empty_like(x)
-        elif out.dtype != t.float64 or not out.is_contiguous() or out.numel() != nc:
+        elif out.dtype != t.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() != nc:
             raise ValueError("bad output tensor")
         _check(lib().shp_apply_adr(self._h, ctypes.c_void_p(adv.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                    ctypes.c_void_p(out.data_ptr()), float(lam), _stream(t)))
@@ -324,7 +324,7 @@ class Plan:
             raise ValueError("b must be a contiguous float64 device tensor of all coefficients")
         if x is None:
             x = t.zeros_like(b)
-        elif x.dtype != t.float64 or not x.is_contiguous() or x.numel() != nc:
+        elif x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != nc:
             raise ValueError("bad initial guess")
         diag = self.helmholtz_diag(lam)
         ws, nb = self._solve_ws(b.device)
@@ -362,6 +362,9 @@ class Plan:
     def c0_assemble(self, c0, vl):
         """A^T vl for a local vector (all coefficients of the block)."""
         t = self._torch
+        nc, _ = self.totals()
+        if vl.dtype != t.float64 or not vl.is_cuda or not vl.is_contiguous() or vl.numel() != nc:
+            raise ValueError(f"vl must be a contiguous float64 device tensor of {nc} values")
         out = t.empty(c0["n_global"], dtype=t.float64, device=vl.device)
         _check(lib().shp_c0_assemble(ctypes.c_void_p(c0["row_ptr"].data_ptr()), ctypes.c_void_p(c0["col"].data_ptr()),
                                      c0["n_global"], ctypes.c_void_p(vl.data_ptr()), ctypes.c_void_p(out.data_ptr()),
@@ -372,8 +375,13 @@ class Plan:
         """Assembled FP64 Helmholtz action A^T H A xg."""
         t = self._torch
         nc, _ = self.totals()
+        ng = c0["n_global"]
+        if xg.dtype != t.float64 or not xg.is_cuda or not xg.is_contiguous() or xg.numel() != ng:
+            raise ValueError(f"xg must be a contiguous float64 device tensor of {ng} values")
         if out is None:
-            out = t.empty(c0["n_global"], dtype=t.float64, device=xg.device)
+            out = t.empty(ng, dtype=t.float64, device=xg.device)
+        elif out.dtype != t.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() != ng:
+            raise ValueError("bad output tensor")
         work = t.empty(2 * nc, dtype=t.float64, device=xg.device)
         _check(lib().shp_c0_apply(self._h, ctypes.c_void_p(c0["l2g"].data_ptr()),
                                   ctypes.c_void_p(c0["row_ptr"].data_ptr()), ctypes.c_void_p(c0["col"].data_ptr()),
@@ -387,10 +395,12 @@ class Plan:
         mixed-precision PCG.  Returns (x, stats)."""
         t = self._torch
         ng = c0["n_global"]
-        if b.dtype != t.float64 or not b.is_cuda or b.numel() != ng:
-            raise ValueError("b must be a float64 device tensor of the global DOFs")
+        if b.dtype != t.float64 or not b.is_cuda or not b.is_contiguous() or b.numel() != ng:
+            raise ValueError("b must be a contiguous float64 device tensor of the global DOFs")
         if x is None:
             x = t.zeros_like(b)
+        elif x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != ng:
+            raise ValueError("bad initial guess")
         nb = ctypes.c_size_t()
         _check(lib().shp_c0_solve_workspace_bytes(self._h, ng, ctypes.byref(nb)))
         ws = t.empty(nb.value + 256, dtype=t.uint8, device=b.device)
@@ -421,6 +431,8 @@ class Plan:
         """Exhaustive tuning of (blk, op) on input x; returns (result dict, list of
         candidate records).  SHP_AUTO then uses the choice."""
         t = self._torch
+        if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != self._in_numel(blk, op):
+            raise ValueError(f"x must be a contiguous float64 device tensor of {self._in_numel(blk, op)} values")
         out = t.empty(self._out_shape(blk, op), dtype=t.float64, device=x.device)
         ref = t.empty_like(out)
         res = TuneResult()

@@ -71,6 +71,10 @@ def test_adr_zero_velocity_is_helmholtz(shp):
     y = plan.apply_adr(x, adv, lam=0.9).cpu().numpy()
     yh = plan.apply(-1, "helmholtz", x, lam=0.9).cpu().numpy()
     assert rel(y, yh) <= 1e-15
+    with pytest.raises(ValueError):      # host memory never reaches a kernel
+        plan.apply_adr(x, adv.cpu())
+    with pytest.raises(ValueError):
+        plan.apply_adr(x, adv, out=torch.empty(nc, dtype=torch.float64))
 
 
 def test_adr_rejects_mixed_orders(shp):
