@@ -63,6 +63,13 @@ def test_c0_action_vs_oracle(shp, n, P):
     y = plan.c0_apply(c0, torch.from_numpy(x).cuda(), lam=LAM).cpu().numpy()
     ref = H @ x
     assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+    if n == 3 and P == 1:                # host or mis-sized vectors never reach a kernel
+        with pytest.raises(ValueError):
+            plan.c0_apply(c0, torch.from_numpy(x))
+        with pytest.raises(ValueError):
+            plan.c0_apply(c0, torch.from_numpy(x[:-1]).cuda())
+        with pytest.raises(ValueError):
+            plan.c0_assemble(c0, torch.zeros(3, dtype=torch.float64, device="cuda"))
 
 
 @pytest.mark.parametrize("inner", ["fp64", "fp32"])
