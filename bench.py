@@ -168,7 +168,7 @@ def mixed_precision_leg(torch, shp, W, ncell: int = 32, P: int = 6, lam: float =
 
 
 def affine_leg(torch, shp, W, dof: float = 4e6, Ps=(1, 2, 3, 4)):
-    """Affine single-shape blocks of about 4M DOF (config-3 style): the FP64
+    """Affine single-shape blocks of about 4M DOF (as in the per-shape order sweep): the FP64
     Helmholtz action with the local-matrix strategy (7 reference matrices on
     FP64 MFMA, 7 coefficients per element) against the collocated
     sum-factorisation (per-point factors), GDOF/s from the median of 20

@@ -95,12 +95,12 @@ def test_gain_over_tuning_time(cm):
     assert reg <= 0.25
 
 
-def test_config2_mesh_per_block(cm):
+def test_mixed_mesh_32_P4_per_block(cm):
     """The selector on the blocks of the mixed mesh (32^3 cells, P = 4, curved):
     its pick for each shape's block against the quick exhaustive tuning of that
     block (the mesh is not in the training data; its batch sizes are)."""
     from paper_2604_04644_amd import shp
-    print("[mlp] config-2 mesh, per block", flush=True)
+    print("[mlp] 32^3-cell mixed mesh P=4, per block", flush=True)
     model = cm.CostModel(seed=0)
     model.fit(cm.load_rows(), epochs=1500, lr=3e-3)
     P = 4

@@ -227,9 +227,9 @@ def test_affine_localmat_whole_mesh(shp):
         assert np.array_equal(y[co:co + n * NP], yb.cpu().numpy().ravel()), s
 
 
-def test_config1_affine_hex_helmholtz(shp):
+def test_affine_hex_grid_64_P2_helmholtz(shp):
     """64 affine hexes of side 1/4, P=2, Q=4, lambda=1, seed 0."""
-    say("[parity] config-1 affine hex grid")
+    say("[parity] 64 affine hexahedra (4^3 grid), P=2")
     maps = W.affine_hex_grid(4)
     P = 2
     x = W.coeffs(64, 27, W.SEED_CFG1)
@@ -364,18 +364,18 @@ def _sample(ne, k, rng):
 
 
 @pytest.fixture(scope="module")
-def cfg2(shp):
+def mesh32_p4(shp):
     say("[parity] building the 32^3 mixed mesh at P=4")
     return _mixed_plan(shp, 32, 4)
 
 
 @pytest.mark.parametrize("op", ["helmholtz", "bwd", "iprod", "physderiv"])
-def test_config2_full_mesh_sampled(shp, cfg2, op):
+def test_mixed_mesh_32_P4_sampled(shp, mesh32_p4, op):
     """The mixed P=4 mesh (32^3 cells, 122,880 curved elements) in one launch;
     the oracle checks a sample of elements of every shape."""
-    say(f"[parity] config-2 full mesh op={op}")
+    say(f"[parity] 32^3-cell mixed mesh P=4, sampled elements, op={op}")
     P = 4
-    mesh, plan = cfg2
+    mesh, plan = mesh32_p4
     nc, npnt = plan.totals()
     seeds = W.SEED_MIXED
     if op in ("iprod", "physderiv"):

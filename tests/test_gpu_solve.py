@@ -197,7 +197,7 @@ def test_diag_vs_oracle(shp, P):
         assert e <= 1e-12, (s, e)
 
 
-def test_config4_full_mesh_sampled(shp):
+def test_mixed_mesh_32_P6_solve_sampled(shp):
     """The mixed mesh at P = 6 (32^3 cells, 122,880 curved elements, 17,031,168
     DOF), manufactured right-hand side built on the device, mixed-precision
     solve to residuals 1e-9 and then (continuing) 2e-11; a sample of elements
@@ -206,7 +206,7 @@ def test_config4_full_mesh_sampled(shp):
     ||H_e^-1||_2 ||db_e||_2 / ||x_e||, with ||H_e^-1||_2 from the oracle's
     eigenvalues; the bars are 1e-6 and 1e-10 plus that allowance."""
     P = 6
-    say("[solve] config-4 mesh P=6: geometry")
+    say("[solve] 32^3-cell mixed mesh P=6: geometry")
     mesh, plan = mixed_plan(shp, 32, P)
     f = torch.cat([W.manufactured_u_torch(mesh[s], shp.quadrature(s, P + 2)[0], torch.device("cuda")).reshape(-1)
                    for s in O.SHAPES]) * (LAM + 3 * np.pi ** 2)
@@ -228,7 +228,7 @@ def test_config4_full_mesh_sampled(shp):
     # ~ h): 9e-12 on this mesh against 1.2e-13 on the 4^3 mesh, so the
     # tolerance for the 1e-10 target is 2e-11 here
     for target, tol in ((1e-6, 1e-9), (1e-10, 2e-11)):
-        say(f"[solve] config-4 mesh P=6: solve fp32 inner, tol {tol:g}")
+        say(f"[solve] 32^3-cell mixed mesh P=6: solve fp32 inner, tol {tol:g}")
         x, st = plan.solve(b, x=x, lam=LAM, inner="fp32", tol=tol, max_outer=60, max_inner=20000)
         say(f"    {st}")
         xs = x.cpu().numpy()
