@@ -4,8 +4,8 @@ The network (libshp's shp_mlp_* kernels: forward, backward and Adam written in
 HIP) maps a configuration -- shape one-hot, P, Q, log2 of the batch size, the
 mapping type and a strategy one-hot -- to the standardised log launch time per
 DOF.  The model's choice for a configuration is the strategy with the smallest
-prediction; exhaustive tuning (Plan.tune) stays the fallback and the judge of
-its regret.  Timings come from paper_2604_04644_amd.sweep.
+prediction; exhaustive tuning (Plan.tune) stays the fallback and the measure
+of its regret.  Timings come from paper_2604_04644_amd.sweep.
 """
 from __future__ import annotations
 

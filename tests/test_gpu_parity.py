@@ -2,8 +2,8 @@
 
 Every case prints its name before touching the GPU.  The bar is the max-norm
 error relative to the max-norm of the oracle's result, <= 1e-12 in FP64 (the
-two differ only by summation order; the survey's scratch check measured
-<= 8e-14).  Inputs: the library's quadrature points feed the GPU geometry, the
+two differ only by summation order; a dense-matrix check of the collocated
+form measured <= 8e-14).  Inputs: the library's quadrature points feed the GPU geometry, the
 oracle's own points feed the oracle's geometry; coefficients and point data are
 U[-1,1] from seeded generators.
 """
