@@ -148,6 +148,26 @@ class CostModel:
         return cand[int(np.argmin(pred))]["strategy"]
 
 
+class CostEnsemble:
+    """Several networks trained from different initial weights; the prediction
+    is the mean of their log-time predictions, which damps the run-to-run
+    variance of a single network's choice near strategy crossovers."""
+
+    def __init__(self, seeds=(0, 1, 2), device="cuda"):
+        self.members = [CostModel(seed=sd, device=device) for sd in seeds]
+
+    def fit(self, rows, epochs: int = 3000, lr: float = 3e-3):
+        return [m.fit(rows, epochs=epochs, lr=lr) for m in self.members]
+
+    def predict_log_time(self, rows) -> np.ndarray:
+        return np.mean([m.predict_log_time(rows) for m in self.members], axis=0)
+
+    def choose(self, shape: str, P: int, n_elem: int, curved: int = 1, strategies=STRATS) -> str:
+        cand = [{"shape": shape, "P": P, "Q": P + 2, "n_elem": n_elem, "curved": curved, "strategy": st}
+                for st in strategies]
+        return cand[int(np.argmin(self.predict_log_time(cand)))]["strategy"]
+
+
 def group_configs(rows):
     g = defaultdict(dict)
     for r in rows:
@@ -155,7 +175,7 @@ def group_configs(rows):
     return g
 
 
-def regret(model: CostModel, rows):
+def regret(model, rows):
     """Per configuration: t(model's pick) / t(fastest measured) - 1, and the same
     for the fixed rule 'always sumfac_coll'."""
     out = []

@@ -121,3 +121,22 @@ def test_mixed_mesh_32_P4_per_block(cm):
         regs.append(reg)
         print(f"    {s}: pick {pick}, times {best_of}, regret {reg:.4f}", flush=True)
     assert max(regs) <= 0.1
+
+
+def test_ensemble_regret(cm):
+    """Three networks from different initial weights, predictions averaged: the
+    held-out regret stays at the single network's level or better, and no timed
+    configuration loses more than 25 %."""
+    print("[mlp] ensemble of three networks, held-out regret", flush=True)
+    train, test = cm.split_heldout(cm.load_rows())
+    ens = cm.CostEnsemble(seeds=(0, 1, 2))
+    ens.fit(train, epochs=3000, lr=3e-3)
+    r = cm.regret(ens, test)
+    mean_reg = float(np.mean([x["regret"] for x in r]))
+    timed = [x for x in r if x["best_ms"] >= 0.05]
+    worst = max(timed, key=lambda x: x["regret"])
+    fixed = float(np.mean([x["fixed_regret"] for x in r]))
+    print(f"    ensemble regret mean {mean_reg:.4f}, max over {len(timed)} timed {worst['regret']:.4f} at {worst}; "
+          f"always-collocated {fixed:.4f}", flush=True)
+    assert mean_reg <= 0.2 * fixed or fixed < 0.01
+    assert worst["regret"] <= 0.25
