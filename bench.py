@@ -87,7 +87,11 @@ def build_mesh_plan(torch, shp, W, ncell: int, P: int):
     return mesh, plan
 
 
-def time_launches(torch, fn, steps: int, warmup: int):
+def time_launches(torch, fn, steps: int, warmup: int, flush=None):
+    """Wall time of `steps` launches, and the mean and median of their HIP-event
+    durations on the current stream.  With flush (a device tensor of at least
+    1 GiB) every launch is preceded, outside its events, by a write of that
+    buffer, which evicts the 256 MiB Infinity Cache (MALL)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -95,6 +99,8 @@ def time_launches(torch, fn, steps: int, warmup: int):
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     t0 = time.perf_counter()
     for i in range(steps):
+        if flush is not None:
+            flush.fill_(i & 0xff)
         starts[i].record()
         fn()
         ends[i].record()
@@ -102,6 +108,85 @@ def time_launches(torch, fn, steps: int, warmup: int):
     wall = time.perf_counter() - t0
     ev = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     return wall, float(np.mean(ev)), float(np.median(ev))
+
+
+def flush_buffer(torch):
+    """1 GiB device buffer whose write evicts the 256 MiB Infinity Cache."""
+    return torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+
+
+def copy_bandwidth(torch, flush, reps: int = 10):
+    """Device-to-device copy of 1 GiB (1 GiB read + 1 GiB written) timed with
+    HIP events after a cache flush: the rate a plain streaming kernel reaches."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    _, _, med = time_launches(torch, lambda: dst.copy_(src), reps, 2, flush=flush)
+    del src, dst
+    return 2.0 * (1 << 30) / (med * 1e-3) / 1e9
+
+
+def flops_per_elem(shape: str, P: int) -> int:
+    """Algorithmic FP64 flops of one collocated Helmholtz element action:
+    2 [2 BT + 6 Q^4 + 11 Q^3] with BT the multiply-adds of one sum-factorised
+    BwdTrans (the three line stages) and 6 Q^4 those of the three collocated
+    derivatives and their transposes, 11 Q^3 the metric and the reaction term."""
+    Q, n = P + 2, P + 1
+    NP = {"hex": n ** 3, "prism": n * n * (P + 2) // 2, "pyr": (P + 1) * (P + 2) * (2 * P + 3) // 6,
+          "tet": (P + 1) * (P + 2) * (P + 3) // 6}[shape]
+    if shape == "hex":
+        bt = n ** 3 * Q + n * n * Q * Q + n * Q ** 3
+    elif shape == "tet":
+        bt = NP * Q + (P + 1) * (P + 2) // 2 * Q * Q + n * Q ** 3
+    else:
+        bt = NP * Q + n * n * Q * Q + n * Q ** 3
+    return 2 * (2 * bt + 6 * Q ** 4 + 11 * Q ** 3)
+
+
+FP64_PEAK_TFS = 78.6
+
+
+def order_table(torch, shp, W, flush, ncell: int = 32, Ps=(2, 4, 6, 8, 10), steps: int = 20):
+    """Per shape and order on the mixed mesh: each block's FP64 Helmholtz launch
+    (collocated, default launch shape) and the whole-mesh launch, timed with
+    HIP events after a cache flush (median of `steps`): GDOF/s, fraction of the
+    8 TB/s HBM peak for the algorithmic bytes and of the 78.6 TF FP64 peak for
+    the algorithmic flops."""
+    out = {}
+    dev = torch.device("cuda")
+    mesh = W.quadrant_mesh(ncell)
+    for P in Ps:
+        plan = shp.Plan([(s, P, len(mesh[s]), "curved") for s in SHAPES])
+        for b, s in enumerate(SHAPES):
+            plan.set_geometry(b, W.jacobian_torch(mesh[s], shp.quadrature(s, P + 2)[0], True, dev))
+        nc, _ = plan.totals()
+        x = torch.from_numpy(np.concatenate([W.coeffs(len(mesh[s]), plan.n_modes[b], W.SEED_MIXED[s]).ravel()
+                                             for b, s in enumerate(SHAPES)])).cuda()
+        y = torch.empty_like(x)
+        row = {}
+        tot_b = tot_f = 0
+        for b, s in enumerate(SHAPES):
+            co, _ = plan.offsets(b)
+            ne, nm = len(mesh[s]), plan.n_modes[b]
+            xb = x[co:co + ne * nm].view(ne, nm)
+            yb = y[co:co + ne * nm].view(ne, nm)
+            _, _, med = time_launches(torch, lambda: plan.apply(b, "helmholtz", xb, out=yb), steps, 3, flush=flush)
+            nb = ne * bytes_per_elem(nm, plan.n_points[b])
+            nf = ne * flops_per_elem(s, P)
+            tot_b += nb
+            tot_f += nf
+            row[s] = {"n_elem": ne, "ms": round(med, 5), "GDOF/s": round(ne * nm / (med * 1e-3) / 1e9, 3),
+                      "hbm_frac": round(nb / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "fp64_frac": round(nf / (med * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)}
+        _, _, med = time_launches(torch, lambda: plan.apply(-1, "helmholtz", x, out=y), steps, 3, flush=flush)
+        row["whole_mesh"] = {"n_elem": int(sum(len(mesh[s]) for s in SHAPES)), "ms": round(med, 5),
+                             "GDOF/s": round(nc / (med * 1e-3) / 1e9, 3),
+                             "hbm_frac": round(tot_b / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "fp64_frac": round(tot_f / (med * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)}
+        out[f"P{P}"] = row
+        log(f"  P={P}: " + ", ".join(f"{k} {v['GDOF/s']} GDOF/s ({v['hbm_frac']:.2f} HBM)" for k, v in row.items()))
+        del plan, x, y
+        torch.cuda.empty_cache()
+    return out
 
 
 def mixed_precision_leg(torch, shp, W, ncell: int = 32, P: int = 6, lam: float = 1.0):
@@ -167,12 +252,13 @@ def mixed_precision_leg(torch, shp, W, ncell: int = 32, P: int = 6, lam: float =
                     "error against the FP64 oracle is asserted by the test suite on sampled elements"}
 
 
-def affine_leg(torch, shp, W, dof: float = 4e6, Ps=(1, 2, 3, 4)):
+def affine_leg(torch, shp, W, flush=None, dof: float = 4e6, Ps=(1, 2, 3, 4)):
     """Affine single-shape blocks of about 4M DOF (as in the per-shape order sweep): the FP64
     Helmholtz action with the local-matrix strategy (7 reference matrices on
     FP64 MFMA, 7 coefficients per element) against the collocated
     sum-factorisation (per-point factors), GDOF/s from the median of 20
-    launches."""
+    launches, each after a cache flush (these batches fit in the 256 MiB
+    Infinity Cache)."""
     out = {}
     for s in SHAPES:
         for P in Ps:
@@ -185,7 +271,8 @@ def affine_leg(torch, shp, W, dof: float = 4e6, Ps=(1, 2, 3, 4)):
             y = torch.empty_like(x)
             row = {"n_elem": ne}
             for st in ("localmat", "sumfac_coll"):
-                _, _, med = time_launches(torch, lambda: plan.apply(0, "helmholtz", x, out=y, strategy=st), 20, 3)
+                _, _, med = time_launches(torch, lambda: plan.apply(0, "helmholtz", x, out=y, strategy=st), 20, 3,
+                                          flush=flush)
                 row[st] = round(ne * nm / (med * 1e-3) / 1e9, 2)
             row["localmat_speedup"] = round(row["localmat"] / row["sumfac_coll"], 3)
             out[f"{s}_P{P}"] = row
@@ -263,37 +350,98 @@ def c0_leg(torch, shp, W, n: int = 32, P: int = 4, lam: float = 1.0):
     return out
 
 
-def cpu_baseline(mesh, P: int, budget_s: float = 15.0):
-    """The oracle's Helmholtz action (form H_e by explicit quadrature, then
-    y = H_e x) on a bounded sample of the mesh: rounds of 1/128 of every
-    shape's elements, drawn at random, until the time budget is spent."""
+def _oracle_piece(args):
+    """One worker's share of the CPU baseline: the oracle's Helmholtz action on
+    a slice of elements, formation of the dense H_e (explicit quadrature) and
+    its application timed apart.  The Jacobian is evaluated first, untimed."""
+    shape, P, x0, A, seed = args
     from oracle import shp_oracle as O
     from paper_2604_04644_amd import workloads as W
+    maps = W.ElementMaps(shape, x0, A)
+    jac = W.jacobian(maps, O.reference_points(shape, P + 2), curved=True)
+    x = W.coeffs(len(maps), O.num_modes(shape, P), seed)
+    t_form = t_apply = 0.0
+    for e0 in range(0, len(maps), 64):
+        e1 = min(len(maps), e0 + 64)
+        t0 = time.perf_counter()
+        H = O.Element(shape, P, P + 2, jac[e0:e1]).helmholtz(1.0)
+        t1 = time.perf_counter()
+        np.einsum("emn,en->em", H, x[e0:e1])
+        t2 = time.perf_counter()
+        t_form += t1 - t0
+        t_apply += t2 - t1
+    return len(maps), len(maps) * O.num_modes(shape, P), t_form, t_apply
+
+
+def _cpu_model() -> str:
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(mesh, P: int, frac: int = 8, frac_1t: int = 256, workers: int = 16):
+    """The oracle's Helmholtz action (form each dense H_e by explicit quadrature,
+    then y = H_e x) on a fixed random sample of every shape's elements (1/frac
+    of each block), spread over `workers` single-threaded processes; and the
+    same on a 1/frac_1t sample in one process.  value = sample DOF over the
+    parallel run's wall time (formation and application); the CPU seconds of
+    each part are reported apart."""
+    import multiprocessing as mp
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    nw = max(1, min(workers, avail))
     rng = np.random.default_rng(5)
-    perm = {s: rng.permutation(len(mesh[s])) for s in SHAPES}
-    per = {s: max(1, len(mesh[s]) // 128) for s in SHAPES}
-    dof = n = rounds = 0
-    t_total = 0.0
-    while t_total < budget_s and rounds < 128:
-        for s in SHAPES:
-            idx = np.sort(perm[s][rounds * per[s]:(rounds + 1) * per[s]])
-            sub = mesh[s].take(idx)
-            jac = W.jacobian(sub, O.reference_points(s, P + 2), curved=True)
-            x = W.coeffs(len(idx), O.num_modes(s, P), 11 + rounds)
+    jobs, jobs_1t = [], []
+    for s in SHAPES:
+        perm = rng.permutation(len(mesh[s]))
+        idx = np.sort(perm[:max(1, len(mesh[s]) // frac)])
+        for k, part in enumerate(np.array_split(idx, 4 * nw)):
+            if len(part):
+                jobs.append((s, P, mesh[s].x0[part], mesh[s].A[part], 11 + k))
+        idx1 = np.sort(perm[:max(1, len(mesh[s]) // frac_1t)])
+        jobs_1t.append((s, P, mesh[s].x0[idx1], mesh[s].A[idx1], 7))
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(nw) as pool:
+            pool.map(_oracle_piece, jobs[:nw], chunksize=1)          # workers up and warm
             t0 = time.perf_counter()
-            O.apply_op("helmholtz", s, P, P + 2, jac, x, lam=1.0, chunk=64)
-            t_total += time.perf_counter() - t0
-            dof += len(idx) * O.num_modes(s, P)
-            n += len(idx)
-        rounds += 1
-    return {"value": dof / t_total / 1e9, "unit": "GDOF/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n} elements ({rounds}/128 of every shape, random), P={P}; the oracle forms each dense "
-                      f"H_e by explicit quadrature and applies it; {t_total:.1f} s of oracle time"}
+            res = pool.map(_oracle_piece, jobs, chunksize=1)
+            wall = time.perf_counter() - t0
+        with ctx.Pool(1) as pool:
+            pool.map(_oracle_piece, jobs_1t[:1])
+            t0 = time.perf_counter()
+            res1 = pool.map(_oracle_piece, jobs_1t)
+            wall1 = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    n = sum(r[0] for r in res)
+    dof = sum(r[1] for r in res)
+    t_form = sum(r[2] for r in res)
+    t_apply = sum(r[3] for r in res)
+    dof1 = sum(r[1] for r in res1)
+    return {"value": round(dof / wall / 1e9, 8), "unit": "GDOF/s", "cores": nw, "kind": "oracle",
+            "sample": f"{n} elements (a fixed random 1/{frac} of every shape's block), P={P}, in {nw} "
+                      f"single-threaded processes; the oracle forms each dense H_e by explicit quadrature and "
+                      f"applies it; {wall:.1f} s wall, {t_form + t_apply:.1f} CPU-s",
+            "cpu_model": _cpu_model(), "host_cpus": avail,
+            "formation_cpu_s": round(t_form, 3), "application_cpu_s": round(t_apply, 3),
+            "application_only_GDOF/s": round(dof / (t_apply / nw) / 1e9, 8),
+            "one_thread_GDOF/s": round(dof1 / wall1 / 1e9, 8),
+            "one_thread_sample": f"{sum(r[0] for r in res1)} elements (1/{frac_1t} of every block), {wall1:.1f} s"}
 
 
 def main():
@@ -304,7 +452,9 @@ def main():
     ap.add_argument("--ncell", type=int, default=32)
     ap.add_argument("--P", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--per-shape", action="store_true", help="also time each shape's block launch")
+    ap.add_argument("--no-per-shape", action="store_true",
+                    help="skip the per-shape x order table (P = 2, 4, 6, 8, 10 on the same mesh)")
+    ap.add_argument("--orders", default="2,4,6,8,10", help="orders of the per-shape table")
     ap.add_argument("--strategies", action="store_true",
                     help="also time collocated vs non-collocated Helmholtz per shape (block launches)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg (P=6 mesh)")
@@ -349,24 +499,16 @@ def main():
     ms = wall / a.steps * 1e3
     dof = nc
     value = dof / (wall / a.steps) / 1e9
+    flush = flush_buffer(torch)
+    _, fl_mean_ms, fl_med_ms = time_launches(torch, fn, a.steps, 1, flush=flush)
+    copy_gbs = copy_bandwidth(torch, flush)
     nbytes = sum(len(mesh[s]) * bytes_per_elem(plan.n_modes[b], plan.n_points[b]) for b, s in enumerate(SHAPES))
-    achieved = nbytes / (ev_mean_ms * 1e-3) / 1e9
-    log(f"  {ms:.3f} ms/step, launch {ev_mean_ms:.3f} ms (median {ev_med_ms:.3f}), {value:.2f} GDOF/s, "
-        f"{achieved:.0f} GB/s")
+    nflops = sum(len(mesh[s]) * flops_per_elem(s, P) for s in SHAPES)
+    achieved = nbytes / (fl_mean_ms * 1e-3) / 1e9
+    log(f"  {ms:.3f} ms/step, launch {ev_mean_ms:.3f} ms (median {ev_med_ms:.3f}); with the cache flushed "
+        f"{fl_mean_ms:.3f} ms (median {fl_med_ms:.3f}); {value:.2f} GDOF/s, {achieved:.0f} GB/s; "
+        f"copy {copy_gbs:.0f} GB/s")
     adr = None if a.no_adr else adr_leg(torch, plan, mesh, x, y, ev_mean_ms)
-    per_shape = None
-    if a.per_shape:
-        per_shape = {}
-        for b, s in enumerate(SHAPES):
-            co, _ = plan.offsets(b)
-            ne = len(mesh[s])
-            xb = x[co:co + ne * plan.n_modes[b]].view(ne, -1)
-            yb = torch.empty_like(xb)
-            _, m, _ = time_launches(torch, lambda: plan.apply(b, "helmholtz", xb, out=yb), 20, 3)
-            bb = ne * bytes_per_elem(plan.n_modes[b], plan.n_points[b])
-            per_shape[s] = {"GDOF/s": ne * plan.n_modes[b] / (m * 1e-3) / 1e9,
-                            "hbm_frac": bb / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, "ms": m}
-            log(f"  {s}: {per_shape[s]}")
     strategies = None
     if a.strategies:
         strategies = {}
@@ -387,11 +529,17 @@ def main():
         c0 = c0_leg(torch, shp, W)
     affine = None
     if a.affine:
-        affine = affine_leg(torch, shp, W)
+        affine = affine_leg(torch, shp, W, flush)
+    del plan, x, y
+    torch.cuda.empty_cache()
+    per_shape = None
+    if not a.no_per_shape:
+        log("  per-shape x order table")
+        per_shape = order_table(torch, shp, W, flush, a.ncell, tuple(int(v) for v in a.orders.split(",")))
+    del flush
+    torch.cuda.empty_cache()
     mixed = None
     if not a.no_mixed:
-        del plan
-        torch.cuda.empty_cache()
         mixed = mixed_precision_leg(torch, shp, W, a.mixed_ncell)
     cpu = None
     if not a.no_cpu:
@@ -416,12 +564,18 @@ def main():
                    "elements_per_shape": {s: len(mesh[s]) for s in SHAPES}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(P, a.ncell),
-                     "algorithmic_bytes": int(nbytes), "launch_ms": round(ev_mean_ms, 5)},
+                     "algorithmic_bytes": int(nbytes), "launch_ms": round(fl_mean_ms, 5),
+                     "launch_ms_median": round(fl_med_ms, 5), "timing": "HIP events on the launch stream, "
+                     "Infinity Cache flushed (1 GiB written) before each launch",
+                     "launch_ms_unflushed": round(ev_mean_ms, 5),
+                     "copy_GB/s": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                     "algorithmic_flops": int(nflops),
+                     "fp64_frac": round(nflops / (fl_mean_ms * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)},
         "cpu_baseline": cpu,
         "mixed_vs_fp64": mixed,
     }
     if per_shape is not None:
-        out["per_shape"] = per_shape
+        out["per_shape_and_order"] = per_shape
     if strategies is not None:
         out["collocated_vs_noncollocated"] = strategies
     if affine is not None:

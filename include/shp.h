@@ -107,7 +107,9 @@ typedef struct shp_plan_s* shp_plan;
 /* Number of modes N_P of a shape at order P (Sec. 2.1, N_P; the mode sets above). */
 int shp_num_modes(int shape, int P, int* n_modes /* host out */);
 
-/* Number of quadrature points N_Q = Q^3 of a shape. */
+/* Number of quadrature points N_Q = Q^3 of a shape: every shape takes the
+ * tensor product of Q points per direction (Sec. 2.1, tensor quadrature; the
+ * collapsed shapes keep the full tensor grid in eta, Sec. 2.3). */
 int shp_num_points(int shape, int Q, int* n_points /* host out */);
 
 /* The block's quadrature points in reference coordinates and their weights
@@ -290,8 +292,15 @@ typedef struct {
  * caller's representative input in; its output must match the default
  * collocated launch's output (written to ref) to 1e-12 in the max norm
  * relative to max |ref| or it is rejected; accepted candidates are timed as the
- * median of reps launches with HIP events on stream.  The fastest becomes the
- * launch shape of its strategy and the choice SHP_AUTO makes for (blk, op).
+ * median of reps launches (at most 64) with HIP events on stream, each launch
+ * preceded, outside the events, by a write of a 1 GiB buffer that the call
+ * allocates and frees, so that the 256 MiB Infinity Cache does not serve the
+ * inputs of small batches.  The fastest becomes the launch shape of its
+ * strategy and the choice SHP_AUTO makes for (blk, op).  With blk = -1 on a
+ * plan whose blocks differ in P the whole-mesh call runs one launch per block
+ * with each block's own launch shape, so only the strategies are candidates.
+ * A candidate whose launch the library rejects counts as rejected; a HIP
+ * error ends the call with SHP_ERR_DEVICE.
  * out and ref are caller device buffers of the operator's output size.
  * records (host, may be NULL) receives up to max_records candidate timings.
  * Synchronises stream.  Returns SHP_ERR_NOT_CONVERGED if no candidate passes. */

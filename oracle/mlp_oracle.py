@@ -56,3 +56,16 @@ def loss_grad(p, X, t):
     gb1 = dZ1.sum(axis=0)
     g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
     return float(np.mean((y - t) ** 2)), g
+
+
+def adam_step(p, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (Kingma and Ba 2015, Algorithm 1) in FP64: exponential
+    moving averages of the gradient and of its square, each divided by its
+    bias factor 1 - beta^step, then p -= lr * mhat / (sqrt(vhat) + eps).
+    Returns the new (p, m, v); step counts from 1."""
+    p, g, m, v = (np.asarray(a, dtype=np.float64) for a in (p, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v

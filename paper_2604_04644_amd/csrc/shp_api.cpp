@@ -745,11 +745,18 @@ int shp_tune(shp_plan p, int blk, int op, const double* in, double* out, double*
   unsigned long long* dd = reinterpret_cast<unsigned long long*>(p->ws + p->off_status + 64);
   // reference: the default launch of the collocated strategy
   set_tiling_raw(p, blk, opks[0], Tiling{0, 0, 2});
-  if (int r = shp_apply(p, blk, op, SHP_SUMFAC_COLL, in, ref, lambda, stream)) return r;
+  if (int r = shp_apply(p, blk, op, SHP_SUMFAC_COLL, in, ref, lambda, stream)) {
+    for (int i = 0; i < nstrat; ++i) set_tiling_raw(p, blk, opks[i], saved[i]);
+    return r;
+  }
   hipEvent_t ev[2 * 64];
   const int nev = std::min(reps, 64);
   for (int i = 0; i < 2 * nev; ++i)
-    if (hipEventCreate(&ev[i]) != hipSuccess) return dev_fail(hipGetLastError(), "hipEventCreate");
+    if (hipEventCreate(&ev[i]) != hipSuccess) {
+      for (int j = 0; j < i; ++j) hipEventDestroy(ev[j]);
+      for (int k = 0; k < nstrat; ++k) set_tiling_raw(p, blk, opks[k], saved[k]);
+      return dev_fail(hipGetLastError(), "hipEventCreate");
+    }
   // smallest P of the blocks involved, for the launch-shape limits
   int P = MAX_P;
   if (blk >= 0)
@@ -757,7 +764,14 @@ int shp_tune(shp_plan p, int blk, int op, const double* in, double* out, double*
   else
     for (const auto& B : p->blocks) P = std::min(P, B.d.P);
   const int Q = P + 2;
-  std::vector<int> Es, NTs, Vs;
+  // candidate list: (strategy, launch shape); blocks of different P under one
+  // whole-mesh call run one launch per block with the blocks' own shapes, so
+  // only the strategy is a candidate there
+  struct Cand {
+    int si, E, NT, V;
+  };
+  std::vector<Cand> cands;
+  std::vector<int> Es, NTs;
   if (quick) {
     Es = {1, 2, 4, 8};
     NTs = {128, 256};
@@ -765,16 +779,15 @@ int shp_tune(shp_plan p, int blk, int op, const double* in, double* out, double*
     for (int E = 1; E <= 16; ++E) Es.push_back(E);
     NTs = {64, 128, 192, 256, 320, 384, 512};
   }
-  int ncand = 0, nrej = 0, nrec = 0;
-  Block::Tuned best;
-  best.ms = 1e300;
-  int rc = SHP_OK;
-  for (int si = 0; si < nstrat && rc == SHP_OK; ++si) {
+  const bool shapes_apply = (blk >= 0 || p->uniform_P);
+  for (int si = 0; si < nstrat; ++si) {
     const int st = strategies[si], opk = opks[si];
-    if (helm && st == SHP_SUMFAC_COLL)
-      Vs = quick ? std::vector<int>{0, 2, 3} : std::vector<int>{0, 1, 2, 3, 4};
-    else
-      Vs = {0};
+    if (!shapes_apply) {
+      cands.push_back(Cand{si, 0, 0, 0});
+      continue;
+    }
+    std::vector<int> Vs = {0};
+    if (helm && st == SHP_SUMFAC_COLL) Vs = quick ? std::vector<int>{0, 2, 3} : std::vector<int>{0, 1, 2, 3, 4};
     const bool lm = (st == SHP_LOCALMAT);  // one launch shape: 16 elements, 4 waves
     for (int E : (lm ? std::vector<int>{16} : Es))
       for (int NT : (lm ? std::vector<int>{256} : NTs))
@@ -788,61 +801,90 @@ int shp_tune(shp_plan p, int blk, int op, const double* in, double* out, double*
           else
             for (const auto& B : p->blocks) fits = fits && op_lds_bytes(B.d.shape, B.d.P, opk, E, V) <= 64 * 1024 * 2;
           if (lm) fits = true;
-          if (!fits) continue;
-          set_tiling_raw(p, blk, opk, Tiling{E, NT, V});
-          if ((rc = shp_apply(p, blk, op, st, in, out, lambda, stream))) break;
-          hipError_t e = hipMemsetAsync(dd, 0, 2 * sizeof(unsigned long long), s);
-          if (e == hipSuccess) e = launch_maxdiff(out, ref, nout, dd, s);
-          unsigned long long h[2] = {0, 0};
-          if (e == hipSuccess) e = hipMemcpyAsync(h, dd, sizeof h, hipMemcpyDeviceToHost, s);
-          if (e == hipSuccess) e = hipStreamSynchronize(s);
-          if (e != hipSuccess) {
-            rc = dev_fail(e, "tuning parity check");
-            break;
-          }
-          double dmax, bmax;
-          std::memcpy(&dmax, &h[0], sizeof dmax);
-          std::memcpy(&bmax, &h[1], sizeof bmax);
-          const bool pass = std::isfinite(dmax) && dmax <= 1e-12 * std::max(bmax, 1e-300);
-          ++ncand;
-          double med = -1.0;
-          if (pass) {
-            for (int r = 0; r < nev && rc == SHP_OK; ++r) {
-              hipEventRecord(ev[2 * r], s);
-              rc = shp_apply(p, blk, op, st, in, out, lambda, stream);
-              hipEventRecord(ev[2 * r + 1], s);
-            }
-            if (rc) break;
-            if ((e = hipStreamSynchronize(s)) != hipSuccess) {
-              rc = dev_fail(e, "tuning timing");
-              break;
-            }
-            std::vector<float> t(nev);
-            for (int r = 0; r < nev; ++r) hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]);
-            std::sort(t.begin(), t.end());
-            med = t[nev / 2];
-            if (med < best.ms) {
-              best.valid = true;
-              best.ms = med;
-              best.strategy = st;
-              best.E = E;
-              best.NT = NT;
-              best.variant = V;
-            }
-          } else {
-            ++nrej;
-          }
-          if (records && nrec < max_records) {
-            shp_tune_record& R = records[nrec++];
-            R.strategy = st;
-            R.elems_per_wg = E;
-            R.threads = NT;
-            R.variant = V;
-            R.ms = med;
-            R.passed = pass ? 1 : 0;
-          }
+          if (fits) cands.push_back(Cand{si, E, NT, V});
         }
   }
+  // the Infinity Cache (MALL, 256 MiB) is flushed before every timed launch by
+  // writing a 1 GiB buffer outside the timing events, so small batches are
+  // timed against HBM as large ones are
+  const size_t flush_bytes = size_t(1) << 30;
+  void* flush = nullptr;
+  if (hipMalloc(&flush, flush_bytes) != hipSuccess) {
+    for (int i = 0; i < 2 * nev; ++i) hipEventDestroy(ev[i]);
+    for (int i = 0; i < nstrat; ++i) set_tiling_raw(p, blk, opks[i], saved[i]);
+    return dev_fail(hipGetLastError(), "hipMalloc of the 1 GiB cache-flush buffer");
+  }
+  int ncand = 0, nrej = 0, nrec = 0;
+  Block::Tuned best;
+  best.ms = 1e300;
+  int rc = SHP_OK;
+  for (const Cand& c : cands) {
+    const int st = strategies[c.si], opk = opks[c.si];
+    set_tiling_raw(p, blk, opk, Tiling{c.E, c.NT, c.V});
+    ++ncand;
+    bool pass = false;
+    double med = -1.0;
+    const int ra = shp_apply(p, blk, op, st, in, out, lambda, stream);
+    if (ra == SHP_ERR_DEVICE) {
+      rc = ra;
+      break;
+    }
+    if (ra == SHP_OK) {
+      hipError_t e = hipMemsetAsync(dd, 0, 2 * sizeof(unsigned long long), s);
+      if (e == hipSuccess) e = launch_maxdiff(out, ref, nout, dd, s);
+      unsigned long long h[2] = {0, 0};
+      if (e == hipSuccess) e = hipMemcpyAsync(h, dd, sizeof h, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        rc = dev_fail(e, "tuning parity check");
+        break;
+      }
+      double dmax, bmax;
+      std::memcpy(&dmax, &h[0], sizeof dmax);
+      std::memcpy(&bmax, &h[1], sizeof bmax);
+      pass = std::isfinite(dmax) && dmax <= 1e-12 * std::max(bmax, 1e-300);
+    }
+    if (pass) {
+      for (int r = 0; r < nev && rc == SHP_OK; ++r) {
+        if (hipMemsetAsync(flush, r & 0xff, flush_bytes, s) != hipSuccess) {
+          rc = dev_fail(hipGetLastError(), "cache flush");
+          break;
+        }
+        hipEventRecord(ev[2 * r], s);
+        rc = shp_apply(p, blk, op, st, in, out, lambda, stream);
+        hipEventRecord(ev[2 * r + 1], s);
+      }
+      if (rc) break;
+      if (hipError_t e = hipStreamSynchronize(s); e != hipSuccess) {
+        rc = dev_fail(e, "tuning timing");
+        break;
+      }
+      std::vector<float> t(nev);
+      for (int r = 0; r < nev; ++r) hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]);
+      std::sort(t.begin(), t.end());
+      med = t[nev / 2];
+      if (med < best.ms) {
+        best.valid = true;
+        best.ms = med;
+        best.strategy = st;
+        best.E = c.E;
+        best.NT = c.NT;
+        best.variant = c.V;
+      }
+    } else {
+      ++nrej;  // failed the parity gate, or a launch shape the operator rejects
+    }
+    if (records && nrec < max_records) {
+      shp_tune_record& R = records[nrec++];
+      R.strategy = st;
+      R.elems_per_wg = c.E;
+      R.threads = c.NT;
+      R.variant = c.V;
+      R.ms = med;
+      R.passed = pass ? 1 : 0;
+    }
+  }
+  hipFree(flush);
   for (int i = 0; i < 2 * nev; ++i) hipEventDestroy(ev[i]);
   for (int i = 0; i < nstrat; ++i) set_tiling_raw(p, blk, opks[i], saved[i]);
   if (rc) return rc;

@@ -38,6 +38,38 @@ def test_kernels_vs_oracle(cm):
     assert np.abs(g - go).max() <= 1e-4 * np.abs(go).max()
 
 
+def test_adam_kernel_vs_oracle(cm):
+    """shp_mlp_adam against the FP64 Adam step of the oracle (Kingma and Ba,
+    Algorithm 1), six steps from random parameters and moments with a new
+    random gradient each step; the oracle starts from the same FP32 values."""
+    import ctypes
+    from paper_2604_04644_amd import shp
+    print("[mlp] Adam kernel vs the FP64 oracle", flush=True)
+    model = cm.CostModel(seed=4)
+    n = model.nparam
+    rng = np.random.default_rng(8)
+    p = rng.normal(0, 1, n).astype(np.float32)
+    m = rng.normal(0, 0.1, n).astype(np.float32)
+    v = rng.uniform(0.0, 0.05, n).astype(np.float32)
+    P, Mo, V = (torch.from_numpy(a.copy()).cuda() for a in (p, m, v))
+    po, mo, vo = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    L = shp.lib()
+    lr, b1, b2, eps = 2e-3, 0.85, 0.99, 1e-7
+    for step in range(1, 7):
+        g = rng.normal(0, 1, n).astype(np.float32)
+        G = torch.from_numpy(g).cuda()
+        shp._check(L.shp_mlp_adam(ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(G.data_ptr()),
+                                  ctypes.c_void_p(Mo.data_ptr()), ctypes.c_void_p(V.data_ptr()), step, lr, b1, b2,
+                                  eps, shp._stream(torch)))
+        po, mo, vo = M.adam_step(po, g.astype(np.float64), mo, vo, step, lr=lr, beta1=b1, beta2=b2, eps=eps)
+        ep = np.abs(P.cpu().numpy() - po).max()
+        em = np.abs(Mo.cpu().numpy() - mo).max() / np.abs(mo).max()
+        ev = np.abs(V.cpu().numpy() - vo).max() / np.abs(vo).max()
+        print(f"    step {step}: params max abs {ep:.2e}, m rel {em:.2e}, v rel {ev:.2e}", flush=True)
+        # FP32 state: each step rounds p (|p| < 6) and the moments once more
+        assert ep <= 4e-6 * step and em <= 1e-6 * step and ev <= 1e-6 * step
+
+
 def test_training_and_regret(cm):
     print("[mlp] train on the sweep timings, evaluate held-out regret", flush=True)
     rows = cm.load_rows()
