@@ -80,7 +80,8 @@ typedef enum {
   SHP_OP_HELMHOLTZ = 6       /* [n][N_P] -> [n][N_P]   y = (lambda M + L) x         */
 } shp_op;
 typedef enum {
-  SHP_AUTO = 0,        /* tuned choice if one is cached, else SHP_SUMFAC_COLL     */
+  SHP_AUTO = 0,        /* tuned or set choice, else the cost model's (when one is
+                          loaded, Laplacian and Helmholtz), else SHP_SUMFAC_COLL */
   SHP_SUMFAC = 1,      /* sum-factorisation, non-collocated derivatives (Alg. 5)  */
   SHP_SUMFAC_COLL = 2, /* sum-factorisation, collocated derivatives (Alg. 6)      */
   SHP_LOCALMAT = 3     /* local matrices on FP64 MFMA (Alg. 1, StdMat): curved
@@ -312,6 +313,49 @@ int shp_tune(shp_plan plan, int blk, int op, const double* in /* device */, doub
 /* Fix the strategy SHP_AUTO uses for (blk, op) without tuning (used by a cost
  * model that predicts the fastest strategy). */
 int shp_set_auto_strategy(shp_plan plan, int blk, int op, int strategy);
+
+/* ---- Learned strategy choice ---------------------------------------------
+ * Different implementation choices may be made per block (Sec. 3.3); besides
+ * exhaustive tuning (shp_tune) a plan can carry a cost model, the MLP of the
+ * shp_mlp_* calls below (or an ensemble of up to 4 such networks whose
+ * predictions are averaged), trained on measured launch times.  For a block it
+ * predicts the standardised log launch time per DOF of each strategy from the
+ * features (shape one-hot, P/10, Q/12, log2(n_elem)/22, curved, strategy
+ * one-hot: local matrix, sum-factorisation, collocated); its choice is the
+ * argmin over the strategies the block supports.
+ *
+ * With a model loaded, SHP_AUTO for the Laplacian and Helmholtz actions of a
+ * block that has no tuned or set choice runs the model once (the first such
+ * apply synchronises the stream to read the prediction) and keeps its choice;
+ * a whole-mesh SHP_AUTO call without a tuned or set whole-mesh choice takes
+ * every block's choice: one whole-mesh collocated launch when all blocks pick
+ * the collocated strategy, else one launch per block with its own choice.
+ * Re-binding the workspace drops the model and the choices it made. */
+
+/* Copy a model into the plan's workspace: params device FP32
+ * [n_members][shp_mlp_num_params] (1 <= n_members <= 4), standardisation
+ * mu, sigma > 0 of the training targets (predicted seconds per DOF =
+ * exp(mu + sigma * output)).  Enqueued on stream. */
+int shp_plan_set_model(shp_plan plan, const float* params /* device */, int n_members, double mu, double sigma,
+                       void* stream);
+
+/* Load a model file into the plan: path (host string) or, when NULL, the
+ * environment variable SHP_MODEL_PATH.  The file is one JSON header line,
+ *   {"format": "shp-mlp", "nin": 11, "nh": 64, "n_params": N, "members": M,
+ *    "mu": mu, "sigma": sigma, ...}
+ * then M * N little-endian FP32 parameters (the layout of shp_mlp_forward)
+ * and nothing else.  A missing or malformed file returns SHP_ERR_INVALID_ARG
+ * before any HIP call; synchronises stream. */
+int shp_plan_load_model(shp_plan plan, const char* path /* host or NULL */, void* stream);
+
+/* The model's choice for operator op (SHP_OP_LAPLACIAN or SHP_OP_HELMHOLTZ)
+ * on block blk (non-empty): strategy (host out) and, when pred_ms is not NULL,
+ * the predicted launch time in ms of the local-matrix, sum-factorisation and
+ * collocated strategies (host out [3], +inf where the block does not support
+ * one).  Does not change what SHP_AUTO runs.  Synchronises stream.
+ * SHP_ERR_STATE when no model is loaded. */
+int shp_model_choose(shp_plan plan, int blk, int op, int* strategy /* host out */, double* pred_ms /* host out or NULL */,
+                     void* stream);
 
 /* Append the plan's tuned choices to a JSON-lines cache file, keyed by device,
  * precision, operator, shape, P, Q, log2 of the block size and mapping type. */

@@ -50,6 +50,22 @@ def _fp(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def save_model(path: str, members, source: str = ""):
+    """Write a cost model file that libshp loads (shp_plan_load_model): one
+    JSON header line, then every member's FP32 parameters."""
+    params = [m.params.detach().cpu().numpy().astype("<f4") for m in members]
+    head = {"format": "shp-mlp", "version": 1, "nin": NIN, "nh": 64, "n_params": int(params[0].size),
+            "members": len(params), "mu": members[0].mu, "sigma": members[0].sigma,
+            "target": "standardised log(launch seconds per DOF)",
+            "features": "shape one-hot(hex,prism,pyr,tet), P/10, Q/12, log2(n_elem)/22, curved, "
+                        "strategy one-hot(localmat,sumfac,sumfac_coll)",
+            "source": source}
+    with open(path, "wb") as f:
+        f.write((json.dumps(head) + "\n").encode())
+        for q in params:
+            f.write(q.tobytes())
+
+
 class CostModel:
     """The network's parameters live in a torch float32 tensor on the GPU."""
 
@@ -147,6 +163,9 @@ class CostModel:
         pred = self.predict_log_time(cand)
         return cand[int(np.argmin(pred))]["strategy"]
 
+    def save(self, path: str, source: str = ""):
+        save_model(path, [self], source)
+
 
 class CostEnsemble:
     """Several networks trained from different initial weights; the prediction
@@ -166,6 +185,9 @@ class CostEnsemble:
         cand = [{"shape": shape, "P": P, "Q": P + 2, "n_elem": n_elem, "curved": curved, "strategy": st}
                 for st in strategies]
         return cand[int(np.argmin(self.predict_log_time(cand)))]["strategy"]
+
+    def save(self, path: str, source: str = ""):
+        save_model(path, self.members, source)
 
 
 def group_configs(rows):
@@ -202,3 +224,25 @@ def split_heldout(rows, held_P=(3, 7)):
         for r in rs:
             (test if (P in held_P or r["n_elem"] in odd) else train).append(r)
     return train, test
+
+
+def main():
+    """Train the ensemble on the committed timings and write a model file:
+    python -m paper_2604_04644_amd.costmodel --out FILE [--seeds 0,1,2] [--epochs 3000]"""
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--seeds", default="0,1,2")
+    ap.add_argument("--epochs", type=int, default=3000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    a = ap.parse_args()
+    rows = load_rows()
+    ens = CostEnsemble(seeds=tuple(int(v) for v in a.seeds.split(",")))
+    hist = ens.fit(rows, epochs=a.epochs, lr=a.lr)
+    ens.save(a.out, source=f"{os.path.basename(DATA)}: {len(rows)} rows; seeds {a.seeds}; {a.epochs} epochs of "
+                           f"full-batch Adam, lr {a.lr}")
+    print(json.dumps({"out": a.out, "rows": len(rows), "final_loss": [h[-1][1] for h in hist]}))
+
+
+if __name__ == "__main__":
+    main()

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -37,6 +38,8 @@ int dev_fail(hipError_t e, const char* what) {
 }
 
 constexpr size_t ALIGN = 256;
+constexpr int MLP_NIN = 11;           // cost-model features (shp_mlp_* in shp_mlp.hip)
+constexpr int MODEL_MAX_MEMBERS = 4;  // networks averaged by a loaded cost model
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Tiling {
@@ -59,6 +62,7 @@ struct Block {
   bool geom_ok = false;
   Tiling tiling[OPK_COUNT];
   int auto_strategy[7] = {2, 2, 2, 2, 2, 2, 2};  // per public operator, used by SHP_AUTO
+  int auto_src[7] = {};  // where auto_strategy came from: 0 default, 1 tuned or set, 2 cost model
   struct Tuned {
     bool valid = false;
     int strategy = 2, E = 0, NT = 0, variant = 0;
@@ -80,7 +84,15 @@ struct shp_plan_s {
   bool mixed_dirty[OPK_COUNT] = {};
   bool uniform_P = true;
   int auto_mixed[7] = {2, 2, 2, 2, 2, 2, 2};
+  int auto_mixed_src[7] = {};  // 0 default, 1 tuned or set
   Block::Tuned tuned_mixed[7];
+  // cost model in the workspace: parameters [MODEL_MAX_MEMBERS][nparam], then
+  // features [3][nin], per-sample work [3][work floats], predictions [members][3]
+  size_t off_model = 0;
+  int model_members = 0;
+  double model_mu = 0.0, model_sigma = 1.0;  // prediction = exp(mu + sigma * score) seconds per DOF
+  int mlp_nparam = 0;
+  long long mlp_work = 0;
 };
 
 namespace {
@@ -223,6 +235,11 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
   }
   p->total_coeff = cofs;
   p->total_phys = pofs;
+  shp_mlp_num_params(&p->mlp_nparam);
+  shp_mlp_work_floats(3, &p->mlp_work);
+  p->off_model = off;
+  off = align_up(off + sizeof(float) * ((size_t)MODEL_MAX_MEMBERS * p->mlp_nparam + 3 * MLP_NIN + p->mlp_work +
+                                        3 * MODEL_MAX_MEMBERS));
   p->max_tiles = std::max<long long>(1, p->total_elem);
   p->off_tiles = off;
   off = align_up(off + sizeof(Tile) * (size_t)p->max_tiles * OPK_COUNT);
@@ -265,6 +282,18 @@ int shp_plan_workspace_bytes(shp_plan p, size_t* bytes) {
   if (!bytes) return fail(SHP_ERR_INVALID_ARG, "null output");
   *bytes = p->ws_bytes;
   return SHP_OK;
+}
+
+// Forget the cost model and the choices it made (the workspace changed or a
+// new model is loaded).
+static void drop_model(shp_plan p) {
+  p->model_members = 0;
+  for (auto& B : p->blocks)
+    for (int op = 0; op < 7; ++op)
+      if (B.auto_src[op] == 2) {
+        B.auto_src[op] = 0;
+        B.auto_strategy[op] = SHP_SUMFAC_COLL;
+      }
 }
 
 static int upload_static(shp_plan p, hipStream_t s) {
@@ -312,6 +341,7 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
     if (e != hipSuccess) return dev_fail(e, "hipMemcpyAsync(tables)");
   }
   for (int k = 0; k < OPK_COUNT; ++k) p->mixed_dirty[k] = true;
+  drop_model(p);
   return upload_static(p, s);
 }
 
@@ -501,10 +531,112 @@ static int build_tiles(shp_plan p, int opk, hipStream_t s) {
   return SHP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Learned strategy choice: the cost model's predictions for a block
+// ---------------------------------------------------------------------------
+
+// Strategies in the order of the model's strategy one-hot features.
+constexpr int MODEL_STRATS[3] = {SHP_LOCALMAT, SHP_SUMFAC, SHP_SUMFAC_COLL};
+
+static bool model_op(int op) { return op == SHP_OP_LAPLACIAN || op == SHP_OP_HELMHOLTZ; }
+
+static bool strategy_available(const Block& B, int op, int st) {
+  if (st == SHP_LOCALMAT) return (model_op(op) || op == SHP_OP_MASS) && B.d.P <= LOCALMAT_MAX_P;
+  if (st == SHP_SUMFAC) return model_op(op);
+  return st == SHP_SUMFAC_COLL;
+}
+
+// Standardised predictions (mean over the model's networks) for the three
+// strategies of block blk; synchronises the stream to read them.
+static int model_predict(shp_plan p, int blk, float pred[3], hipStream_t s) {
+  const Block& B = p->blocks[blk];
+  float X[3][MLP_NIN] = {};
+  for (int j = 0; j < 3; ++j) {
+    X[j][B.d.shape] = 1.f;
+    X[j][4] = B.d.P / 10.f;
+    X[j][5] = B.d.Q / 12.f;
+    X[j][6] = (float)(std::log2((double)B.d.n_elem) / 22.0);
+    X[j][7] = B.d.geom == SHP_CURVED ? 1.f : 0.f;
+    X[j][8 + j] = 1.f;
+  }
+  float* prm = reinterpret_cast<float*>(p->ws + p->off_model);
+  float* dX = prm + (size_t)MODEL_MAX_MEMBERS * p->mlp_nparam;
+  float* work = dX + 3 * MLP_NIN;
+  float* dy = work + p->mlp_work;
+  hipError_t e = hipMemcpyAsync(dX, X, sizeof X, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return dev_fail(e, "cost model features");
+  for (int m = 0; m < p->model_members; ++m)
+    if (shp_mlp_forward(prm + (size_t)m * p->mlp_nparam, dX, 3, dy + 3 * m, work, s) != SHP_OK)
+      return dev_fail(hipGetLastError(), "cost model forward");
+  float y[MODEL_MAX_MEMBERS * 3];
+  e = hipMemcpyAsync(y, dy, sizeof(float) * 3 * p->model_members, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_fail(e, "cost model prediction");
+  for (int j = 0; j < 3; ++j) {
+    float acc = 0.f;
+    for (int m = 0; m < p->model_members; ++m) acc += y[3 * m + j];
+    pred[j] = acc / p->model_members;
+  }
+  return SHP_OK;
+}
+
+// The strategy SHP_AUTO runs for (blk, op): a tuned or set choice; else the
+// cost model's argmin over the block's available strategies (Laplacian and
+// Helmholtz, when a model is loaded; remembered for later calls); else the
+// collocated sum-factorisation.
+static int resolve_auto(shp_plan p, int blk, int op, hipStream_t s, int* strategy) {
+  Block& B = p->blocks[blk];
+  if (B.auto_src[op] == 0 && p->model_members > 0 && model_op(op) && B.d.n_elem > 0) {
+    float pred[3];
+    if (int r = model_predict(p, blk, pred, s)) return r;
+    int best = SHP_SUMFAC_COLL;
+    float bv = 0.f;
+    bool have = false;
+    for (int j = 0; j < 3; ++j)
+      if (strategy_available(B, op, MODEL_STRATS[j]) && std::isfinite(pred[j]) && (!have || pred[j] < bv)) {
+        best = MODEL_STRATS[j];
+        bv = pred[j];
+        have = true;
+      }
+    B.auto_strategy[op] = best;
+    B.auto_src[op] = 2;
+  }
+  *strategy = B.auto_strategy[op];
+  return SHP_OK;
+}
+
 int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, double* out, double lambda, void* stream) {
   if (int r = check_plan(p)) return r;
-  if (strategy == SHP_AUTO && op >= 0 && op <= SHP_OP_HELMHOLTZ && blk >= -1 && blk < (int)p->blocks.size())
-    strategy = blk >= 0 ? p->blocks[blk].auto_strategy[op] : p->auto_mixed[op];
+  if (strategy == SHP_AUTO && op >= 0 && op <= SHP_OP_HELMHOLTZ && blk >= -1 && blk < (int)p->blocks.size()) {
+    if (!in || !out) return fail(SHP_ERR_INVALID_ARG, "null in/out");
+    if (!std::isfinite(lambda)) return fail(SHP_ERR_INVALID_ARG, "lambda not finite");
+    if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+    hipStream_t s0 = static_cast<hipStream_t>(stream);
+    if (blk >= 0) {
+      if (int r = resolve_auto(p, blk, op, s0, &strategy)) return r;
+    } else if (p->auto_mixed_src[op] == 0 && p->model_members > 0 && model_op(op)) {
+      // every block's own choice: one whole-mesh collocated launch when all
+      // blocks pick it, else one launch per block
+      bool one_launch = p->uniform_P;
+      for (int b = 0; b < (int)p->blocks.size(); ++b) {
+        if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %d: geometry not set", b);
+        int st;
+        if (int r = resolve_auto(p, b, op, s0, &st)) return r;
+        if (st != SHP_SUMFAC_COLL) one_launch = false;
+      }
+      if (!one_launch) {
+        for (int b = 0; b < (int)p->blocks.size(); ++b) {
+          const Block& B = p->blocks[b];
+          if (int r = shp_apply(p, b, op, B.auto_strategy[op], in + B.coeff_off, out + B.coeff_off, lambda, stream))
+            return r;
+        }
+        return SHP_OK;
+      }
+      strategy = SHP_SUMFAC_COLL;
+    } else {
+      strategy = p->auto_mixed[op];
+    }
+  }
   int opk;
   if (int r = opk_of(op, strategy, &opk)) return r;
   if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
@@ -895,9 +1027,11 @@ int shp_tune(shp_plan p, int blk, int op, const double* in, double* out, double*
   set_tiling_raw(p, blk, bopk, Tiling{best.E, best.NT, best.variant});
   if (blk >= 0) {
     p->blocks[blk].auto_strategy[op] = best.strategy;
+    p->blocks[blk].auto_src[op] = 1;
     p->blocks[blk].tuned[op] = best;
   } else {
     p->auto_mixed[op] = best.strategy;
+    p->auto_mixed_src[op] = 1;
     p->tuned_mixed[op] = best;
   }
   res->strategy = best.strategy;
@@ -915,10 +1049,112 @@ int shp_set_auto_strategy(shp_plan p, int blk, int op, int strategy) {
   if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
   if (op < 0 || op > SHP_OP_HELMHOLTZ) return fail(SHP_ERR_INVALID_ARG, "bad operator %d", op);
   if (strategy < SHP_SUMFAC || strategy > SHP_LOCALMAT) return fail(SHP_ERR_INVALID_ARG, "bad strategy");
-  if (blk >= 0)
+  if (blk >= 0) {
     p->blocks[blk].auto_strategy[op] = strategy;
-  else
+    p->blocks[blk].auto_src[op] = 1;
+  } else {
     p->auto_mixed[op] = strategy;
+    p->auto_mixed_src[op] = 1;
+  }
+  return SHP_OK;
+}
+
+
+// ---- cost model ------------------------------------------------------------
+
+int shp_plan_set_model(shp_plan p, const float* params, int n_members, double mu, double sigma, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!params) return fail(SHP_ERR_INVALID_ARG, "null params");
+  if (n_members < 1 || n_members > MODEL_MAX_MEMBERS)
+    return fail(SHP_ERR_INVALID_ARG, "n_members=%d outside [1,%d]", n_members, MODEL_MAX_MEMBERS);
+  if (!std::isfinite(mu) || !(sigma > 0.0) || !std::isfinite(sigma))
+    return fail(SHP_ERR_INVALID_ARG, "mu, sigma must be finite with sigma > 0");
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  drop_model(p);
+  hipError_t e = hipMemcpyAsync(p->ws + p->off_model, params, sizeof(float) * (size_t)n_members * p->mlp_nparam,
+                                hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return dev_fail(e, "cost model upload");
+  p->model_members = n_members;
+  p->model_mu = mu;
+  p->model_sigma = sigma;
+  return SHP_OK;
+}
+
+// value of "key": <number> in a one-line JSON header, or NAN
+static double json_number(const std::string& h, const char* key) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t i = h.find(k);
+  if (i == std::string::npos) return NAN;
+  i += k.size();
+  while (i < h.size() && (h[i] == ' ' || h[i] == ':')) ++i;
+  char* end = nullptr;
+  const double v = std::strtod(h.c_str() + i, &end);
+  return end == h.c_str() + i ? NAN : v;
+}
+
+int shp_plan_load_model(shp_plan p, const char* path, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!path) path = std::getenv("SHP_MODEL_PATH");
+  if (!path || !*path) return fail(SHP_ERR_INVALID_ARG, "no model path (argument NULL and SHP_MODEL_PATH unset)");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(SHP_ERR_INVALID_ARG, "cannot open model file %s", path);
+  std::string head;
+  int c;
+  while ((c = std::fgetc(f)) != EOF && c != '\n' && head.size() < 4096) head.push_back((char)c);
+  std::vector<float> prm;
+  bool ok = (c == '\n') && head.find("\"shp-mlp\"") != std::string::npos;
+  const double nin = json_number(head, "nin"), nh = json_number(head, "nh"), np = json_number(head, "n_params");
+  const double nm = json_number(head, "members"), mu = json_number(head, "mu"), sg = json_number(head, "sigma");
+  ok = ok && nin == MLP_NIN && nh == 64 && np == p->mlp_nparam && nm >= 1 && nm <= MODEL_MAX_MEMBERS &&
+       nm == std::floor(nm) && std::isfinite(mu) && sg > 0.0 && std::isfinite(sg);
+  if (ok) {
+    prm.resize((size_t)nm * p->mlp_nparam);
+    ok = std::fread(prm.data(), sizeof(float), prm.size(), f) == prm.size() && std::fgetc(f) == EOF;
+    for (float v : prm) ok = ok && std::isfinite(v);
+  }
+  std::fclose(f);
+  if (!ok)
+    return fail(SHP_ERR_INVALID_ARG, "%s is not a cost model file (one JSON header line with format \"shp-mlp\", "
+                "nin 11, nh 64, n_params %d, members 1..%d, mu, sigma > 0; then members x n_params finite FP32 values)",
+                path, p->mlp_nparam, MODEL_MAX_MEMBERS);
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  drop_model(p);
+  hipError_t e = hipMemcpyAsync(p->ws + p->off_model, prm.data(), sizeof(float) * prm.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_fail(e, "cost model upload");
+  p->model_members = (int)nm;
+  p->model_mu = mu;
+  p->model_sigma = sg;
+  return SHP_OK;
+}
+
+int shp_model_choose(shp_plan p, int blk, int op, int* strategy, double* pred_ms, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (blk < 0 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
+  if (op < 0 || op > SHP_OP_HELMHOLTZ) return fail(SHP_ERR_INVALID_ARG, "bad operator %d", op);
+  if (!strategy) return fail(SHP_ERR_INVALID_ARG, "null strategy");
+  if (!model_op(op)) return fail(SHP_ERR_UNSUPPORTED, "the cost model predicts Laplacian and Helmholtz launches");
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  if (p->model_members == 0) return fail(SHP_ERR_STATE, "no cost model loaded");
+  const Block& B = p->blocks[blk];
+  if (B.d.n_elem == 0) return fail(SHP_ERR_INVALID_ARG, "block %d is empty", blk);
+  float pred[3];
+  if (int r = model_predict(p, blk, pred, static_cast<hipStream_t>(stream))) return r;
+  int best = SHP_SUMFAC_COLL;
+  double bv = INFINITY;
+  const double dof = (double)B.d.n_elem * B.NP;
+  for (int j = 0; j < 3; ++j) {
+    const bool av = strategy_available(B, op, MODEL_STRATS[j]) && std::isfinite(pred[j]);
+    const double ms = av ? std::exp(p->model_mu + p->model_sigma * pred[j]) * dof * 1e3 : INFINITY;
+    if (pred_ms) pred_ms[j] = ms;
+    if (ms < bv) {
+      bv = ms;
+      best = MODEL_STRATS[j];
+    }
+  }
+  *strategy = best;
   return SHP_OK;
 }
 
@@ -1032,6 +1268,7 @@ int shp_tune_cache_load(shp_plan p, const char* path, int* n_applied) {
         if (op_lds_bytes(B.d.shape, B.d.P, opk, (int)E, (int)V) > LDS_LIMIT) continue;
         B.tiling[opk] = Tiling{(int)E, (int)NT, (int)V};
         B.auto_strategy[op] = (int)st;
+        B.auto_src[op] = 1;
         ++applied;
       }
     } else if (kind == "mixed") {
@@ -1040,6 +1277,7 @@ int shp_tune_cache_load(shp_plan p, const char* path, int* n_applied) {
       p->mixed[opk] = Tiling{(int)E, (int)NT, (int)V};
       p->mixed_dirty[opk] = true;
       p->auto_mixed[op] = (int)st;
+      p->auto_mixed_src[op] = 1;
       ++applied;
     }
   }

@@ -67,6 +67,11 @@ _SIGS = {
                                ctypes.c_void_p, ctypes.c_void_p],
     "shp_helmholtz_diag": [ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                            ctypes.c_void_p],
+    "shp_plan_set_model": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                           ctypes.c_void_p],
+    "shp_plan_load_model": [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p],
+    "shp_model_choose": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
+                         ctypes.c_void_p],
     "shp_helmholtz_solve": [ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p],
@@ -157,9 +162,11 @@ def _stream(torch):
 class Plan:
     """A plan over blocks [(shape, P, n_elem, geom[, pts])], with its workspace
     held as a torch uint8 tensor on the current device.  geom defaults to
-    "curved", pts (the collapsed directions' points) to "gj"."""
+    "curved", pts (the collapsed directions' points) to "gj".  model: a cost
+    model file to load (see load_model); by default the file named by the
+    environment variable SHP_MODEL_PATH, if it is set."""
 
-    def __init__(self, blocks: Sequence, device=None):
+    def __init__(self, blocks: Sequence, device=None, model=None):
         import torch
         self._torch = torch
         if not torch.cuda.is_available():
@@ -181,6 +188,35 @@ class Plan:
         _check(lib().shp_plan_bind_workspace(self._h, ctypes.c_void_p(self._ws_ptr), nb.value, _stream(torch)))
         self.n_modes = [num_modes(sh, P) for sh, P, _, _ in self.blocks]
         self.n_points = [(P + 2) ** 3 for _, P, _, _ in self.blocks]
+        if model is not None or os.environ.get("SHP_MODEL_PATH"):
+            self.load_model(model)
+
+    # ---------------------------------------------------------------
+    def load_model(self, path=None):
+        """Load a cost model file (path, else $SHP_MODEL_PATH): SHP_AUTO then
+        uses its per-block choice for the Laplacian and Helmholtz actions."""
+        _check(lib().shp_plan_load_model(self._h, None if path is None else str(path).encode(),
+                                         _stream(self._torch)))
+
+    def set_model(self, params, mu: float, sigma: float):
+        """Copy a model's parameters (float32 device tensor [members][n_params]
+        or [n_params]) into the plan."""
+        t = self._torch
+        if params.dtype != t.float32 or not params.is_cuda or not params.is_contiguous():
+            raise ValueError("params must be a contiguous float32 device tensor")
+        members = params.shape[0] if params.dim() == 2 else 1
+        _check(lib().shp_plan_set_model(self._h, ctypes.c_void_p(params.data_ptr()), members, float(mu),
+                                        float(sigma), _stream(t)))
+
+    def model_choose(self, blk: int, op: str = "helmholtz"):
+        """The loaded model's strategy for (blk, op) and its predicted launch
+        times in ms {strategy: ms} (inf where the block has no such strategy)."""
+        import numpy as np
+        st = ctypes.c_int()
+        pred = np.empty(3)
+        _check(lib().shp_model_choose(self._h, blk, OPS[op], ctypes.byref(st), ctypes.c_void_p(pred.ctypes.data),
+                                      _stream(self._torch)))
+        return STRATEGY_NAME[st.value], dict(zip(("localmat", "sumfac", "sumfac_coll"), pred.tolist()))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -227,8 +263,10 @@ class Plan:
             return {"iprod": npnt, "physderiv": npnt, "iprod_deriv": 3 * npnt}.get(op, nc)
         return {"iprod": ne * nq, "physderiv": ne * nq, "iprod_deriv": 3 * ne * nq}.get(op, ne * nm)
 
-    def apply(self, blk: int, op: str, x, out=None, lam: float = 1.0, strategy: str = "sumfac_coll"):
-        """y = op(x) for block blk (or the whole mesh, blk = -1)."""
+    def apply(self, blk: int, op: str, x, out=None, lam: float = 1.0, strategy: str = "auto"):
+        """y = op(x) for block blk (or the whole mesh, blk = -1); strategy
+        "auto" runs the tuned or set choice, else the cost model's (when one is
+        loaded), else the collocated sum-factorisation."""
         t = self._torch
         if x.dtype != t.float64 or not x.is_cuda or not x.is_contiguous():
             raise ValueError("x must be a contiguous float64 device tensor")

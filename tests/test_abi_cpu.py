@@ -188,3 +188,38 @@ def test_no_fallback_without_library_or_device(tmp_path):
         from paper_2604_04644_amd import shp
         with pytest.raises(RuntimeError):
             shp.Plan([("hex", 2, 4, "curved")])
+
+
+def test_model_file_validation_without_device(L, tmp_path):
+    """shp_plan_load_model checks the file before any HIP call: a missing,
+    truncated, mis-sized or non-finite file is INVALID_ARG; a good file on a
+    plan without a workspace is STATE (the upload needs the device)."""
+    import json
+    import struct
+    from paper_2604_04644_amd import shp
+    arr = (shp._BlockDesc * 1)(shp._BlockDesc(0, 2, 4, 10, 1, 0))
+    h = ctypes.c_void_p()
+    assert L.shp_plan_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p), 1) == 0
+    L.shp_plan_load_model.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p]
+    n = 64 * 11 + 64 + 64 * 64 + 64 + 64 + 1
+
+    def write(name, head, values):
+        p = tmp_path / name
+        with open(p, "wb") as f:
+            f.write((json.dumps(head) + "\n").encode())
+            f.write(struct.pack(f"<{len(values)}f", *values))
+        return str(p).encode()
+
+    good = {"format": "shp-mlp", "nin": 11, "nh": 64, "n_params": n, "members": 2, "mu": -20.0, "sigma": 1.5}
+    ok = write("ok.bin", good, [0.01] * (2 * n))
+    assert L.shp_plan_load_model(h, ok, None) == -5
+    assert L.shp_plan_load_model(h, str(tmp_path / "none.bin").encode(), None) == -1
+    assert L.shp_plan_load_model(h, write("short.bin", good, [0.01] * (2 * n - 1)), None) == -1
+    assert L.shp_plan_load_model(h, write("long.bin", good, [0.01] * (2 * n + 1)), None) == -1
+    assert L.shp_plan_load_model(h, write("nan.bin", good, [0.01] * (2 * n - 1) + [float("nan")]), None) == -1
+    assert L.shp_plan_load_model(h, write("sig.bin", dict(good, sigma=0.0), [0.01] * (2 * n)), None) == -1
+    assert L.shp_plan_load_model(h, write("mem.bin", dict(good, members=5), [0.01] * (5 * n)), None) == -1
+    assert L.shp_plan_load_model(h, write("fmt.bin", dict(good, format="other"), [0.01] * (2 * n)), None) == -1
+    assert L.shp_plan_load_model(h, write("nh.bin", dict(good, nh=32), [0.01] * (2 * n)), None) == -1
+    assert "cost model file" in L.shp_last_error().decode()
+    L.shp_plan_destroy(h)

@@ -172,3 +172,82 @@ def test_ensemble_regret(cm):
           f"always-collocated {fixed:.4f}", flush=True)
     assert mean_reg <= 0.2 * fixed or fixed < 0.01
     assert worst["regret"] <= 0.25
+
+
+def _model_file(cm, tmp_path, rows):
+    ens = cm.CostEnsemble(seeds=(0, 1, 2))
+    ens.fit(rows, epochs=3000, lr=3e-3)
+    path = str(tmp_path / "model.shpmlp")
+    ens.save(path, source="test")
+    return ens, path
+
+
+def test_library_selector_matches_python_and_regret(cm, tmp_path):
+    """The library's choice (shp_model_choose, the C ABI) on every held-out
+    configuration equals the Python argmin of the same ensemble's predictions
+    (except at near-ties of the prediction), and the regret of the library's
+    picks against the measured timings stays within the ensemble's bar."""
+    from paper_2604_04644_amd import shp
+    print("[mlp] library selector vs Python argmin, held-out regret through the C ABI", flush=True)
+    train, test = cm.split_heldout(cm.load_rows())
+    ens, path = _model_file(cm, tmp_path, train)
+    regs, ties, n = [], 0, 0
+    for (shape, P, ne, curved), byst in sorted(cm.group_configs(test).items()):
+        strats = tuple(s for s in cm.STRATS if s in byst)
+        plan = shp.Plan([(shape, P, ne, "curved" if curved else "affine")], model=path)
+        pick, pred_ms = plan.model_choose(0, "helmholtz")
+        del plan
+        cand = [{"shape": shape, "P": P, "Q": P + 2, "n_elem": ne, "curved": curved, "strategy": s} for s in strats]
+        lt = ens.predict_log_time(cand)
+        order = np.argsort(lt)
+        n += 1
+        if len(lt) > 1 and lt[order[1]] - lt[order[0]] < 1e-4:
+            ties += 1
+        else:
+            assert pick == strats[order[0]], (shape, P, ne, curved, pick, dict(zip(strats, lt)))
+        # predicted launch times: exp of the same predictions
+        for s, v in zip(strats, lt):
+            assert abs(pred_ms[s] / (np.exp(v) * byst[s]["dof"] * 1e3) - 1) < 1e-3, (s, pred_ms[s])
+        best = min(r["ms"] for r in byst.values())
+        regs.append(byst[pick]["ms"] / best - 1.0)
+    timed = [r for r, ((_, _, _, _), byst) in zip(regs, sorted(cm.group_configs(test).items()))
+             if min(x["ms"] for x in byst.values()) >= 0.05]
+    print(f"    {n} configurations, {ties} near-ties; library regret mean {np.mean(regs):.4f}, "
+          f"max over {len(timed)} timed {max(timed):.4f}", flush=True)
+    assert ties <= n // 20
+    assert np.mean(regs) <= 0.02 and max(timed) <= 0.25
+
+
+def test_auto_strategy_uses_the_model(cm, tmp_path):
+    """With a model loaded, SHP_AUTO on a block runs the model's choice (the
+    same bits as that strategy run explicitly) and a whole-mesh SHP_AUTO call
+    runs every block's choice; a tuned choice overrides the model."""
+    from paper_2604_04644_amd import shp
+    print("[mlp] SHP_AUTO with a loaded model", flush=True)
+    _, path = _model_file(cm, tmp_path, cm.load_rows())
+    blocks = [("hex", 1, 60000, "affine"), ("tet", 6, 3000, "curved")]
+    plan = shp.Plan(blocks, model=path)
+    for b, (s, P, ne, geom) in enumerate(blocks):
+        maps = W.shape_batch(s, ne)
+        if geom == "affine":
+            plan.set_geometry(b, torch.from_numpy(W.affine_jacobian(maps)).cuda())
+        else:
+            plan.set_geometry(b, W.jacobian_torch(maps, shp.quadrature(s, P + 2)[0], True, "cuda"))
+    picks = [plan.model_choose(b, "helmholtz")[0] for b in range(2)]
+    print(f"    picks {picks}", flush=True)
+    assert picks[0] == "localmat"      # affine low order: the measured winner by far
+    nc, _ = plan.totals()
+    x = torch.from_numpy(W.coeffs(1, nc, 5)[0]).cuda()
+    y_auto = plan.apply(-1, "helmholtz", x).cpu().numpy()
+    for b in range(2):
+        co, _ = plan.offsets(b)
+        ne, NP = blocks[b][2], plan.n_modes[b]
+        xb = x[co:co + ne * NP].view(ne, NP).contiguous()
+        yb_auto = plan.apply(b, "helmholtz", xb).cpu().numpy().ravel()
+        yb = plan.apply(b, "helmholtz", xb, strategy=picks[b]).cpu().numpy().ravel()
+        assert np.array_equal(yb_auto, yb) and np.array_equal(y_auto[co:co + ne * NP], yb)
+    plan.set_auto_strategy(0, "helmholtz", "sumfac_coll")
+    co, _ = plan.offsets(0)
+    xb = x[:blocks[0][2] * plan.n_modes[0]].view(blocks[0][2], -1).contiguous()
+    assert np.array_equal(plan.apply(0, "helmholtz", xb).cpu().numpy(),
+                          plan.apply(0, "helmholtz", xb, strategy="sumfac_coll").cpu().numpy())
