@@ -210,8 +210,11 @@ int shp_solve_workspace_bytes(shp_plan plan, size_t* bytes /* host out */);
 
 /* Jacobi preconditioner: diag[i] = H_e[m][m] for the coefficient i = mode m of
  * element e, in the whole-mesh layout (device FP64 out, [total coefficients]).
- * Formed with FP64 collocated actions on the unit vectors of each local mode
- * index (max N_P whole-mesh actions). */
+ * Sum-factorised in FP64 from the geometric factors: with the collocated
+ * derivatives (Sec. 2.2.1, eq. helm1) each mode's values and derivatives at
+ * the points are products of its 1D factors, so H_mm is each of the 7 factor
+ * fields contracted direction by direction with squared 1D values (about one
+ * operator action of work).  ws is validated as for the solve but not used. */
 int shp_helmholtz_diag(shp_plan plan, double lambda, double* diag /* device out */, void* ws /* device */,
                        size_t ws_bytes, void* stream);
 

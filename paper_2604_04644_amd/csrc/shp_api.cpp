@@ -58,6 +58,10 @@ struct Block {
   std::vector<double> am;  // affine blocks: 7 reference matrices, MFMA fragment order
   size_t off_am = 0, off_coef = 0;
   std::vector<float> tabf; // the reference tables rounded to FP32
+  std::vector<double> dtab; // sum-factorised Helmholtz diagonal: 1D factor tables
+  std::vector<int> ditab;   //   and their pair and mode indices
+  int dn1 = 0, dn12 = 0;
+  size_t off_dtab = 0, off_ditab = 0;
   long long coeff_off = 0, phys_off = 0;
   bool geom_ok = false;
   Tiling tiling[OPK_COUNT];
@@ -221,6 +225,7 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     B.NP = num_modes(B.d.shape, B.d.P);
     B.NQ = B.d.Q * B.d.Q * B.d.Q;
     build_tables(B.d.shape, B.d.P, B.d.pts, B.tab, B.itab);
+    build_diag_tables(B.d.shape, B.d.P, B.d.pts, B.dtab, B.ditab, B.dn1, B.dn12);
     if (B.d.P <= LOCALMAT_MAX_P) {
       int q3p, kp;
       build_localmat(B.d.shape, B.d.P, B.d.pts, B.lm, q3p, kp);
@@ -254,6 +259,10 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     off = align_up(off + sizeof(float) * B.tab.size());
     B.off_am = off;
     off = align_up(off + sizeof(double) * B.am.size());
+    B.off_dtab = off;
+    off = align_up(off + sizeof(double) * B.dtab.size());
+    B.off_ditab = off;
+    off = align_up(off + sizeof(int) * B.ditab.size());
   }
   for (auto& B : p->blocks) {
     B.off_fac = off;
@@ -334,6 +343,10 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
       e = hipMemcpyAsync(p->ws + B.off_lm, B.lm.data(), sizeof(double) * B.lm.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.am.empty())
       e = hipMemcpyAsync(p->ws + B.off_am, B.am.data(), sizeof(double) * B.am.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->ws + B.off_dtab, B.dtab.data(), sizeof(double) * B.dtab.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->ws + B.off_ditab, B.ditab.data(), sizeof(int) * B.ditab.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
       B.tabf.assign(B.tab.begin(), B.tab.end());
       e = hipMemcpyAsync(p->ws + B.off_tabf, B.tabf.data(), sizeof(float) * B.tabf.size(), hipMemcpyHostToDevice, s);
@@ -389,18 +402,18 @@ int shp_plan_set_geometry(shp_plan p, int blk, const double* jac, void* stream) 
 
 namespace shp {
 
-int plan_mode_index(shp_plan_s* p, std::vector<int>& mode) {
-  if (int r = check_plan(p)) return r;
-  mode.assign(p->total_coeff, 0);
-  for (const auto& B : p->blocks) {
-    const int nm = num_modes(B.d.shape, B.d.P);
-    for (long long e = 0; e < B.d.n_elem; ++e)
-      for (int m = 0; m < nm; ++m) mode[B.coeff_off + e * nm + m] = m;
+long long plan_total_coeff(const shp_plan_s* p) { return p ? p->total_coeff : 0; }
+
+int plan_helm_diag(shp_plan_s* p, double lambda, double* diag, hipStream_t s) {
+  for (const Block& B : p->blocks) {
+    const hipError_t e = launch_helm_diag(reinterpret_cast<const double*>(p->ws + B.off_fac),
+                                          reinterpret_cast<const double*>(p->ws + B.off_dtab),
+                                          reinterpret_cast<const int*>(p->ws + B.off_ditab), B.d.Q, B.dn1, B.dn12,
+                                          B.NP, B.d.n_elem, lambda, diag + B.coeff_off, s);
+    if (e != hipSuccess) return dev_fail(e, "Helmholtz diagonal");
   }
   return SHP_OK;
 }
-
-long long plan_total_coeff(const shp_plan_s* p) { return p ? p->total_coeff : 0; }
 
 int plan_check_solve(shp_plan_s* p, int inner_prec) {
   if (int r = check_plan(p)) return r;

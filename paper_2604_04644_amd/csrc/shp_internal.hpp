@@ -40,6 +40,12 @@ void rule_1d(int Q, int alpha, int pts, double* x, double* w);
 void build_tables(int sh, int P, int pts, std::vector<double>& tab, std::vector<int>& itab);
 void reference_points(int sh, int Q, int pts, double* xi, double* w);
 void build_localmat(int sh, int P, int pts, std::vector<double>& bcat, int& Q3p, int& Kp);
+// tables of the sum-factorised Helmholtz diagonal (see shp_tables.cpp)
+void build_diag_tables(int sh, int P, int pts, std::vector<double>& dt, std::vector<int>& di, int& n1, int& n12);
+// diag(lambda M + L) of n_elem elements of one block from its factors
+// fac [n_elem][NFAC][Q^3]: one work-group per element; diag [n_elem][NP]
+hipError_t launch_helm_diag(const double* fac, const double* dt, const int* di, int Q, int n1, int n12, int NP,
+                            long long n_elem, double lambda, double* diag, hipStream_t s);
 constexpr int LOCALMAT_MAX_P = 4;  // dense reference matrices only at low order
 // affine blocks: the 7 reference matrices of H = sum_k c_{e,k} A_k in MFMA
 // fragment order (Kp = modes padded to 16, 7 Kp^2 values); coefficients per element
@@ -78,11 +84,11 @@ hipError_t launch_maxdiff(const double* a, const double* b, long long n, unsigne
 constexpr int MAX_P = 10;
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
-// Plan queries for the solver (shp_api.cpp): the local mode index of every
-// coefficient of the whole mesh, the mesh's coefficient count, and the error
-// text reported by shp_last_error.
-int plan_mode_index(shp_plan_s* p, std::vector<int>& mode);
+// Plan queries for the solver (shp_api.cpp): the mesh's coefficient count,
+// the Helmholtz diagonal, and the error text reported by shp_last_error.
 long long plan_total_coeff(const shp_plan_s* p);
+// diag(lambda M + L) of every element, whole-mesh layout (sum-factorised, FP64)
+int plan_helm_diag(shp_plan_s* p, double lambda, double* diag, hipStream_t s);
 int plan_check_solve(shp_plan_s* p, int inner_prec);  // workspace, geometry, FP32 needs one P
 int set_error(int code, const char* msg);
 

@@ -165,16 +165,6 @@ __global__ void k_cg2_r(T* __restrict__ p, const T* __restrict__ r, const T* __r
     p[i] = r[i] / dg[i] + beta * p[i];
 }
 
-// unit vectors of one local mode index, and the diagonal gather
-__global__ void k_unit(double* __restrict__ x, const int* __restrict__ mode, int m, long long n) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    x[i] = (mode[i] == m) ? 1.0 : 0.0;
-}
-__global__ void k_gather(const double* __restrict__ y, const int* __restrict__ mode, int m, double* __restrict__ d,
-                         long long n) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    if (mode[i] == m) d[i] = y[i];
-}
 __global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     b[i] = (float)a[i];
@@ -210,7 +200,6 @@ struct SolveWs {
   double *r, *y, *xb, *slot, *part, *part_rz;  // part_rz: r^T z partials of k_cg1_rz
   float* diagf;
   void* vec;  // inner vectors: rs, z, p, q, d (5 n of the inner type)
-  int* mode;
   unsigned long long* rmax;
 };
 
@@ -230,7 +219,6 @@ size_t carve(void* base, long long n, SolveWs* w) {
   s.xb = reinterpret_cast<double*>(take(sizeof(double) * n));
   s.diagf = reinterpret_cast<float*>(take(sizeof(float) * n));
   s.vec = take(sizeof(double) * 5 * n);
-  s.mode = reinterpret_cast<int*>(take(sizeof(int) * n));
   s.slot = reinterpret_cast<double*>(take(sizeof(double) * 16));
   s.part = reinterpret_cast<double*>(take(sizeof(double) * NB));
   s.part_rz = reinterpret_cast<double*>(take(sizeof(double) * NB));
@@ -506,25 +494,8 @@ int shp_helmholtz_diag(shp_plan plan, double lambda, double* diag, void* ws, siz
     return sfail(SHP_ERR_WORKSPACE, "solver workspace missing, misaligned or too small");
   if (int r = shp::plan_check_solve(plan, SHP_FP64)) return r;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  SolveWs w;
-  carve(ws, n, &w);
-  const dim3 g = grid_for(n), bl(256);
-  int maxm = 0;
-  {
-    std::vector<int> hm;
-    if (int r = shp::plan_mode_index(plan, hm)) return r;
-    for (long long i = 0; i < n; ++i) maxm = std::max(maxm, hm[i] + 1);
-    if (hipMemcpyAsync(w.mode, hm.data(), sizeof(int) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return sfail(SHP_ERR_DEVICE, "mode index upload");
-  }
-  // every element's H_e applied to its m-th unit vector at once; entry m of
-  // the result is H_e[m][m]
-  for (int m = 0; m < maxm; ++m) {
-    hipLaunchKernelGGL(k_unit, g, bl, 0, s, w.r, w.mode, m, n);
-    if (int r = shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, w.r, w.y, lambda, s)) return r;
-    hipLaunchKernelGGL(k_gather, g, bl, 0, s, w.y, w.mode, m, diag, n);
-  }
+  // sum-factorised: every mode's 1D factors contracted with the 7 factors
+  if (int r = shp::plan_helm_diag(plan, lambda, diag, s)) return r;
   if (hipStreamSynchronize(s) != hipSuccess) return sfail(SHP_ERR_DEVICE, "diagonal");
   return SHP_OK;
 }

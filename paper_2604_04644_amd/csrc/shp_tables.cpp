@@ -226,6 +226,44 @@ void build_tables(int sh, int P, int pts, std::vector<double>& tab, std::vector<
 // multiple of 16, columns to a multiple of 16 (zeros).  Each mode is a product
 // of 1D functions of eta (the collapsed-vertex modes drop the factors of the
 // collapsed coordinates), differentiated factor by factor.
+// 1D factors of mode (p, q, r): every mode is a product a(eta1) b(eta2)
+// c(eta3) of 1D functions; the collapsed-vertex modes drop the factors of the
+// collapsed coordinates (constant 1).  Kinds: 0 = constant 1, 1 = A_a,
+// 2 = C_{a,b}, 3 = v1.
+struct Factor {
+  int kind, a, b;
+  bool operator==(const Factor& o) const { return kind == o.kind && a == o.a && b == o.b; }
+};
+
+static void mode_factors(int sh, int p, int q, int r, Factor f[3]) {
+  if (sh == HEX) {
+    f[0] = {1, p, 0}; f[1] = {1, q, 0}; f[2] = {1, r, 0};
+  } else if (sh == PRISM) {
+    if (p == 0 && r == 1) { f[0] = {0, 0, 0}; f[1] = {1, q, 0}; f[2] = {3, 0, 0}; }
+    else { f[0] = {1, p, 0}; f[1] = {1, q, 0}; f[2] = {2, p, r}; }
+  } else if (sh == PYR) {
+    if (p == 0 && q == 0 && r == 1) { f[0] = {0, 0, 0}; f[1] = {0, 0, 0}; f[2] = {3, 0, 0}; }
+    else { f[0] = {1, p, 0}; f[1] = {1, q, 0}; f[2] = {2, imax(p, q), r}; }
+  } else {
+    if (p == 0 && q == 0 && r == 1) { f[0] = {0, 0, 0}; f[1] = {0, 0, 0}; f[2] = {3, 0, 0}; }
+    else if (p == 0 && q == 1) { f[0] = {0, 0, 0}; f[1] = {3, 0, 0}; f[2] = {2, 1, r}; }
+    else { f[0] = {1, p, 0}; f[1] = {2, p, q}; f[2] = {2, p + q, r}; }
+  }
+}
+
+static double factor_value(const Factor& f, double x, bool der) {
+  switch (f.kind) {
+    case 0: return der ? 0.0 : 1.0;
+    case 1: return der ? fdA(f.a, x) : fA(f.a, x);
+    case 2: return der ? fdC(f.a, f.b, x) : fC(f.a, f.b, x);
+    default: return der ? 0.5 : 0.5 * (1.0 + x);
+  }
+}
+
+// Dense reference matrices [B; d_1 B; d_2 B; d_3 B] at the quadrature points
+// for the local-matrix strategy: row d*Q3p + q, column m; rows padded to a
+// multiple of 16, columns to a multiple of 16 (zeros).  Each mode's 1D factors
+// are differentiated factor by factor.
 void build_localmat(int sh, int P, int pts, std::vector<double>& bcat, int& Q3p, int& Kp) {
   const int Q = P + 2, Q3 = Q * Q * Q, NP = num_modes(sh, P);
   Q3p = (Q3 + 15) / 16 * 16;
@@ -233,34 +271,12 @@ void build_localmat(int sh, int P, int pts, std::vector<double>& bcat, int& Q3p,
   bcat.assign((size_t)4 * Q3p * Kp, 0.0);
   std::vector<double> z(3 * Q), w(3 * Q);
   for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), pts, z.data() + d * Q, w.data() + d * Q);
-  // 1D factor kinds: 0 = constant 1, 1 = A_p, 2 = C_{k,r}, 3 = v1
-  struct F { int kind, a, b; };
-  auto fval = [](const F& f, double x, bool der) {
-    switch (f.kind) {
-      case 0: return der ? 0.0 : 1.0;
-      case 1: return der ? fdA(f.a, x) : fA(f.a, x);
-      case 2: return der ? fdC(f.a, f.b, x) : fC(f.a, f.b, x);
-      default: return der ? 0.5 : 0.5 * (1.0 + x);
-    }
-  };
   int m = 0;
   for (int p = 0; p <= P; ++p)
     for (int q = 0; q < nq_of(sh, P, p); ++q)
       for (int r = 0; r < col_len(sh, P, p, q); ++r, ++m) {
-        F f[3];
-        if (sh == HEX) {
-          f[0] = {1, p, 0}; f[1] = {1, q, 0}; f[2] = {1, r, 0};
-        } else if (sh == PRISM) {
-          if (p == 0 && r == 1) { f[0] = {0, 0, 0}; f[1] = {1, q, 0}; f[2] = {3, 0, 0}; }
-          else { f[0] = {1, p, 0}; f[1] = {1, q, 0}; f[2] = {2, p, r}; }
-        } else if (sh == PYR) {
-          if (p == 0 && q == 0 && r == 1) { f[0] = {0, 0, 0}; f[1] = {0, 0, 0}; f[2] = {3, 0, 0}; }
-          else { f[0] = {1, p, 0}; f[1] = {1, q, 0}; f[2] = {2, imax(p, q), r}; }
-        } else {
-          if (p == 0 && q == 0 && r == 1) { f[0] = {0, 0, 0}; f[1] = {0, 0, 0}; f[2] = {3, 0, 0}; }
-          else if (p == 0 && q == 1) { f[0] = {0, 0, 0}; f[1] = {3, 0, 0}; f[2] = {2, 1, r}; }
-          else { f[0] = {1, p, 0}; f[1] = {2, p, q}; f[2] = {2, p + q, r}; }
-        }
+        Factor f[3];
+        mode_factors(sh, p, q, r, f);
         for (int i = 0; i < Q; ++i)
           for (int j = 0; j < Q; ++j)
             for (int k = 0; k < Q; ++k) {
@@ -268,8 +284,8 @@ void build_localmat(int sh, int P, int pts, std::vector<double>& bcat, int& Q3p,
               const double x[3] = {z[i], z[Q + j], z[2 * Q + k]};
               double v[3], dv[3];
               for (int d = 0; d < 3; ++d) {
-                v[d] = fval(f[d], x[d], false);
-                dv[d] = fval(f[d], x[d], true);
+                v[d] = factor_value(f[d], x[d], false);
+                dv[d] = factor_value(f[d], x[d], true);
               }
               bcat[(size_t)(0 * Q3p + pt) * Kp + m] = v[0] * v[1] * v[2];
               bcat[(size_t)(1 * Q3p + pt) * Kp + m] = dv[0] * v[1] * v[2];
@@ -277,6 +293,62 @@ void build_localmat(int sh, int P, int pts, std::vector<double>& bcat, int& Q3p,
               bcat[(size_t)(3 * Q3p + pt) * Kp + m] = v[0] * v[1] * dv[2];
             }
       }
+}
+
+// Tables of the sum-factorised Helmholtz diagonal.  The distinct eta1 factors
+// (rows), the distinct (eta1 row, eta2 factor) pairs and every mode's eta3
+// factor, each as values and derivatives at the direction's points:
+//   doubles: U1[n1][Q] W1[n1][Q] U2[n12][Q] W2[n12][Q] U3[NP][Q] W3[NP][Q]
+//   ints:    row of pair [n12], pair of mode [NP]
+void build_diag_tables(int sh, int P, int pts, std::vector<double>& dt, std::vector<int>& di, int& n1, int& n12) {
+  const int Q = P + 2, NP = num_modes(sh, P);
+  std::vector<double> z(3 * Q), w(3 * Q);
+  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), pts, z.data() + d * Q, w.data() + d * Q);
+  std::vector<Factor> rows;
+  std::vector<std::pair<int, Factor>> pairs;
+  std::vector<int> mode_pair;
+  std::vector<Factor> mode_c;
+  for (int p = 0; p <= P; ++p)
+    for (int q = 0; q < nq_of(sh, P, p); ++q)
+      for (int r = 0; r < col_len(sh, P, p, q); ++r) {
+        Factor f[3];
+        mode_factors(sh, p, q, r, f);
+        int ir = 0;
+        while (ir < (int)rows.size() && !(rows[ir] == f[0])) ++ir;
+        if (ir == (int)rows.size()) rows.push_back(f[0]);
+        int ip = 0;
+        while (ip < (int)pairs.size() && !(pairs[ip].first == ir && pairs[ip].second == f[1])) ++ip;
+        if (ip == (int)pairs.size()) pairs.push_back({ir, f[1]});
+        mode_pair.push_back(ip);
+        mode_c.push_back(f[2]);
+      }
+  n1 = (int)rows.size();
+  n12 = (int)pairs.size();
+  dt.assign((size_t)2 * Q * (n1 + n12 + NP), 0.0);
+  double* U1 = dt.data();
+  double* W1 = U1 + n1 * Q;
+  double* U2 = W1 + n1 * Q;
+  double* W2 = U2 + n12 * Q;
+  double* U3 = W2 + n12 * Q;
+  double* W3 = U3 + NP * Q;
+  for (int a = 0; a < n1; ++a)
+    for (int i = 0; i < Q; ++i) {
+      U1[a * Q + i] = factor_value(rows[a], z[i], false);
+      W1[a * Q + i] = factor_value(rows[a], z[i], true);
+    }
+  for (int b = 0; b < n12; ++b)
+    for (int j = 0; j < Q; ++j) {
+      U2[b * Q + j] = factor_value(pairs[b].second, z[Q + j], false);
+      W2[b * Q + j] = factor_value(pairs[b].second, z[Q + j], true);
+    }
+  for (int m = 0; m < NP; ++m)
+    for (int k = 0; k < Q; ++k) {
+      U3[m * Q + k] = factor_value(mode_c[m], z[2 * Q + k], false);
+      W3[m * Q + k] = factor_value(mode_c[m], z[2 * Q + k], true);
+    }
+  di.assign(n12 + NP, 0);
+  for (int b = 0; b < n12; ++b) di[b] = pairs[b].first;
+  for (int m = 0; m < NP; ++m) di[n12 + m] = mode_pair[m];
 }
 
 // d eta / d xi of the collapse at (e1, e2, e3), rows eta_d, columns xi_a, and

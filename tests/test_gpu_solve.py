@@ -197,6 +197,38 @@ def test_diag_vs_oracle(shp, P):
         assert e <= 1e-12, (s, e)
 
 
+@pytest.mark.parametrize("P,geom,pts", [(P, "curved", "gj") for P in (1, 3, 4, 5, 7, 8, 9, 10)] +
+                         [(3, "curved", "radau"), (7, "curved", "radau"), (2, "affine", "gj"), (5, "affine", "gj")])
+def test_diag_orders_and_point_sets(shp, P, geom, pts):
+    """The sum-factorised diagonal at every order, on Radau points and on
+    affine blocks, against the oracle's dense H_e (a few elements per shape,
+    ragged block sizes)."""
+    say(f"[solve] Jacobi diagonal P={P} {geom} {pts}")
+    ne = {s: n for s, n in zip(O.SHAPES, (3, 5, 4, 6))} if P >= 7 else {s: 13 for s in O.SHAPES}
+    blocks = [(s, P, ne[s], geom, pts) for s in O.SHAPES]
+    plan = shp.Plan(blocks)
+    maps = {}
+    for b, s in enumerate(O.SHAPES):
+        maps[s] = W.shape_batch(s, ne[s])
+        if geom == "curved":
+            xi, _ = shp.quadrature(s, P + 2, pts)
+            plan.set_geometry(b, torch.from_numpy(W.jacobian(maps[s], xi, curved=True)).cuda())
+        else:
+            plan.set_geometry(b, torch.from_numpy(W.affine_jacobian(maps[s])).cuda())
+    lam = 0.37
+    d = plan.helmholtz_diag(lam).cpu().numpy()
+    for b, s in enumerate(O.SHAPES):
+        co, _ = plan.offsets(b)
+        NP = plan.n_modes[b]
+        jo = (W.jacobian(maps[s], O.reference_points(s, P + 2, pts), curved=True) if geom == "curved"
+              else W.affine_jacobian(maps[s]))
+        H = O.Element(s, P, P + 2, jo, pts).helmholtz(lam)
+        ref = np.diagonal(H, axis1=1, axis2=2)
+        e = rel(d[co:co + ne[s] * NP].reshape(ne[s], NP), ref)
+        say(f"    {s:5s} rel={e:.2e}")
+        assert e <= 1e-12, (s, e)
+
+
 def test_mixed_mesh_32_P6_solve_sampled(shp):
     """The mixed mesh at P = 6 (32^3 cells, 122,880 curved elements, 17,031,168
     DOF), manufactured right-hand side built on the device, mixed-precision
