@@ -1000,32 +1000,77 @@ struct GeoRegs {
   double v[PPT][NFAC];
 };
 
+// Every slot issues its loads (slots past the tile's last point re-read that
+// point), so the number of loads in flight is a compile-time constant: a wait
+// for data loaded before the prefetch then counts past these loads instead of
+// draining them.
 template <int P, int PPT>
 __device__ __forceinline__ void prefetch_geo(const double* __restrict__ fac, long long e0, int ne, GeoRegs<PPT>& g) {
   constexpr int Q3 = (P + 2) * (P + 2) * (P + 2);
   const gptr_t base = as_global(fac) + e0 * (long long)(NFAC * Q3);
+  const int last = ne * Q3 - 1;
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
-    const int t = tid() + it * nthr();
-    if (t < ne * Q3) {
-      const int e = t / Q3, pt = t - e * Q3;
-      const gptr_t f = base + e * (NFAC * Q3) + pt;
+    const int t0 = tid() + it * nthr();
+    const int t = t0 < last ? t0 : last;
+    const int e = t / Q3, pt = t - e * Q3;
+    const gptr_t f = base + e * (NFAC * Q3) + pt;
 #pragma unroll
-      for (int c = 0; c < NFAC; ++c) g.v[it][c] = __builtin_nontemporal_load(f + c * Q3);
-    }
+    for (int c = 0; c < NFAC; ++c) g.v[it][c] = __builtin_nontemporal_load(f + c * Q3);
   }
 }
+
+// register slots per thread for a tile's modes when its points fill at most
+// PPT slots per thread (E N_P / threads <= PPT N_P / Q^3)
+template <int SH, int P, int PPT>
+constexpr int mode_slots() {
+  constexpr int Q3 = (P + 2) * (P + 2) * (P + 2);
+  return (PPT * num_modes(SH, P) + Q3 - 1) / Q3;
+}
+
+struct NoPrefetch {
+  __device__ void operator()() const {}
+};
 
 // OP = OPK_ADR adds the advection term sum_d a_d D_d u at the points to the
 // reaction term, with a_d = jw sum_i b_i d eta_d / d x_i read from adv
 // ([n_elem][3][Q^3] of the tile's block).
-template <int SH, int P, int OP, int PPT, typename Next, typename R>
+// pre() runs after the tile's modes are requested and before they are written
+// to LDS: the one-tile-per-work-group launches issue the tile's geometry
+// prefetch there, so the first stages run while the geometry streams in.
+template <int SH, int P, int OP, int PPT, typename Next, typename R, typename Pre = NoPrefetch>
 __device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH, P, R>& T, GeoRegs<PPT>& g,
-                          bool tables, Next next, const double* __restrict__ adv = nullptr) {
+                          bool tables, Next next, const double* __restrict__ adv = nullptr, Pre pre = Pre{}) {
   using D = Dims<SH, P>;
   constexpr int Q3 = D::Q3;
   if (tables) load_tables_helm<SH, P>(a, T);
-  load_modes<SH, P>(T, reinterpret_cast<const R*>(a.in), e0, ne, 0);
+  {
+    // modes into registers (every slot loads; slots past the tile re-read
+    // its last mode), then the prefetch, then the LDS writes
+    constexpr int MS = mode_slots<SH, P, PPT>();
+    const int nm = ne * D::NP;
+    const R* src = reinterpret_cast<const R*>(a.in) + e0 * D::NP;
+    R mv[MS];
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+      const int t = tid() + s * nthr();
+      mv[s] = src[t < nm ? t : nm - 1];
+    }
+    pre();
+    // slots past the tile write their (re-read) last mode to its own place,
+    // so every slot's load has a use on every path and stays ahead of pre()
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+      const int t0 = tid() + s * nthr();
+      const int t = t0 < nm ? t0 : nm - 1;
+      const int e = t / D::NP, m = t - e * D::NP;
+      T.G(e, 0)[m] = mv[s];
+    }
+    for (int t = tid() + MS * nthr(); t < nm; t += nthr()) {
+      const int e = t / D::NP, m = t - e * D::NP;
+      T.G(e, 0)[m] = src[t];
+    }
+  }
   __syncthreads();
   // modes in G0 -> F in G1 -> G in G2 -> U, with G0 = D_0 U from the same task
   bwd_r<SH, P, false>(T, ne, 0, 1);
@@ -1158,8 +1203,8 @@ __global__ void __launch_bounds__(512) k_helm_block_pf(OpArgs a) {
   const int ne = rem < a.E ? (int)rem : a.E;
   if (ne <= 0) return;
   GeoRegs<PPT> g;
-  prefetch_geo<P, PPT>(a.fac, e0, ne, g);
-  helm_tile<SH, P, OP, PPT>(a, e0, ne, make_tile<SH, P>(smem, a.tab), g, true, []() {});
+  helm_tile<SH, P, OP, PPT>(a, e0, ne, make_tile<SH, P>(smem, a.tab), g, true, []() {}, nullptr,
+                            [&]() { prefetch_geo<P, PPT>(a.fac, e0, ne, g); });
 }
 
 template <int P, int OP, int PPT, typename R = double>
@@ -1172,7 +1217,6 @@ __global__ void __launch_bounds__(512) k_helm_mixed_pf(const BlockStatic* __rest
   const Tile tl = tiles[ti];
   const BlockStatic b = blocks[tl.blk];
   GeoRegs<PPT> g;
-  prefetch_geo<P, PPT>(b.fac, tl.e0, tl.ne, g);
   OpArgs a;
   a.tab = b.tab;
   a.itab = b.itab;
@@ -1189,11 +1233,20 @@ __global__ void __launch_bounds__(512) k_helm_mixed_pf(const BlockStatic* __rest
   a.pad_ = 0;
   const R* gt = sizeof(R) == sizeof(double) ? reinterpret_cast<const R*>(b.tab) : reinterpret_cast<const R*>(b.tabf);
   auto none = []() {};
+  auto pf = [&]() { prefetch_geo<P, PPT>(b.fac, tl.e0, tl.ne, g); };
   switch (b.shape) {
-    case HEX: helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<HEX, P, R>(smem, gt), g, true, none); break;
-    case PRISM: helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<PRISM, P, R>(smem, gt), g, true, none); break;
-    case PYR: helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<PYR, P, R>(smem, gt), g, true, none); break;
-    default: helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<TET, P, R>(smem, gt), g, true, none); break;
+    case HEX:
+      helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<HEX, P, R>(smem, gt), g, true, none, nullptr, pf);
+      break;
+    case PRISM:
+      helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<PRISM, P, R>(smem, gt), g, true, none, nullptr, pf);
+      break;
+    case PYR:
+      helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<PYR, P, R>(smem, gt), g, true, none, nullptr, pf);
+      break;
+    default:
+      helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<TET, P, R>(smem, gt), g, true, none, nullptr, pf);
+      break;
   }
 }
 
@@ -1210,7 +1263,6 @@ __global__ void __launch_bounds__(512) k_adr_mixed_pf(const BlockStatic* __restr
   const Tile tl = tiles[ti];
   const BlockStatic b = blocks[tl.blk];
   GeoRegs<PPT> g;
-  prefetch_geo<P, PPT>(b.fac, tl.e0, tl.ne, g);
   OpArgs a;
   a.tab = b.tab;
   a.itab = b.itab;
@@ -1226,13 +1278,14 @@ __global__ void __launch_bounds__(512) k_adr_mixed_pf(const BlockStatic* __restr
   a.pad_ = 0;
   const double* ab = adv + 3 * b.phys_off;
   auto none = []() {};
+  auto pf = [&]() { prefetch_geo<P, PPT>(b.fac, tl.e0, tl.ne, g); };
   switch (b.shape) {
-    case HEX: helm_tile<HEX, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem, b.tab), g, true, none, ab); break;
+    case HEX: helm_tile<HEX, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem, b.tab), g, true, none, ab, pf); break;
     case PRISM:
-      helm_tile<PRISM, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem, b.tab), g, true, none, ab);
+      helm_tile<PRISM, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem, b.tab), g, true, none, ab, pf);
       break;
-    case PYR: helm_tile<PYR, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem, b.tab), g, true, none, ab); break;
-    default: helm_tile<TET, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<TET, P>(smem, b.tab), g, true, none, ab); break;
+    case PYR: helm_tile<PYR, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem, b.tab), g, true, none, ab, pf); break;
+    default: helm_tile<TET, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<TET, P>(smem, b.tab), g, true, none, ab, pf); break;
   }
 }
 

@@ -10,10 +10,38 @@ the GPU and do not inherit the parent's HIP state.
 """
 from __future__ import annotations
 
+import atexit
 import multiprocessing as mp
 import os
 
 import numpy as np
+
+_POOL = None
+_POOL_N = 0
+
+
+def _pool(workers: int):
+    """One pool of worker processes for the whole test session (started on
+    first use: starting processes costs about a second each time)."""
+    global _POOL, _POOL_N
+    if _POOL is None or _POOL_N != workers:
+        if _POOL is not None:
+            _POOL.terminate()
+        # one BLAS thread per worker: the workers already fill the cores
+        keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+        saved = {k: os.environ.get(k) for k in keys}
+        os.environ.update({k: "1" for k in keys})
+        try:
+            _POOL = mp.get_context("spawn").Pool(workers)
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        _POOL_N = workers
+        atexit.register(_POOL.terminate)
+    return _POOL
 
 
 def n_workers(limit: int = 16) -> int:
@@ -57,6 +85,5 @@ def apply_op(op: str, shape: str, P: int, maps, x, lam: float = 1.0, curved: boo
     if workers == 1 or len(jobs) == 1:
         outs = [_work(j) for j in jobs]
     else:
-        with mp.get_context("spawn").Pool(min(workers, len(jobs))) as pool:
-            outs = pool.map(_work, jobs, chunksize=1)
+        outs = _pool(workers).map(_work, jobs, chunksize=1)
     return np.concatenate(outs, axis=1 if op == "physderiv" else 0)
