@@ -392,6 +392,42 @@ VERTEX_MODES = {
 }
 
 
+# the reference vertex at which each mode of VERTEX_MODES is one (and the other
+# vertex modes vanish): A_0 is one at z = -1, A_1 and v1 at z = +1, and a
+# collapsed coordinate's vertex sits at xi = -1 in the collapsed directions
+VERTEX_XI = {
+    "hex": [(2 * p - 1, 2 * q - 1, 2 * r - 1) for p in (0, 1) for q in (0, 1) for r in (0, 1)],
+    "prism": [(2 * p - 1, 2 * q - 1, -1) for p in (0, 1) for q in (0, 1)] + [(-1, -1, 1), (-1, 1, 1)],
+    "pyr": [(2 * p - 1, 2 * q - 1, -1) for p in (0, 1) for q in (0, 1)] + [(-1, -1, 1)],
+    "tet": [(-1, -1, -1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)],
+}
+
+
+def vertex_modes(shape: str, P: int):
+    """Mode indices of the vertex modes and the reference coordinates xi
+    [n_vertices, 3] of the vertex where each is one."""
+    ml = modes(shape, P)
+    return [ml.index(m) for m in VERTEX_MODES[shape]], np.array(VERTEX_XI[shape], dtype=np.float64)
+
+
+def isoparametric_jacobian(shape: str, P: int, Q: int, X, pts: str = "gj") -> np.ndarray:
+    """d x_i/d xi_j at the quadrature points of iso-parametric elements, whose
+    map is a polynomial of the solution's degree in the element's own basis
+    (Sec. 2.1: J is then polynomial; Sec. 4: curvilinear elements with
+    iso-parametric mappings): x_c = sum_m X[e, c, m] phi_m.  The basis
+    derivatives give d x/d eta = sum_m X_m (d phi_m/d eta) at the points, and
+    d x/d xi = (d x/d eta)(d eta/d xi) with the collapse's d eta/d xi the
+    numerical inverse of d xi/d eta.  X: [n_elem, 3, N_P].  Returns
+    [n_elem][9][n_pts] with component i*3 + j, the layout Element takes."""
+    X = np.asarray(X, dtype=np.float64)
+    eta, _, _ = quadrature(shape, Q, pts)
+    _, dB = basis(shape, P, eta)                              # [3(d), nq, N_P]
+    Jeta = np.einsum("ecm,dqm->eqcd", X, dB)                  # d x_c / d eta_d
+    deta_dxi = np.linalg.inv(dxi_deta(shape, eta))            # [nq, 3(d), 3(j)]
+    Jxi = np.einsum("eqcd,qdj->eqcj", Jeta, deta_dxi)
+    return np.ascontiguousarray(np.transpose(Jxi.reshape(X.shape[0], eta.shape[0], 9), (0, 2, 1)))
+
+
 def vertex_indicator(shape: str, P: int) -> np.ndarray:
     """Coefficients of the constant function 1: the vertex modes sum to one.
     For the collapsed shapes (1, q, 1) is an edge mode, not a vertex mode."""

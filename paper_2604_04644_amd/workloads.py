@@ -246,6 +246,22 @@ def manufactured_u_torch(maps: ElementMaps, xi: np.ndarray, device, amp: float =
     return out
 
 
+def iso_coords(maps: ElementMaps, vertex_idx, vertex_xi: np.ndarray, n_modes: int, seed: int,
+               curved: bool = True, amp: float = 0.02) -> np.ndarray:
+    """Coordinate coefficients [n_elem][3][n_modes] of iso-parametric elements:
+    the mesh map's vertex positions x(xi_v) on the vertex coefficients
+    vertex_idx (the caller gives the index of each vertex's coefficient and
+    its reference coordinates xi_v), and every other coefficient uniform in
+    [-amp h, amp h] per coordinate, h the element's size (the largest column
+    norm of its affine map), from the seed: curved elements near the mesh's."""
+    rng = np.random.default_rng(seed)
+    ne = len(maps)
+    h = np.linalg.norm(maps.A, axis=1).max(axis=1)                      # [ne]
+    X = rng.uniform(-1.0, 1.0, size=(ne, 3, n_modes)) * (amp * h)[:, None, None]
+    X[:, :, list(vertex_idx)] = coords(maps, np.asarray(vertex_xi, dtype=np.float64), curved)
+    return X
+
+
 def affine_jacobian(maps: ElementMaps) -> np.ndarray:
     """Constant d x_i / d xi_j of straight-sided elements, layout [n_elem][9]."""
     return np.ascontiguousarray((0.5 * maps.A).reshape(len(maps), 9))

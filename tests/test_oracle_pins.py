@@ -507,3 +507,57 @@ def test_advection_of_linear_fields(shape, P):
         assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
         assert np.abs(C[e] @ c1).max() < 1e-13 * np.abs(C[e]).max()
         assert np.abs(C[e].T @ xf - rhs).max() > 1e-3 * np.abs(rhs).max()
+
+
+# ---------------------------------------------------------------------------
+# iso-parametric geometry (J from coordinate coefficients)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", O.SHAPES)
+def test_isoparametric_jacobian_affine_vertices(shape):
+    """Vertex positions of straight-sided elements on the vertex coefficients
+    (all others zero) reproduce the affine map: J equals the element's constant
+    d x/d xi at every point, for several orders."""
+    maps = W.shape_batch(shape, 7)
+    for P in (1, 2, 4):
+        idx, vxi = O.vertex_modes(shape, P)
+        X = np.zeros((7, 3, O.num_modes(shape, P)))
+        X[:, :, idx] = W.coords(maps, vxi, curved=False)
+        J = O.isoparametric_jacobian(shape, P, P + 2, X)
+        assert np.abs(J - W.affine_jacobian(maps)[:, :, None]).max() < 1e-14
+
+
+def _quadratic_map(xi, c):
+    x = xi.copy()
+    x[..., 0] += c * xi[..., 0] ** 2
+    x[..., 1] += c * xi[..., 1] * xi[..., 2]
+    x[..., 2] += c * xi[..., 0] * xi[..., 2]
+    return x
+
+
+def _quadratic_jac(xi, c):
+    J = np.broadcast_to(np.eye(3), xi.shape[:-1] + (3, 3)).copy()
+    J[..., 0, 0] += 2 * c * xi[..., 0]
+    J[..., 1, 1] += c * xi[..., 2]
+    J[..., 1, 2] += c * xi[..., 1]
+    J[..., 2, 0] += c * xi[..., 2]
+    J[..., 2, 2] += c * xi[..., 0]
+    return J
+
+
+@pytest.mark.parametrize("pts", ["gj", "radau"])
+@pytest.mark.parametrize("shape", O.SHAPES)
+def test_isoparametric_jacobian_quadratic_map(shape, pts):
+    """A quadratic map x = xi + c (xi1^2, xi2 xi3, xi1 xi3) lies in every
+    shape's space at P >= 2; its coefficients (least squares through the
+    quadrature points, exact for a map in the space) give J equal to the
+    analytic gradient at the points."""
+    P, Q, c = 3, 5, 0.15
+    eta, _, _ = O.quadrature(shape, Q, pts)
+    xi = O.collapse(shape, eta)
+    B, _ = O.basis(shape, P, eta)
+    coef, *_ = np.linalg.lstsq(B, _quadratic_map(xi, c), rcond=None)     # [N_P, 3]
+    assert np.abs(B @ coef - _quadratic_map(xi, c)).max() < 1e-13     # the map is in the space
+    J = O.isoparametric_jacobian(shape, P, Q, coef.T[None, :, :], pts)[0]
+    Ja = np.transpose(_quadratic_jac(xi, c).reshape(-1, 9), (1, 0))
+    assert np.abs(J - Ja).max() < 1e-12
