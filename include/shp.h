@@ -428,6 +428,15 @@ int shp_mlp_num_params(int* n /* host out */);
 int shp_mlp_work_floats(int n_samples, long long* n /* host out */);
 /* y [n] = network(X [n][11]). */
 int shp_mlp_forward(const float* params, const float* X, int n, float* y, float* work, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops): shp_mlp_forward without the work argument.
+ * Its per-sample work lives in a static device array of the library, one per
+ * device, sized for n <= 4096 samples (6.3 MB), held until the process ends;
+ * larger n returns SHP_ERR_INVALID_ARG.  Runs on the current device (stream
+ * must belong to it) and allocates nothing.  All calls on one device share
+ * that array: calls that overlap on one device (different streams or host
+ * threads without ordering) race and must be serialised by the caller. */
+int shp_mlp_forward_noalloc(const float* params, const float* X, int n, float* y, void* stream);
 /* Mean squared error of the network against target [n] (loss [1]) and its
  * gradient with respect to the parameters (grad [num_params]). */
 int shp_mlp_loss_grad(const float* params, const float* X, const float* target, int n, float* grad, float* loss,

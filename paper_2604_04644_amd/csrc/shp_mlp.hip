@@ -11,8 +11,15 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "../../include/shp.h"
+#include "shp_internal.hpp"
+
+// Work buffer of the allocation-free forward pass (shp_mlp_forward_noalloc):
+// 4096 samples of 6 * 64 + 2 floats.
+constexpr int NOALLOC_MAX_SAMPLES = 4096;
+static __device__ __align__(256) float scratch[(size_t)NOALLOC_MAX_SAMPLES * (6 * 64 + 2)];
 
 namespace {
 
@@ -20,6 +27,7 @@ constexpr int NIN = 11, NH = 64;
 constexpr int OW1 = 0, OB1 = OW1 + NH * NIN, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH, OB3 = OW3 + NH;
 constexpr int NPARAM = OB3 + 1;
 constexpr int WS = 6 * NH + 2;  // work floats per sample
+static_assert(WS == 6 * 64 + 2, "scratch is sized for 6 * 64 + 2 work floats per sample");
 // work layout per sample s: Z1 H1 Z2 H2 dZ2 dZ1 at s*WS + k*NH, y at s*WS + 6NH, dy at +1
 
 // Z = W x + b, H = relu(Z); one thread per (sample, output)
@@ -105,6 +113,36 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 
 inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Work buffer of the allocation-free forward pass: one array per device for at
+// most NOALLOC_MAX_SAMPLES samples (6.3 MB), held until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is a stand-in
+// symbol, not a device address): each device's address comes from
+// hipGetSymbolAddress on the first call with that device current.
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+
+// the current device's address of scratch, or nullptr with the error set
+float* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+    shp::set_error(SHP_ERR_DEVICE, "shp_mlp_forward_noalloc: no current HIP device");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      shp::set_error(SHP_ERR_DEVICE, "shp_mlp_forward_noalloc: hipGetSymbolAddress(scratch) failed");
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
 int forward(const float* prm, const float* X, int n, float* work, hipStream_t s) {
   hipLaunchKernelGGL(k_dense, dim3(nblk((long long)n * NH, 256)), dim3(256), 0, s, X, NIN, NIN, prm + OW1,
                      prm + OB1, work, 0, n, NH);
@@ -136,6 +174,21 @@ int shp_mlp_forward(const float* params, const float* X, int n, float* y, float*
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (int r = forward(params, X, n, work, s)) return r;
   // gather y (strided in the work buffer) with a device copy
+  if (hipMemcpy2DAsync(y, sizeof(float), work + 6 * NH, WS * sizeof(float), sizeof(float), n,
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return SHP_ERR_DEVICE;
+  return SHP_OK;
+}
+
+int shp_mlp_forward_noalloc(const float* params, const float* X, int n, float* y, void* stream) {
+  if (!params || !X || !y) return shp::set_error(SHP_ERR_INVALID_ARG, "shp_mlp_forward_noalloc: null argument");
+  if (n < 1 || n > NOALLOC_MAX_SAMPLES)
+    return shp::set_error(SHP_ERR_INVALID_ARG,
+                          "shp_mlp_forward_noalloc: n must be in [1, 4096] (the size of its static work buffer)");
+  float* work = scratch_on_current_device();
+  if (!work) return SHP_ERR_DEVICE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (int r = forward(params, X, n, work, s)) return r;
   if (hipMemcpy2DAsync(y, sizeof(float), work + 6 * NH, WS * sizeof(float), sizeof(float), n,
                        hipMemcpyDeviceToDevice, s) != hipSuccess)
     return SHP_ERR_DEVICE;
