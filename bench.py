@@ -281,6 +281,72 @@ def affine_leg(torch, shp, W, flush=None, dof: float = 4e6, Ps=(1, 2, 3, 4)):
     return out
 
 
+def iso_flops_per_elem(shape: str, P: int) -> int:
+    """Algorithmic FP64 flops of the iso-parametric Helmholtz element action:
+    the collocated action, plus per coordinate the sum-factorised BwdTrans and
+    the three collocated derivatives (BT + 3 Q^4 multiply-adds), plus about 85
+    flops per point for the determinant, the inverse and the metric."""
+    Q, n = P + 2, P + 1
+    NP = {"hex": n ** 3, "prism": n * n * (P + 2) // 2, "pyr": (P + 1) * (P + 2) * (2 * P + 3) // 6,
+          "tet": (P + 1) * (P + 2) * (P + 3) // 6}[shape]
+    if shape == "hex":
+        bt = n ** 3 * Q + n * n * Q * Q + n * Q ** 3
+    elif shape == "tet":
+        bt = NP * Q + (P + 1) * (P + 2) // 2 * Q * Q + n * Q ** 3
+    else:
+        bt = NP * Q + n * n * Q * Q + n * Q ** 3
+    return flops_per_elem(shape, P) + 2 * 3 * (bt + 3 * Q ** 4) + 85 * Q ** 3
+
+
+def iso_leg(torch, shp, W, flush, ncell: int = 32, Ps=(4, 6), steps: int = 20):
+    """The mixed mesh made iso-parametric (each element's map a polynomial of
+    degree P in its own basis: the curved mesh's vertex positions on the vertex
+    modes, seeded perturbations of 2 % of the element size on the others),
+    FP64 Helmholtz action with the geometry rebuilt in the launch (40 N_P bytes
+    per element: x, y and 3 coordinate coefficients per mode), against the
+    action that streams the 7 precomputed factors per point of the curved mesh
+    (16 N_P + 56 Q^3 bytes per element).  HIP events after a cache flush,
+    median of `steps`."""
+    out = {}
+    mesh = W.quadrant_mesh(ncell)
+    dev = torch.device("cuda")
+    for P in Ps:
+        row = {}
+        iso = shp.Plan([(s, P, len(mesh[s]), "isoparam") for s in SHAPES])
+        for b, s in enumerate(SHAPES):
+            idx, vxi = shp.vertex_modes(s, P)
+            X = W.iso_coords(mesh[s], idx, vxi, iso.n_modes[b], 40 + b)
+            iso.set_geometry(b, torch.from_numpy(X).to(dev))
+            del X
+        nc, _ = iso.totals()
+        x = torch.from_numpy(np.concatenate([W.coeffs(len(mesh[s]), iso.n_modes[b], W.SEED_MIXED[s]).ravel()
+                                             for b, s in enumerate(SHAPES)])).to(dev)
+        y = torch.empty_like(x)
+        _, _, t_iso = time_launches(torch, lambda: iso.apply(-1, "helmholtz", x, out=y), steps, 3, flush=flush)
+        del iso
+        torch.cuda.empty_cache()
+        pre = shp.Plan([(s, P, len(mesh[s]), "curved") for s in SHAPES])
+        for b, s in enumerate(SHAPES):
+            pre.set_geometry(b, W.jacobian_torch(mesh[s], shp.quadrature(s, P + 2)[0], True, dev))
+        _, _, t_pre = time_launches(torch, lambda: pre.apply(-1, "helmholtz", x, out=y), steps, 3, flush=flush)
+        del pre
+        torch.cuda.empty_cache()
+        nm = {s: shp.num_modes(s, P) for s in SHAPES}
+        b_iso = sum(len(mesh[s]) * 40 * nm[s] for s in SHAPES)
+        b_pre = sum(len(mesh[s]) * bytes_per_elem(nm[s], (P + 2) ** 3) for s in SHAPES)
+        f_iso = sum(len(mesh[s]) * iso_flops_per_elem(s, P) for s in SHAPES)
+        row = {"dof": int(nc), "iso_ms": round(t_iso, 5), "precomputed_ms": round(t_pre, 5),
+               "iso_GDOF/s": round(nc / (t_iso * 1e-3) / 1e9, 3), "precomputed_GDOF/s": round(nc / (t_pre * 1e-3) / 1e9, 3),
+               "iso_vs_precomputed": round(t_pre / t_iso, 3),
+               "iso_bytes": int(b_iso), "precomputed_bytes": int(b_pre),
+               "iso_hbm_frac": round(b_iso / (t_iso * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "iso_flops": int(f_iso), "iso_fp64_frac": round(f_iso / (t_iso * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)}
+        out[f"P{P}"] = row
+        log(f"  iso-parametric P={P}: {row}")
+        del x, y
+    return out
+
+
 def adr_leg(torch, plan, mesh, x, y, helm_ms: float, steps: int = 20):
     """The advection-diffusion-reaction action (Helmholtz plus b . grad u tested
     with the basis) on the same mesh, velocity U[-1,1] at every point: launch
@@ -384,7 +450,7 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(mesh, P: int, frac: int = 8, frac_1t: int = 256, workers: int = 16):
+def cpu_baseline(mesh, P: int, frac: int = 3, frac_1t: int = 128, workers: int = 16):
     """The oracle's Helmholtz action (form each dense H_e by explicit quadrature,
     then y = H_e x) on a fixed random sample of every shape's elements (1/frac
     of each block), spread over `workers` single-threaded processes; and the
@@ -459,6 +525,8 @@ def main():
                     help="also time collocated vs non-collocated Helmholtz per shape (block launches)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg (P=6 mesh)")
     ap.add_argument("--no-adr", action="store_true", help="skip the advection-diffusion-reaction action")
+    ap.add_argument("--no-iso", action="store_true",
+                    help="skip the iso-parametric leg (geometry rebuilt in the launch, P = 4 and 6)")
     ap.add_argument("--c0", action="store_true",
                     help="also run the C0-assembled Helmholtz problem on a 32^3 curved hexahedral grid, P=4")
     ap.add_argument("--affine", action="store_true",
@@ -536,6 +604,10 @@ def main():
     if not a.no_per_shape:
         log("  per-shape x order table")
         per_shape = order_table(torch, shp, W, flush, a.ncell, tuple(int(v) for v in a.orders.split(",")))
+    iso = None
+    if not a.no_iso:
+        log("  iso-parametric leg")
+        iso = iso_leg(torch, shp, W, flush, a.ncell)
     del flush
     torch.cuda.empty_cache()
     mixed = None
@@ -584,6 +656,8 @@ def main():
         out["c0_assembled"] = c0
     if adr is not None:
         out["adr_action"] = adr
+    if iso is not None:
+        out["isoparametric_vs_precomputed"] = iso
     print(json.dumps(out), flush=True)
 
 

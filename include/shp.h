@@ -68,7 +68,19 @@ extern "C" {
 #define SHP_ERR_NOT_CONVERGED (-7) /* an iterative solve did not reach its tolerance */
 
 typedef enum { SHP_HEX = 0, SHP_PRISM = 1, SHP_PYR = 2, SHP_TET = 3 } shp_shape;
-typedef enum { SHP_AFFINE = 0, SHP_CURVED = 1 } shp_geom;
+/* Mapping of a block's elements.  SHP_AFFINE and SHP_CURVED take d x/d xi
+ * and keep 7 FP64 geometric factors per point in the workspace (Sec. 4:
+ * precomputed factors).  SHP_ISOPARAM takes the map as a polynomial of the
+ * solution's degree in the block's own basis (Sec. 2.1: J is then polynomial;
+ * Sec. 4: iso-parametric curvilinear elements), 3 N_P FP64 coordinate
+ * coefficients per element, and the collocated Laplacian and Helmholtz
+ * actions rebuild J and the factors in FP64 at every point in every launch:
+ * 24 N_P bytes per element in place of 56 Q^3.  Iso-parametric blocks support
+ * the backward transform and those two actions (FP64, SHP_SUMFAC_COLL or
+ * SHP_AUTO; a whole-mesh launch only over iso-parametric blocks of one P);
+ * other operators, precisions, the solve and the advection-diffusion-reaction
+ * action return SHP_ERR_UNSUPPORTED for them. */
+typedef enum { SHP_AFFINE = 0, SHP_CURVED = 1, SHP_ISOPARAM = 2 } shp_geom;
 typedef enum { SHP_PTS_GJ = 0, SHP_PTS_RADAU = 1 } shp_points;
 typedef enum {
   SHP_OP_BWDTRANS = 0,       /* [n][N_P] -> [n][N_Q]   u = B x                      */
@@ -99,7 +111,8 @@ typedef struct {
   int P;           /* polynomial order, 1..10 */
   int Q;           /* points per direction, P + 2 */
   int64_t n_elem;  /* elements in the block, >= 0 */
-  int geom;        /* shp_geom: SHP_CURVED takes d x/d xi per point, SHP_AFFINE per element */
+  int geom;        /* shp_geom: SHP_CURVED takes d x/d xi per point, SHP_AFFINE per element,
+                      SHP_ISOPARAM coordinate coefficients per element */
   int pts;         /* shp_points of the collapsed directions; 0 (SHP_PTS_GJ) by default */
 } shp_block_desc;
 
@@ -120,6 +133,15 @@ int shp_num_points(int shape, int Q, int* n_points /* host out */);
  * expected at exactly these points. */
 int shp_quadrature(int shape, int Q, int pts, double* xi /* host out */, double* w /* host out or NULL */);
 
+/* The vertex modes of a shape at order P (Sec. 2.3: the collapsed-vertex
+ * construction; each is one at its vertex and zero at the others): idx (host
+ * out, at most 8) the mode index of each, xi (host out [8][3]) the reference
+ * coordinates of that vertex, n_vertices (host out) their number (hex 8,
+ * prism 6, pyramid 5, tet 4).  Iso-parametric coordinates of straight-sided
+ * elements are the vertex positions on these modes and zero elsewhere. */
+int shp_vertex_modes(int shape, int P, int* idx /* host out */, double* xi /* host out */,
+                     int* n_vertices /* host out */);
+
 /* Create a plan for nblk blocks (host metadata only; copies blk). */
 int shp_plan_create(shp_plan* plan /* host out */, const shp_block_desc* blk /* host [nblk] */,
                     int nblk);
@@ -139,7 +161,11 @@ int shp_plan_bind_workspace(shp_plan plan, void* ws, size_t ws_bytes, void* stre
  *   SHP_CURVED: jac [n_elem][9][Q^3], component i*3+j, at shp_quadrature points;
  *   SHP_AFFINE: jac [n_elem][9], constant per element (also the 7 coefficients
  *               |J| and |J| (J^-1 J^-T)_ab per element of the local-matrix
- *               strategy, for P <= 4).
+ *               strategy, for P <= 4);
+ *   SHP_ISOPARAM: jac [n_elem][3][N_P], the coordinate coefficients X of
+ *               x_c = sum_m X[e][c][m] phi_m, copied into the workspace; the
+ *               geometry they give is checked at every point with the FP64
+ *               reconstruction the actions use.
  * Synchronises stream to report SHP_ERR_BAD_GEOMETRY when det <= 0 or a value
  * is not finite.  Not safe to call concurrently with applies of the plan. */
 int shp_plan_set_geometry(shp_plan plan, int blk, const double* jac /* device */, void* stream);

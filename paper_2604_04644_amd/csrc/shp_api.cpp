@@ -16,6 +16,7 @@
 #include "shp_kernels.hpp"
 #include "shp_kernels_geom.hpp"
 #include "shp_kernels_lm.hpp"
+#include "shp_kernels_iso.hpp"
 
 using namespace shp;
 
@@ -62,6 +63,9 @@ struct Block {
   std::vector<int> ditab;   //   and their pair and mode indices
   int dn1 = 0, dn12 = 0;
   size_t off_dtab = 0, off_ditab = 0;
+  std::vector<double> wref; // iso-parametric blocks: reference weights [Q^3]
+  size_t off_xco = 0, off_wref = 0;
+  bool iso() const { return d.geom == SHP_ISOPARAM; }
   long long coeff_off = 0, phys_off = 0;
   bool geom_ok = false;
   Tiling tiling[OPK_COUNT];
@@ -146,11 +150,29 @@ bool out_is_modes(int opk) { return !(opk == OPK_BWD || opk == OPK_DERIV); }
 // 64 KiB where 40 KiB leaves at most 2 points per thread, which happens at
 // P = 6 (8^3 points): two elements per work-group there take 0.95 ms per FP64
 // action on the 32^3-cell mixed mesh against 1.21 ms for one.
+// From P = 7 on (729 or more points per element) the Laplacian / Helmholtz
+// launches take the shapes the tuner measured fastest on the 32^3-cell mixed
+// mesh's blocks (FP64, HIP events after a cache flush): mostly 512 threads, so
+// that 4 geometry slots per thread hold the tile's points, and two elements
+// per work-group at P = 7 and 8.  Per shape (hex, prism, pyramid, tet) and
+// P = 7..10: elements per work-group, threads.
+constexpr int HI_E[4][4] = {{1, 2, 1, 1}, {2, 2, 1, 1}, {2, 2, 1, 1}, {2, 1, 1, 1}};
+constexpr int HI_NT[4][4] = {{256, 512, 512, 512}, {512, 512, 512, 512}, {512, 512, 512, 512}, {512, 256, 512, 512}};
+// the whole-mesh launch at P = 7..10 (one launch shape for every block)
+constexpr int HI_MESH_E[4] = {2, 1, 1, 1};
+constexpr int HI_MESH_NT[4] = {512, 256, 512, 512};
+
 Tiling default_tiling(int sh, int P, int opk, size_t lds_budget = 40 * 1024) {
   Tiling t;
   t.NT = 256;
   const bool helm = (opk == OPK_HELM || opk == OPK_LAP || opk == OPK_ADR);
   const long long Q3 = (long long)(P + 2) * (P + 2) * (P + 2);
+  if (helm && P >= 7) {
+    t.E = HI_E[sh][P - 7];
+    t.NT = HI_NT[sh][P - 7];
+    t.persist = points_per_thread((long long)t.E * Q3, t.NT) > 0 ? 2 : 0;
+    return t;
+  }
   int E = 1;
   while (E < 16 && op_lds_bytes(sh, P, opk, E + 1, 2) <= lds_budget && (!helm || (E + 1) * Q3 <= 4LL * t.NT)) ++E;
   t.E = E;
@@ -158,7 +180,21 @@ Tiling default_tiling(int sh, int P, int opk, size_t lds_budget = 40 * 1024) {
   return t;
 }
 
+// Iso-parametric launches keep 9 FP64 derivatives per owned point in
+// registers while they rebuild the geometry, so they own at most 2 points per
+// thread (4 from P = 9, where one element has more than 1024 points): as many
+// elements as fill 512 points on 256 threads, else one element on 512.
+Tiling iso_tiling(int P) {
+  const int Q3 = (P + 2) * (P + 2) * (P + 2);
+  Tiling t;
+  t.E = std::max(1, std::min(16, 512 / Q3));
+  t.NT = (t.E * Q3 <= 512) ? 256 : 512;
+  t.persist = 2;
+  return t;
+}
+
 Tiling effective(const Tiling& set, int sh, int P, int opk) {
+  if (opk == OPK_HELM_ISO || opk == OPK_LAP_ISO) return iso_tiling(P);
   return (set.E > 0 && set.NT > 0) ? set : default_tiling(sh, P, opk);
 }
 
@@ -189,6 +225,42 @@ int shp_num_points(int shape, int Q, int* n) {
   return SHP_OK;
 }
 
+int shp_vertex_modes(int shape, int P, int* idx, double* xi, int* n_vertices) {
+  if (!idx || !xi || !n_vertices) return fail(SHP_ERR_INVALID_ARG, "null output");
+  if (!valid_shape(shape)) return fail(SHP_ERR_INVALID_ARG, "bad shape %d", shape);
+  if (P < 1 || P > MAX_P) return fail(SHP_ERR_UNSUPPORTED, "P=%d outside [1,%d]", P, MAX_P);
+  // (p, q, r) of each vertex mode and the reference vertex where it is one
+  struct V {
+    int p, q, r;
+    double x, y, z;
+  };
+  std::vector<V> vs;
+  if (shape == SHP_HEX) {
+    for (int p = 0; p < 2; ++p)
+      for (int q = 0; q < 2; ++q)
+        for (int r = 0; r < 2; ++r) vs.push_back({p, q, r, 2.0 * p - 1, 2.0 * q - 1, 2.0 * r - 1});
+  } else if (shape == SHP_TET) {
+    vs = {{0, 0, 0, -1, -1, -1}, {1, 0, 0, 1, -1, -1}, {0, 1, 0, -1, 1, -1}, {0, 0, 1, -1, -1, 1}};
+  } else {
+    for (int p = 0; p < 2; ++p)
+      for (int q = 0; q < 2; ++q) vs.push_back({p, q, 0, 2.0 * p - 1, 2.0 * q - 1, -1});
+    vs.push_back({0, 0, 1, -1, -1, 1});
+    if (shape == SHP_PRISM) vs.push_back({0, 1, 1, -1, 1, 1});
+  }
+  for (size_t v = 0; v < vs.size(); ++v) {
+    int off = 0;  // modes before column (p, q): columns are p-major, then q
+    for (int p = 0; p < vs[v].p; ++p)
+      for (int q = 0; q < nq_of(shape, P, p); ++q) off += col_len(shape, P, p, q);
+    for (int q = 0; q < vs[v].q; ++q) off += col_len(shape, P, vs[v].p, q);
+    idx[v] = off + vs[v].r;
+    xi[3 * v + 0] = vs[v].x;
+    xi[3 * v + 1] = vs[v].y;
+    xi[3 * v + 2] = vs[v].z;
+  }
+  *n_vertices = (int)vs.size();
+  return SHP_OK;
+}
+
 int shp_quadrature(int shape, int Q, int pts, double* xi, double* w) {
   if (!xi) return fail(SHP_ERR_INVALID_ARG, "null xi");
   if (!valid_shape(shape)) return fail(SHP_ERR_INVALID_ARG, "bad shape %d", shape);
@@ -207,7 +279,8 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     if (d.P < 1 || d.P > MAX_P) return fail(SHP_ERR_UNSUPPORTED, "block %d: P=%d outside [1,%d]", b, d.P, MAX_P);
     if (d.Q != d.P + 2) return fail(SHP_ERR_UNSUPPORTED, "block %d: Q=%d, only Q=P+2 is built", b, d.Q);
     if (d.n_elem < 0 || d.n_elem > (1LL << 31)) return fail(SHP_ERR_INVALID_ARG, "block %d: n_elem=%lld", b, (long long)d.n_elem);
-    if (d.geom != SHP_AFFINE && d.geom != SHP_CURVED) return fail(SHP_ERR_INVALID_ARG, "block %d: bad geom %d", b, d.geom);
+    if (d.geom != SHP_AFFINE && d.geom != SHP_CURVED && d.geom != SHP_ISOPARAM)
+      return fail(SHP_ERR_INVALID_ARG, "block %d: bad geom %d", b, d.geom);
     if (d.pts != SHP_PTS_GJ && d.pts != SHP_PTS_RADAU) return fail(SHP_ERR_INVALID_ARG, "block %d: bad point set %d", b, d.pts);
   }
   shp_plan p = new (std::nothrow) shp_plan_s;
@@ -226,7 +299,8 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     B.NQ = B.d.Q * B.d.Q * B.d.Q;
     build_tables(B.d.shape, B.d.P, B.d.pts, B.tab, B.itab);
     build_diag_tables(B.d.shape, B.d.P, B.d.pts, B.dtab, B.ditab, B.dn1, B.dn12);
-    if (B.d.P <= LOCALMAT_MAX_P) {
+    if (B.iso()) build_ref_weights(B.d.shape, B.d.P, B.d.pts, B.wref);
+    if (B.d.P <= LOCALMAT_MAX_P && !B.iso()) {
       int q3p, kp;
       build_localmat(B.d.shape, B.d.P, B.d.pts, B.lm, q3p, kp);
       if (B.d.geom == SHP_AFFINE) build_affine_mats(B.d.shape, B.d.P, B.d.pts, B.am, kp);
@@ -265,6 +339,15 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     off = align_up(off + sizeof(int) * B.ditab.size());
   }
   for (auto& B : p->blocks) {
+    if (B.iso()) {
+      // coordinate coefficients instead of the per-point factors
+      B.off_xco = off;
+      off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * 3 * B.NP);
+      B.off_wref = off;
+      off = align_up(off + sizeof(double) * B.wref.size());
+      B.off_fac = B.off_dxi = 0;
+      continue;
+    }
     B.off_fac = off;
     off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * NFAC * B.NQ);
     B.off_dxi = off;
@@ -314,6 +397,8 @@ static int upload_static(shp_plan p, hipStream_t s) {
     bs[b].fac = reinterpret_cast<const double*>(p->ws + B.off_fac);
     bs[b].dxi = reinterpret_cast<const double*>(p->ws + B.off_dxi);
     bs[b].tabf = reinterpret_cast<const float*>(p->ws + B.off_tabf);
+    bs[b].xco = B.iso() ? reinterpret_cast<const double*>(p->ws + B.off_xco) : nullptr;
+    bs[b].wref = B.iso() ? reinterpret_cast<const double*>(p->ws + B.off_wref) : nullptr;
     bs[b].n_elem = B.d.n_elem;
     bs[b].coeff_off = B.coeff_off;
     bs[b].phys_off = B.phys_off;
@@ -343,6 +428,8 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
       e = hipMemcpyAsync(p->ws + B.off_lm, B.lm.data(), sizeof(double) * B.lm.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.am.empty())
       e = hipMemcpyAsync(p->ws + B.off_am, B.am.data(), sizeof(double) * B.am.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && B.iso())
+      e = hipMemcpyAsync(p->ws + B.off_wref, B.wref.data(), sizeof(double) * B.wref.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(p->ws + B.off_dtab, B.dtab.data(), sizeof(double) * B.dtab.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -372,6 +459,18 @@ int shp_plan_set_geometry(shp_plan p, int blk, const double* jac, void* stream) 
   int* status = reinterpret_cast<int*>(p->ws + p->off_status);
   hipError_t e = hipMemsetAsync(status, 0, sizeof(int), s);
   if (e != hipSuccess) return dev_fail(e, "hipMemsetAsync(status)");
+  if (B.iso()) {
+    // keep the coordinate coefficients; check the geometry they give at
+    // every point with the launches' own FP64 reconstruction
+    e = hipMemcpyAsync(p->ws + B.off_xco, jac, sizeof(double) * (size_t)B.d.n_elem * 3 * B.NP,
+                       hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return dev_fail(e, "coordinate copy");
+    const Tiling t = iso_tiling(B.d.P);
+    e = launch_iso_check(B.d.P, reinterpret_cast<const BlockStatic*>(p->ws + p->off_bstat), blk, t.E,
+                         (B.d.n_elem + t.E - 1) / t.E, t.NT, op_lds_bytes(B.d.shape, B.d.P, OPK_HELM, t.E, 2),
+                         status, s);
+    if (e != hipSuccess) return dev_fail(e, "iso-parametric geometry check launch");
+  } else {
   GeomArgs g;
   g.tab = reinterpret_cast<const double*>(p->ws + B.off_tab);
   g.jac = jac;
@@ -385,6 +484,7 @@ int shp_plan_set_geometry(shp_plan p, int blk, const double* jac, void* stream) 
   if (!B.am.empty()) {
     e = launch_affine_coef(jac, reinterpret_cast<double*>(p->ws + B.off_coef), B.d.n_elem, status, s);
     if (e != hipSuccess) return dev_fail(e, "affine coefficient kernel launch");
+  }
   }
   int h = 0;
   e = hipMemcpyAsync(&h, status, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -418,6 +518,8 @@ int plan_helm_diag(shp_plan_s* p, double lambda, double* diag, hipStream_t s) {
 int plan_check_solve(shp_plan_s* p, int inner_prec) {
   if (int r = check_plan(p)) return r;
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  for (const auto& B : p->blocks)
+    if (B.iso()) return fail(SHP_ERR_UNSUPPORTED, "the solve and its diagonal need precomputed factors, not iso-parametric blocks");
   for (size_t b = 0; b < p->blocks.size(); ++b)
     if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
   if (inner_prec == SHP_FP32 && !p->uniform_P)
@@ -497,6 +599,14 @@ int shp_get_tiling(shp_plan p, int blk, int op, int strategy, int* E, int* NT, i
 static Tiling mixed_tiling(shp_plan p, int opk) {
   Tiling t = p->mixed[opk];
   if (t.E > 0 && t.NT > 0) return t;
+  if (opk == OPK_HELM_ISO || opk == OPK_LAP_ISO) return iso_tiling(p->blocks[0].d.P);
+  const int P0 = p->blocks[0].d.P;
+  if ((opk == OPK_HELM || opk == OPK_LAP || opk == OPK_ADR) && p->uniform_P && P0 >= 7) {
+    t.E = HI_MESH_E[P0 - 7];
+    t.NT = HI_MESH_NT[P0 - 7];
+    t.persist = 2;
+    return t;
+  }
   t = Tiling{64, 512, 2};
   for (const auto& B : p->blocks) {
     Tiling d = default_tiling(B.d.shape, B.d.P, opk);
@@ -510,6 +620,16 @@ static Tiling mixed_tiling(shp_plan p, int opk) {
   return t;
 }
 
+// Relative cost of one element by shape (hex, prism, pyramid, tet) and
+// P = 1..10: the FP64 collocated Helmholtz launch time per element of the
+// largest curved batch of each shape in the MI355X order sweep (about 4M DOF,
+// default launch shape), divided by the hexahedron's at the same P.
+constexpr double LPT_WEIGHT[4][10] = {
+    {1.00, 1.00, 1.00, 1.00, 1.00, 1.00, 1.00, 1.00, 1.00, 1.00},
+    {1.03, 1.11, 1.08, 1.02, 1.06, 1.04, 1.13, 1.07, 1.30, 1.70},
+    {1.03, 1.08, 1.04, 0.99, 1.03, 1.03, 1.08, 1.05, 1.28, 1.65},
+    {1.23, 1.11, 1.06, 1.07, 1.07, 1.14, 1.15, 1.58, 1.44, 1.75}};
+
 static int build_tiles(shp_plan p, int opk, hipStream_t s) {
   const int E = mixed_tiling(p, opk).E;
   struct T2 {
@@ -519,8 +639,9 @@ static int build_tiles(shp_plan p, int opk, hipStream_t s) {
   std::vector<T2> tl;
   for (int b = 0; b < (int)p->blocks.size(); ++b) {
     const Block& B = p->blocks[b];
-    // per-element cost weight: streamed bytes (dominant) plus a shape term
-    const double w = 1.0 + 0.02 * B.d.shape;
+    // per-element cost weight: the measured Helmholtz launch time per element
+    // of the shape relative to the hexahedron at the same P
+    const double w = LPT_WEIGHT[B.d.shape][B.d.P - 1];
     for (long long e0 = 0; e0 < B.d.n_elem; e0 += E) {
       T2 x;
       x.t.blk = b;
@@ -599,7 +720,7 @@ static int model_predict(shp_plan p, int blk, float pred[3], hipStream_t s) {
 // collocated sum-factorisation.
 static int resolve_auto(shp_plan p, int blk, int op, hipStream_t s, int* strategy) {
   Block& B = p->blocks[blk];
-  if (B.auto_src[op] == 0 && p->model_members > 0 && model_op(op) && B.d.n_elem > 0) {
+  if (B.auto_src[op] == 0 && p->model_members > 0 && model_op(op) && B.d.n_elem > 0 && !B.iso()) {
     float pred[3];
     if (int r = model_predict(p, blk, pred, s)) return r;
     int best = SHP_SUMFAC_COLL;
@@ -658,6 +779,43 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
   const bool needs_geom = !(opk == OPK_BWD);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  {
+    // iso-parametric blocks: the backward transform as for any block, and the
+    // collocated Laplacian / Helmholtz with the geometry rebuilt in the launch
+    const int b0 = blk >= 0 ? blk : 0, b1 = blk >= 0 ? blk + 1 : (int)p->blocks.size();
+    int niso = 0;
+    for (int b = b0; b < b1; ++b) niso += p->blocks[b].iso() ? 1 : 0;
+    if (niso > 0 && opk != OPK_BWD) {
+      if (opk != OPK_HELM && opk != OPK_LAP)
+        return fail(SHP_ERR_UNSUPPORTED, "iso-parametric blocks support the backward transform and the collocated "
+                                         "Laplacian and Helmholtz actions");
+      if (niso != b1 - b0)
+        return fail(SHP_ERR_UNSUPPORTED, "a whole-mesh launch takes iso-parametric blocks only with each other");
+      if (blk < 0 && !p->uniform_P) return fail(SHP_ERR_UNSUPPORTED, "the whole-mesh launch needs one P for all blocks");
+      for (int b = b0; b < b1; ++b)
+        if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %d: geometry not set", b);
+      const int iopk = (opk == OPK_HELM) ? OPK_HELM_ISO : OPK_LAP_ISO;
+      const BlockStatic* bst = reinterpret_cast<const BlockStatic*>(p->ws + p->off_bstat);
+      hipError_t e;
+      if (blk >= 0) {
+        const Block& B = p->blocks[blk];
+        const Tiling t = iso_tiling(B.d.P);
+        e = launch_iso(B.d.P, iopk, bst, nullptr, 0, in, out, lambda, t.NT,
+                       op_lds_bytes(B.d.shape, B.d.P, OPK_HELM, t.E, 2), t.E, blk, (B.d.n_elem + t.E - 1) / t.E, s);
+      } else {
+        if (p->mixed_dirty[iopk])
+          if (int r = build_tiles(p, iopk, s)) return r;
+        const Tiling t = mixed_tiling(p, iopk);
+        size_t lds = 0;
+        for (const auto& B : p->blocks) lds = std::max(lds, op_lds_bytes(B.d.shape, B.d.P, OPK_HELM, t.E, 2));
+        const Tile* tiles = reinterpret_cast<const Tile*>(p->ws + p->off_tiles) + (size_t)iopk * p->max_tiles;
+        e = launch_iso(p->blocks[0].d.P, iopk, bst, tiles, p->mixed_ntiles[iopk], in, out, lambda, t.NT, lds, t.E, -1,
+                       p->mixed_ntiles[iopk], s);
+      }
+      if (e != hipSuccess) return dev_fail(e, "iso-parametric launch");
+      return SHP_OK;
+    }
+  }
   if (is_localmat(opk)) {
     const int b0 = blk >= 0 ? blk : 0, b1 = blk >= 0 ? blk + 1 : (int)p->blocks.size();
     for (int b = b0; b < b1; ++b) {
@@ -769,8 +927,10 @@ int shp_apply_prec(shp_plan p, int blk, int op, int strategy, int prec, const vo
   if (!std::isfinite(lambda)) return fail(SHP_ERR_INVALID_ARG, "lambda not finite");
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
   if (!p->uniform_P) return fail(SHP_ERR_UNSUPPORTED, "FP32 whole-mesh launch needs one P for all blocks");
-  for (size_t b = 0; b < p->blocks.size(); ++b)
+  for (size_t b = 0; b < p->blocks.size(); ++b) {
     if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
+    if (p->blocks[b].iso()) return fail(SHP_ERR_UNSUPPORTED, "FP32 contractions need precomputed factors");
+  }
   const int opk = (op == SHP_OP_HELMHOLTZ) ? OPK_HELM : OPK_LAP;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (p->mixed_dirty[opk])
@@ -792,8 +952,10 @@ int shp_advection_factors(shp_plan p, const double* vel, double* adv, void* stre
   if (int r = check_plan(p)) return r;
   if (!vel || !adv) return fail(SHP_ERR_INVALID_ARG, "null vel/adv");
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
-  for (size_t b = 0; b < p->blocks.size(); ++b)
+  for (size_t b = 0; b < p->blocks.size(); ++b) {
     if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
+    if (p->blocks[b].iso()) return fail(SHP_ERR_UNSUPPORTED, "advection factors need precomputed factors");
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (const Block& B : p->blocks) {
     const hipError_t e = launch_adv_factors(reinterpret_cast<const double*>(p->ws + B.off_fac),
@@ -810,8 +972,10 @@ int shp_apply_adr(shp_plan p, const double* adv, const double* in, double* out, 
   if (!std::isfinite(lambda)) return fail(SHP_ERR_INVALID_ARG, "lambda not finite");
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
   if (!p->uniform_P) return fail(SHP_ERR_UNSUPPORTED, "the whole-mesh launch needs one P for all blocks");
-  for (size_t b = 0; b < p->blocks.size(); ++b)
+  for (size_t b = 0; b < p->blocks.size(); ++b) {
     if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
+    if (p->blocks[b].iso()) return fail(SHP_ERR_UNSUPPORTED, "the advection-diffusion-reaction action needs precomputed factors");
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (p->mixed_dirty[OPK_ADR])
     if (int r = build_tiles(p, OPK_ADR, s)) return r;

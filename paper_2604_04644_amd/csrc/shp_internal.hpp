@@ -25,6 +25,8 @@ struct BlockStatic {
   const double* fac;
   const double* dxi;
   const float* tabf;    // the reference tables rounded to FP32
+  const double* xco;    // iso-parametric blocks: coordinate coefficients [n_elem][3][N_P]
+  const double* wref;   // iso-parametric blocks: w / prod (1 - eta_d)^alpha_d per point [Q^3]
   long long n_elem;
   long long coeff_off;  // element offset * N_P of the block in whole-mesh coefficient buffers
   long long phys_off;   // element offset * N_Q in whole-mesh point buffers
@@ -69,6 +71,16 @@ hipError_t launch_adv_factors(const double* fac, const double* dxi, const double
 hipError_t launch_mixed(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
                         double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds, int E,
                         int persist, hipStream_t s);
+// iso-parametric blocks of one order P: Laplacian/Helmholtz action with the
+// geometry recomputed from coordinates (tile list, or one block's tiles of E
+// elements when blk_only >= 0), and the geometry check of one block
+hipError_t launch_iso(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
+                      double* out, double lambda, int threads, size_t lds, int E, int blk_only, long long nwg,
+                      hipStream_t s);
+hipError_t launch_iso_check(int P, const BlockStatic* blocks, int blk, int E, long long nwg, int threads, size_t lds,
+                            int* status, hipStream_t s);
+// reference weights w / prod (1 - eta_d)^alpha_d of the tensor points [Q^3]
+void build_ref_weights(int sh, int P, int pts, std::vector<double>& wref);
 // FP32 contractions (whole-mesh collocated Laplacian/Helmholtz, prefetch variant)
 size_t lds_bytes_f32(int sh, int P, int E);
 hipError_t launch_mixed_f32(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const float* in,

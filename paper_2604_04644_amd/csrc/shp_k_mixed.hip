@@ -167,7 +167,12 @@ hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s) {
                                    hipStream_t s);                                                                   \
   hipError_t launch_adr_P##p(const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,            \
                              double* out, const double* adv, double lambda, int threads, size_t lds, int E,          \
-                             hipStream_t s);
+                             hipStream_t s);                                                                         \
+  hipError_t launch_iso_P##p(int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,   \
+                             double* out, double lambda, int threads, size_t lds, int E, int blk_only, long long nwg, \
+                             hipStream_t s);                                                                         \
+  hipError_t launch_iso_check_P##p(const BlockStatic* blocks, int blk, int E, long long nwg, int threads, size_t lds, \
+                                   int* status, hipStream_t s);
 D_(1) D_(2) D_(3) D_(4) D_(5) D_(6) D_(7) D_(8) D_(9) D_(10)
 #undef D_
 
@@ -186,6 +191,29 @@ hipError_t launch_adr(int P, const BlockStatic* blocks, const Tile* tiles, int n
   switch (P) {
 #define C_(p) \
   case p: return launch_adr_P##p(blocks, tiles, ntiles, in, out, adv, lambda, threads, lds, E, s);
+    C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10)
+#undef C_
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_iso(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
+                      double* out, double lambda, int threads, size_t lds, int E, int blk_only, long long nwg,
+                      hipStream_t s) {
+  switch (P) {
+#define C_(p) \
+  case p: return launch_iso_P##p(opk, blocks, tiles, ntiles, in, out, lambda, threads, lds, E, blk_only, nwg, s);
+    C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10)
+#undef C_
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_iso_check(int P, const BlockStatic* blocks, int blk, int E, long long nwg, int threads, size_t lds,
+                            int* status, hipStream_t s) {
+  switch (P) {
+#define C_(p) \
+  case p: return launch_iso_check_P##p(blocks, blk, E, nwg, threads, lds, status, s);
     C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10)
 #undef C_
   }

@@ -43,7 +43,9 @@ enum : int {
   OPK_LAP_LM = 10,  //   Laplacian
   OPK_HELM_LM = 11, //   Helmholtz
   OPK_ADR = 12,     // advection-diffusion-reaction: Helmholtz plus b . grad u tested with the basis
-  OPK_COUNT = 13
+  OPK_HELM_ISO = 13,  // iso-parametric blocks, geometry recomputed in the launch: Helmholtz
+  OPK_LAP_ISO = 14,   //   Laplacian
+  OPK_COUNT = 15
 };
 
 // Arguments of one block for one operator call.

@@ -463,3 +463,25 @@ void reference_points(int sh, int Q, int pts, double* xi, double* wout) {
 }
 
 }  // namespace shp
+
+namespace shp {
+
+// Reference weights of the tensor points: the product of the three 1D weights
+// divided by prod (1 - eta_d)^alpha_d, the Jacobi weight that the rule of a
+// collapsed direction carries (Sec. 2.3), so that jw = wref |det d x/d eta|.
+void build_ref_weights(int sh, int P, int pts, std::vector<double>& wref) {
+  const int Q = P + 2;
+  std::vector<double> z(3 * Q), w(3 * Q);
+  for (int d = 0; d < 3; ++d) rule_1d(Q, alpha_dir(sh, d), pts, z.data() + d * Q, w.data() + d * Q);
+  wref.assign((size_t)Q * Q * Q, 0.0);
+  for (int i = 0; i < Q; ++i)
+    for (int j = 0; j < Q; ++j)
+      for (int k = 0; k < Q; ++k) {
+        double v = w[i] * w[Q + j] * w[2 * Q + k];
+        v /= std::pow(1.0 - z[i], alpha_dir(sh, 0)) * std::pow(1.0 - z[Q + j], alpha_dir(sh, 1)) *
+             std::pow(1.0 - z[2 * Q + k], alpha_dir(sh, 2));
+        wref[(size_t)(i * Q + j) * Q + k] = v;
+      }
+}
+
+}  // namespace shp

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libshp.so")
 
 SHAPES = {"hex": 0, "prism": 1, "pyr": 2, "tet": 3}
-GEOM = {"affine": 0, "curved": 1}
+GEOM = {"affine": 0, "curved": 1, "isoparam": 2}
 POINTS = {"gj": 0, "radau": 1}
 OPS = {"bwd": 0, "iprod": 1, "physderiv": 2, "iprod_deriv": 3, "mass": 4, "laplacian": 5, "helmholtz": 6}
 STRATEGY = {"auto": 0, "sumfac": 1, "sumfac_coll": 2, "localmat": 3}
@@ -28,6 +28,7 @@ _SIGS = {
     "shp_num_points": [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "shp_quadrature": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
     "shp_plan_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_int],
+    "shp_vertex_modes": [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
     "shp_plan_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
     "shp_plan_bind_workspace": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "shp_plan_set_geometry": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
@@ -155,6 +156,17 @@ def quadrature(shape: str, Q: int, pts: str = "gj"):
     return np.ascontiguousarray(xi.T), w
 
 
+def vertex_modes(shape: str, P: int):
+    """Mode indices of the vertex modes and the reference coordinates xi
+    [n_vertices, 3] of the vertex where each is one (numpy, host)."""
+    import numpy as np
+    idx = np.zeros(8, dtype=np.int32)
+    xi = np.zeros((8, 3))
+    n = ctypes.c_int()
+    _check(lib().shp_vertex_modes(SHAPES[shape], P, idx.ctypes.data, xi.ctypes.data, ctypes.byref(n)))
+    return idx[:n.value].tolist(), xi[:n.value].copy()
+
+
 def _stream(torch):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -226,11 +238,12 @@ class Plan:
 
     # ---------------------------------------------------------------
     def set_geometry(self, blk: int, jac):
-        """jac: float64 device tensor [n][9][Q^3] (curved) or [n][9] (affine)."""
+        """jac: float64 device tensor [n][9][Q^3] (curved), [n][9] (affine) or
+        the coordinate coefficients [n][3][N_P] (isoparam)."""
         t = self._torch
         self.__dict__.pop("_diag", None)
         sh, P, ne, geom = self.blocks[blk]
-        want = (ne, 9, (P + 2) ** 3) if geom == "curved" else (ne, 9)
+        want = {"curved": (ne, 9, (P + 2) ** 3), "affine": (ne, 9), "isoparam": (ne, 3, self.n_modes[blk])}[geom]
         if tuple(jac.shape) != want or jac.dtype != t.float64 or not jac.is_cuda or not jac.is_contiguous():
             raise ValueError(f"jac must be a contiguous float64 device tensor of shape {want}")
         _check(lib().shp_plan_set_geometry(self._h, blk, ctypes.c_void_p(jac.data_ptr()), _stream(t)))

@@ -53,11 +53,15 @@ def n_workers(limit: int = 16) -> int:
 
 
 def _work(args):
-    op, shape, P, x0, A, curved, x, lam, pts = args
+    op, shape, P, x0, A, curved, x, lam, pts, X = args
     from oracle import shp_oracle as O
     from paper_2604_04644_amd import workloads as W
-    maps = W.ElementMaps(shape, x0, A)
     Q = P + 2
+    if X is not None:
+        jac = O.isoparametric_jacobian(shape, P, Q, X, pts)
+        chunk = max(1, min(64, int(4e8 // (8 * 4 * Q ** 3 * O.num_modes(shape, P)))))
+        return O.apply_op(op, shape, P, Q, jac, x, lam=lam, chunk=chunk, pts=pts)
+    maps = W.ElementMaps(shape, x0, A)
     if curved:
         jac = W.jacobian(maps, O.reference_points(shape, Q, pts), curved=True)
     else:
@@ -67,12 +71,14 @@ def _work(args):
 
 
 def apply_op(op: str, shape: str, P: int, maps, x, lam: float = 1.0, curved: bool = True, pts: str = "gj",
-             workers: int | None = None, pieces_per_worker: int = 4):
+             workers: int | None = None, pieces_per_worker: int = 4, X=None):
     """oracle.apply_op(op, shape, P, P + 2, jac(maps), x) with the batch split
     over worker processes.  x: [n_elem][..] (coefficients or point values) or
-    [3][n_elem][N_Q] for iprod_deriv."""
+    [3][n_elem][N_Q] for iprod_deriv.  With X (iso-parametric coordinate
+    coefficients [n_elem][3][N_P]) the Jacobian is the oracle's
+    isoparametric_jacobian of X and maps only gives the element count."""
     x = np.asarray(x, dtype=np.float64)
-    ne = len(maps)
+    ne = len(maps) if X is None else X.shape[0]
     workers = workers or n_workers()
     npiece = max(1, min(ne, workers * pieces_per_worker))
     bounds = np.linspace(0, ne, npiece + 1).astype(int)
@@ -81,7 +87,11 @@ def apply_op(op: str, shape: str, P: int, maps, x, lam: float = 1.0, curved: boo
         if b <= a:
             continue
         xs = x[:, a:b] if op == "iprod_deriv" else x[a:b]
-        jobs.append((op, shape, P, maps.x0[a:b], maps.A[a:b], curved, np.ascontiguousarray(xs), lam, pts))
+        if X is None:
+            jobs.append((op, shape, P, maps.x0[a:b], maps.A[a:b], curved, np.ascontiguousarray(xs), lam, pts, None))
+        else:
+            jobs.append((op, shape, P, None, None, curved, np.ascontiguousarray(xs), lam, pts,
+                         np.ascontiguousarray(X[a:b])))
     if workers == 1 or len(jobs) == 1:
         outs = [_work(j) for j in jobs]
     else:

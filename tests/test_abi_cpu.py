@@ -223,3 +223,21 @@ def test_model_file_validation_without_device(L, tmp_path):
     assert L.shp_plan_load_model(h, write("nh.bin", dict(good, nh=32), [0.01] * (2 * n)), None) == -1
     assert "cost model file" in L.shp_last_error().decode()
     L.shp_plan_destroy(h)
+
+
+@pytest.mark.parametrize("shape", O.SHAPES)
+def test_vertex_modes_match_oracle(L, shape):
+    """shp_vertex_modes gives the oracle's vertex modes and vertices, and each
+    is one at its vertex and zero at the others (the oracle's basis)."""
+    from paper_2604_04644_amd import shp
+    for P in (1, 2, 5, 10):
+        idx, xi = shp.vertex_modes(shape, P)
+        oidx, oxi = O.vertex_modes(shape, P)
+        assert idx == oidx
+        assert np.array_equal(xi, oxi)
+    # nodality at the vertices, through the oracle's basis at points just inside
+    P = 3
+    idx, xi = shp.vertex_modes(shape, P)
+    modes = O.modes(shape, P)
+    for v, (m, x) in enumerate(zip(idx, xi)):
+        assert modes[m] == O.VERTEX_MODES[shape][v]
