@@ -267,6 +267,58 @@ def affine_jacobian(maps: ElementMaps) -> np.ndarray:
     return np.ascontiguousarray((0.5 * maps.A).reshape(len(maps), 9))
 
 
+# ---------------------------------------------------------------------------
+# two-dimensional meshes
+# ---------------------------------------------------------------------------
+
+SHAPES2 = ("quad", "tri")
+
+
+def quad_tri_mesh(ncell: int = 256) -> dict:
+    """The unit square in ncell^2 cells: cells with centre x < 1/2 are
+    quadrilaterals, the others two triangles each (lower-left: vertices x0,
+    x0 + h e1, x0 + h e2; upper-right: its point reflection through the cell
+    centre).  Reference square [-1,1]^2, reference triangle {xi1 + xi2 <= 0}
+    with vertices (-1,-1), (1,-1), (-1,1).  {shape: ElementMaps} with 2D x0, A."""
+    if ncell % 2:
+        raise ValueError("ncell must be even")
+    h = 1.0 / ncell
+    ii, jj = np.meshgrid(np.arange(ncell), np.arange(ncell), indexing="ij")
+    x0 = np.stack([ii.ravel() * h, jj.ravel() * h], axis=1)
+    left = x0[:, 0] + 0.5 * h < 0.5
+    q0 = x0[left]
+    t0 = x0[~left]
+    I = np.eye(2)
+    quads = ElementMaps("quad", q0, np.broadcast_to(h * I, (len(q0), 2, 2)).copy())
+    tx0 = np.concatenate([t0, t0 + h], axis=0)
+    tA = np.concatenate([np.broadcast_to(h * I, (len(t0), 2, 2)), np.broadcast_to(-h * I, (len(t0), 2, 2))], axis=0)
+    order = np.argsort(np.concatenate([np.arange(len(t0)) * 2, np.arange(len(t0)) * 2 + 1]), kind="stable")
+    tris = ElementMaps("tri", tx0[order], tA[order])
+    return {"quad": quads, "tri": tris}
+
+
+def jacobian2d(maps: ElementMaps, xi: np.ndarray, curved: bool, amp: float = AMP) -> np.ndarray:
+    """d x_i / d xi_j of 2D elements, [n_elem][4][n_pts] (component i*2 + j):
+    the affine map composed with Phi(X) = X + amp sin(2 pi X) sin(2 pi Y) (1,1)
+    when curved."""
+    xi = np.asarray(xi, dtype=np.float64)
+    ne, npts = len(maps), xi.shape[0]
+    Ah = 0.5 * maps.A                                       # [ne,2,2]
+    if not curved:
+        return np.ascontiguousarray(np.repeat(Ah.reshape(ne, 4, 1), npts, axis=2))
+    X = _chi(maps, xi)                                      # [ne,npts,2]
+    sn, cs = np.sin(2 * np.pi * X), np.cos(2 * np.pi * X)
+    ds = np.stack([2 * np.pi * cs[..., 0] * sn[..., 1], 2 * np.pi * sn[..., 0] * cs[..., 1]], axis=-1)
+    g = np.einsum("epk,ekj->epj", ds, Ah)
+    J = Ah[:, None, :, :] + amp * g[:, :, None, :]
+    return np.ascontiguousarray(np.transpose(J.reshape(ne, npts, 4), (0, 2, 1)))
+
+
+def affine_jacobian2d(maps: ElementMaps) -> np.ndarray:
+    """Constant d x_i / d xi_j of straight-sided 2D elements, [n_elem][4]."""
+    return np.ascontiguousarray((0.5 * maps.A).reshape(len(maps), 4))
+
+
 def coeffs(n_elem: int, n_modes: int, seed: int) -> np.ndarray:
     """Elemental coefficients uniform in [-1, 1], [n_elem][n_modes], FP64."""
     rng = np.random.default_rng(seed)
