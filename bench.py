@@ -347,6 +347,35 @@ def iso_leg(torch, shp, W, flush, ncell: int = 32, Ps=(4, 6), steps: int = 20):
     return out
 
 
+def leg_2d(torch, shp, W, flush, cases=((512, 2), (512, 4), (256, 8)), steps: int = 20):
+    """The 2D operators: a curved quadrilateral/triangle mesh of the unit
+    square (ncell^2 cells, quadrilaterals left of x = 1/2, two triangles per
+    cell right of it), FP64 Helmholtz action in one launch, HIP events after a
+    cache flush (median of `steps`); algorithmic bytes 16 N_P + 32 Q^2 per
+    element (x, y and 4 factors per point)."""
+    out = {}
+    dev = torch.device("cuda")
+    for ncell, P in cases:
+        mesh = W.quad_tri_mesh(ncell)
+        shapes = ("quad", "tri")
+        plan = shp.Plan([(s, P, len(mesh[s]), "curved") for s in shapes])
+        for b, s in enumerate(shapes):
+            plan.set_geometry(b, torch.from_numpy(W.jacobian2d(mesh[s], shp.quadrature(s, P + 2)[0], True)).to(dev))
+        nc, _ = plan.totals()
+        x = torch.from_numpy(W.coeffs(1, nc, 90 + P)[0]).to(dev)
+        y = torch.empty_like(x)
+        _, _, med = time_launches(torch, lambda: plan.apply(-1, "helmholtz", x, out=y), steps, 3, flush=flush)
+        nb = sum(len(mesh[s]) * (16 * plan.n_modes[b] + 32 * (P + 2) ** 2) for b, s in enumerate(shapes))
+        row = {"cells": ncell, "elements": {s: len(mesh[s]) for s in shapes}, "dof": int(nc), "ms": round(med, 5),
+               "GDOF/s": round(nc / (med * 1e-3) / 1e9, 3), "algorithmic_bytes": int(nb),
+               "hbm_frac": round(nb / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        out[f"P{P}"] = row
+        log(f"  2D P={P}: {row}")
+        del plan, x, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def adr_leg(torch, plan, mesh, x, y, helm_ms: float, steps: int = 20):
     """The advection-diffusion-reaction action (Helmholtz plus b . grad u tested
     with the basis) on the same mesh, velocity U[-1,1] at every point: launch
@@ -525,6 +554,7 @@ def main():
                     help="also time collocated vs non-collocated Helmholtz per shape (block launches)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg (P=6 mesh)")
     ap.add_argument("--no-adr", action="store_true", help="skip the advection-diffusion-reaction action")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D quadrilateral/triangle leg")
     ap.add_argument("--no-iso", action="store_true",
                     help="skip the iso-parametric leg (geometry rebuilt in the launch, P = 4 and 6)")
     ap.add_argument("--c0", action="store_true",
@@ -604,6 +634,10 @@ def main():
     if not a.no_per_shape:
         log("  per-shape x order table")
         per_shape = order_table(torch, shp, W, flush, a.ncell, tuple(int(v) for v in a.orders.split(",")))
+    two_d = None
+    if not a.no_2d:
+        log("  2D leg")
+        two_d = leg_2d(torch, shp, W, flush)
     iso = None
     if not a.no_iso:
         log("  iso-parametric leg")
@@ -658,6 +692,8 @@ def main():
         out["adr_action"] = adr
     if iso is not None:
         out["isoparametric_vs_precomputed"] = iso
+    if two_d is not None:
+        out["quad_tri_2d"] = two_d
     print(json.dumps(out), flush=True)
 
 

@@ -67,7 +67,21 @@ extern "C" {
 #define SHP_ERR_DEVICE (-6)        /* a HIP runtime call failed (message included) */
 #define SHP_ERR_NOT_CONVERGED (-7) /* an iterative solve did not reach its tolerance */
 
-typedef enum { SHP_HEX = 0, SHP_PRISM = 1, SHP_PYR = 2, SHP_TET = 3 } shp_shape;
+/* Shapes.  The 2D shapes follow the two-dimensional formulation (Sec. 2.2)
+ * and the triangle as a collapsed square (Sec. 2.3): modes (p,q), q fastest,
+ * quadrilateral A_p(eta1) A_q(eta2) with 0 <= p,q <= P (N_P = (P+1)^2),
+ * triangle A_p(eta1) C_{p,q}(eta2) with p+q <= P (N_P = (P+1)(P+2)/2) and the
+ * collapsed-vertex mode (0,1) = v1(eta2); Q^2 points (i,j) at i*Q + j, GLL
+ * in eta1 and in the quadrilateral's eta2, Gauss-Jacobi(1,0) (or Radau) in the
+ * triangle's eta2.  Geometry d x_i/d xi_j at component i*2 + j: curved
+ * [n_elem][4][Q^2], affine [n_elem][4]; vector fields [2][n][Q^2].  A plan
+ * holds 2D or 3D blocks, not both.  2D blocks run every operator with the
+ * collocated sum-factorisation (SHP_AUTO or SHP_SUMFAC_COLL, per block or as
+ * one whole-mesh launch); tuning, launch shapes, the cost model, FP32
+ * contractions, the solve, iso-parametric maps and the
+ * advection-diffusion-reaction action cover the 3D shapes only
+ * (SHP_ERR_UNSUPPORTED). */
+typedef enum { SHP_HEX = 0, SHP_PRISM = 1, SHP_PYR = 2, SHP_TET = 3, SHP_QUAD = 4, SHP_TRI = 5 } shp_shape;
 /* Mapping of a block's elements.  SHP_AFFINE and SHP_CURVED take d x/d xi
  * and keep 7 FP64 geometric factors per point in the workspace (Sec. 4:
  * precomputed factors).  SHP_ISOPARAM takes the map as a polynomial of the
@@ -121,15 +135,15 @@ typedef struct shp_plan_s* shp_plan;
 /* Number of modes N_P of a shape at order P (Sec. 2.1, N_P; the mode sets above). */
 int shp_num_modes(int shape, int P, int* n_modes /* host out */);
 
-/* Number of quadrature points N_Q = Q^3 of a shape: every shape takes the
- * tensor product of Q points per direction (Sec. 2.1, tensor quadrature; the
- * collapsed shapes keep the full tensor grid in eta, Sec. 2.3). */
+/* Number of quadrature points N_Q = Q^3 (Q^2 for the 2D shapes): every
+ * shape takes the tensor product of Q points per direction (Sec. 2.1, tensor
+ * quadrature; the collapsed shapes keep the full tensor grid in eta, Sec. 2.3). */
 int shp_num_points(int shape, int Q, int* n_points /* host out */);
 
 /* The block's quadrature points in reference coordinates and their weights
  * (Sec. 2.1 tensor quadrature; Sec. 2.3 collapse) for point set pts
- * (shp_points).  xi: host [3][Q^3], component slowest; w: host [Q^3] = product
- * of the three 1D weights, may be NULL.  The mesh's Jacobian d x/d xi is
+ * (shp_points).  xi: host [3][Q^3], component slowest ([2][Q^2] for the 2D
+ * shapes); w: host [Q^3] (or [Q^2]) = product of the 1D weights, may be NULL.  The mesh's Jacobian d x/d xi is
  * expected at exactly these points. */
 int shp_quadrature(int shape, int Q, int pts, double* xi /* host out */, double* w /* host out or NULL */);
 

@@ -17,6 +17,7 @@
 #include "shp_kernels_geom.hpp"
 #include "shp_kernels_lm.hpp"
 #include "shp_kernels_iso.hpp"
+#include "shp_kernels_2d.hpp"
 
 using namespace shp;
 
@@ -105,7 +106,7 @@ struct shp_plan_s {
 
 namespace {
 
-bool valid_shape(int s) { return s >= SHP_HEX && s <= SHP_TET; }
+bool valid_shape(int s) { return s >= SHP_HEX && s <= SHP_TRI; }
 
 int opk_of(int op, int strategy, int* opk) {
   if (strategy < SHP_AUTO || strategy > SHP_LOCALMAT) return fail(SHP_ERR_INVALID_ARG, "bad strategy %d", strategy);
@@ -167,6 +168,15 @@ Tiling default_tiling(int sh, int P, int opk, size_t lds_budget = 40 * 1024) {
   t.NT = 256;
   const bool helm = (opk == OPK_HELM || opk == OPK_LAP || opk == OPK_ADR);
   const long long Q3 = (long long)(P + 2) * (P + 2) * (P + 2);
+  if (is_2d(sh)) {
+    // enough elements that a stage has about two line tasks per thread
+    const int Q = P + 2;
+    int E = 1;
+    while (E < 64 && lds_bytes_2d(sh, P, E + 1) <= 48 * 1024 && (E + 1) * Q <= 2 * t.NT) ++E;
+    t.E = E;
+    t.persist = 0;
+    return t;
+  }
   if (helm && P >= 7) {
     t.E = HI_E[sh][P - 7];
     t.NT = HI_NT[sh][P - 7];
@@ -213,7 +223,7 @@ int shp_num_modes(int shape, int P, int* n) {
   if (!n) return fail(SHP_ERR_INVALID_ARG, "null output");
   if (!valid_shape(shape)) return fail(SHP_ERR_INVALID_ARG, "bad shape %d", shape);
   if (P < 1 || P > MAX_P) return fail(SHP_ERR_UNSUPPORTED, "P=%d outside [1,%d]", P, MAX_P);
-  *n = num_modes(shape, P);
+  *n = is_2d(shape) ? num_modes2(shape, P) : num_modes(shape, P);
   return SHP_OK;
 }
 
@@ -221,13 +231,13 @@ int shp_num_points(int shape, int Q, int* n) {
   if (!n) return fail(SHP_ERR_INVALID_ARG, "null output");
   if (!valid_shape(shape)) return fail(SHP_ERR_INVALID_ARG, "bad shape %d", shape);
   if (Q < 3 || Q > MAX_P + 2) return fail(SHP_ERR_UNSUPPORTED, "Q=%d outside [3,%d]", Q, MAX_P + 2);
-  *n = Q * Q * Q;
+  *n = is_2d(shape) ? Q * Q : Q * Q * Q;
   return SHP_OK;
 }
 
 int shp_vertex_modes(int shape, int P, int* idx, double* xi, int* n_vertices) {
   if (!idx || !xi || !n_vertices) return fail(SHP_ERR_INVALID_ARG, "null output");
-  if (!valid_shape(shape)) return fail(SHP_ERR_INVALID_ARG, "bad shape %d", shape);
+  if (!valid_shape(shape) || is_2d(shape)) return fail(SHP_ERR_INVALID_ARG, "bad shape %d", shape);
   if (P < 1 || P > MAX_P) return fail(SHP_ERR_UNSUPPORTED, "P=%d outside [1,%d]", P, MAX_P);
   // (p, q, r) of each vertex mode and the reference vertex where it is one
   struct V {
@@ -266,7 +276,10 @@ int shp_quadrature(int shape, int Q, int pts, double* xi, double* w) {
   if (!valid_shape(shape)) return fail(SHP_ERR_INVALID_ARG, "bad shape %d", shape);
   if (pts != SHP_PTS_GJ && pts != SHP_PTS_RADAU) return fail(SHP_ERR_INVALID_ARG, "bad point set %d", pts);
   if (Q < 3 || Q > MAX_P + 2) return fail(SHP_ERR_UNSUPPORTED, "Q=%d outside [3,%d]", Q, MAX_P + 2);
-  reference_points(shape, Q, pts, xi, w);
+  if (is_2d(shape))
+    reference_points2d(shape, Q, pts, xi, w);
+  else
+    reference_points(shape, Q, pts, xi, w);
   return SHP_OK;
 }
 
@@ -283,6 +296,12 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
       return fail(SHP_ERR_INVALID_ARG, "block %d: bad geom %d", b, d.geom);
     if (d.pts != SHP_PTS_GJ && d.pts != SHP_PTS_RADAU) return fail(SHP_ERR_INVALID_ARG, "block %d: bad point set %d", b, d.pts);
   }
+  for (int b = 1; b < nblk; ++b)
+    if (is_2d(blk[b].shape) != is_2d(blk[0].shape))
+      return fail(SHP_ERR_INVALID_ARG, "block %d: a plan holds 2D or 3D shapes, not both", b);
+  for (int b = 0; b < nblk; ++b)
+    if (is_2d(blk[b].shape) && blk[b].geom == SHP_ISOPARAM)
+      return fail(SHP_ERR_UNSUPPORTED, "block %d: iso-parametric 2D blocks are not built", b);
   shp_plan p = new (std::nothrow) shp_plan_s;
   if (!p) return fail(SHP_ERR_INVALID_ARG, "out of host memory");
   p->blocks.resize(nblk);
@@ -295,6 +314,19 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
   for (int b = 0; b < nblk; ++b) {
     Block& B = p->blocks[b];
     B.d = blk[b];
+    if (is_2d(B.d.shape)) {
+      // 2D: the tables only (the solve, tuning and local matrices are 3D)
+      B.NP = num_modes2(B.d.shape, B.d.P);
+      B.NQ = B.d.Q * B.d.Q;
+      build_tables2d(B.d.shape, B.d.P, B.d.pts, B.tab);
+      B.coeff_off = cofs;
+      B.phys_off = pofs;
+      cofs += B.d.n_elem * B.NP;
+      pofs += B.d.n_elem * B.NQ;
+      p->total_elem += B.d.n_elem;
+      if (B.d.P != blk[0].P) p->uniform_P = false;
+      continue;
+    }
     B.NP = num_modes(B.d.shape, B.d.P);
     B.NQ = B.d.Q * B.d.Q * B.d.Q;
     build_tables(B.d.shape, B.d.P, B.d.pts, B.tab, B.itab);
@@ -348,10 +380,11 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
       B.off_fac = B.off_dxi = 0;
       continue;
     }
+    const int nfac = is_2d(B.d.shape) ? NFAC2 : NFAC, ndxi = is_2d(B.d.shape) ? NDXI2 : NDXI;
     B.off_fac = off;
-    off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * NFAC * B.NQ);
+    off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * nfac * B.NQ);
     B.off_dxi = off;
-    off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * NDXI * B.NQ);
+    off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * ndxi * B.NQ);
     if (!B.am.empty()) {
       B.off_coef = off;
       off = align_up(off + sizeof(double) * (size_t)B.d.n_elem * NAFF);
@@ -422,7 +455,7 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
     B.geom_ok = false;
     hipError_t e = hipMemcpyAsync(p->ws + B.off_tab, B.tab.data(), sizeof(double) * B.tab.size(),
                                   hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !B.itab.empty())
       e = hipMemcpyAsync(p->ws + B.off_itab, B.itab.data(), sizeof(int) * B.itab.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.lm.empty())
       e = hipMemcpyAsync(p->ws + B.off_lm, B.lm.data(), sizeof(double) * B.lm.size(), hipMemcpyHostToDevice, s);
@@ -430,9 +463,9 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
       e = hipMemcpyAsync(p->ws + B.off_am, B.am.data(), sizeof(double) * B.am.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && B.iso())
       e = hipMemcpyAsync(p->ws + B.off_wref, B.wref.data(), sizeof(double) * B.wref.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !B.dtab.empty())
       e = hipMemcpyAsync(p->ws + B.off_dtab, B.dtab.data(), sizeof(double) * B.dtab.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !B.ditab.empty())
       e = hipMemcpyAsync(p->ws + B.off_ditab, B.ditab.data(), sizeof(int) * B.ditab.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
       B.tabf.assign(B.tab.begin(), B.tab.end());
@@ -459,7 +492,12 @@ int shp_plan_set_geometry(shp_plan p, int blk, const double* jac, void* stream) 
   int* status = reinterpret_cast<int*>(p->ws + p->off_status);
   hipError_t e = hipMemsetAsync(status, 0, sizeof(int), s);
   if (e != hipSuccess) return dev_fail(e, "hipMemsetAsync(status)");
-  if (B.iso()) {
+  if (is_2d(B.d.shape)) {
+    e = launch_geometry2d(B.d.shape, B.d.P, reinterpret_cast<const double*>(p->ws + B.off_tab), jac,
+                          reinterpret_cast<double*>(p->ws + B.off_fac), reinterpret_cast<double*>(p->ws + B.off_dxi),
+                          B.d.n_elem, B.d.geom == SHP_AFFINE, status, s);
+    if (e != hipSuccess) return dev_fail(e, "2D geometry kernel launch");
+  } else if (B.iso()) {
     // keep the coordinate coefficients; check the geometry they give at
     // every point with the launches' own FP64 reconstruction
     e = hipMemcpyAsync(p->ws + B.off_xco, jac, sizeof(double) * (size_t)B.d.n_elem * 3 * B.NP,
@@ -518,8 +556,10 @@ int plan_helm_diag(shp_plan_s* p, double lambda, double* diag, hipStream_t s) {
 int plan_check_solve(shp_plan_s* p, int inner_prec) {
   if (int r = check_plan(p)) return r;
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
-  for (const auto& B : p->blocks)
+  for (const auto& B : p->blocks) {
     if (B.iso()) return fail(SHP_ERR_UNSUPPORTED, "the solve and its diagonal need precomputed factors, not iso-parametric blocks");
+    if (is_2d(B.d.shape)) return fail(SHP_ERR_UNSUPPORTED, "the solve covers the 3D shapes");
+  }
   for (size_t b = 0; b < p->blocks.size(); ++b)
     if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
   if (inner_prec == SHP_FP32 && !p->uniform_P)
@@ -543,6 +583,7 @@ int shp_block_offsets(shp_plan p, int blk, int64_t* coeff_off, int64_t* phys_off
 
 int shp_set_tiling(shp_plan p, int blk, int op, int strategy, int E, int NT, int persistent) {
   if (int r = check_plan(p)) return r;
+  if (is_2d(p->blocks[0].d.shape)) return fail(SHP_ERR_UNSUPPORTED, "2D blocks keep their default launch shape");
   int opk;
   if (int r = opk_of(op, strategy, &opk)) return r;
   if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
@@ -601,7 +642,8 @@ static Tiling mixed_tiling(shp_plan p, int opk) {
   if (t.E > 0 && t.NT > 0) return t;
   if (opk == OPK_HELM_ISO || opk == OPK_LAP_ISO) return iso_tiling(p->blocks[0].d.P);
   const int P0 = p->blocks[0].d.P;
-  if ((opk == OPK_HELM || opk == OPK_LAP || opk == OPK_ADR) && p->uniform_P && P0 >= 7) {
+  const bool dim2 = is_2d(p->blocks[0].d.shape);
+  if ((opk == OPK_HELM || opk == OPK_LAP || opk == OPK_ADR) && p->uniform_P && P0 >= 7 && !dim2) {
     t.E = HI_MESH_E[P0 - 7];
     t.NT = HI_MESH_NT[P0 - 7];
     t.persist = 2;
@@ -611,7 +653,7 @@ static Tiling mixed_tiling(shp_plan p, int opk) {
   for (const auto& B : p->blocks) {
     Tiling d = default_tiling(B.d.shape, B.d.P, opk);
     const long long Q3 = (long long)B.d.Q * B.d.Q * B.d.Q;
-    if ((opk == OPK_HELM || opk == OPK_LAP || opk == OPK_ADR) && d.E * Q3 <= 2LL * d.NT)
+    if ((opk == OPK_HELM || opk == OPK_LAP || opk == OPK_ADR) && !dim2 && d.E * Q3 <= 2LL * d.NT)
       d = default_tiling(B.d.shape, B.d.P, opk, 64 * 1024);
     t.E = std::min(t.E, d.E);
     t.NT = std::min(t.NT, d.NT);
@@ -641,7 +683,7 @@ static int build_tiles(shp_plan p, int opk, hipStream_t s) {
     const Block& B = p->blocks[b];
     // per-element cost weight: the measured Helmholtz launch time per element
     // of the shape relative to the hexahedron at the same P
-    const double w = LPT_WEIGHT[B.d.shape][B.d.P - 1];
+    const double w = is_2d(B.d.shape) ? 1.0 : LPT_WEIGHT[B.d.shape][B.d.P - 1];
     for (long long e0 = 0; e0 < B.d.n_elem; e0 += E) {
       T2 x;
       x.t.blk = b;
@@ -720,7 +762,8 @@ static int model_predict(shp_plan p, int blk, float pred[3], hipStream_t s) {
 // collocated sum-factorisation.
 static int resolve_auto(shp_plan p, int blk, int op, hipStream_t s, int* strategy) {
   Block& B = p->blocks[blk];
-  if (B.auto_src[op] == 0 && p->model_members > 0 && model_op(op) && B.d.n_elem > 0 && !B.iso()) {
+  if (B.auto_src[op] == 0 && p->model_members > 0 && model_op(op) && B.d.n_elem > 0 && !B.iso() &&
+      !is_2d(B.d.shape)) {
     float pred[3];
     if (int r = model_predict(p, blk, pred, s)) return r;
     int best = SHP_SUMFAC_COLL;
@@ -779,6 +822,43 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
   const bool needs_geom = !(opk == OPK_BWD);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (is_2d(p->blocks[0].d.shape)) {
+    // quadrilaterals and triangles: the collocated sum-factorisation
+    if (opk > OPK_HELM)
+      return fail(SHP_ERR_UNSUPPORTED, "2D blocks run the collocated sum-factorisation (SHP_SUMFAC_COLL)");
+    const int b0 = blk >= 0 ? blk : 0, b1 = blk >= 0 ? blk + 1 : (int)p->blocks.size();
+    for (int b = b0; b < b1; ++b)
+      if (needs_geom && !p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %d: geometry not set", b);
+    hipError_t e = hipSuccess;
+    if (blk >= 0 || !p->uniform_P) {
+      for (int b = b0; b < b1 && e == hipSuccess; ++b) {
+        const Block& B = p->blocks[b];
+        const Tiling t = effective(B.tiling[opk], B.d.shape, B.d.P, opk);
+        OpArgs a{};
+        a.tab = reinterpret_cast<const double*>(p->ws + B.off_tab);
+        a.fac = reinterpret_cast<const double*>(p->ws + B.off_fac);
+        a.dxi = reinterpret_cast<const double*>(p->ws + B.off_dxi);
+        a.in = in + (blk >= 0 ? 0 : (in_is_modes(opk) ? B.coeff_off : B.phys_off));
+        a.out = out + (blk >= 0 ? 0 : (out_is_modes(opk) ? B.coeff_off : B.phys_off));
+        a.n_elem = B.d.n_elem;
+        a.in_cs = a.out_cs = (blk >= 0) ? B.d.n_elem * (long long)B.NQ : p->total_phys;
+        a.lambda = lambda;
+        a.E = t.E;
+        e = launch_block2d(B.d.shape, B.d.P, opk, a, t.NT, s);
+      }
+    } else {
+      if (p->mixed_dirty[opk])
+        if (int r = build_tiles(p, opk, s)) return r;
+      const Tiling mt = mixed_tiling(p, opk);
+      size_t lds = 0;
+      for (const auto& B : p->blocks) lds = std::max(lds, lds_bytes_2d(B.d.shape, B.d.P, mt.E));
+      const Tile* tiles = reinterpret_cast<const Tile*>(p->ws + p->off_tiles) + (size_t)opk * p->max_tiles;
+      e = launch_mixed2d(p->blocks[0].d.P, opk, reinterpret_cast<const BlockStatic*>(p->ws + p->off_bstat), tiles,
+                         p->mixed_ntiles[opk], in, out, p->total_phys, p->total_phys, lambda, mt.NT, lds, s);
+    }
+    if (e != hipSuccess) return dev_fail(e, "2D launch");
+    return SHP_OK;
+  }
   {
     // iso-parametric blocks: the backward transform as for any block, and the
     // collocated Laplacian / Helmholtz with the geometry rebuilt in the launch
@@ -930,6 +1010,7 @@ int shp_apply_prec(shp_plan p, int blk, int op, int strategy, int prec, const vo
   for (size_t b = 0; b < p->blocks.size(); ++b) {
     if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
     if (p->blocks[b].iso()) return fail(SHP_ERR_UNSUPPORTED, "FP32 contractions need precomputed factors");
+    if (is_2d(p->blocks[b].d.shape)) return fail(SHP_ERR_UNSUPPORTED, "FP32 contractions cover the 3D shapes");
   }
   const int opk = (op == SHP_OP_HELMHOLTZ) ? OPK_HELM : OPK_LAP;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -954,7 +1035,8 @@ int shp_advection_factors(shp_plan p, const double* vel, double* adv, void* stre
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
   for (size_t b = 0; b < p->blocks.size(); ++b) {
     if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
-    if (p->blocks[b].iso()) return fail(SHP_ERR_UNSUPPORTED, "advection factors need precomputed factors");
+    if (p->blocks[b].iso() || is_2d(p->blocks[b].d.shape))
+      return fail(SHP_ERR_UNSUPPORTED, "advection factors need 3D blocks with precomputed factors");
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (const Block& B : p->blocks) {
@@ -974,7 +1056,8 @@ int shp_apply_adr(shp_plan p, const double* adv, const double* in, double* out, 
   if (!p->uniform_P) return fail(SHP_ERR_UNSUPPORTED, "the whole-mesh launch needs one P for all blocks");
   for (size_t b = 0; b < p->blocks.size(); ++b) {
     if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
-    if (p->blocks[b].iso()) return fail(SHP_ERR_UNSUPPORTED, "the advection-diffusion-reaction action needs precomputed factors");
+    if (p->blocks[b].iso() || is_2d(p->blocks[b].d.shape))
+      return fail(SHP_ERR_UNSUPPORTED, "the advection-diffusion-reaction action needs 3D blocks with precomputed factors");
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (p->mixed_dirty[OPK_ADR])
@@ -1032,6 +1115,7 @@ int shp_tune(shp_plan p, int blk, int op, const double* in, double* out, double*
   if (op < 0 || op > SHP_OP_HELMHOLTZ) return fail(SHP_ERR_INVALID_ARG, "bad operator %d", op);
   if (!in || !out || !ref || !res) return fail(SHP_ERR_INVALID_ARG, "null argument");
   if (reps < 1 || reps > 1000) return fail(SHP_ERR_INVALID_ARG, "reps=%d outside [1,1000]", reps);
+  if (is_2d(p->blocks[0].d.shape)) return fail(SHP_ERR_UNSUPPORTED, "tuning covers the 3D shapes");
   if (max_records > 0 && !records) return fail(SHP_ERR_INVALID_ARG, "null records");
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1317,6 +1401,7 @@ int shp_model_choose(shp_plan p, int blk, int op, int* strategy, double* pred_ms
   if (p->model_members == 0) return fail(SHP_ERR_STATE, "no cost model loaded");
   const Block& B = p->blocks[blk];
   if (B.d.n_elem == 0) return fail(SHP_ERR_INVALID_ARG, "block %d is empty", blk);
+  if (is_2d(B.d.shape)) return fail(SHP_ERR_UNSUPPORTED, "the cost model covers the 3D shapes");
   float pred[3];
   if (int r = model_predict(p, blk, pred, static_cast<hipStream_t>(stream))) return r;
   int best = SHP_SUMFAC_COLL;

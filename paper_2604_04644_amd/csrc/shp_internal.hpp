@@ -79,6 +79,17 @@ hipError_t launch_iso(int P, int opk, const BlockStatic* blocks, const Tile* til
                       hipStream_t s);
 hipError_t launch_iso_check(int P, const BlockStatic* blocks, int blk, int E, long long nwg, int threads, size_t lds,
                             int* status, hipStream_t s);
+// 2D shapes (quadrilateral, triangle): tables, points, and the launchers
+// (shp_k_2d_*.hip): block launch, whole-mesh launch, geometry, LDS bytes
+void build_tables2d(int sh, int P, int pts, std::vector<double>& tab);
+void reference_points2d(int sh, int Q, int pts, double* xi, double* w);
+hipError_t launch_block2d(int sh, int P, int opk, const OpArgs& a, int threads, hipStream_t s);
+hipError_t launch_mixed2d(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
+                          double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds,
+                          hipStream_t s);
+hipError_t launch_geometry2d(int sh, int P, const double* tab, const double* jac, double* fac, double* dxi,
+                             long long n_elem, int affine, int* status, hipStream_t s);
+size_t lds_bytes_2d(int sh, int P, int E);
 // reference weights w / prod (1 - eta_d)^alpha_d of the tensor points [Q^3]
 void build_ref_weights(int sh, int P, int pts, std::vector<double>& wref);
 // FP32 contractions (whole-mesh collocated Laplacian/Helmholtz, prefetch variant)

@@ -220,6 +220,54 @@ hipError_t launch_iso_check(int P, const BlockStatic* blocks, int blk, int E, lo
   return hipErrorInvalidValue;
 }
 
+#define D2_(lo)                                                                                                    \
+  hipError_t dispatch2d_P##lo(int which, int sh, int p, int opk, const OpArgs* a, int threads,                     \
+                              const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,          \
+                              double* out, long long in_cs, long long out_cs, double lambda, size_t lds,           \
+                              const double* tab, const double* jac, double* fac, double* dxi, long long n_elem,    \
+                              int affine, int* status, size_t* bytes, int E, hipStream_t s);
+D2_(1) D2_(6)
+#undef D2_
+
+static hipError_t dispatch2d(int which, int sh, int P, int opk, const OpArgs* a, int threads,
+                             const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in, double* out,
+                             long long in_cs, long long out_cs, double lambda, size_t lds, const double* tab,
+                             const double* jac, double* fac, double* dxi, long long n_elem, int affine, int* status,
+                             size_t* bytes, int E, hipStream_t s) {
+  if (P >= 1 && P <= 5)
+    return dispatch2d_P1(which, sh, P, opk, a, threads, blocks, tiles, ntiles, in, out, in_cs, out_cs, lambda, lds,
+                         tab, jac, fac, dxi, n_elem, affine, status, bytes, E, s);
+  if (P >= 6 && P <= 10)
+    return dispatch2d_P6(which, sh, P, opk, a, threads, blocks, tiles, ntiles, in, out, in_cs, out_cs, lambda, lds,
+                         tab, jac, fac, dxi, n_elem, affine, status, bytes, E, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_block2d(int sh, int P, int opk, const OpArgs& a, int threads, hipStream_t s) {
+  return dispatch2d(0, sh, P, opk, &a, threads, nullptr, nullptr, 0, nullptr, nullptr, 0, 0, 0.0, 0, nullptr, nullptr,
+                    nullptr, nullptr, 0, 0, nullptr, nullptr, a.E, s);
+}
+
+hipError_t launch_mixed2d(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
+                          double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds,
+                          hipStream_t s) {
+  return dispatch2d(1, QUAD, P, opk, nullptr, threads, blocks, tiles, ntiles, in, out, in_cs, out_cs, lambda, lds,
+                    nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, 0, s);
+}
+
+hipError_t launch_geometry2d(int sh, int P, const double* tab, const double* jac, double* fac, double* dxi,
+                             long long n_elem, int affine, int* status, hipStream_t s) {
+  return dispatch2d(2, sh, P, 0, nullptr, 0, nullptr, nullptr, 0, nullptr, nullptr, 0, 0, 0.0, 0, tab, jac, fac, dxi,
+                    n_elem, affine, status, nullptr, 0, s);
+}
+
+size_t lds_bytes_2d(int sh, int P, int E) {
+  size_t b = 0;
+  dispatch2d(3, sh, P, 0, nullptr, 0, nullptr, nullptr, 0, nullptr, nullptr, 0, 0, 0.0, 0, nullptr, nullptr, nullptr,
+             nullptr, 0, 0, nullptr, &b, E, nullptr);
+  return b;
+}
+
 // Advection factors of one block: a_d = jw sum_i b_i d eta_d / d x_i at every
 // point, from the block's factors (jw first of NFAC per point) and d eta/d x
 // (NDXI = 9 per point, row eta_d, column x_i); vel is [3][vstride] with the

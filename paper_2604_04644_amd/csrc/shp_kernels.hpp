@@ -1002,23 +1002,26 @@ struct GeoRegs {
   double v[PPT][NFAC];
 };
 
-// Every slot issues its loads (slots past the tile's last point re-read that
-// point), so the number of loads in flight is a compile-time constant: a wait
-// for data loaded before the prefetch then counts past these loads instead of
-// draining them.
+// Every slot issues its loads, so the number of loads in flight is a
+// compile-time constant: a wait for data loaded before the prefetch then
+// counts past these loads instead of draining them.  The loads go through a
+// buffer resource that spans the tile's factors: a slot past the tile's last
+// point reads out of range, which returns zero without touching memory.
 template <int P, int PPT>
 __device__ __forceinline__ void prefetch_geo(const double* __restrict__ fac, long long e0, int ne, GeoRegs<PPT>& g) {
   constexpr int Q3 = (P + 2) * (P + 2) * (P + 2);
-  const gptr_t base = as_global(fac) + e0 * (long long)(NFAC * Q3);
-  const int last = ne * Q3 - 1;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(fac + e0 * (long long)(NFAC * Q3)), (short)0, ne * (NFAC * Q3 * 8), 0x00020000);
+  const int n = ne * Q3;
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
-    const int t0 = tid() + it * nthr();
-    const int t = t0 < last ? t0 : last;
+    const int t = tid() + it * nthr();
     const int e = t / Q3, pt = t - e * Q3;
-    const gptr_t f = base + e * (NFAC * Q3) + pt;
+    // byte offset of factor 0 of this point; out of range past the tile
+    const int off = t < n ? (e * (NFAC * Q3) + pt) * 8 : ne * (NFAC * Q3 * 8);
 #pragma unroll
-    for (int c = 0; c < NFAC; ++c) g.v[it][c] = __builtin_nontemporal_load(f + c * Q3);
+    for (int c = 0; c < NFAC; ++c)
+      g.v[it][c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off + c * Q3 * 8, 0, 2));
   }
 }
 

@@ -10,7 +10,7 @@
 
 namespace shp {
 
-enum : int { HEX = 0, PRISM = 1, PYR = 2, TET = 3 };
+enum : int { HEX = 0, PRISM = 1, PYR = 2, TET = 3, QUAD = 4, TRI = 5 };
 
 constexpr int imax(int a, int b) { return a > b ? a : b; }
 
@@ -21,6 +21,9 @@ constexpr int num_modes(int sh, int P) {
        : sh == PYR ? (P + 1) * (P + 2) * (2 * P + 3) / 6
                    : (P + 1) * (P + 2) * (P + 3) / 6;
 }
+// number of modes of the 2D shapes: quadrilateral (P+1)^2, triangle (P+1)(P+2)/2
+constexpr int num_modes2(int sh, int P) { return sh == QUAD ? (P + 1) * (P + 1) : (P + 1) * (P + 2) / 2; }
+constexpr bool is_2d(int sh) { return sh == QUAD || sh == TRI; }
 // number of (p,q) columns
 constexpr int num_cols(int sh, int P) { return sh == TET ? (P + 1) * (P + 2) / 2 : (P + 1) * (P + 1); }
 // run length of r in column (p,q)

@@ -485,3 +485,62 @@ void build_ref_weights(int sh, int P, int pts, std::vector<double>& wref) {
 }
 
 }  // namespace shp
+
+namespace shp {
+
+// Reference tables of a 2D shape (quadrilateral, triangle) at order P in the
+// layout of tab_layout2d: points and weights per direction (GLL in eta1 and in
+// the quadrilateral's eta2; Gauss-Jacobi(1,0) or Gauss-Radau-Jacobi(1,0) in
+// the triangle's collapsed eta2), A_p and derivatives in eta1, the eta2
+// functions (A_q, or C_{p,q} at row fam_index(P, p, q)) and derivatives, and
+// the collocation derivative of each direction.
+void build_tables2d(int sh, int P, int pts, std::vector<double>& tab) {
+  const int Q = P + 2, n = P + 1;
+  const int nb2 = (sh == TRI) ? (P + 1) * (P + 2) / 2 : n;
+  const int oz = 0, ow = 2 * Q, oA = 4 * Q, odA = oA + n * Q, oB = odA + n * Q, odB = oB + nb2 * Q, oD = odB + nb2 * Q;
+  tab.assign(oD + 2 * Q * Q, 0.0);
+  double* z = tab.data() + oz;
+  double* w = tab.data() + ow;
+  rule_1d(Q, 0, pts, z, w);
+  rule_1d(Q, sh == TRI ? 1 : 0, pts, z + Q, w + Q);
+  for (int p = 0; p < n; ++p)
+    for (int i = 0; i < Q; ++i) {
+      tab[oA + p * Q + i] = fA(p, z[i]);
+      tab[odA + p * Q + i] = fdA(p, z[i]);
+    }
+  if (sh == TRI) {
+    for (int p = 0; p <= P; ++p)
+      for (int q = 0; q <= P - p; ++q)
+        for (int j = 0; j < Q; ++j) {
+          tab[oB + fam_index(P, p, q) * Q + j] = fC(p, q, z[Q + j]);
+          tab[odB + fam_index(P, p, q) * Q + j] = fdC(p, q, z[Q + j]);
+        }
+  } else {
+    for (int q = 0; q < n; ++q)
+      for (int j = 0; j < Q; ++j) {
+        tab[oB + q * Q + j] = fA(q, z[Q + j]);
+        tab[odB + q * Q + j] = fdA(q, z[Q + j]);
+      }
+  }
+  for (int d = 0; d < 2; ++d) colloc_deriv(Q, z + d * Q, tab.data() + oD + d * Q * Q);
+}
+
+// Quadrature points of a 2D shape in reference coordinates (xi [2][Q^2],
+// component slowest; the triangle's collapse xi1 = (1 + eta1)(1 - eta2)/2 - 1)
+// and the products of the 1D weights.
+void reference_points2d(int sh, int Q, int pts, double* xi, double* wout) {
+  std::vector<double> z(2 * Q), w(2 * Q);
+  rule_1d(Q, 0, pts, z.data(), w.data());
+  rule_1d(Q, sh == TRI ? 1 : 0, pts, z.data() + Q, w.data() + Q);
+  const int Q2 = Q * Q;
+  for (int i = 0; i < Q; ++i)
+    for (int j = 0; j < Q; ++j) {
+      const int pt = i * Q + j;
+      const double e1 = z[i], e2 = z[Q + j];
+      xi[pt] = (sh == TRI) ? 0.5 * (1.0 + e1) * (1.0 - e2) - 1.0 : e1;
+      xi[Q2 + pt] = e2;
+      if (wout) wout[pt] = w[i] * w[Q + j];
+    }
+}
+
+}  // namespace shp

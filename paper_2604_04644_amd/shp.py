@@ -13,7 +13,8 @@ from typing import Sequence
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libshp.so")
 
-SHAPES = {"hex": 0, "prism": 1, "pyr": 2, "tet": 3}
+SHAPES = {"hex": 0, "prism": 1, "pyr": 2, "tet": 3, "quad": 4, "tri": 5}
+SHAPES_2D = ("quad", "tri")
 GEOM = {"affine": 0, "curved": 1, "isoparam": 2}
 POINTS = {"gj": 0, "radau": 1}
 OPS = {"bwd": 0, "iprod": 1, "physderiv": 2, "iprod_deriv": 3, "mass": 4, "laplacian": 5, "helmholtz": 6}
@@ -149,8 +150,9 @@ def quadrature(shape: str, Q: int, pts: str = "gj"):
     """Reference points xi [Q^3, 3] and weights [Q^3] (numpy, host) of point set
     pts ("gj" or "radau" in the collapsed directions)."""
     import numpy as np
-    Q3 = Q ** 3
-    xi = np.empty((3, Q3))
+    dim = 2 if shape in SHAPES_2D else 3
+    Q3 = Q ** dim
+    xi = np.empty((dim, Q3))
     w = np.empty(Q3)
     _check(lib().shp_quadrature(SHAPES[shape], Q, POINTS[pts], xi.ctypes.data, w.ctypes.data))
     return np.ascontiguousarray(xi.T), w
@@ -199,7 +201,8 @@ class Plan:
         self._ws_ptr = (base + 255) // 256 * 256
         _check(lib().shp_plan_bind_workspace(self._h, ctypes.c_void_p(self._ws_ptr), nb.value, _stream(torch)))
         self.n_modes = [num_modes(sh, P) for sh, P, _, _ in self.blocks]
-        self.n_points = [(P + 2) ** 3 for _, P, _, _ in self.blocks]
+        self.dim = 2 if self.blocks[0][0] in SHAPES_2D else 3
+        self.n_points = [(P + 2) ** self.dim for _, P, _, _ in self.blocks]
         if model is not None or os.environ.get("SHP_MODEL_PATH"):
             self.load_model(model)
 
@@ -243,7 +246,10 @@ class Plan:
         t = self._torch
         self.__dict__.pop("_diag", None)
         sh, P, ne, geom = self.blocks[blk]
-        want = {"curved": (ne, 9, (P + 2) ** 3), "affine": (ne, 9), "isoparam": (ne, 3, self.n_modes[blk])}[geom]
+        if self.dim == 2:
+            want = {"curved": (ne, 4, (P + 2) ** 2), "affine": (ne, 4)}[geom]
+        else:
+            want = {"curved": (ne, 9, (P + 2) ** 3), "affine": (ne, 9), "isoparam": (ne, 3, self.n_modes[blk])}[geom]
         if tuple(jac.shape) != want or jac.dtype != t.float64 or not jac.is_cuda or not jac.is_contiguous():
             raise ValueError(f"jac must be a contiguous float64 device tensor of shape {want}")
         _check(lib().shp_plan_set_geometry(self._h, blk, ctypes.c_void_p(jac.data_ptr()), _stream(t)))
@@ -262,9 +268,9 @@ class Plan:
         if blk >= 0:
             ne = self.blocks[blk][2]
             nm, nq = self.n_modes[blk], self.n_points[blk]
-            return {"bwd": (ne, nq), "physderiv": (3, ne, nq)}.get(op, (ne, nm))
+            return {"bwd": (ne, nq), "physderiv": (self.dim, ne, nq)}.get(op, (ne, nm))
         nc, npnt = self.totals()
-        return {"bwd": (npnt,), "physderiv": (3, npnt)}.get(op, (nc,))
+        return {"bwd": (npnt,), "physderiv": (self.dim, npnt)}.get(op, (nc,))
 
     def _in_numel(self, blk: int, op: str):
         if blk >= 0:
@@ -273,8 +279,8 @@ class Plan:
         else:
             nm, nq, ne = None, None, None
             nc, npnt = self.totals()
-            return {"iprod": npnt, "physderiv": npnt, "iprod_deriv": 3 * npnt}.get(op, nc)
-        return {"iprod": ne * nq, "physderiv": ne * nq, "iprod_deriv": 3 * ne * nq}.get(op, ne * nm)
+            return {"iprod": npnt, "physderiv": npnt, "iprod_deriv": self.dim * npnt}.get(op, nc)
+        return {"iprod": ne * nq, "physderiv": ne * nq, "iprod_deriv": self.dim * ne * nq}.get(op, ne * nm)
 
     def apply(self, blk: int, op: str, x, out=None, lam: float = 1.0, strategy: str = "auto"):
         """y = op(x) for block blk (or the whole mesh, blk = -1); strategy

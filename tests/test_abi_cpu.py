@@ -241,3 +241,35 @@ def test_vertex_modes_match_oracle(L, shape):
     modes = O.modes(shape, P)
     for v, (m, x) in enumerate(zip(idx, xi)):
         assert modes[m] == O.VERTEX_MODES[shape][v]
+
+
+@pytest.mark.parametrize("pts", ["gj", "radau"])
+@pytest.mark.parametrize("shape", ["quad", "tri"])
+def test_2d_sizes_and_quadrature(L, shape, pts):
+    """2D mode and point counts, and the library's 2D points and weights
+    against the 2D oracle's (Golub-Welsch)."""
+    from oracle import shp_oracle2d as O2
+    from paper_2604_04644_amd import shp
+    for P in (1, 4, 10):
+        assert shp.num_modes(shape, P) == O2.num_modes(shape, P)
+        assert shp.num_points(shape, P + 2) == (P + 2) ** 2
+    for Q in (3, 6, 12):
+        xi, w = shp.quadrature(shape, Q, pts)
+        eta, wo, _ = O2.quadrature(shape, Q, pts)
+        assert np.abs(xi - O2.collapse(shape, eta)).max() < 2e-15
+        assert np.abs(w - wo).max() < 1e-14 * max(1.0, np.abs(wo).max())
+
+
+def test_2d_plan_rules_without_device(L):
+    """A plan holds 2D or 3D blocks, not both; 2D blocks are not iso-parametric."""
+    from paper_2604_04644_amd import shp
+    h = ctypes.c_void_p()
+    mixed = (shp._BlockDesc * 2)(shp._BlockDesc(4, 2, 4, 10, 1, 0), shp._BlockDesc(0, 2, 4, 10, 1, 0))
+    assert L.shp_plan_create(ctypes.byref(h), ctypes.cast(mixed, ctypes.c_void_p), 2) == -1
+    iso2 = (shp._BlockDesc * 1)(shp._BlockDesc(5, 2, 4, 10, 2, 0))
+    assert L.shp_plan_create(ctypes.byref(h), ctypes.cast(iso2, ctypes.c_void_p), 1) == -2
+    ok = (shp._BlockDesc * 2)(shp._BlockDesc(4, 2, 4, 10, 1, 0), shp._BlockDesc(5, 2, 4, 7, 0, 1))
+    assert L.shp_plan_create(ctypes.byref(h), ctypes.cast(ok, ctypes.c_void_p), 2) == 0
+    nb = ctypes.c_size_t()
+    assert L.shp_plan_workspace_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
+    L.shp_plan_destroy(h)
