@@ -590,13 +590,19 @@ int shp_set_tiling(shp_plan p, int blk, int op, int strategy, int E, int NT, int
   if (!(E == 0 && NT == 0)) {
     if (E < 1 || E > 64) return fail(SHP_ERR_INVALID_ARG, "elements per work-group %d outside [1,64]", E);
     if (NT < 64 || NT > 512 || NT % 64) return fail(SHP_ERR_INVALID_ARG, "threads %d: multiple of 64 in [64,512]", NT);
+    // a prefetch variant whose points do not fit 8 register slots per thread
+    // runs the plain tile, with every table in LDS
+    auto variant_of = [&](const Block& B) {
+      const long long Q3 = (long long)B.d.Q * B.d.Q * B.d.Q;
+      return ((persistent == 1 || persistent == 2) && points_per_thread(E * Q3, NT) == 0) ? 0 : persistent;
+    };
     if (blk >= 0) {
       const Block& B = p->blocks[blk];
-      if (op_lds_bytes(B.d.shape, B.d.P, opk, E, persistent) > LDS_LIMIT)
+      if (op_lds_bytes(B.d.shape, B.d.P, opk, E, variant_of(B)) > LDS_LIMIT)
         return fail(SHP_ERR_UNSUPPORTED, "%d elements exceed the LDS of a work-group", E);
     } else {
       for (const auto& B : p->blocks)
-        if (op_lds_bytes(B.d.shape, B.d.P, opk, E, persistent) > LDS_LIMIT)
+        if (op_lds_bytes(B.d.shape, B.d.P, opk, E, variant_of(B)) > LDS_LIMIT)
           return fail(SHP_ERR_UNSUPPORTED, "%d elements exceed the LDS of a work-group", E);
     }
   }

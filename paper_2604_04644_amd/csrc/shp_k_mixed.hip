@@ -107,8 +107,13 @@ size_t lds_bytes_pyr(int P, int E, int nbuf);
 size_t lds_bytes_tet(int P, int E, int nbuf);
 
 size_t op_lds_bytes(int sh, int P, int opk, int E, int variant) {
+  // nbuf 0: the Laplacian / Helmholtz tile of the prefetch launches (variants
+  // 1 and 2, advection-diffusion-reaction, iso-parametric), whose LDS head
+  // holds only the tables it reads per lane
+  const bool helm = opk == OPK_HELM || opk == OPK_LAP || opk == OPK_ADR;
   const int nbuf = (opk == OPK_HELM_NC || opk == OPK_LAP_NC) ? 5
-                   : (variant >= 3 && (opk == OPK_HELM || opk == OPK_LAP)) ? 3 : 4;
+                   : (variant >= 3 && helm) ? 3
+                   : (helm && (variant == 1 || variant == 2)) ? 0 : 4;
   switch (sh) {
     case HEX: return lds_bytes_hex(P, E, nbuf);
     case PRISM: return lds_bytes_prism(P, E, nbuf);

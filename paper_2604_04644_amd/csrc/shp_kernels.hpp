@@ -118,6 +118,7 @@ struct Tile_ {
   using D = Dims<SH, P>;
   R* tab;
   int* itab;
+  R* b2;       // the tet's eta2 table B2 in LDS (inside tab, or alone in the compact head)
   ctab<R> ct;  // the same tables in global memory, for lane-uniform reads
   R* el;       // E * per
   int per;     // values per element: 4 buffers (U, G0, G1, G2), 3 fused, 5 non-collocated
@@ -143,7 +144,7 @@ __device__ void load_tables_helm(const OpArgs& a, const Tile_<SH, P, R>& T) {
   using D = Dims<SH, P>;
   if (SH == HEX) return;
   if (SH == TET)
-    for (int t = tid(); t < D::L.nb2 * D::Q; t += nthr()) T.tab[D::L.B2 + t] = (R)a.tab[D::L.B2 + t];
+    for (int t = tid(); t < D::L.nb2 * D::Q; t += nthr()) T.b2[t] = (R)a.tab[D::L.B2 + t];
   for (int t = tid(); t < D::NITAB; t += nthr()) T.itab[t] = a.itab[t];
 }
 
@@ -267,7 +268,7 @@ __device__ void bwd_q(const Tile_<SH, P, R>& T, int ne, int fbuf, int gbuf) {
     }
     return;
   }
-  const R* B2 = T.tab + (DER ? D::L.dB2 : D::L.B2);
+  const R* B2 = DER ? T.tab + D::L.dB2 : T.b2;
   // v1 in eta2 (or its derivative) is the family (0,1) row of the tet's table
   const R* V1 = B2 + 1 * Q;
   for (int t = tid(); t < ne * n * Q; t += nthr()) {
@@ -394,7 +395,7 @@ __device__ void ipr_q(const Tile_<SH, P, R>& T, int ne, int gbuf, int fbuf) {
     }
     return;
   }
-  const R* B2 = T.tab + (DER ? D::L.dB2 : D::L.B2);
+  const R* B2 = DER ? T.tab + D::L.dB2 : T.b2;
   const R* V1 = B2 + 1 * Q;
   for (int t = tid(); t < ne * n * Q; t += nthr()) {
     const int e = t / (n * Q);
@@ -902,6 +903,7 @@ __device__ Tile_<SH, P> make_tile(double* smem, const double* gtab) {
   Tile_<SH, P> T;
   T.tab = smem;
   T.itab = reinterpret_cast<int*>(smem + D::NTAB);
+  T.b2 = smem + D::L.B2;
   T.ct = as_const(gtab);
   T.el = smem + D::HEAD;
   T.per = D::PER_ELEM;
@@ -921,6 +923,7 @@ __device__ Tile_<SH, P, R> make_tile_r(void* smem, const R* gtab) {
   Tile_<SH, P, R> T;
   T.tab = reinterpret_cast<R*>(smem);
   T.itab = reinterpret_cast<int*>(T.tab + D::NTAB);
+  T.b2 = T.tab + D::L.B2;
   T.ct = (ctab<R>)(gtab);
   T.el = T.tab + head_r<SH, P, R>();
   T.per = D::PER_ELEM;
@@ -930,6 +933,37 @@ __device__ Tile_<SH, P, R> make_tile_r(void* smem, const R* gtab) {
 template <int SH, int P, typename R>
 constexpr size_t lds_bytes_r(int E) {
   return sizeof(R) * (size_t)(head_r<SH, P, R>() + E * Dims<SH, P>::PER_ELEM);
+}
+
+// Compact LDS head of the Laplacian / Helmholtz tile (helm_tile), in units of
+// R: only the tables that tile reads per lane, the tet's eta2 table B2 and the
+// collapsed shapes' column table (every other table is read at wave-uniform
+// indices through the constant path).  At P = 10 it takes the tet's tile from
+// 88 to 63 KB of LDS, so two work-groups fit a CU's 160 KB instead of one.
+template <int SH, int P, typename R>
+constexpr int head_h() {
+  using D = Dims<SH, P>;
+  constexpr int b2 = SH == TET ? D::L.nb2 * D::Q : 0;
+  constexpr int it = SH == HEX ? 0 : (int)((D::NITAB * sizeof(int) + sizeof(R) - 1) / sizeof(R));
+  return b2 + it;
+}
+
+template <int SH, int P, typename R>
+__device__ Tile_<SH, P, R> make_tile_h(void* smem, const R* gtab) {
+  using D = Dims<SH, P>;
+  Tile_<SH, P, R> T;
+  T.tab = reinterpret_cast<R*>(smem);  // no full table: only b2 and itab are read
+  T.b2 = T.tab;
+  T.itab = reinterpret_cast<int*>(T.tab + (SH == TET ? D::L.nb2 * D::Q : 0));
+  T.ct = (ctab<R>)(gtab);
+  T.el = T.tab + head_h<SH, P, R>();
+  T.per = D::PER_ELEM;
+  return T;
+}
+
+template <int SH, int P, typename R>
+constexpr size_t lds_bytes_h(int E) {
+  return sizeof(R) * (size_t)(head_h<SH, P, R>() + E * Dims<SH, P>::PER_ELEM);
 }
 
 template <int SH, int P>
@@ -1131,7 +1165,7 @@ __global__ void __launch_bounds__(512) k_helm_persist(OpArgs a, int ntiles) {
   extern __shared__ double smem[];
   int ti = blockIdx.x;
   if (ti >= ntiles) return;
-  const Tile_<SH, P> T = make_tile<SH, P>(smem, a.tab);
+  const Tile_<SH, P> T = make_tile_h<SH, P, double>(smem, a.tab);
   auto ne_of = [&](int i) {
     const long long r = a.n_elem - (long long)i * a.E;
     return (int)(r < a.E ? r : a.E);
@@ -1186,10 +1220,10 @@ __global__ void __launch_bounds__(512) k_helm_mixed_persist(const BlockStatic* _
     };
     __syncthreads();
     switch (b.shape) {
-      case HEX: helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem, a.tab), g, tables, next); break;
-      case PRISM: helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem, a.tab), g, tables, next); break;
-      case PYR: helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem, a.tab), g, tables, next); break;
-      default: helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile<TET, P>(smem, a.tab), g, tables, next); break;
+      case HEX: helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_h<HEX, P, double>(smem, a.tab), g, tables, next); break;
+      case PRISM: helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_h<PRISM, P, double>(smem, a.tab), g, tables, next); break;
+      case PYR: helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_h<PYR, P, double>(smem, a.tab), g, tables, next); break;
+      default: helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_h<TET, P, double>(smem, a.tab), g, tables, next); break;
     }
     prev = tl.blk;
     if (nx >= ntiles) break;
@@ -1208,7 +1242,7 @@ __global__ void __launch_bounds__(512) k_helm_block_pf(OpArgs a) {
   const int ne = rem < a.E ? (int)rem : a.E;
   if (ne <= 0) return;
   GeoRegs<PPT> g;
-  helm_tile<SH, P, OP, PPT>(a, e0, ne, make_tile<SH, P>(smem, a.tab), g, true, []() {}, nullptr,
+  helm_tile<SH, P, OP, PPT>(a, e0, ne, make_tile_h<SH, P, double>(smem, a.tab), g, true, []() {}, nullptr,
                             [&]() { prefetch_geo<P, PPT>(a.fac, e0, ne, g); });
 }
 
@@ -1241,16 +1275,16 @@ __global__ void __launch_bounds__(512) k_helm_mixed_pf(const BlockStatic* __rest
   auto pf = [&]() { prefetch_geo<P, PPT>(b.fac, tl.e0, tl.ne, g); };
   switch (b.shape) {
     case HEX:
-      helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<HEX, P, R>(smem, gt), g, true, none, nullptr, pf);
+      helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_h<HEX, P, R>(smem, gt), g, true, none, nullptr, pf);
       break;
     case PRISM:
-      helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<PRISM, P, R>(smem, gt), g, true, none, nullptr, pf);
+      helm_tile<PRISM, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_h<PRISM, P, R>(smem, gt), g, true, none, nullptr, pf);
       break;
     case PYR:
-      helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<PYR, P, R>(smem, gt), g, true, none, nullptr, pf);
+      helm_tile<PYR, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_h<PYR, P, R>(smem, gt), g, true, none, nullptr, pf);
       break;
     default:
-      helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_r<TET, P, R>(smem, gt), g, true, none, nullptr, pf);
+      helm_tile<TET, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_h<TET, P, R>(smem, gt), g, true, none, nullptr, pf);
       break;
   }
 }
@@ -1285,12 +1319,12 @@ __global__ void __launch_bounds__(512) k_adr_mixed_pf(const BlockStatic* __restr
   auto none = []() {};
   auto pf = [&]() { prefetch_geo<P, PPT>(b.fac, tl.e0, tl.ne, g); };
   switch (b.shape) {
-    case HEX: helm_tile<HEX, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem, b.tab), g, true, none, ab, pf); break;
+    case HEX: helm_tile<HEX, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile_h<HEX, P, double>(smem, b.tab), g, true, none, ab, pf); break;
     case PRISM:
-      helm_tile<PRISM, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem, b.tab), g, true, none, ab, pf);
+      helm_tile<PRISM, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile_h<PRISM, P, double>(smem, b.tab), g, true, none, ab, pf);
       break;
-    case PYR: helm_tile<PYR, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem, b.tab), g, true, none, ab, pf); break;
-    default: helm_tile<TET, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile<TET, P>(smem, b.tab), g, true, none, ab, pf); break;
+    case PYR: helm_tile<PYR, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile_h<PYR, P, double>(smem, b.tab), g, true, none, ab, pf); break;
+    default: helm_tile<TET, P, OPK_ADR, PPT>(a, tl.e0, tl.ne, make_tile_h<TET, P, double>(smem, b.tab), g, true, none, ab, pf); break;
   }
 }
 

@@ -127,7 +127,7 @@ __device__ __forceinline__ void iso_helm(const BlockStatic& b, const Tile& tl, c
   a.lambda = lambda;
   a.E = 0;
   a.pad_ = 0;
-  const Tile_<SH, P> T = make_tile<SH, P>(smem, b.tab);
+  const Tile_<SH, P> T = make_tile_h<SH, P, double>(smem, b.tab);
   load_tables_helm<SH, P>(a, T);
   GeoRegs<PPT> g;
   iso_geometry<SH, P, PPT>(b.xco, b.wref, tl.e0, tl.ne, T, g);
@@ -160,7 +160,7 @@ __device__ __forceinline__ void iso_check_tile(const BlockStatic& b, const Tile&
   OpArgs a;
   a.tab = b.tab;
   a.itab = b.itab;
-  const Tile_<SH, P> T = make_tile<SH, P>(smem, b.tab);
+  const Tile_<SH, P> T = make_tile_h<SH, P, double>(smem, b.tab);
   load_tables_helm<SH, P>(a, T);
   GeoRegs<PPT> g;
   if (!iso_geometry<SH, P, PPT>(b.xco, b.wref, tl.e0, tl.ne, T, g)) atomicOr(status, 1);
