@@ -9,11 +9,16 @@ N_Q bytes per element: x, y and 7 FP64 geometric factors per point) over the
 launch's mean duration from HIP events on the launch stream, against the 8 TB/s
 HBM3E peak; cpu_baseline = the FP64 oracle (dense elemental matrices) on a
 bounded sample of the same mesh; mixed_vs_fp64 = the mixed-precision leg on the
-same mesh at P = 6 (FP32 vs FP64 action, and the Helmholtz solve by FP64
-iterative refinement around FP32 PCG vs plain FP64 PCG at the residual
-tolerances of the 1e-6 and 1e-10 error targets).
+same mesh at P = 6 (FP32 vs FP64 action, and the Helmholtz solve by FP32
+Jacobi-PCG with FP64 reliable updates vs plain FP64 PCG at the residual
+tolerances of the 1e-6 and 1e-10 error targets); per_shape_and_order = each
+shape's block and the whole mesh at P = 2, 4, 6, 8, 10; further legs: the
+advection-diffusion-reaction action, iso-parametric against precomputed
+geometry, and a 2D quadrilateral/triangle mesh.  Every timed launch follows a
+1 GiB write that flushes the 256 MiB Infinity Cache.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--no-cpu] [--no-mixed]
+                    [--no-adr] [--no-iso] [--no-2d] [--no-per-shape] [--orders 2,4,...]
 """
 from __future__ import annotations
 

@@ -1,15 +1,19 @@
-// Mixed-precision Helmholtz solve on the broken (elemental) space: iterative
-// refinement with an FP64 residual and update around a Jacobi-preconditioned
-// CG whose actions and vectors are FP32 (or FP64).
+// Mixed-precision Helmholtz solve on the broken (elemental) space: a
+// Jacobi-preconditioned CG whose actions and vectors are FP32 (or FP64), with
+// FP64 reliable updates.
 //
-//   x = x0;  repeat:  r = b - H x                       (FP64 action)
-//                     stop when ||r|| <= tol ||b||
-//                     s = 1 / max|r|;  solve H d = s r   (inner PCG, FP32)
-//                     x += d / s                         (FP64)
+//   r = b - H x0 (FP64), scaled by 1/max|r| into the inner precision
+//   CG on H d = r in the inner precision (FP64 dot products); whenever the
+//   recursive residual has fallen by inner_tol since the last update:
+//       x += d (FP64);  r = b - H x (FP64 action)  -- residual replacement
+//       keep the search direction, or restart it when the true residual
+//       exceeds the recursive one twice over; undo an update that does not
+//       lower the FP64 residual
+//   stop when ||b - H x|| <= tol ||b||
 //
 // The system is block diagonal (one SPD H_e per element, lambda > 0).  CG
 // scalars stay on the device (dot products write them, the update kernels read
-// them); the host reads a residual norm every few inner iterations.
+// them); the host reads a residual norm every few iterations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
