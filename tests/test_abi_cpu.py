@@ -127,7 +127,9 @@ def test_error_paths_without_device(L):
     rc6, h6 = plan([(0, 6, 8, 10, 1), (3, 6, 8, 7, 1)])
     assert rc6 == 0
     assert L.shp_get_tiling(h6, 1, 6, 2, ctypes.byref(E), ctypes.byref(NT), ctypes.byref(pe)) == 0
-    assert (E.value, NT.value, pe.value) == (1, 256, 2)          # tet block at P=6: 40 KiB holds one
+    # tet block at P=6: the Helmholtz tile's LDS head holds only its per-lane
+    # tables, so 40 KiB holds two elements (4 point buffers of 8^3 doubles each)
+    assert (E.value, NT.value, pe.value) == (2, 256, 2)
     assert L.shp_get_tiling(h6, -1, 6, 2, ctypes.byref(E), ctypes.byref(NT), ctypes.byref(pe)) == 0
     assert (E.value, NT.value, pe.value) == (2, 256, 2)          # whole mesh: 64 KiB, two elements
     assert L.shp_plan_destroy(h6) == 0
