@@ -432,18 +432,59 @@ int shp_c0_hex_sizes(int n0, int n1, int n2, int P, int64_t* n_global /* host ou
  * the local copies of each global DOF in ascending local order (CSR). */
 int shp_c0_hex_map(int n0, int n1, int n2, int P, int64_t* l2g, int64_t* row_ptr, int64_t* col);
 
+/* ---- C0 assembly on a conforming tetrahedral mesh ------------------------
+ * The same global problem (Sec. 2.1) on tetrahedra that meet face to face.
+ * verts: host [n_elem][4], the global vertex ids of each tet in its local
+ * order (the reference vertices (-1,-1,-1), (1,-1,-1), (-1,1,-1),
+ * (-1,-1,1)).  Local order rule: vertex 3 has the largest id of the four and
+ * vertex 2 the second largest (then each face's collapse vertex is its
+ * largest id in every element that holds it); vertices 0 and 1 in either
+ * order, e.g. the one that makes the element positively oriented.  A shared
+ * edge or face whose direction differs between two elements gets a sign
+ * change on its odd modes (A_k(-t) = (-1)^k A_k(t)).
+ *
+ * Global numbering: vertices by increasing id; edges by (lower, higher) id,
+ * then mode k = 2..P (the trace A_k running from the lower to the higher id);
+ * faces by their sorted ids, then mode (p, q), p >= 2, q >= 1, p + q <= P,
+ * lexicographic (trace A_p(a) C_{p,q}(b) in the face's collapsed coordinates:
+ * collapse vertex the largest id, a from the smallest to the middle one); then
+ * the element interiors, element by element in local mode order.  Homogeneous
+ * Dirichlet data on the boundary faces (faces of one element): their vertex,
+ * edge and face DOFs are dropped.  A face shared by more than two elements, a
+ * repeated or negative id, or a local order against the rule is
+ * SHP_ERR_INVALID_ARG.
+ *
+ * l2g: host [n_elem N_P]: g for a copy with sign +1, -2 - g for a copy with
+ * sign -1, -1 for a dropped DOF.  row_ptr: host [n_global + 1], col: host
+ * [n_entries]: the copies of each global DOF in ascending local order, col =
+ * i, or -1 - i for a copy with sign -1.  The plan for shp_c0_apply and
+ * shp_c0_helmholtz_solve holds these elements as its only block (shape
+ * SHP_TET, order P, element order as in verts), with geometry continuous
+ * across faces (a global mesh map). */
+int shp_c0_tet_sizes(int64_t n_elem, const int64_t* verts /* host */, int P, int64_t* n_global /* host out */,
+                     int64_t* n_local /* host out */, int64_t* n_entries /* host out */);
+int shp_c0_tet_map(int64_t n_elem, const int64_t* verts /* host */, int P, int64_t* l2g, int64_t* row_ptr,
+                   int64_t* col);
+
 /* Assembled FP64 Helmholtz action yg = A^T H A xg (gather, whole-mesh
  * collocated action, scatter-sum in the fixed CSR order).  l2g, row_ptr, col,
- * xg, yg: device; work: device FP64 scratch of 2 n_local values. */
+ * xg, yg: device, from either map (signs as encoded there); work: device FP64
+ * scratch of 2 n_local values. */
 int shp_c0_apply(shp_plan plan, const int64_t* l2g, const int64_t* row_ptr, const int64_t* col, int64_t n_global,
                  const double* xg /* device */, double* yg /* device */, double lambda, double* work /* device */,
                  void* stream);
 
-/* Assembled vector vg = A^T vl (each global DOF the sum of its local copies
- * in the fixed CSR order), e.g. a right-hand side from shp_apply's inner
- * products.  All arrays device; vl [n_local], vg [n_global]. */
+/* Assembled vector vg = A^T vl (each global DOF the sum of its local copies,
+ * with their signs, in the fixed CSR order), e.g. a right-hand side from
+ * shp_apply's inner products.  All arrays device; vl [n_local], vg [n_global]. */
 int shp_c0_assemble(const int64_t* row_ptr, const int64_t* col, int64_t n_global, const double* vl /* device */,
                     double* vg /* device */, void* stream);
+
+/* Local copies xl = A xg of a global vector (with their signs; 0 for dropped
+ * DOFs): the element coefficients of an assembled solution, for shp_apply.
+ * All arrays device; l2g, xl [n_local]. */
+int shp_c0_gather(const int64_t* l2g, int64_t n_local, const double* xg /* device */, double* xl /* device */,
+                  void* stream);
 
 /* Solve A^T H A x = b with the mixed-precision PCG of shp_helmholtz_solve
  * (inner_prec, tol, max_outer, max_inner, inner_tol and the stats as there);

@@ -175,23 +175,34 @@ __global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, 
 }
 
 // assembled (C0) operator: local copies of global values and the sum of the
-// local copies of each global DOF in a fixed (ascending local) order
+// local copies of each global DOF in a fixed (ascending local) order.  A copy
+// may carry a sign change (an odd edge or face mode traversed against the
+// global orientation): l2g holds g, -2 - g for a negated copy, or -1 for a
+// dropped (Dirichlet) DOF; col holds i, or -1 - i for a negated copy.
 template <typename T>
 __global__ void k_c0_gather(const int64_t* __restrict__ l2g, long long n_local, const T* __restrict__ xg,
                             T* __restrict__ xl) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_local;
        i += (long long)gridDim.x * blockDim.x) {
     const int64_t g = l2g[i];
-    xl[i] = g >= 0 ? xg[g] : (T)0;
+    xl[i] = g >= 0 ? xg[g] : g <= -2 ? -xg[-2 - g] : (T)0;
   }
 }
-template <typename T>
+// SIGNED = false sums the copies without their signs (for the diagonal of
+// A^T H A, where each sign appears squared)
+template <typename T, bool SIGNED = true>
 __global__ void k_c0_scatter(const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ col, long long n_global,
                              const T* __restrict__ yl, T* __restrict__ yg) {
   for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n_global;
        g += (long long)gridDim.x * blockDim.x) {
     T acc = 0;
-    for (int64_t j = row_ptr[g]; j < row_ptr[g + 1]; ++j) acc += yl[col[j]];
+    for (int64_t j = row_ptr[g]; j < row_ptr[g + 1]; ++j) {
+      const int64_t c = col[j];
+      if (c >= 0)
+        acc += yl[c];
+      else
+        acc += SIGNED ? -yl[-1 - c] : yl[-1 - c];
+    }
     yg[g] = acc;
   }
 }
@@ -541,6 +552,13 @@ int shp_c0_assemble(const int64_t* row_ptr, const int64_t* col, int64_t n_global
   return hipGetLastError() == hipSuccess ? SHP_OK : sfail(SHP_ERR_DEVICE, "assembly launch");
 }
 
+int shp_c0_gather(const int64_t* l2g, int64_t n_local, const double* xg, double* xl, void* stream) {
+  if (!l2g || !xg || !xl || n_local < 1) return sfail(SHP_ERR_INVALID_ARG, "null argument");
+  hipLaunchKernelGGL(k_c0_gather<double>, grid_for(n_local), dim3(256), 0, static_cast<hipStream_t>(stream), l2g,
+                     (long long)n_local, xg, xl);
+  return hipGetLastError() == hipSuccess ? SHP_OK : sfail(SHP_ERR_DEVICE, "gather launch");
+}
+
 int shp_c0_solve_workspace_bytes(shp_plan plan, int64_t n_global, size_t* bytes) {
   if (!plan || !bytes || n_global < 1) return sfail(SHP_ERR_INVALID_ARG, "null argument");
   *bytes = c0_carve(nullptr, shp::plan_total_coeff(plan), n_global, nullptr);
@@ -565,8 +583,8 @@ int shp_c0_helmholtz_solve(shp_plan plan, const int64_t* l2g, const int64_t* row
   // Jacobi diagonal of A^T H A: the elemental diagonals summed over the local
   // copies of each global DOF
   if (int r = shp_helmholtz_diag(plan, lambda, c.xl, c.elem_ws, c.elem_bytes, s)) return r;
-  hipLaunchKernelGGL(k_c0_scatter<double>, grid_for(n_global), dim3(256), 0, s, row_ptr, col, (long long)n_global,
-                     c.xl, c.diag);
+  hipLaunchKernelGGL((k_c0_scatter<double, false>), grid_for(n_global), dim3(256), 0, s, row_ptr, col,
+                     (long long)n_global, c.xl, c.diag);
   C0Op op{plan, lambda, l2g, row_ptr, col, n_local, n_global, c.xl, c.yl, c.xlf, c.ylf};
   return solve_with(op, n_global, c.w, c.diag, b, x, inner_prec, tol, max_outer, max_inner, inner_tol, st, s);
 }

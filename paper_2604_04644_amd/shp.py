@@ -58,6 +58,11 @@ _SIGS = {
                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "shp_c0_hex_map": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                        ctypes.c_void_p],
+    "shp_c0_tet_sizes": [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+    "shp_c0_tet_map": [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_void_p],
+    "shp_c0_gather": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "shp_c0_apply": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p],
     "shp_c0_assemble": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
@@ -171,6 +176,23 @@ def vertex_modes(shape: str, P: int):
 
 def _stream(torch):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def c0_tet_map(verts, P: int):
+    """Host call of shp_c0_tet_map: (l2g, row_ptr, col, n_global) as int64
+    numpy arrays for the tetrahedra with vertex ids verts [n_elem][4]."""
+    import numpy as np
+    v = np.ascontiguousarray(verts, dtype=np.int64)
+    if v.ndim != 2 or v.shape[1] != 4:
+        raise ValueError("verts must be [n_elem][4]")
+    ng, nl, nent = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().shp_c0_tet_sizes(len(v), v.ctypes.data, int(P), ctypes.byref(ng), ctypes.byref(nl),
+                                  ctypes.byref(nent)))
+    l2g = np.empty(nl.value, dtype=np.int64)
+    rp = np.empty(ng.value + 1, dtype=np.int64)
+    col = np.empty(max(nent.value, 1), dtype=np.int64)
+    _check(lib().shp_c0_tet_map(len(v), v.ctypes.data, int(P), l2g.ctypes.data, rp.ctypes.data, col.ctypes.data))
+    return l2g, rp, col, ng.value   # col holds max(n_entries, 1) values
 
 
 class Plan:
@@ -415,6 +437,33 @@ class Plan:
         dev = self.device
         return {"n_global": ng.value, "l2g": t.from_numpy(l2g).to(dev), "row_ptr": t.from_numpy(rp).to(dev),
                 "col": t.from_numpy(col).to(dev)}
+
+    def c0_tet_mesh(self, verts):
+        """Local-to-global map of the plan's single tet block on a conforming
+        mesh with vertex ids verts [n_elem][4] (local order rule of
+        shp_c0_tet_map; homogeneous Dirichlet data on the boundary faces);
+        returns a C0 handle dict like c0_hex_grid."""
+        t = self._torch
+        (sh, P, ne, _), = self.blocks
+        if sh != "tet" or ne != len(verts):
+            raise ValueError("the plan must hold the mesh's tetrahedra as its only block")
+        l2g, rp, col, ng = c0_tet_map(verts, P)
+        dev = self.device
+        return {"n_global": ng, "l2g": t.from_numpy(l2g).to(dev), "row_ptr": t.from_numpy(rp).to(dev),
+                "col": t.from_numpy(col).to(dev)}
+
+    def c0_gather(self, c0, xg):
+        """The local coefficients A xg of a global vector (signed copies, 0 on
+        the Dirichlet boundary)."""
+        t = self._torch
+        nc, _ = self.totals()
+        ng = c0["n_global"]
+        if xg.dtype != t.float64 or not xg.is_cuda or not xg.is_contiguous() or xg.numel() != ng:
+            raise ValueError(f"xg must be a contiguous float64 device tensor of {ng} values")
+        out = t.empty(nc, dtype=t.float64, device=xg.device)
+        _check(lib().shp_c0_gather(ctypes.c_void_p(c0["l2g"].data_ptr()), nc, ctypes.c_void_p(xg.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), _stream(t)))
+        return out
 
     def c0_assemble(self, c0, vl):
         """A^T vl for a local vector (all coefficients of the block)."""

@@ -154,6 +154,43 @@ def affine_hex_grid(n: int = 4) -> ElementMaps:
     return ElementMaps("hex", X0, A)
 
 
+
+def conforming_tet_mesh(n: int):
+    """The unit cube in n^3 cubes, each split into the 6 tetrahedra of the
+    Freudenthal (Kuhn) triangulation: the paths (0,0,0) -> e_a -> e_a + e_b ->
+    (1,1,1) over the 6 orders (a, b, c) of the axes.  Neighbouring cubes split
+    their shared faces along the same diagonal, so the mesh is conforming.
+
+    Grid vertex (i, j, k) has id (i (n+1) + j)(n+1) + k.  Along a path the ids
+    increase, so its last vertex has the largest id of the four and its third
+    the second largest: these are each tet's local vertices 3 and 2.  Local
+    vertices 0 and 1 are the path's first two, swapped where needed so that
+    det(V1 - V0, V2 - V0, V3 - V0) > 0 (reference vertices (-1,-1,-1),
+    (1,-1,-1), (-1,1,-1), (-1,-1,1)); about half the tets swap them.
+
+    Returns (ElementMaps of shape 'tet' with x0 = V0 and A = [V1 - V0, V2 - V0,
+    V3 - V0], verts [n_elem][4] int64 in local order)."""
+    h = 1.0 / n
+    I = np.eye(3, dtype=np.int64)
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    ii, jj, kk = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    c0 = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1).astype(np.int64)      # [ncube, 3]
+    gid = lambda g: (g[..., 0] * (n + 1) + g[..., 1]) * (n + 1) + g[..., 2]
+    X0, A, V = [], [], []
+    for a, b, c in perms:
+        path = [c0, c0 + I[a], c0 + I[a] + I[b], c0 + 1]
+        sign = int(round(np.linalg.det(np.stack([I[a], I[b], I[c]]).astype(float))))
+        loc = path if sign > 0 else [path[1], path[0], path[2], path[3]]
+        pos = [x.astype(np.float64) * h for x in loc]
+        X0.append(pos[0])
+        A.append(np.stack([pos[1] - pos[0], pos[2] - pos[0], pos[3] - pos[0]], axis=2))
+        V.append(np.stack([gid(x) for x in loc], axis=1))
+    ne = len(c0) * 6
+    X0 = np.stack(X0, axis=1).reshape(ne, 3)
+    A = np.stack(A, axis=1).reshape(ne, 3, 3)
+    V = np.stack(V, axis=1).reshape(ne, 4)
+    return ElementMaps("tet", X0, A), np.ascontiguousarray(V, dtype=np.int64)
+
 # ---------------------------------------------------------------------------
 # point evaluation
 # ---------------------------------------------------------------------------
