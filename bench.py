@@ -404,19 +404,24 @@ def adr_leg(torch, plan, mesh, x, y, helm_ms: float, steps: int = 20):
     return row
 
 
-def c0_leg(torch, shp, W, n: int = 32, P: int = 4, lam: float = 1.0):
-    """The C0-assembled problem on an n^3 grid of hexahedra curved by the mesh
-    map, homogeneous Dirichlet data: the assembled action (gather, elemental
-    action, scatter-sum) against the elemental action alone, and the assembled
-    solve of -lap u + lambda u = f for u = sin(pi x) sin(pi y) sin(pi z), FP32
-    PCG with FP64 reliable updates against FP64 PCG."""
-    log(f"c0: {n}^3 curved hexahedra, P={P}")
+def c0_leg(torch, shp, W, shape: str = "hex", n: int = 32, P: int = 4, lam: float = 1.0):
+    """The C0-assembled problem on the unit cube in n^3 cubes curved by the
+    mesh map, homogeneous Dirichlet data: hexahedra (one per cube, aligned
+    axes) or the conforming tetrahedral mesh (six per cube; the map carries
+    sign changes of odd edge and face modes).  The assembled action (gather,
+    elemental action, scatter-sum) against the elemental action alone, and the
+    assembled solve of -lap u + lambda u = f for u = sin(pi x) sin(pi y)
+    sin(pi z), FP32 PCG with FP64 reliable updates against FP64 PCG."""
+    log(f"c0: {n}^3 cubes, curved {shape}, P={P}")
     dev = torch.device("cuda")
-    maps = W.affine_hex_grid(n)
-    xi = shp.quadrature("hex", P + 2)[0]
-    plan = shp.Plan([("hex", P, len(maps), "curved")])
+    if shape == "hex":
+        maps = W.affine_hex_grid(n)
+    else:
+        maps, verts = W.conforming_tet_mesh(n)
+    xi = shp.quadrature(shape, P + 2)[0]
+    plan = shp.Plan([(shape, P, len(maps), "curved")])
     plan.set_geometry(0, W.jacobian_torch(maps, xi, True, dev))
-    c0 = plan.c0_hex_grid(n, n, n)
+    c0 = plan.c0_hex_grid(n, n, n) if shape == "hex" else plan.c0_tet_mesh(verts)
     nc, _ = plan.totals()
     ng = c0["n_global"]
     xg = torch.from_numpy(W.coeffs(1, ng, 17)[0]).cuda()
@@ -435,13 +440,12 @@ def c0_leg(torch, shp, W, n: int = 32, P: int = 4, lam: float = 1.0):
         x, st = plan.c0_solve(c0, b, lam=lam, inner=inner, tol=1e-10, check=False)
         torch.cuda.synchronize()
         st["s"] = round(time.perf_counter() - t0, 4)
-        l2g = c0["l2g"]
-        xloc = torch.where(l2g >= 0, x[l2g.clamp(min=0)], torch.zeros((), dtype=x.dtype, device=dev))
-        u = plan.apply(-1, "bwd", xloc.contiguous())
+        u = plan.apply(-1, "bwd", plan.c0_gather(c0, x))
         st["max_err_vs_u"] = float((u - u_exact).abs().max())
         solves[name] = st
         log(f"  c0 solve {name}: {st}")
-    out = {"workload": f"{n}^3 hexahedra curved by the mesh map, P={P}, Dirichlet boundary, lambda={lam}",
+    out = {"workload": f"{n}^3 cubes, {len(maps)} {shape} elements curved by the mesh map, P={P}, "
+                       f"Dirichlet boundary, lambda={lam}",
            "global_dof": int(ng), "local_dof": int(nc),
            "assembled_action_ms": round(t_c0, 5), "elemental_action_ms": round(t_el, 5),
            "assembled_action_GDOF/s_global": round(ng / t_c0 / 1e6, 3), "solve_resid_tol": 1e-10,
@@ -563,7 +567,8 @@ def main():
     ap.add_argument("--no-iso", action="store_true",
                     help="skip the iso-parametric leg (geometry rebuilt in the launch, P = 4 and 6)")
     ap.add_argument("--c0", action="store_true",
-                    help="also run the C0-assembled Helmholtz problem on a 32^3 curved hexahedral grid, P=4")
+                    help="also run the C0-assembled Helmholtz problem, P=4: 32^3 curved hexahedra and the "
+                         "conforming tetrahedral mesh of 16^3 cubes")
     ap.add_argument("--affine", action="store_true",
                     help="also time affine blocks per shape and P=1..4: local matrices on MFMA vs sum-factorisation")
     ap.add_argument("--mixed-ncell", type=int, default=32)
@@ -629,7 +634,7 @@ def main():
             log(f"  {s}: {row}")
     c0 = None
     if a.c0:
-        c0 = c0_leg(torch, shp, W)
+        c0 = {"hex": c0_leg(torch, shp, W, "hex", 32), "tet": c0_leg(torch, shp, W, "tet", 16)}
     affine = None
     if a.affine:
         affine = affine_leg(torch, shp, W, flush)
