@@ -204,7 +204,9 @@ int shp_apply(shp_plan plan, int blk, int op, int strategy, const double* in /* 
 
 /* Contraction precision: SHP_FP64, or SHP_FP32 (FP32 data, tables and
  * accumulation in the sum-factorisation stages; the FP64 geometric factors are
- * applied in FP64 and the results rounded); SHP_BF16 is reserved. */
+ * applied in FP64 and the results rounded, or, once shp_plan_set_fp32_factors
+ * has attached an FP32 copy of the factors, that copy is read and the metric
+ * applied in FP32); SHP_BF16 is reserved (not built). */
 typedef enum { SHP_FP64 = 0, SHP_FP32 = 1, SHP_BF16 = 2 } shp_prec;
 
 /* shp_apply with a contraction precision: in/out are device arrays of doubles
@@ -213,6 +215,21 @@ typedef enum { SHP_FP64 = 0, SHP_FP32 = 1, SHP_BF16 = 2 } shp_prec;
  * one P for all blocks); other combinations return SHP_ERR_UNSUPPORTED. */
 int shp_apply_prec(shp_plan plan, int blk, int op, int strategy, int prec, const void* in /* device */,
                    void* out /* device */, double lambda, void* stream);
+
+/* FP32 copy of the geometric factors for the FP32 actions (the data type of
+ * the paper's fields is a template parameter, float or double; here the
+ * factors of the FP32 inner operator may be float too).  The FP32 action
+ * streams 8 N_P + 56 Q^3 bytes per element with FP64 factors, 8 N_P + 28 Q^3
+ * with this copy.  fac32: device floats [sum over blocks of n_elem 7 Q^3],
+ * blocks concatenated like point buffers, each element's 7 factors as in the
+ * plan ([7][Q^3]); owned by the caller, 4-byte aligned, kept unchanged and
+ * alive while attached.  The call rounds the plan's FP64 factors into it
+ * (every block's geometry must be set; 3D blocks with precomputed factors
+ * only), and shp_plan_set_geometry refreshes its block's part while attached.
+ * From then on SHP_FP32 actions, and so the FP32 inner iterations of
+ * shp_helmholtz_solve, read it; the FP64 actions and residuals are
+ * unchanged.  fac32 = NULL detaches it.  Synchronises stream. */
+int shp_plan_set_fp32_factors(shp_plan plan, float* fac32 /* device */, void* stream);
 
 /* ---- Advection-diffusion-reaction action --------------------------------
  * The collocated form of the Helmholtz action carries over to any operator

@@ -85,6 +85,7 @@ struct shp_plan_s {
   std::vector<Block> blocks;
   size_t ws_bytes = 0;
   char* ws = nullptr;
+  float* fac32 = nullptr;  // caller's FP32 copy of the factors for the FP32 actions, or null
   size_t off_status = 0, off_bstat = 0, off_tiles = 0;
   long long total_elem = 0, total_coeff = 0, total_phys = 0;
   long long max_tiles = 0;  // tile slots reserved per operator
@@ -432,6 +433,7 @@ static int upload_static(shp_plan p, hipStream_t s) {
     bs[b].tabf = reinterpret_cast<const float*>(p->ws + B.off_tabf);
     bs[b].xco = B.iso() ? reinterpret_cast<const double*>(p->ws + B.off_xco) : nullptr;
     bs[b].wref = B.iso() ? reinterpret_cast<const double*>(p->ws + B.off_wref) : nullptr;
+    bs[b].fac32 = (p->fac32 && !B.iso() && !is_2d(B.d.shape)) ? p->fac32 + B.phys_off * NFAC : nullptr;
     bs[b].n_elem = B.d.n_elem;
     bs[b].coeff_off = B.coeff_off;
     bs[b].phys_off = B.phys_off;
@@ -533,7 +535,38 @@ int shp_plan_set_geometry(shp_plan p, int blk, const double* jac, void* stream) 
     return fail(SHP_ERR_BAD_GEOMETRY, "block %d: det(dx/dxi) <= 0 or non-finite factor", blk);
   }
   B.geom_ok = true;
+  if (p->fac32 && !B.iso() && !is_2d(B.d.shape)) {
+    // keep the FP32 copy of the factors current
+    e = launch_round_f32(reinterpret_cast<const double*>(p->ws + B.off_fac), p->fac32 + B.phys_off * NFAC,
+                         B.d.n_elem * NFAC * (long long)B.NQ, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return dev_fail(e, "FP32 factor copy");
+  }
   return SHP_OK;
+}
+
+int shp_plan_set_fp32_factors(shp_plan p, float* fac32, void* stream) {
+  if (int r = check_plan(p)) return r;
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!fac32) {
+    p->fac32 = nullptr;
+    return upload_static(p, s);
+  }
+  if (reinterpret_cast<uintptr_t>(fac32) % 4) return fail(SHP_ERR_INVALID_ARG, "fac32 not 4-byte aligned");
+  for (size_t b = 0; b < p->blocks.size(); ++b) {
+    const Block& B = p->blocks[b];
+    if (B.iso() || is_2d(B.d.shape))
+      return fail(SHP_ERR_UNSUPPORTED, "block %zu: FP32 factors need 3D blocks with precomputed factors", b);
+    if (!B.geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
+  }
+  for (const Block& B : p->blocks) {
+    const hipError_t e = launch_round_f32(reinterpret_cast<const double*>(p->ws + B.off_fac),
+                                          fac32 + B.phys_off * NFAC, B.d.n_elem * NFAC * (long long)B.NQ, s);
+    if (e != hipSuccess) return dev_fail(e, "FP32 factor copy");
+  }
+  p->fac32 = fac32;
+  return upload_static(p, s);
 }
 
 }  // extern "C"
@@ -1030,7 +1063,7 @@ int shp_apply_prec(shp_plan p, int blk, int op, int strategy, int prec, const vo
   const Tile* tiles = reinterpret_cast<const Tile*>(p->ws + p->off_tiles) + (size_t)opk * p->max_tiles;
   hipError_t e = launch_mixed_f32(p->blocks[0].d.P, opk, reinterpret_cast<const BlockStatic*>(p->ws + p->off_bstat),
                                   tiles, p->mixed_ntiles[opk], static_cast<const float*>(in), static_cast<float*>(out),
-                                  lambda, mt.NT, lds, mt.E, s);
+                                  lambda, mt.NT, lds, mt.E, p->fac32 != nullptr, s);
   if (e != hipSuccess) return dev_fail(e, "FP32 launch");
   return SHP_OK;
 }

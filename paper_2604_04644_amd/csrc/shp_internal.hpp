@@ -27,6 +27,7 @@ struct BlockStatic {
   const float* tabf;    // the reference tables rounded to FP32
   const double* xco;    // iso-parametric blocks: coordinate coefficients [n_elem][3][N_P]
   const double* wref;   // iso-parametric blocks: w / prod (1 - eta_d)^alpha_d per point [Q^3]
+  const float* fac32;   // FP32 copy of fac for the FP32 actions, or null
   long long n_elem;
   long long coeff_off;  // element offset * N_P of the block in whole-mesh coefficient buffers
   long long phys_off;   // element offset * N_Q in whole-mesh point buffers
@@ -95,7 +96,9 @@ void build_ref_weights(int sh, int P, int pts, std::vector<double>& wref);
 // FP32 contractions (whole-mesh collocated Laplacian/Helmholtz, prefetch variant)
 size_t lds_bytes_f32(int sh, int P, int E);
 hipError_t launch_mixed_f32(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const float* in,
-                            float* out, double lambda, int threads, size_t lds, int E, hipStream_t s);
+                            float* out, double lambda, int threads, size_t lds, int E, bool fac32, hipStream_t s);
+// round n FP64 values to FP32
+hipError_t launch_round_f32(const double* a, float* b, long long n, hipStream_t s);
 // persistent launches: CUs of the current device, grid = occupancy * CUs, and
 // the register slots per thread of the metric stage (2, 4, 8; 0 = too many)
 int num_cus();

@@ -169,7 +169,7 @@ hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s) {
                                size_t lds, int E, int persist, hipStream_t s);                                      \
   hipError_t launch_mixed_f32_P##p(int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles,               \
                                    const float* in, float* out, double lambda, int threads, size_t lds, int E,       \
-                                   hipStream_t s);                                                                   \
+                                   bool fac32, hipStream_t s);                                                       \
   hipError_t launch_adr_P##p(const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,            \
                              double* out, const double* adv, double lambda, int threads, size_t lds, int E,          \
                              hipStream_t s);                                                                         \
@@ -182,9 +182,10 @@ D_(1) D_(2) D_(3) D_(4) D_(5) D_(6) D_(7) D_(8) D_(9) D_(10)
 #undef D_
 
 hipError_t launch_mixed_f32(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const float* in,
-                            float* out, double lambda, int threads, size_t lds, int E, hipStream_t s) {
+                            float* out, double lambda, int threads, size_t lds, int E, bool fac32, hipStream_t s) {
   switch (P) {
-#define C_(p) case p: return launch_mixed_f32_P##p(opk, blocks, tiles, ntiles, in, out, lambda, threads, lds, E, s);
+#define C_(p) \
+  case p: return launch_mixed_f32_P##p(opk, blocks, tiles, ntiles, in, out, lambda, threads, lds, E, fac32, s);
     C_(1) C_(2) C_(3) C_(4) C_(5) C_(6) C_(7) C_(8) C_(9) C_(10)
 #undef C_
   }
@@ -347,6 +348,18 @@ hipError_t launch_maxdiff(const double* a, const double* b, long long n, unsigne
   if (n <= 0) return hipSuccess;
   const long long nb = std::min<long long>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_maxdiff, dim3((unsigned)nb), dim3(256), 0, s, a, b, n, out);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_round_f32(const double* __restrict__ a, float* __restrict__ b, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+hipError_t launch_round_f32(const double* a, float* b, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long nb = std::min<long long>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_round_f32, dim3((unsigned)nb), dim3(256), 0, s, a, b, n);
   return hipGetLastError();
 }
 

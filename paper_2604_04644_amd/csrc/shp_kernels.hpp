@@ -1031,9 +1031,11 @@ __global__ void __launch_bounds__(512) k_mixed(const BlockStatic* __restrict__ b
 // HBM latency of the dominant byte stream overlaps the sum-factorisation stages.
 // PPT is the number of points a thread owns in the metric stage.
 
-template <int PPT>
+// G: the type the factors are stored in (double, or float for the FP32
+// actions of a plan with an FP32 copy of its factors)
+template <int PPT, typename G = double>
 struct GeoRegs {
-  double v[PPT][NFAC];
+  G v[PPT][NFAC];
 };
 
 // Every slot issues its loads, so the number of loads in flight is a
@@ -1041,21 +1043,26 @@ struct GeoRegs {
 // counts past these loads instead of draining them.  The loads go through a
 // buffer resource that spans the tile's factors: a slot past the tile's last
 // point reads out of range, which returns zero without touching memory.
-template <int P, int PPT>
-__device__ __forceinline__ void prefetch_geo(const double* __restrict__ fac, long long e0, int ne, GeoRegs<PPT>& g) {
+template <int P, int PPT, typename G>
+__device__ __forceinline__ void prefetch_geo(const G* __restrict__ fac, long long e0, int ne, GeoRegs<PPT, G>& g) {
   constexpr int Q3 = (P + 2) * (P + 2) * (P + 2);
+  constexpr int W = (int)sizeof(G);
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(fac + e0 * (long long)(NFAC * Q3)), (short)0, ne * (NFAC * Q3 * 8), 0x00020000);
+      (void*)(fac + e0 * (long long)(NFAC * Q3)), (short)0, ne * (NFAC * Q3 * W), 0x00020000);
   const int n = ne * Q3;
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
     const int t = tid() + it * nthr();
     const int e = t / Q3, pt = t - e * Q3;
     // byte offset of factor 0 of this point; out of range past the tile
-    const int off = t < n ? (e * (NFAC * Q3) + pt) * 8 : ne * (NFAC * Q3 * 8);
+    const int off = t < n ? (e * (NFAC * Q3) + pt) * W : ne * (NFAC * Q3 * W);
 #pragma unroll
-    for (int c = 0; c < NFAC; ++c)
-      g.v[it][c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off + c * Q3 * 8, 0, 2));
+    for (int c = 0; c < NFAC; ++c) {
+      if constexpr (W == 8)
+        g.v[it][c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off + c * Q3 * 8, 0, 2));
+      else
+        g.v[it][c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + c * Q3 * 4, 0, 2));
+    }
   }
 }
 
@@ -1077,8 +1084,8 @@ struct NoPrefetch {
 // pre() runs after the tile's modes are requested and before they are written
 // to LDS: the one-tile-per-work-group launches issue the tile's geometry
 // prefetch there, so the first stages run while the geometry streams in.
-template <int SH, int P, int OP, int PPT, typename Next, typename R, typename Pre = NoPrefetch>
-__device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH, P, R>& T, GeoRegs<PPT>& g,
+template <int SH, int P, int OP, int PPT, typename Next, typename R, typename G, typename Pre = NoPrefetch>
+__device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH, P, R>& T, GeoRegs<PPT, G>& g,
                           bool tables, Next next, const double* __restrict__ adv = nullptr, Pre pre = Pre{}) {
   using D = Dims<SH, P>;
   constexpr int Q3 = D::Q3;
@@ -1120,18 +1127,20 @@ __device__ void helm_tile(const OpArgs& a, long long e0, int ne, const Tile_<SH,
   __syncthreads();
   grad12<SH, P, false>(T, ne);
   __syncthreads();
-  const double lam = (OP == OPK_HELM || OP == OPK_ADR) ? a.lambda : 0.0;
+  // the metric in FP64, or in FP32 when the factors are stored in FP32
+  using MT = G;
+  const MT lam = (OP == OPK_HELM || OP == OPK_ADR) ? (MT)a.lambda : (MT)0;
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
     const int t = tid() + it * nthr();
     if (t < ne * Q3) {
       const int e = t / Q3, pt = t - e * Q3;
       const int lp = lds_pt<SH, P>(pt);
-      const double* gg = g.v[it];
+      const MT* gg = g.v[it];
       R* p0 = T.G(e, 0) + lp;
       R* p1 = T.G(e, 1) + lp;
       R* p2 = T.G(e, 2) + lp;
-      const double d0 = *p0, d1 = *p1, d2 = *p2;
+      const MT d0 = *p0, d1 = *p1, d2 = *p2;
       *p0 = gg[1] * d0 + gg[2] * d1 + gg[3] * d2;
       *p1 = gg[2] * d0 + gg[4] * d1 + gg[5] * d2;
       *p2 = gg[3] * d0 + gg[5] * d1 + gg[6] * d2;
@@ -1246,7 +1255,8 @@ __global__ void __launch_bounds__(512) k_helm_block_pf(OpArgs a) {
                             [&]() { prefetch_geo<P, PPT>(a.fac, e0, ne, g); });
 }
 
-template <int P, int OP, int PPT, typename R = double>
+// G = float reads the plan's FP32 copy of the factors (BlockStatic::fac32)
+template <int P, int OP, int PPT, typename R = double, typename G = double>
 __global__ void __launch_bounds__(512) k_helm_mixed_pf(const BlockStatic* __restrict__ blocks,
                                                        const Tile* __restrict__ tiles, int ntiles, const double* in,
                                                        double* out, double lambda) {
@@ -1255,7 +1265,7 @@ __global__ void __launch_bounds__(512) k_helm_mixed_pf(const BlockStatic* __rest
   if (ti >= ntiles) return;
   const Tile tl = tiles[ti];
   const BlockStatic b = blocks[tl.blk];
-  GeoRegs<PPT> g;
+  GeoRegs<PPT, G> g;
   OpArgs a;
   a.tab = b.tab;
   a.itab = b.itab;
@@ -1271,8 +1281,13 @@ __global__ void __launch_bounds__(512) k_helm_mixed_pf(const BlockStatic* __rest
   a.E = 0;
   a.pad_ = 0;
   const R* gt = sizeof(R) == sizeof(double) ? reinterpret_cast<const R*>(b.tab) : reinterpret_cast<const R*>(b.tabf);
+  const G* gf;
+  if constexpr (sizeof(G) == sizeof(double))
+    gf = b.fac;
+  else
+    gf = b.fac32;
   auto none = []() {};
-  auto pf = [&]() { prefetch_geo<P, PPT>(b.fac, tl.e0, tl.ne, g); };
+  auto pf = [&]() { prefetch_geo<P, PPT>(gf, tl.e0, tl.ne, g); };
   switch (b.shape) {
     case HEX:
       helm_tile<HEX, P, OP, PPT>(a, tl.e0, tl.ne, make_tile_h<HEX, P, R>(smem, gt), g, true, none, nullptr, pf);

@@ -58,6 +58,7 @@ _SIGS = {
                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "shp_c0_hex_map": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                        ctypes.c_void_p],
+    "shp_plan_set_fp32_factors": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "shp_c0_tet_sizes": [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "shp_c0_tet_map": [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
@@ -341,6 +342,21 @@ class Plan:
                                     ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), float(lam),
                                     _stream(t)))
         return out
+
+    def set_fp32_factors(self, enable: bool = True):
+        """Attach (or detach) an FP32 copy of the geometric factors, held by
+        this Plan, for the FP32 actions and the FP32 inner iterations of the
+        solve.  Call after every block's geometry is set."""
+        t = self._torch
+        if not enable:
+            _check(lib().shp_plan_set_fp32_factors(self._h, None, _stream(t)))
+            self._fac32 = None
+            return None
+        _, npnt = self.totals()
+        buf = t.empty(7 * npnt, dtype=t.float32, device=self.device)
+        _check(lib().shp_plan_set_fp32_factors(self._h, ctypes.c_void_p(buf.data_ptr()), _stream(t)))
+        self._fac32 = buf
+        return buf
 
     def advection_factors(self, vel):
         """Advection factors [3 * total points] (float64, device) from the

@@ -90,6 +90,43 @@ def test_fp32_action_vs_oracle(shp, P, op):
     say(f"    worst rel {worst:.2e}")
 
 
+@pytest.mark.parametrize("P", [2, 4, 6])
+def test_fp32_factors_action_vs_oracle(shp, P):
+    """The FP32 action reading an FP32 copy of the factors (metric in FP32)
+    against the FP64 oracle; detaching the copy gives back the FP64-factor
+    FP32 action bit for bit, and set_geometry keeps an attached copy current."""
+    say(f"[fp32] whole-mesh helmholtz with FP32 factors P={P}")
+    mesh, plan = mixed_plan(shp, 4, P)
+    nc, _ = plan.totals()
+    x = W.coeffs(1, nc, 700 + P)[0].astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    y64f = plan.apply_prec("helmholtz", xt, lam=LAM, prec="fp32")
+    plan.set_fp32_factors(True)
+    y = plan.apply_prec("helmholtz", xt, lam=LAM, prec="fp32").cpu().numpy()
+    worst = 0.0
+    for b, s in enumerate(O.SHAPES):
+        co, _ = plan.offsets(b)
+        ne, NP = len(mesh[s]), plan.n_modes[b]
+        xb = x[co:co + ne * NP].reshape(ne, NP).astype(np.float64)
+        ref = O.apply_op("helmholtz", s, P, P + 2, oracle_jac(mesh[s], s, P), xb, lam=LAM)
+        e = rel(y[co:co + ne * NP].reshape(ne, NP).astype(np.float64), ref)
+        worst = max(worst, e)
+        assert e <= FP32_TOL, (s, e)
+    say(f"    worst rel {worst:.2e}")
+    # a new geometry for block 0 (uncurved) reaches the attached copy
+    s0 = O.SHAPES[0]
+    xi, _ = shp.quadrature(s0, P + 2)
+    plan.set_geometry(0, W.jacobian_torch(mesh[s0], xi, False, torch.device("cuda")))
+    y2 = plan.apply_prec("helmholtz", xt, lam=LAM, prec="fp32").cpu().numpy()
+    ne0, NP0 = len(mesh[s0]), plan.n_modes[0]
+    ref0 = O.apply_op("helmholtz", s0, P, P + 2, W.jacobian(mesh[s0], O.reference_points(s0, P + 2), curved=False),
+                      x[:ne0 * NP0].reshape(ne0, NP0).astype(np.float64), lam=LAM)
+    assert rel(y2[:ne0 * NP0].reshape(ne0, NP0).astype(np.float64), ref0) <= FP32_TOL
+    plan.set_geometry(0, W.jacobian_torch(mesh[s0], xi, True, torch.device("cuda")))
+    plan.set_fp32_factors(False)
+    assert torch.equal(plan.apply_prec("helmholtz", xt, lam=LAM, prec="fp32"), y64f)
+
+
 def test_fp32_matches_fp64_entry_point(shp):
     """shp_apply_prec with SHP_FP64 is the FP64 action, bit for bit."""
     say("[fp32] apply_prec fp64 == apply")
@@ -145,16 +182,25 @@ def small_problem(shp):
     return mesh, plan, bflat, xref
 
 
-@pytest.mark.parametrize("inner", ["fp32", "fp64"])
+@pytest.mark.parametrize("inner", ["fp32", "fp32-fac32", "fp64"])
 @pytest.mark.parametrize("target", [1e-6, 1e-10])
 def test_solve_vs_oracle(shp, small_problem, inner, target):
     """Mixed-precision (and plain FP64) PCG with FP64 reliable updates on the
     manufactured problem against the oracle's Cholesky solution of every
-    element."""
+    element; "fp32-fac32": the FP32 iterations read an FP32 copy of the
+    geometric factors (the FP64 residuals still use the FP64 factors)."""
     mesh, plan, b, xref = small_problem
     say(f"[solve] inner={inner} target={target:g}")
     bt = torch.from_numpy(b).cuda()
-    x, st = plan.solve(bt, lam=LAM, inner=inner, tol=RESID_TOL[target], max_outer=60, max_inner=20000)
+    fac32 = inner == "fp32-fac32"
+    if fac32:
+        plan.set_fp32_factors(True)
+    try:
+        x, st = plan.solve(bt, lam=LAM, inner="fp32" if fac32 else inner, tol=RESID_TOL[target], max_outer=60,
+                           max_inner=20000)
+    finally:
+        if fac32:
+            plan.set_fp32_factors(False)
     say(f"    {st}")
     assert st["converged"]
     xs = x.cpu().numpy()
