@@ -170,10 +170,16 @@ Tiling default_tiling(int sh, int P, int opk, size_t lds_budget = 40 * 1024) {
   const bool helm = (opk == OPK_HELM || opk == OPK_LAP || opk == OPK_ADR);
   const long long Q3 = (long long)(P + 2) * (P + 2) * (P + 2);
   if (is_2d(sh)) {
-    // enough elements that a stage has about two line tasks per thread
     const int Q = P + 2;
     int E = 1;
-    while (E < 64 && lds_bytes_2d(sh, P, E + 1) <= 48 * 1024 && (E + 1) * Q <= 2 * t.NT) ++E;
+    if (opk == OPK_HELM || opk == OPK_LAP) {
+      // the fused tile: the tile's points in at most 8 register slots per
+      // thread, and LDS for four work-groups per CU
+      while (E < 64 && (E + 1) * Q * Q <= 8 * t.NT && lds_bytes_2d(sh, P, E + 1, opk, t.NT) <= 40 * 1024) ++E;
+    } else {
+      // enough elements that a stage has about two line tasks per thread
+      while (E < 64 && lds_bytes_2d(sh, P, E + 1) <= 48 * 1024 && (E + 1) * Q <= 2 * t.NT) ++E;
+    }
     t.E = E;
     t.persist = 0;
     return t;
@@ -890,10 +896,10 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
         if (int r = build_tiles(p, opk, s)) return r;
       const Tiling mt = mixed_tiling(p, opk);
       size_t lds = 0;
-      for (const auto& B : p->blocks) lds = std::max(lds, lds_bytes_2d(B.d.shape, B.d.P, mt.E));
+      for (const auto& B : p->blocks) lds = std::max(lds, lds_bytes_2d(B.d.shape, B.d.P, mt.E, opk, mt.NT));
       const Tile* tiles = reinterpret_cast<const Tile*>(p->ws + p->off_tiles) + (size_t)opk * p->max_tiles;
       e = launch_mixed2d(p->blocks[0].d.P, opk, reinterpret_cast<const BlockStatic*>(p->ws + p->off_bstat), tiles,
-                         p->mixed_ntiles[opk], in, out, p->total_phys, p->total_phys, lambda, mt.NT, lds, s);
+                         p->mixed_ntiles[opk], in, out, p->total_phys, p->total_phys, lambda, mt.NT, lds, mt.E, s);
     }
     if (e != hipSuccess) return dev_fail(e, "2D launch");
     return SHP_OK;

@@ -87,10 +87,12 @@ void reference_points2d(int sh, int Q, int pts, double* xi, double* w);
 hipError_t launch_block2d(int sh, int P, int opk, const OpArgs& a, int threads, hipStream_t s);
 hipError_t launch_mixed2d(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
                           double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds,
-                          hipStream_t s);
+                          int E, hipStream_t s);
 hipError_t launch_geometry2d(int sh, int P, const double* tab, const double* jac, double* fac, double* dxi,
                              long long n_elem, int affine, int* status, hipStream_t s);
-size_t lds_bytes_2d(int sh, int P, int E);
+// LDS of the 2D launch of operator opk with E elements on threads threads
+// (the fused Laplacian / Helmholtz tile when its points fit the registers)
+size_t lds_bytes_2d(int sh, int P, int E, int opk = 0 /* the backward transform */, int threads = 256);
 // reference weights w / prod (1 - eta_d)^alpha_d of the tensor points [Q^3]
 void build_ref_weights(int sh, int P, int pts, std::vector<double>& wref);
 // FP32 contractions (whole-mesh collocated Laplacian/Helmholtz, prefetch variant)

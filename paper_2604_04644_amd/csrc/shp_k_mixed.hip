@@ -256,9 +256,9 @@ hipError_t launch_block2d(int sh, int P, int opk, const OpArgs& a, int threads, 
 
 hipError_t launch_mixed2d(int P, int opk, const BlockStatic* blocks, const Tile* tiles, int ntiles, const double* in,
                           double* out, long long in_cs, long long out_cs, double lambda, int threads, size_t lds,
-                          hipStream_t s) {
+                          int E, hipStream_t s) {
   return dispatch2d(1, QUAD, P, opk, nullptr, threads, blocks, tiles, ntiles, in, out, in_cs, out_cs, lambda, lds,
-                    nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, 0, s);
+                    nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, E, s);
 }
 
 hipError_t launch_geometry2d(int sh, int P, const double* tab, const double* jac, double* fac, double* dxi,
@@ -267,10 +267,10 @@ hipError_t launch_geometry2d(int sh, int P, const double* tab, const double* jac
                     n_elem, affine, status, nullptr, 0, s);
 }
 
-size_t lds_bytes_2d(int sh, int P, int E) {
+size_t lds_bytes_2d(int sh, int P, int E, int opk, int threads) {
   size_t b = 0;
-  dispatch2d(3, sh, P, 0, nullptr, 0, nullptr, nullptr, 0, nullptr, nullptr, 0, 0, 0.0, 0, nullptr, nullptr, nullptr,
-             nullptr, 0, 0, nullptr, &b, E, nullptr);
+  dispatch2d(3, sh, P, opk, nullptr, threads, nullptr, nullptr, 0, nullptr, nullptr, 0, 0, 0.0, 0, nullptr, nullptr,
+             nullptr, nullptr, 0, 0, nullptr, &b, E, nullptr);
   return b;
 }
 

@@ -399,6 +399,317 @@ __global__ void __launch_bounds__(512) k_mixed2d(const BlockStatic* __restrict__
     tile2d<TRI, P, OP>(a, tl.e0, tl.ne, make_tile2<TRI, P>(smem));
 }
 
+// ---------------------------------------------------------------------------
+// Collocated Laplacian / Helmholtz tile (eq. helm1 in two dimensions)
+// ---------------------------------------------------------------------------
+// The 2D counterpart of the 3D helm_tile: the tile's 4 factors per point are
+// issued into registers (PPT points per thread) right after its modes reach
+// LDS, so their HBM latency overlaps the backward transform and gradients;
+// tables read at wave-uniform indices (A_p, the collocation derivatives, the
+// quadrilateral's A_q) are scalar loads; only the triangle's eta2 table,
+// whose row depends on the lane's column p, sits in LDS (the compact head).
+// Stages, 7 barriers:
+//   q:   modes -> F[p][j]                    (G0 rows)
+//   p:   F -> U[i][j], and G0 = D_1 U from the same column in registers
+//   j:   G1 = D_2 U                          (rows of U)
+//   metric (registers): (G0, G1) <- g (G0, G1), U <- lambda jw U
+//   jT:  G1 <- D_2^T G1                      (rows)
+//   pT:  per column j, v = U + G1 + D_1^T G0, then A_p^T v -> G1 rows
+//   qT:  G1 rows -> modes, with the triangle's collapsed-vertex adjoint
+
+template <int PPT>
+struct GeoRegs2 {
+  double v[PPT][NFAC2];
+};
+
+// compact LDS head (doubles): the triangle's eta2 table only
+template <int SH, int P>
+constexpr int head2h() {
+  return SH == TRI ? Dims2<SH, P>::L.nb2 * Dims2<SH, P>::Q : 0;
+}
+
+template <int SH, int P>
+constexpr size_t lds_bytes2h(int E) {
+  return sizeof(double) * ((size_t)head2h<SH, P>() + (size_t)E * Dims2<SH, P>::PER);
+}
+
+template <int SH, int P>
+__device__ Tile2<SH, P> make_tile2h(double* smem) {
+  Tile2<SH, P> T;
+  T.tab = smem;  // the triangle's eta2 table (row fam_index(P, p, q))
+  T.el = smem + head2h<SH, P>();
+  return T;
+}
+
+template <int P, int PPT>
+__device__ __forceinline__ void prefetch_geo2(const double* __restrict__ fac, long long e0, int ne, GeoRegs2<PPT>& g) {
+  constexpr int Q2 = (P + 2) * (P + 2);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(fac + e0 * (long long)(NFAC2 * Q2)), (short)0, ne * (NFAC2 * Q2 * 8), 0x00020000);
+  const int n = ne * Q2;
+#pragma unroll
+  for (int it = 0; it < PPT; ++it) {
+    const int t = threadIdx.x + it * blockDim.x;
+    const int e = t / Q2, pt = t - e * Q2;
+    // out of range past the tile: the load returns zero without a memory access
+    const int off = t < n ? (e * (NFAC2 * Q2) + pt) * 8 : ne * (NFAC2 * Q2 * 8);
+#pragma unroll
+    for (int c = 0; c < NFAC2; ++c)
+      g.v[it][c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off + c * Q2 * 8, 0, 2));
+  }
+}
+
+// eta2 row of mode (p, q): wave-uniform table for the quadrilateral, the
+// lane's own LDS row for the triangle
+template <int SH, int P>
+struct Eta2Rows {
+  ctab_t ct;
+  const double* lds;
+};
+
+template <int SH, int P, int OP, int PPT>
+__device__ void helm2d_tile(const OpArgs& a, long long e0, int ne, const Tile2<SH, P>& T) {
+  using D = Dims2<SH, P>;
+  constexpr int Q = D::Q, Q2 = D::Q2, n = D::n, NP = D::NP;
+  const ctab_t ct = as_const(a.tab);
+  if (SH == TRI)
+    for (int t = threadIdx.x; t < D::L.nb2 * Q; t += blockDim.x) T.tab[t] = a.tab[D::L.B2 + t];
+  {
+    const double* src = a.in + e0 * NP;
+    for (int t = threadIdx.x; t < ne * NP; t += blockDim.x) {
+      const int e = t / NP, m = t - e * NP;
+      T.X(e)[m] = src[t];
+    }
+  }
+  GeoRegs2<PPT> g;
+  prefetch_geo2<P, PPT>(a.fac, e0, ne, g);
+  __syncthreads();
+  // q: modes of column p -> F[p][j] in G0
+  for (int t = threadIdx.x; t < ne * n; t += blockDim.x) {
+    const int e = t / n, p = t - e * n;
+    const double* x = T.X(e) + col2_base<SH, P>(p);
+    const int nq = col2_len<SH, P>(p);
+    double acc[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int q = 0; q < n; ++q) {
+      if (q < nq) {
+        const double xv = x[q];
+        if (SH == QUAD) {
+          const ctab_t b = launder(ct) + D::L.B2 + q * Q;
+#pragma unroll
+          for (int j = 0; j < Q; ++j) acc[j] = fma(b[j], xv, acc[j]);
+        } else {
+          const double* b = T.tab + fam_index(P, p, q) * Q;
+#pragma unroll
+          for (int j = 0; j < Q; ++j) acc[j] = fma(b[j], xv, acc[j]);
+        }
+      }
+    }
+    if (SH == TRI && p == 1) {
+      // the collapsed-vertex mode (0,1): v1(eta2) = C_{0,1} on the p = 1 column too
+      const double xv = T.X(e)[1];
+      const ctab_t b = launder(ct) + D::L.B2 + fam_index(P, 0, 1) * Q;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) acc[j] = fma(b[j], xv, acc[j]);
+    }
+    double* F = T.G(e, 0) + p * Q;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) F[j] = acc[j];
+  }
+  __syncthreads();
+  // p: column j of F -> U[.][j], and D_1 of that column into G0[.][j]
+  for (int t = threadIdx.x; t < ne * Q; t += blockDim.x) {
+    const int e = t / Q, j = t - e * Q;
+    double* G0 = T.G(e, 0) + j;
+    double f[n];
+#pragma unroll
+    for (int p = 0; p < n; ++p) f[p] = G0[p * Q];
+    double u[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const ctab_t A1 = launder(ct) + D::L.A1;
+      double s = 0.0;
+#pragma unroll
+      for (int p = 0; p < n; ++p) s = fma(A1[p * Q + i], f[p], s);
+      u[i] = s;
+    }
+    double* U = T.U(e) + j;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) U[i * Q] = u[i];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const ctab_t Dm = launder(ct) + D::L.D;
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) s = fma(Dm[i * Q + l], u[l], s);
+      G0[i * Q] = s;
+    }
+  }
+  __syncthreads();
+  // j: G1 = D_2 U along the rows
+  for (int t = threadIdx.x; t < ne * Q; t += blockDim.x) {
+    const int e = t / Q, i = t - e * Q;
+    const double* U = T.U(e) + i * Q;
+    double v[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) v[l] = U[l];
+    double* G1 = T.G(e, 1) + i * Q;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const ctab_t Dm = launder(ct) + D::L.D + Q * Q;
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) s = fma(Dm[j * Q + l], v[l], s);
+      G1[j] = s;
+    }
+  }
+  __syncthreads();
+  // metric from the registers
+  const double lam = (OP == OPK_HELM) ? a.lambda : 0.0;
+#pragma unroll
+  for (int it = 0; it < PPT; ++it) {
+    const int t = threadIdx.x + it * blockDim.x;
+    if (t < ne * Q2) {
+      const int e = t / Q2, pt = t - e * Q2;
+      const double* f = g.v[it];
+      double* p0 = T.G(e, 0) + pt;
+      double* p1 = T.G(e, 1) + pt;
+      const double d0 = *p0, d1 = *p1;
+      *p0 = f[1] * d0 + f[2] * d1;
+      *p1 = f[2] * d0 + f[3] * d1;
+      if (OP == OPK_HELM) {
+        double* u = T.U(e) + pt;
+        *u = lam * f[0] * (*u);
+      }
+    }
+  }
+  __syncthreads();
+  // jT: G1 <- D_2^T G1 along the rows
+  for (int t = threadIdx.x; t < ne * Q; t += blockDim.x) {
+    const int e = t / Q, i = t - e * Q;
+    double* G1 = T.G(e, 1) + i * Q;
+    double w[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) w[l] = G1[l];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const ctab_t Dm = launder(ct) + D::L.D + Q * Q;
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) s = fma(Dm[l * Q + j], w[l], s);
+      G1[j] = s;
+    }
+  }
+  __syncthreads();
+  // pT: per column j, v = U + G1 + D_1^T G0, then F[p][j] = sum_i A_p(z_i) v_i into G1
+  for (int t = threadIdx.x; t < ne * Q; t += blockDim.x) {
+    const int e = t / Q, j = t - e * Q;
+    const double* G0 = T.G(e, 0) + j;
+    double* G1 = T.G(e, 1) + j;
+    const double* U = T.U(e) + j;
+    double w[Q], v[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) w[l] = G0[l * Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const ctab_t Dm = launder(ct) + D::L.D;
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < Q; ++l) s = fma(Dm[l * Q + i], w[l], s);
+      v[i] = (OP == OPK_HELM ? U[i * Q] : 0.0) + G1[i * Q] + s;
+    }
+#pragma unroll
+    for (int p = 0; p < n; ++p) {
+      const ctab_t A1 = launder(ct) + D::L.A1;
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) s = fma(A1[p * Q + i], v[i], s);
+      G1[p * Q] = s;
+    }
+  }
+  __syncthreads();
+  // qT: G1 rows -> modes in X (the triangle's column 0 also takes the adjoint
+  // of the collapsed-vertex term from row 1)
+  for (int t = threadIdx.x; t < ne * n; t += blockDim.x) {
+    const int e = t / n, p = t - e * n;
+    const double* F = T.G(e, 1) + p * Q;
+    double f[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) f[j] = F[j];
+    const int nq = col2_len<SH, P>(p);
+    double* y = T.X(e) + col2_base<SH, P>(p);
+#pragma unroll
+    for (int q = 0; q < n; ++q) {
+      if (q < nq) {
+        double s = 0.0;
+        if (SH == QUAD) {
+          const ctab_t b = launder(ct) + D::L.B2 + q * Q;
+#pragma unroll
+          for (int j = 0; j < Q; ++j) s = fma(b[j], f[j], s);
+        } else {
+          const double* b = T.tab + fam_index(P, p, q) * Q;
+#pragma unroll
+          for (int j = 0; j < Q; ++j) s = fma(b[j], f[j], s);
+        }
+        y[q] = s;
+      }
+    }
+    if (SH == TRI && p == 0) {
+      const double* F1 = T.G(e, 1) + 1 * Q;
+      const ctab_t v1 = launder(ct) + D::L.B2 + fam_index(P, 0, 1) * Q;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) s = fma(v1[j], F1[j], s);
+      y[1] += s;
+    }
+  }
+  __syncthreads();
+  double* dst = a.out + e0 * NP;
+  for (int t = threadIdx.x; t < ne * NP; t += blockDim.x) {
+    const int e = t / NP, m = t - e * NP;
+    dst[t] = T.X(e)[m];
+  }
+}
+
+template <int SH, int P, int OP, int PPT>
+__global__ void __launch_bounds__(512) k_helm_block2d(OpArgs a) {
+  extern __shared__ double smem[];
+  const long long e0 = (long long)blockIdx.x * a.E;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < a.E ? (int)rem : a.E;
+  if (ne <= 0) return;
+  helm2d_tile<SH, P, OP, PPT>(a, e0, ne, make_tile2h<SH, P>(smem));
+}
+
+template <int P, int OP, int PPT>
+__global__ void __launch_bounds__(512) k_helm_mixed2d(const BlockStatic* __restrict__ blocks,
+                                                      const Tile* __restrict__ tiles, int ntiles, const double* in,
+                                                      double* out, double lambda) {
+  extern __shared__ double smem[];
+  if ((int)blockIdx.x >= ntiles) return;
+  const Tile tl = tiles[blockIdx.x];
+  const BlockStatic b = blocks[tl.blk];
+  OpArgs a;
+  a.tab = b.tab;
+  a.itab = b.itab;
+  a.fac = b.fac;
+  a.dxi = b.dxi;
+  a.n_elem = b.n_elem;
+  a.in = in + b.coeff_off;
+  a.out = out + b.coeff_off;
+  a.in_cs = 0;
+  a.out_cs = 0;
+  a.lambda = lambda;
+  a.E = 0;
+  a.pad_ = 0;
+  if (b.shape == QUAD)
+    helm2d_tile<QUAD, P, OP, PPT>(a, tl.e0, tl.ne, make_tile2h<QUAD, P>(smem));
+  else
+    helm2d_tile<TRI, P, OP, PPT>(a, tl.e0, tl.ne, make_tile2h<TRI, P>(smem));
+}
+
 // 2D geometric factors from d x_i/d xi_j (curved [n][4][Q^2], affine [n][4])
 template <int SH, int P>
 __global__ void __launch_bounds__(256) k_geometry2d(const double* __restrict__ tab, const double* __restrict__ jac,
