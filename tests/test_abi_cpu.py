@@ -275,3 +275,14 @@ def test_2d_plan_rules_without_device(L):
     nb = ctypes.c_size_t()
     assert L.shp_plan_workspace_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
     L.shp_plan_destroy(h)
+    # launch shapes of 2D blocks: elements and threads, the collocated form only
+    p10 = (shp._BlockDesc * 1)(shp._BlockDesc(4, 10, 12, 100, 1, 0))
+    assert L.shp_plan_create(ctypes.byref(h), ctypes.cast(p10, ctypes.c_void_p), 1) == 0
+    assert L.shp_set_tiling(h, 0, 6, 2, 8, 256, 0) == 0
+    assert L.shp_set_tiling(h, -1, 6, 2, 12, 512, 0) == 0
+    assert L.shp_set_tiling(h, 0, 6, 2, 64, 256, 0) == -2           # 64 elements of 12^2 points overflow LDS
+    assert L.shp_set_tiling(h, 0, 6, 1, 8, 256, 0) == -2            # non-collocated strategy
+    E, NT, pe = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert L.shp_get_tiling(h, 0, 6, 2, ctypes.byref(E), ctypes.byref(NT), ctypes.byref(pe)) == 0
+    assert (E.value, NT.value) == (8, 256)
+    L.shp_plan_destroy(h)
