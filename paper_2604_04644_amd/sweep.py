@@ -75,7 +75,7 @@ def main():
     ap.add_argument("--P", default="1-10")
     ap.add_argument("--kmin", type=float, default=14)
     ap.add_argument("--kmax", type=float, default=22)
-    ap.add_argument("--nk", type=int, default=8)
+    ap.add_argument("--nk", type=int, default=12)
     ap.add_argument("--shapes", default=",".join(SHAPES))
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--geom", choices=("curved", "affine"), default="curved")
