@@ -677,40 +677,48 @@ __device__ void grad0T_ipr_p(const Tile_<SH, P, R>& T, int ne, bool with_u) {
     const int rem = t - e * (Q * Q);
     const int j = rem / Q, k = rem - j * Q;
     const int o = j * QP + k;
-    R v[Q], u[Q], w1[Q], w2[Q];
-    {
-      const R* g0 = T.G(e, 0) + o;
-      const R* pu = T.U(e) + o;
-      const R* g1 = T.G(e, 1) + o;
-      const R* g2 = T.G(e, 2) + o;
+    // The eta1 line of G0 is held in registers. Up to Q = 8 the U, G1 and G2
+    // lines are too; above that they are read per output, since holding all
+    // four lines spills registers there. The sums are the same either way.
+    constexpr bool hold = Q <= 8;
+    R v[Q], u[hold ? Q : 1], w1[hold ? Q : 1], w2[hold ? Q : 1];
+    const R* g0 = T.G(e, 0) + o;
+    const R* pu = T.U(e) + o;
+    const R* g1 = T.G(e, 1) + o;
+    const R* g2 = T.G(e, 2) + o;
 #pragma unroll
-      for (int l = 0; l < Q; ++l) {
-        v[l] = g0[l * Q * QP];
+    for (int l = 0; l < Q; ++l) {
+      v[l] = g0[l * Q * QP];
+      if constexpr (hold) {
         if (with_u) u[l] = pu[l * Q * QP];
         w1[l] = g1[l * Q * QP];
         w2[l] = g2[l * Q * QP];
       }
     }
     R s[Q];
-    {
-      const ctab<R> Dm = launder(T.ct) + D::L.D;
+    const ctab<R> Dm0 = hold ? launder(T.ct) + D::L.D : T.ct + D::L.D;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        R d0 = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      // above Q = 8 re-derived per output, so only one column of D is live
+      // in SGPRs (the whole table does not fit)
+      ctab<R> Dm = Dm0;
+      if constexpr (!hold) Dm = launder(T.ct) + D::L.D;
+      R d0 = 0.0;
 #pragma unroll
-        for (int l = 0; l < Q; ++l) d0 = fma(Dm[l * Q + i], v[l], d0);
-        R a = 0.0;
-        if (with_u) a += u[i];
-        a += d0;
-        a += w1[i];
-        a += w2[i];
-        s[i] = a;
-      }
+      for (int l = 0; l < Q; ++l) d0 = fma(Dm[l * Q + i], v[l], d0);
+      R a = 0.0;
+      if (with_u) a += hold ? u[hold ? i : 0] : pu[i * Q * QP];
+      a += d0;
+      a += hold ? w1[hold ? i : 0] : g1[i * Q * QP];
+      a += hold ? w2[hold ? i : 0] : g2[i * Q * QP];
+      s[i] = a;
     }
-    const ctab<R> A1 = launder(T.ct) + D::L.A1;
+    const ctab<R> A10 = hold ? launder(T.ct) + D::L.A1 : T.ct + D::L.A1;
     R* G = T.U(e) + o;
 #pragma unroll
     for (int p = 0; p < n; ++p) {
+      ctab<R> A1 = A10;
+      if constexpr (!hold) A1 = launder(T.ct) + D::L.A1;
       R a = 0.0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) a = fma(A1[p * Q + i], s[i], a);
