@@ -148,6 +148,7 @@ def flops_per_elem(shape: str, P: int) -> int:
 
 
 FP64_PEAK_TFS = 78.6
+BF16_PEAK_TFS = 2500.0   # dense BF16 MFMA
 
 
 def order_table(torch, shp, W, flush, ncell: int = 32, Ps=(2, 4, 6, 8, 10), steps: int = 20):
@@ -276,7 +277,8 @@ def affine_leg(torch, shp, W, flush=None, dof: float = 4e6, Ps=(1, 2, 3, 4)):
     """Affine single-shape blocks of about 4M DOF (as in the per-shape order sweep): the FP64
     Helmholtz action with the local-matrix strategy (7 reference matrices on
     FP64 MFMA, 7 coefficients per element) against the collocated
-    sum-factorisation (per-point factors), GDOF/s from the median of 20
+    sum-factorisation (per-point factors), and the local matrices in split
+    BF16 (three and two parts, FP32 vectors); GDOF/s from the median of 20
     launches, each after a cache flush (these batches fit in the 256 MiB
     Infinity Cache)."""
     out = {}
@@ -289,16 +291,109 @@ def affine_leg(torch, shp, W, flush=None, dof: float = 4e6, Ps=(1, 2, 3, 4)):
             plan.set_geometry(0, torch.from_numpy(W.affine_jacobian(maps)).cuda())
             x = torch.from_numpy(W.coeffs(ne, nm, W.seed_sweep(P))).cuda()
             y = torch.empty_like(x)
+            x32, y32 = x.float(), torch.empty(x.shape, dtype=torch.float32, device=x.device)
             row = {"n_elem": ne}
             for st in ("localmat", "sumfac_coll"):
                 _, _, med = time_launches(torch, lambda: plan.apply(0, "helmholtz", x, out=y, strategy=st), 20, 3,
                                           flush=flush)
                 row[st] = round(ne * nm / (med * 1e-3) / 1e9, 2)
             row["localmat_speedup"] = round(row["localmat"] / row["sumfac_coll"], 3)
+            for pr in ("bf16", "bf16x3"):
+                _, _, med = time_launches(torch, lambda: plan.apply_prec("helmholtz", x32, out=y32, prec=pr, blk=0),
+                                          20, 3, flush=flush)
+                row[f"localmat_{pr}"] = round(ne * nm / (med * 1e-3) / 1e9, 2)
+                ex = (ne + 15) // 16 * bf16_mfma_flops(s, P, 3 if pr == "bf16" else 2)
+                row[f"localmat_{pr}_mfma_frac"] = round(ex / (med * 1e-3) / 1e12 / BF16_PEAK_TFS, 4)
             out[f"{s}_P{P}"] = row
             log(f"  affine {s} P={P}: {row}")
-            del plan, x, y
+            del plan, x, y, x32, y32
     return out
+
+
+def bf16_mfma_flops(shape: str, P: int, nparts: int) -> int:
+    """Executed BF16 MFMA flops per 16 elements of the split-BF16 affine
+    Helmholtz action: K = 7 N_P (N_P padded to 8) in steps of 32, output rows
+    in blocks of 16, nparts (nparts + 1) / 2 part products, 2 16 16 32 flops
+    per v_mfma_f32_16x16x32_bf16."""
+    nm = {"hex": (P + 1) ** 3, "prism": (P + 1) ** 2 * (P + 2) // 2, "pyr": (P + 1) * (P + 2) * (2 * P + 3) // 6,
+          "tet": (P + 1) * (P + 2) * (P + 3) // 6}[shape]
+    npp = (nm + 7) // 8 * 8
+    ks, mb = (7 * npp + 31) // 32, (nm + 15) // 16
+    return ks * mb * (nparts * (nparts + 1) // 2) * 2 * 16 * 16 * 32
+
+
+def bf16_leg(torch, shp, W, flush, ncell: int = 32, P: int = 4, lam: float = 1.0, steps: int = 20):
+    """Split-BF16 MFMA contractions on the mixed mesh made affine (each element
+    its affine map, no curvature), P = 4: the Helmholtz action as FP64
+    collocated sum-factorisation, FP64 local matrices (FP64 MFMA), FP32
+    collocated sum-factorisation, and split-BF16 local matrices with three
+    parts (six products, "bf16") and two parts (three products, "bf16x3"),
+    HIP-event medians after a cache flush; then the Jacobi-PCG with FP64
+    reliable updates to the error targets 1e-6 and 1e-10 with each inner
+    precision (wall time per solve)."""
+    log(f"bf16: affine mesh ncell={ncell} P={P}")
+    mesh = W.quadrant_mesh(ncell)
+    plan = shp.Plan([(s, P, len(mesh[s]), "affine") for s in SHAPES])
+    for b, s in enumerate(SHAPES):
+        plan.set_geometry(b, torch.from_numpy(np.ascontiguousarray(W.affine_jacobian(mesh[s]))).cuda())
+    nc, _ = plan.totals()
+    x64 = torch.from_numpy(np.concatenate([W.coeffs(len(mesh[s]), plan.n_modes[b], W.SEED_MIXED[s]).ravel()
+                                           for b, s in enumerate(SHAPES)])).cuda()
+    x32 = x64.float()
+    y64, y32 = torch.empty_like(x64), torch.empty_like(x32)
+    nel = sum(len(mesh[s]) for s in SHAPES)
+    useful = sum(len(mesh[s]) * 14 * plan.n_modes[b] ** 2 for b, s in enumerate(SHAPES))
+    action = {}
+    ref = plan.apply(-1, "helmholtz", x64, lam=lam, strategy="sumfac_coll")
+    for name, fn, out in (
+            ("fp64_sumfac", lambda: plan.apply(-1, "helmholtz", x64, out=y64, lam=lam, strategy="sumfac_coll"), y64),
+            ("fp64_localmat", lambda: plan.apply(-1, "helmholtz", x64, out=y64, lam=lam, strategy="localmat"), y64),
+            ("fp32_sumfac", lambda: plan.apply_prec("helmholtz", x32, out=y32, lam=lam, prec="fp32"), y32),
+            ("bf16", lambda: plan.apply_prec("helmholtz", x32, out=y32, lam=lam, prec="bf16"), y32),
+            ("bf16x3", lambda: plan.apply_prec("helmholtz", x32, out=y32, lam=lam, prec="bf16x3"), y32)):
+        _, _, med = time_launches(torch, fn, steps, 3, flush=flush)
+        dev = float((out.double() - ref).abs().max() / ref.abs().max())
+        row = {"ms": round(med, 5), "GDOF/s": round(nc / (med * 1e-3) / 1e9, 3), "maxrel_vs_fp64": dev}
+        if name.startswith("bf16") or name == "fp64_localmat":
+            row["useful_TFLOP/s"] = round(useful / (med * 1e-3) / 1e12, 2)
+        if name.startswith("bf16"):
+            parts = 3 if name == "bf16" else 2
+            ex = sum((len(mesh[s]) + 15) // 16 * bf16_mfma_flops(s, P, parts) for s in SHAPES)
+            row["mfma_TFLOP/s"] = round(ex / (med * 1e-3) / 1e12, 1)
+            row["mfma_frac"] = round(ex / (med * 1e-3) / 1e12 / BF16_PEAK_TFS, 4)
+            row["hbm_frac"] = round((nc * 8 + nel * 56) / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        action[name] = row
+        log(f"  action {name}: {row}")
+    del x32, y32, y64, ref
+    f = torch.cat([W.manufactured_u_torch(mesh[s], shp.quadrature(s, P + 2)[0], torch.device("cuda"),
+                                          amp=0.0).reshape(-1) for s in SHAPES]) * (lam + 3 * np.pi ** 2)
+    b = plan.apply(-1, "iprod", f)
+    del f
+    plan.helmholtz_diag(lam)
+    solves = {}
+    for target, tol in ((1e-6, 1e-9), (1e-10, 2e-11)):
+        row = {}
+        sols = {}
+        for inner in ("fp64", "fp32", "bf16", "bf16x3"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xs, st = plan.solve(b, lam=lam, tol=tol, check=False, inner=inner, max_outer=100, max_inner=30000)
+            torch.cuda.synchronize()
+            st["s"] = round(time.perf_counter() - t0, 4)
+            row[inner] = st
+            sols[inner] = xs
+            log(f"  solve tol={tol:g} {inner}: {st}")
+        for inner in ("fp32", "bf16", "bf16x3"):
+            row[f"speedup_{inner}"] = round(row["fp64"]["s"] / row[inner]["s"], 3)
+            row[f"{inner}_vs_fp64_rel2"] = float((sols[inner] - sols["fp64"]).norm() / sols["fp64"].norm())
+        row["resid_tol"] = tol
+        solves[f"err_target_{target:g}"] = row
+    del plan, x64, b
+    return {"workload": f"mixed-element mesh {ncell}^3 cells, affine, P={P}, Q={P + 2}, lambda={lam}",
+            "dof": int(nc), "action": action, "solve": solves,
+            "note": "useful flops 14 N_P^2 per element (7 matrix-vector products); mfma flops as executed "
+                    "(padding and part products included) against the dense BF16 peak; hbm_frac from 8 N_P + 56 "
+                    "bytes per element (FP32 x and y, FP64 coefficients); solve wall time per solve"}
 
 
 def iso_flops_per_elem(shape: str, P: int) -> int:
@@ -578,6 +673,8 @@ def main():
                     help="also time collocated vs non-collocated Helmholtz per shape (block launches)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg (P=6 mesh)")
     ap.add_argument("--no-adr", action="store_true", help="skip the advection-diffusion-reaction action")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the split-BF16 leg (affine mesh, P=4: actions and solves per inner precision)")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D quadrilateral/triangle leg")
     ap.add_argument("--no-iso", action="store_true",
                     help="skip the iso-parametric leg (geometry rebuilt in the launch, P = 4 and 6)")
@@ -669,6 +766,12 @@ def main():
         iso = iso_leg(torch, shp, W, flush, a.ncell)
     del flush
     torch.cuda.empty_cache()
+    bf16 = None
+    if not a.no_bf16:
+        flush = flush_buffer(torch)
+        bf16 = bf16_leg(torch, shp, W, flush, a.ncell)
+        del flush
+        torch.cuda.empty_cache()
     mixed = None
     if not a.no_mixed:
         mixed = mixed_precision_leg(torch, shp, W, a.mixed_ncell)
@@ -717,6 +820,8 @@ def main():
         out["adr_action"] = adr
     if iso is not None:
         out["isoparametric_vs_precomputed"] = iso
+    if bf16 is not None:
+        out["bf16_split_affine"] = bf16
     if two_d is not None:
         out["quad_tri_2d"] = two_d
     print(json.dumps(out), flush=True)

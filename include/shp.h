@@ -206,13 +206,25 @@ int shp_apply(shp_plan plan, int blk, int op, int strategy, const double* in /* 
  * accumulation in the sum-factorisation stages; the FP64 geometric factors are
  * applied in FP64 and the results rounded, or, once shp_plan_set_fp32_factors
  * has attached an FP32 copy of the factors, that copy is read and the metric
- * applied in FP32); SHP_BF16 is reserved (not built). */
-typedef enum { SHP_FP64 = 0, SHP_FP32 = 1, SHP_BF16 = 2 } shp_prec;
+ * applied in FP32), or split BF16 on the BF16 matrix cores with FP32
+ * accumulation (the paper's fields take float or double, App. A.2; BF16 is
+ * this library's addition): every operand is a sum of bfloat16 parts, each
+ * the bfloat16 rounding of what the previous parts leave, and a product keeps
+ * the part products of order below the part count:
+ *   SHP_BF16    three parts, six products per product (about 2^-24 of |a||b|);
+ *   SHP_BF16X3  two parts, three products (about 2^-16 of |a||b|). */
+typedef enum { SHP_FP64 = 0, SHP_FP32 = 1, SHP_BF16 = 2, SHP_BF16X3 = 3 } shp_prec;
 
 /* shp_apply with a contraction precision: in/out are device arrays of doubles
- * (SHP_FP64) or floats (SHP_FP32) in the same layouts.  SHP_FP32 covers the
+ * (SHP_FP64) or floats (the others) in the same layouts.  SHP_FP32 covers the
  * collocated Laplacian and Helmholtz actions as a whole-mesh launch (blk = -1,
- * one P for all blocks); other combinations return SHP_ERR_UNSUPPORTED. */
+ * one P for all blocks).  SHP_BF16 and SHP_BF16X3 cover the mass, Laplacian
+ * and Helmholtz actions of affine 3D blocks with P <= 4 in the local-matrix
+ * form (strategy SHP_AUTO or SHP_LOCALMAT; Sec. 3.3.1): y_e = sum_k c_{e,k}
+ * A_k x_e as one contraction over the 7 reference matrices, with B operand
+ * c_{e,k} x_e rounded to FP32 before the split; one block (blk >= 0, its own
+ * buffers) or every block (blk = -1, whole-mesh buffers, one launch per
+ * block).  Other combinations return SHP_ERR_UNSUPPORTED. */
 int shp_apply_prec(shp_plan plan, int blk, int op, int strategy, int prec, const void* in /* device */,
                    void* out /* device */, double lambda, void* stream);
 
@@ -276,8 +288,10 @@ int shp_helmholtz_diag(shp_plan plan, double lambda, double* diag /* device out 
                        size_t ws_bytes, void* stream);
 
 /* Mixed-precision solve: a Jacobi-preconditioned conjugate-gradient iteration
- * whose operator actions, vectors and updates run in inner_prec (SHP_FP32
- * through shp_apply_prec, or SHP_FP64) with FP64 dot products, refined in FP64
+ * whose operator actions, vectors and updates run in inner_prec (SHP_FP64;
+ * SHP_FP32 through shp_apply_prec's collocated action; SHP_BF16 or SHP_BF16X3
+ * through its split-BF16 affine local matrices, FP32 vectors) with FP64 dot
+ * products, refined in FP64
  * by reliable updates: whenever the recursive residual has fallen by the factor
  * inner_tol since the last update (or predicts the tolerance), the correction
  * accumulated in inner_prec is added to x in FP64 and the residual is replaced
@@ -298,8 +312,8 @@ int shp_helmholtz_diag(shp_plan plan, double lambda, double* diag /* device out 
  * max_outer updates or max_inner iterations in all (convergence is tested
  * every 10 iterations), or on error.  Returns SHP_ERR_NOT_CONVERGED (stats
  * filled in) when the tolerance is not reached, SHP_ERR_INVALID_ARG for b = 0,
- * SHP_ERR_UNSUPPORTED for SHP_BF16 or an FP32 request on a plan with more than
- * one P. */
+ * SHP_ERR_UNSUPPORTED for an FP32 request on a plan with more than one P or a
+ * BF16 request on a plan with a block that is not affine with P <= 4. */
 typedef struct {
   int outer_iters;     /* reliable updates (FP64 residual replacements) taken */
   int inner_iters;     /* CG iterations in all */

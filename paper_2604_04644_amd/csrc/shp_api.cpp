@@ -59,6 +59,8 @@ struct Block {
   std::vector<double> lm;  // [B; d_d B] for the local-matrix strategy (P <= 4)
   std::vector<double> am;  // affine blocks: 7 reference matrices, MFMA fragment order
   size_t off_am = 0, off_coef = 0;
+  std::vector<uint16_t> am16;  // the same as BF16 parts, BF16 MFMA fragment order
+  size_t off_am16 = 0;
   std::vector<float> tabf; // the reference tables rounded to FP32
   std::vector<double> dtab; // sum-factorised Helmholtz diagonal: 1D factor tables
   std::vector<int> ditab;   //   and their pair and mode indices
@@ -343,7 +345,11 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     if (B.d.P <= LOCALMAT_MAX_P && !B.iso()) {
       int q3p, kp;
       build_localmat(B.d.shape, B.d.P, B.d.pts, B.lm, q3p, kp);
-      if (B.d.geom == SHP_AFFINE) build_affine_mats(B.d.shape, B.d.P, B.d.pts, B.am, kp);
+      if (B.d.geom == SHP_AFFINE) {
+        build_affine_mats(B.d.shape, B.d.P, B.d.pts, B.am, kp);
+        int npp, ks, mb;
+        build_affine_mats_bf16(B.d.shape, B.d.P, B.d.pts, B.am16, npp, ks, mb);
+      }
     }
     B.coeff_off = cofs;
     B.phys_off = pofs;
@@ -373,6 +379,8 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     off = align_up(off + sizeof(float) * B.tab.size());
     B.off_am = off;
     off = align_up(off + sizeof(double) * B.am.size());
+    B.off_am16 = off;
+    off = align_up(off + sizeof(uint16_t) * B.am16.size());
     B.off_dtab = off;
     off = align_up(off + sizeof(double) * B.dtab.size());
     B.off_ditab = off;
@@ -470,6 +478,9 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
       e = hipMemcpyAsync(p->ws + B.off_lm, B.lm.data(), sizeof(double) * B.lm.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.am.empty())
       e = hipMemcpyAsync(p->ws + B.off_am, B.am.data(), sizeof(double) * B.am.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !B.am16.empty())
+      e = hipMemcpyAsync(p->ws + B.off_am16, B.am16.data(), sizeof(uint16_t) * B.am16.size(), hipMemcpyHostToDevice,
+                         s);
     if (e == hipSuccess && B.iso())
       e = hipMemcpyAsync(p->ws + B.off_wref, B.wref.data(), sizeof(double) * B.wref.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.dtab.empty())
@@ -604,6 +615,11 @@ int plan_check_solve(shp_plan_s* p, int inner_prec) {
     if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %zu: geometry not set", b);
   if (inner_prec == SHP_FP32 && !p->uniform_P)
     return fail(SHP_ERR_UNSUPPORTED, "FP32 whole-mesh launch needs one P for all blocks");
+  if (inner_prec == SHP_BF16 || inner_prec == SHP_BF16X3)
+    for (size_t b = 0; b < p->blocks.size(); ++b)
+      if (p->blocks[b].am16.empty())
+        return fail(SHP_ERR_UNSUPPORTED, "block %zu: BF16 inner actions need affine blocks with P <= %d", b,
+                    LOCALMAT_MAX_P);
   return SHP_OK;
 }
 
@@ -1044,12 +1060,45 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
 }
 
 
+// split-BF16 affine local-matrix actions of one block or of every block
+static int apply_bf16(shp_plan p, int blk, int op, int strategy, int prec, const void* in, void* out, double lambda,
+                      void* stream) {
+  if (op != SHP_OP_MASS && op != SHP_OP_LAPLACIAN && op != SHP_OP_HELMHOLTZ)
+    return fail(SHP_ERR_UNSUPPORTED, "BF16 contractions cover the mass, Laplacian and Helmholtz actions");
+  if (strategy != SHP_AUTO && strategy != SHP_LOCALMAT)
+    return fail(SHP_ERR_UNSUPPORTED, "BF16 contractions use the affine local matrices (SHP_LOCALMAT)");
+  if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
+  if (!in || !out) return fail(SHP_ERR_INVALID_ARG, "null in/out");
+  if (!std::isfinite(lambda)) return fail(SHP_ERR_INVALID_ARG, "lambda not finite");
+  const int b0 = blk >= 0 ? blk : 0, b1 = blk >= 0 ? blk + 1 : (int)p->blocks.size();
+  for (int b = b0; b < b1; ++b)
+    if (p->blocks[b].am16.empty())
+      return fail(SHP_ERR_UNSUPPORTED, "block %d: BF16 contractions need an affine 3D block with P <= %d", b,
+                  LOCALMAT_MAX_P);
+  if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
+  for (int b = b0; b < b1; ++b)
+    if (!p->blocks[b].geom_ok) return fail(SHP_ERR_STATE, "block %d: geometry not set", b);
+  const int opk = op == SHP_OP_MASS ? OPK_MASS_LM : op == SHP_OP_LAPLACIAN ? OPK_LAP_LM : OPK_HELM_LM;
+  const int nparts = prec == SHP_BF16 ? 3 : 2;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int b = b0; b < b1; ++b) {
+    const Block& B = p->blocks[b];
+    const long long off = blk >= 0 ? 0 : B.coeff_off;
+    hipError_t e = launch_localmat_affine_bf16(
+        B.d.shape, B.d.P, opk, nparts, reinterpret_cast<const bf16_frag*>(p->ws + B.off_am16),
+        reinterpret_cast<const double*>(p->ws + B.off_coef), static_cast<const float*>(in) + off,
+        static_cast<float*>(out) + off, B.d.n_elem, lambda, s);
+    if (e != hipSuccess) return dev_fail(e, "BF16 local-matrix launch");
+  }
+  return SHP_OK;
+}
+
 int shp_apply_prec(shp_plan p, int blk, int op, int strategy, int prec, const void* in, void* out, double lambda,
                    void* stream) {
   if (int r = check_plan(p)) return r;
   if (prec == SHP_FP64)
     return shp_apply(p, blk, op, strategy, static_cast<const double*>(in), static_cast<double*>(out), lambda, stream);
-  if (prec == SHP_BF16) return fail(SHP_ERR_UNSUPPORTED, "BF16 contractions are not built");
+  if (prec == SHP_BF16 || prec == SHP_BF16X3) return apply_bf16(p, blk, op, strategy, prec, in, out, lambda, stream);
   if (prec != SHP_FP32) return fail(SHP_ERR_INVALID_ARG, "bad precision %d", prec);
   if (op != SHP_OP_HELMHOLTZ && op != SHP_OP_LAPLACIAN)
     return fail(SHP_ERR_UNSUPPORTED, "FP32 contractions cover the Laplacian and Helmholtz actions");

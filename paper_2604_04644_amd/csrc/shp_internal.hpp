@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 #include <vector>
 
 #include "shp_layout.hpp"
@@ -55,6 +56,22 @@ constexpr int LOCALMAT_MAX_P = 4;  // dense reference matrices only at low order
 // (|J|, |J| K00, |J| K01, |J| K02, |J| K11, |J| K12, |J| K22), K = J^-1 J^-T
 void build_affine_mats(int sh, int P, int pts, std::vector<double>& acat, int& Kp);
 constexpr int NAFF = 7;
+// the same matrices as sums of BF16_PARTS bfloat16 parts (each the rounding of
+// what the previous parts leave) for the split-BF16 MFMA kernels: columns
+// kappa = k NPp + n (N_P padded to NPp, a multiple of 8), KS steps of 32,
+// rows in MB blocks of 16; A operand of v_mfma_f32_16x16x32_bf16 with lane l
+// holding row 16 mb + l%16 and columns 32 kb + 8 (l/16) + j, j = 0..7:
+//   frag[(((kb MB + mb) BF16_PARTS + part) 64 + l) 8 + j]
+constexpr int BF16_PARTS = 3;
+void build_affine_mats_bf16(int sh, int P, int pts, std::vector<uint16_t>& frag, int& NPp, int& KS, int& MB);
+// the affine local-matrix action (opk = OPK_MASS_LM, OPK_LAP_LM, OPK_HELM_LM)
+// of one block in split-BF16 with nparts = 2 or 3 parts, FP32 in/out; afrag
+// from build_affine_mats_bf16 (16-byte fragments), coef [n][7]
+struct bf16_frag {
+  uint16_t h[8];
+};
+hipError_t launch_localmat_affine_bf16(int sh, int P, int opk, int nparts, const bf16_frag* afrag, const double* coef,
+                                       const float* in, float* out, long long n_elem, double lambda, hipStream_t s);
 
 // launchers (shp_k_*.hip); return hipSuccess or the launch error
 size_t op_lds_bytes(int sh, int P, int opk, int E, int variant);

@@ -249,10 +249,19 @@ int dot(const T* a, const T* b, long long n, SolveWs& w, int slot, hipStream_t s
   return hipGetLastError() == hipSuccess ? SHP_OK : SHP_ERR_DEVICE;
 }
 
+// inner precisions whose vectors are FP32: the FP32 sum-factorisation and the
+// split-BF16 affine local matrices
+bool f32_vectors(int prec) { return prec == SHP_FP32 || prec == SHP_BF16 || prec == SHP_BF16X3; }
+
 template <typename T>
-int apply_inner(shp_plan plan, const T* in, T* out, double lambda, hipStream_t s) {
-  const int prec = sizeof(T) == sizeof(float) ? SHP_FP32 : SHP_FP64;
-  return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, prec, in, out, lambda, s);
+int apply_inner(shp_plan plan, const T* in, T* out, double lambda, int prec, hipStream_t s) {
+  if constexpr (sizeof(T) == sizeof(float)) {
+    if (prec == SHP_BF16 || prec == SHP_BF16X3)
+      return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_LOCALMAT, prec, in, out, lambda, s);
+    return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, SHP_FP32, in, out, lambda, s);
+  } else {
+    return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, SHP_FP64, in, out, lambda, s);
+  }
 }
 
 // The operators of the solve: the FP64 action apply64 and the action in the
@@ -262,18 +271,20 @@ int apply_inner(shp_plan plan, const T* in, T* out, double lambda, hipStream_t s
 struct ElemOp {
   shp_plan plan;
   double lambda;
+  int prec;  // inner precision
   int apply64(const double* x, double* y, hipStream_t s) const {
     return shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, x, y, lambda, s);
   }
   template <typename T>
   int apply(const T* x, T* y, hipStream_t s) const {
-    return apply_inner<T>(plan, x, y, lambda, s);
+    return apply_inner<T>(plan, x, y, lambda, prec, s);
   }
 };
 
 struct C0Op {
   shp_plan plan;
   double lambda;
+  int prec;  // inner precision
   const int64_t *l2g, *row_ptr, *col;
   long long n_local, n_global;
   double *xl, *yl;
@@ -281,7 +292,7 @@ struct C0Op {
   template <typename T>
   int run(const T* x, T* y, T* xl_, T* yl_, hipStream_t s) const {
     hipLaunchKernelGGL(k_c0_gather<T>, grid_for(n_local), dim3(256), 0, s, l2g, n_local, x, xl_);
-    if (int r = apply_inner<T>(plan, xl_, yl_, lambda, s)) return r;
+    if (int r = apply_inner<T>(plan, xl_, yl_, lambda, prec, s)) return r;
     hipLaunchKernelGGL(k_c0_scatter<T>, grid_for(n_global), dim3(256), 0, s, row_ptr, col, n_global, yl_, y);
     return hipGetLastError() == hipSuccess ? SHP_OK : SHP_ERR_DEVICE;
   }
@@ -420,8 +431,7 @@ int pcg_reliable(const Op& op, const double* b, double* x, long long n, SolveWs&
 int check_solve_args(double lambda, double tol, double inner_tol, int max_outer, int max_inner, int inner_prec) {
   if (!(lambda > 0.0) || !(tol > 0.0) || !(inner_tol > 0.0) || max_outer < 1 || max_inner < 1)
     return sfail(SHP_ERR_INVALID_ARG, "lambda, tolerances and iteration limits must be positive");
-  if (inner_prec == SHP_BF16) return sfail(SHP_ERR_UNSUPPORTED, "BF16 contractions are not built");
-  if (inner_prec != SHP_FP64 && inner_prec != SHP_FP32) return sfail(SHP_ERR_INVALID_ARG, "bad inner precision");
+  if (inner_prec != SHP_FP64 && !f32_vectors(inner_prec)) return sfail(SHP_ERR_INVALID_ARG, "bad inner precision");
   return SHP_OK;
 }
 
@@ -432,10 +442,10 @@ int solve_with(const Op& op, long long n, SolveWs& w, const double* diag, const 
                double tol, int max_outer, int max_inner, double inner_tol, shp_solve_stats* st, hipStream_t s) {
   const dim3 g = grid_for(n), bl(256);
   std::memset(st, 0, sizeof *st);
-  if (inner_prec == SHP_FP32) hipLaunchKernelGGL(k_to_float, g, bl, 0, s, diag, w.diagf, n);
+  if (f32_vectors(inner_prec)) hipLaunchKernelGGL(k_to_float, g, bl, 0, s, diag, w.diagf, n);
   // ||b|| and the initial FP64 residual
   if (int r = dot(b, b, n, w, BB, s)) return r;
-  if (int r = (inner_prec == SHP_FP32 ? true_residual<float>(op, b, x, n, w, false, s)
+  if (int r = (f32_vectors(inner_prec) ? true_residual<float>(op, b, x, n, w, false, s)
                                       : true_residual<double>(op, b, x, n, w, false, s)))
     return r;
   double hs[NSLOT + 1];
@@ -449,7 +459,7 @@ int solve_with(const Op& op, long long n, SolveWs& w, const double* diag, const 
     st->converged = 1;
     return SHP_OK;
   }
-  if (inner_prec == SHP_FP32)
+  if (f32_vectors(inner_prec))
     return pcg_reliable<float>(op, b, x, n, w, w.diagf, tol, max_outer, max_inner, inner_tol, hs[BB], st, s);
   return pcg_reliable<double>(op, b, x, n, w, diag, tol, max_outer, max_inner, inner_tol, hs[BB], st, s);
 }
@@ -527,7 +537,7 @@ int shp_helmholtz_solve(shp_plan plan, double lambda, const double* diag, const 
   if (int r = shp::plan_check_solve(plan, inner_prec)) return r;
   SolveWs w;
   carve(ws, n_dof, &w);
-  return solve_with(ElemOp{plan, lambda}, n_dof, w, diag, b, x, inner_prec, tol, max_outer, max_inner, inner_tol, st,
+  return solve_with(ElemOp{plan, lambda, inner_prec}, n_dof, w, diag, b, x, inner_prec, tol, max_outer, max_inner, inner_tol, st,
                     static_cast<hipStream_t>(stream));
 }
 
@@ -540,7 +550,7 @@ int shp_c0_apply(shp_plan plan, const int64_t* l2g, const int64_t* row_ptr, cons
   const long long n_local = shp::plan_total_coeff(plan);
   if (n_local < 1) return sfail(SHP_ERR_INVALID_ARG, "empty mesh");
   if (int r = shp::plan_check_solve(plan, SHP_FP64)) return r;
-  C0Op op{plan, lambda, l2g, row_ptr, col, n_local, n_global, work, work + n_local, nullptr, nullptr};
+  C0Op op{plan, lambda, SHP_FP64, l2g, row_ptr, col, n_local, n_global, work, work + n_local, nullptr, nullptr};
   return op.apply64(xg, yg, static_cast<hipStream_t>(stream));
 }
 
@@ -585,7 +595,7 @@ int shp_c0_helmholtz_solve(shp_plan plan, const int64_t* l2g, const int64_t* row
   if (int r = shp_helmholtz_diag(plan, lambda, c.xl, c.elem_ws, c.elem_bytes, s)) return r;
   hipLaunchKernelGGL((k_c0_scatter<double, false>), grid_for(n_global), dim3(256), 0, s, row_ptr, col,
                      (long long)n_global, c.xl, c.diag);
-  C0Op op{plan, lambda, l2g, row_ptr, col, n_local, n_global, c.xl, c.yl, c.xlf, c.ylf};
+  C0Op op{plan, lambda, inner_prec, l2g, row_ptr, col, n_local, n_global, c.xl, c.yl, c.xlf, c.ylf};
   return solve_with(op, n_global, c.w, c.diag, b, x, inner_prec, tol, max_outer, max_inner, inner_tol, st, s);
 }
 

@@ -11,6 +11,7 @@
 // derivative of the Lagrange interpolant, D_ij = (l_j / l_i) / (x_i - x_j),
 // D_ii = -sum_{j != i} D_ij.
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "../../include/shp.h"
@@ -377,7 +378,9 @@ static void collapse_deriv(int sh, double e1, double e2, double e3, double G[9],
   }
 }
 
-void build_affine_mats(int sh, int P, int pts, std::vector<double>& acat, int& Kp) {
+// the 7 reference matrices of an affine element, row-major
+// Acat[m][k Kp + n] (Kp = N_P padded to 16)
+static void affine_mats_rows(int sh, int P, int pts, std::vector<double>& acat, int& Kp) {
   std::vector<double> bcat;
   int Q3p = 0;
   build_localmat(sh, P, pts, bcat, Q3p, Kp);
@@ -423,6 +426,11 @@ void build_affine_mats(int sh, int P, int pts, std::vector<double>& acat, int& K
         row[(1 + c) * Kp + n] = (a == b) ? S[a][a] : S[a][b] + S[b][a];
       }
     }
+}
+
+void build_affine_mats(int sh, int P, int pts, std::vector<double>& acat, int& Kp) {
+  affine_mats_rows(sh, P, pts, acat, Kp);
+  const int NK = NAFF, W7 = NK * Kp;
   // MFMA fragment order: A operand of v_mfma_f64_16x16x4f64, lane l holding
   // row 16 mb + l%16 and column 4 kb + l/16 of A_k
   const int MB = Kp / 16;
@@ -434,6 +442,46 @@ void build_affine_mats(int sh, int P, int pts, std::vector<double>& acat, int& K
           frag[(((size_t)kb * NK + k) * MB + mb) * 64 + l] =
               acat[(size_t)(mb * 16 + l % 16) * W7 + k * Kp + 4 * kb + l / 16];
   acat.swap(frag);
+}
+
+// bfloat16 bits of a float, rounded to nearest even (finite values)
+static uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+static double bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+void build_affine_mats_bf16(int sh, int P, int pts, std::vector<uint16_t>& frag, int& NPp, int& KS, int& MB) {
+  std::vector<double> acat;
+  int Kp = 0;
+  affine_mats_rows(sh, P, pts, acat, Kp);
+  const int NP = num_modes(sh, P), W7 = NAFF * Kp;
+  NPp = (NP + 7) / 8 * 8;
+  KS = (NAFF * NPp + 31) / 32;
+  MB = (NP + 15) / 16;
+  frag.assign((size_t)KS * MB * BF16_PARTS * 64 * 8, 0);
+  for (int kb = 0; kb < KS; ++kb)
+    for (int mb = 0; mb < MB; ++mb)
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < 8; ++j) {
+          const int m = 16 * mb + l % 16, kap = 32 * kb + 8 * (l / 16) + j;
+          const int k = kap / NPp, n = kap - k * NPp;
+          if (m >= NP || k >= NAFF || n >= NP) continue;
+          double rest = acat[(size_t)m * W7 + k * Kp + n];
+          for (int part = 0; part < BF16_PARTS; ++part) {
+            const uint16_t h = bf16_bits((float)rest);
+            frag[((((size_t)kb * MB + mb) * BF16_PARTS + part) * 64 + l) * 8 + j] = h;
+            rest -= bf16_value(h);
+          }
+        }
 }
 
 void reference_points(int sh, int Q, int pts, double* xi, double* wout) {

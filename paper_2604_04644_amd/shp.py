@@ -19,7 +19,7 @@ GEOM = {"affine": 0, "curved": 1, "isoparam": 2}
 POINTS = {"gj": 0, "radau": 1}
 OPS = {"bwd": 0, "iprod": 1, "physderiv": 2, "iprod_deriv": 3, "mass": 4, "laplacian": 5, "helmholtz": 6}
 STRATEGY = {"auto": 0, "sumfac": 1, "sumfac_coll": 2, "localmat": 3}
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "BAD_GEOMETRY", -4: "WORKSPACE",
           -5: "STATE", -6: "DEVICE", -7: "NOT_CONVERGED"}
 
@@ -323,22 +323,28 @@ class Plan:
                                ctypes.c_void_p(out.data_ptr()), float(lam), _stream(t)))
         return out
 
-    def apply_prec(self, op: str, x, out=None, lam: float = 1.0, prec: str = "fp32"):
-        """Whole-mesh collocated Laplacian/Helmholtz action with contractions in
-        prec; x and out are float32 (fp32) or float64 (fp64) device tensors."""
+    def apply_prec(self, op: str, x, out=None, lam: float = 1.0, prec: str = "fp32", blk: int = -1,
+                   strategy: str | None = None):
+        """The action of op with contractions in prec: "fp32" (whole-mesh
+        collocated Laplacian/Helmholtz), "bf16" / "bf16x3" (split-BF16 affine
+        local matrices: mass, Laplacian, Helmholtz of block blk or, blk = -1,
+        every block) or "fp64"; x and out are float32 device tensors (float64
+        for fp64)."""
         t = self._torch
-        dt = {"fp64": t.float64, "fp32": t.float32}.get(prec)
-        if dt is None:
-            raise ShpError(-2, f"precision {prec} is not built")
+        if prec not in PREC:
+            raise ShpError(-1, f"unknown precision {prec}")
+        dt = t.float64 if prec == "fp64" else t.float32
+        if strategy is None:
+            strategy = "localmat" if prec.startswith("bf16") else "sumfac_coll"
         if x.dtype != dt or not x.is_cuda or not x.is_contiguous():
             raise ValueError(f"x must be a contiguous {dt} device tensor")
-        if x.numel() != self._in_numel(-1, op):
-            raise ValueError(f"x has {x.numel()} values, {op} takes {self._in_numel(-1, op)}")
+        if x.numel() != self._in_numel(blk, op):
+            raise ValueError(f"x has {x.numel()} values, {op} on block {blk} takes {self._in_numel(blk, op)}")
         if out is None:
-            out = t.empty(self._out_shape(-1, op), dtype=dt, device=x.device)
+            out = t.empty(self._out_shape(blk, op), dtype=dt, device=x.device)
         elif out.dtype != dt or not out.is_cuda or not out.is_contiguous() or out.numel() != x.numel():
             raise ValueError("bad output tensor")
-        _check(lib().shp_apply_prec(self._h, -1, OPS[op], STRATEGY["sumfac_coll"], PREC[prec],
+        _check(lib().shp_apply_prec(self._h, int(blk), OPS[op], STRATEGY[strategy], PREC[prec],
                                     ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), float(lam),
                                     _stream(t)))
         return out

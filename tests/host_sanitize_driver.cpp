@@ -7,6 +7,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -82,6 +84,34 @@ int main() {
           build_localmat(sh, P, pts, bcat, Q3p, Kp);
           build_affine_mats(sh, P, pts, acat, Ka);
           CHECK(!bcat.empty() && !acat.empty() && (int)acat.size() == NAFF * Ka * Ka);
+          // the BF16 parts sum to the FP64 matrices within 2^-26 of each
+          // entry (or 1e-38 where the last part falls among FP32's subnormals:
+          // entries of 1e-34 are rounding noise of zero), and the padding is zero
+          std::vector<uint16_t> f16;
+          int npp = 0, ks = 0, mb16 = 0;
+          build_affine_mats_bf16(sh, P, pts, f16, npp, ks, mb16);
+          CHECK((int)f16.size() == ks * mb16 * BF16_PARTS * 64 * 8 && npp % 8 == 0 && ks * 32 >= NAFF * npp);
+          auto part = [&](uint16_t h) {
+            const uint32_t u = (uint32_t)h << 16;
+            float f;
+            std::memcpy(&f, &u, 4);
+            return (double)f;
+          };
+          const int MB64 = Ka / 16;
+          double worst = 0.0;
+          for (int k = 0; k < NAFF; ++k)
+            for (int m = 0; m < mb16 * 16; ++m)
+              for (int n = 0; n < npp; ++n) {
+                const int kap = k * npp + n, kb = kap / 32, l = m % 16 + 16 * ((kap % 32) / 8), j = kap % 8;
+                double sum = 0.0;
+                for (int pt = 0; pt < BF16_PARTS; ++pt)
+                  sum += part(f16[((((size_t)kb * mb16 + m / 16) * BF16_PARTS + pt) * 64 + l) * 8 + j]);
+                const double a = (m < Ka && n < Ka)
+                                     ? acat[(((size_t)(n / 4) * NAFF + k) * MB64 + m / 16) * 64 + m % 16 + 16 * (n % 4)]
+                                     : 0.0;
+                worst = std::max(worst, std::fabs(sum - a) - std::max(std::ldexp(std::fabs(a), -26), 1e-38));
+              }
+          CHECK(worst <= 0.0);
         }
       }
   // the 2D shapes

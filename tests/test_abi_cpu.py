@@ -137,7 +137,10 @@ def test_error_paths_without_device(L):
     assert L.shp_block_offsets(h, 1, ctypes.byref(c), ctypes.byref(q)) == 0
     assert (c.value, q.value) == (10 * 125, 10 * 216)
     # precision and solver validation (no device call is reached)
-    assert L.shp_apply_prec(h, -1, 6, 2, 2, p, p, 1.0, None) == -2    # BF16 not built
+    assert L.shp_apply_prec(h, -1, 6, 2, 2, p, p, 1.0, None) == -2    # BF16: local matrices only
+    assert L.shp_apply_prec(h, -1, 6, 3, 2, p, p, 1.0, None) == -2    # BF16 on curved blocks
+    assert L.shp_apply_prec(h, 0, 6, 3, 3, p, p, 1.0, None) == -2     # BF16x3 on a curved block
+    assert L.shp_apply_prec(h, -1, 1, 3, 2, p, p, 1.0, None) == -2    # BF16 inner product
     assert L.shp_apply_prec(h, -1, 6, 2, 5, p, p, 1.0, None) == -1    # bad precision
     assert L.shp_apply_prec(h, -1, 4, 2, 1, p, p, 1.0, None) == -2    # FP32 mass
     assert L.shp_apply_prec(h, 0, 6, 2, 1, p, p, 1.0, None) == -2     # FP32 per block
@@ -152,7 +155,7 @@ def test_error_paths_without_device(L):
 
     def solve(lam=1.0, prec=1, tol=1e-10, mo=10, mi=100, itol=1e-3, w=ws, nbytes=sb.value):
         return L.shp_helmholtz_solve(h, lam, p, p, p, prec, tol, mo, mi, itol, w, nbytes, ctypes.byref(st), None)
-    assert solve(prec=2) == -2                                    # BF16 not built
+    assert solve(prec=2) == -5 and solve(prec=3) == -5            # BF16 inner: no workspace bound
     assert solve(prec=4) == -1
     assert solve(lam=0.0) == -1                                   # H only semidefinite
     assert solve(tol=0.0) == -1
