@@ -1081,6 +1081,30 @@ static int apply_bf16(shp_plan p, int blk, int op, int strategy, int prec, const
   const int opk = op == SHP_OP_MASS ? OPK_MASS_LM : op == SHP_OP_LAPLACIAN ? OPK_LAP_LM : OPK_HELM_LM;
   const int nparts = prec == SHP_BF16 ? 3 : 2;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  bool one_p = b1 - b0 <= 8;
+  for (int b = b0; b < b1; ++b) one_p = one_p && p->blocks[b].d.P == p->blocks[b0].d.P;
+  if (blk < 0 && one_p) {
+    // every block in one launch (their work overlaps on the chip)
+    int shape[8];
+    const bf16_frag* af[8];
+    const double* cf[8];
+    const float* xi[8];
+    float* yo[8];
+    long long ne[8];
+    for (int b = b0; b < b1; ++b) {
+      const Block& B = p->blocks[b];
+      shape[b] = B.d.shape;
+      af[b] = reinterpret_cast<const bf16_frag*>(p->ws + B.off_am16);
+      cf[b] = reinterpret_cast<const double*>(p->ws + B.off_coef);
+      xi[b] = static_cast<const float*>(in) + B.coeff_off;
+      yo[b] = static_cast<float*>(out) + B.coeff_off;
+      ne[b] = B.d.n_elem;
+    }
+    hipError_t e = launch_localmat_affine_bf16_mesh(p->blocks[b0].d.P, opk, nparts, b1 - b0, shape, af, cf, xi, yo, ne,
+                                                    lambda, s);
+    if (e != hipSuccess) return dev_fail(e, "BF16 local-matrix launch");
+    return SHP_OK;
+  }
   for (int b = b0; b < b1; ++b) {
     const Block& B = p->blocks[b];
     const long long off = blk >= 0 ? 0 : B.coeff_off;

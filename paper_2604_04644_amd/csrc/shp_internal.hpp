@@ -72,6 +72,12 @@ struct bf16_frag {
 };
 hipError_t launch_localmat_affine_bf16(int sh, int P, int opk, int nparts, const bf16_frag* afrag, const double* coef,
                                        const float* in, float* out, long long n_elem, double lambda, hipStream_t s);
+// the same for nblk <= 8 blocks of one order P in one launch (per-block
+// arrays of shapes, fragments, coefficients, in/out pointers and sizes)
+hipError_t launch_localmat_affine_bf16_mesh(int P, int opk, int nparts, int nblk, const int* shape,
+                                            const bf16_frag* const* afrag, const double* const* coef,
+                                            const float* const* in, float* const* out, const long long* n_elem,
+                                            double lambda, hipStream_t s);
 
 // launchers (shp_k_*.hip); return hipSuccess or the launch error
 size_t op_lds_bytes(int sh, int P, int opk, int E, int variant);

@@ -5,25 +5,40 @@
 
 namespace shp {
 
-// output row blocks per wave: at most 4, so that a tile's rows spread over
-// several waves (a block of a few thousand elements still fills the chip)
-// while a K step's MFMA work (MBW x 3 or 6) keeps up with forming its split B
-// operand (about 70 VALU instructions per step)
-template <int SH, int P>
-constexpr int bf16_mbw() {
-  constexpr int MB = (num_modes(SH, P) + 15) / 16;
-  return MB < 4 ? MB : 4;
-}
-
 template <int SH, int P, int OP, int NPART>
 static hipError_t launch_bf16_op(const AffineBf16Args& a, hipStream_t s) {
-  constexpr int MBW = bf16_mbw<SH, P>();
-  constexpr int MB = (num_modes(SH, P) + 15) / 16;
-  constexpr int NMW = (MB + MBW - 1) / MBW;
-  const long long nwave = (a.n_elem + 15) / 16 * NMW;
+  const long long nwave = (a.n_elem + 15) / 16 * bf16_waves_per_tile<SH, P>();
   if (nwave <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_localmat_affine_bf16<SH, P, OP, NPART, MBW>), dim3((unsigned)((nwave + 3) / 4)), dim3(256), 0,
-                     s, a);
+  hipLaunchKernelGGL((k_localmat_affine_bf16<SH, P, OP, NPART>), dim3((unsigned)((nwave + 3) / 4)), dim3(256), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
+template <int P>
+static int waves_per_tile(int sh) {
+  switch (sh) {
+    case HEX: return bf16_waves_per_tile<HEX, P>();
+    case PRISM: return bf16_waves_per_tile<PRISM, P>();
+    case PYR: return bf16_waves_per_tile<PYR, P>();
+    default: return bf16_waves_per_tile<TET, P>();
+  }
+}
+
+template <int P, int NPART>
+static hipError_t launch_bf16_mesh_pn(int opk, AffineBf16Mesh& m, hipStream_t s) {
+  long long g = 0;
+  for (int b = 0; b < m.nblk; ++b) {
+    m.wg0[b] = g;
+    g += ((m.blk[b].n_elem + 15) / 16 * waves_per_tile<P>(m.shape[b]) + 3) / 4;
+  }
+  m.wg0[m.nblk] = g;
+  if (g <= 0) return hipSuccess;
+  switch (opk) {
+    case OPK_MASS_LM: hipLaunchKernelGGL((k_localmat_affine_bf16_mesh<P, OPK_MASS, NPART>), dim3((unsigned)g), dim3(256), 0, s, m); break;
+    case OPK_LAP_LM: hipLaunchKernelGGL((k_localmat_affine_bf16_mesh<P, OPK_LAP, NPART>), dim3((unsigned)g), dim3(256), 0, s, m); break;
+    case OPK_HELM_LM: hipLaunchKernelGGL((k_localmat_affine_bf16_mesh<P, OPK_HELM, NPART>), dim3((unsigned)g), dim3(256), 0, s, m); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -67,6 +82,32 @@ hipError_t launch_localmat_affine_bf16(int sh, int P, int opk, int nparts, const
     case PRISM: return launch_bf16_s<PRISM>(P, opk, nparts, a, s);
     case PYR: return launch_bf16_s<PYR>(P, opk, nparts, a, s);
     case TET: return launch_bf16_s<TET>(P, opk, nparts, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_localmat_affine_bf16_mesh(int P, int opk, int nparts, int nblk, const int* shape,
+                                            const bf16_frag* const* afrag, const double* const* coef,
+                                            const float* const* in, float* const* out, const long long* n_elem,
+                                            double lambda, hipStream_t s) {
+  if ((nparts != 2 && nparts != 3) || nblk < 1 || nblk > BF16_MAX_BLOCKS) return hipErrorInvalidValue;
+  AffineBf16Mesh m{};
+  m.nblk = nblk;
+  for (int b = 0; b < nblk; ++b) {
+    m.shape[b] = shape[b];
+    m.blk[b].afrag = reinterpret_cast<const bf16x8*>(afrag[b]);
+    m.blk[b].coef = coef[b];
+    m.blk[b].in = in[b];
+    m.blk[b].out = out[b];
+    m.blk[b].n_elem = n_elem[b];
+    m.blk[b].lambda = lambda;
+  }
+  const bool three = nparts == 3;
+  switch (P) {
+    case 1: return three ? launch_bf16_mesh_pn<1, 3>(opk, m, s) : launch_bf16_mesh_pn<1, 2>(opk, m, s);
+    case 2: return three ? launch_bf16_mesh_pn<2, 3>(opk, m, s) : launch_bf16_mesh_pn<2, 2>(opk, m, s);
+    case 3: return three ? launch_bf16_mesh_pn<3, 3>(opk, m, s) : launch_bf16_mesh_pn<3, 2>(opk, m, s);
+    case 4: return three ? launch_bf16_mesh_pn<4, 3>(opk, m, s) : launch_bf16_mesh_pn<4, 2>(opk, m, s);
   }
   return hipErrorInvalidValue;
 }

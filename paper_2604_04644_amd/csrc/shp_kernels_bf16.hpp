@@ -45,17 +45,35 @@ struct AffineBf16Args {
 // parts are truncations, so three parts hold an FP32 value exactly:
 // v = h0 + h1 + h2 with h the top 16 bits of what is left; two parts leave
 // at most 2^-16 of it.
-template <int SH, int P, int OP, int NPART, int MBW>
-__global__ void __launch_bounds__(256) k_localmat_affine_bf16(AffineBf16Args a) {
+// output row blocks per wave: at most 4, so that a tile's rows spread over
+// several waves (a block of a few thousand elements still fills the chip)
+// while a K step's MFMA work (MBW x 3 or 6) keeps up with forming its split B
+// operand (about 70 VALU instructions per step)
+template <int SH, int P>
+constexpr int bf16_mbw() {
+  constexpr int MB = (num_modes(SH, P) + 15) / 16;
+  return MB < 4 ? MB : 4;
+}
+
+// waves of a block: (MB / MBW) per 16-element tile
+template <int SH, int P>
+constexpr int bf16_waves_per_tile() {
+  constexpr int MB = (num_modes(SH, P) + 15) / 16;
+  return (MB + bf16_mbw<SH, P>() - 1) / bf16_mbw<SH, P>();
+}
+
+// wave w of one block
+template <int SH, int P, int OP, int NPART>
+__device__ __forceinline__ void bf16_wave(const AffineBf16Args& a, long long w) {
   constexpr int NP = num_modes(SH, P);
   constexpr int NPp = (NP + 7) / 8 * 8;
   constexpr int MB = (NP + 15) / 16;
-  constexpr int NMW = (MB + MBW - 1) / MBW;                // waves per tile
+  constexpr int MBW = bf16_mbw<SH, P>();
+  constexpr int NMW = bf16_waves_per_tile<SH, P>();
   constexpr int K0 = (OP == OPK_LAP) ? NPp : 0;           // the Laplacian has no mass term
   constexpr int K1 = (OP == OPK_MASS) ? NPp : NAFF * NPp;  // the mass has only A_0
   constexpr int KB0 = K0 / 32, KB1 = (K1 + 31) / 32;
   const int lane = threadIdx.x & 63;
-  const long long w = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const long long e0 = (w / NMW) * 16;
   const int mb0 = (int)(w % NMW) * MBW;
   if (e0 >= a.n_elem) return;  // whole waves only
@@ -131,6 +149,36 @@ __global__ void __launch_bounds__(256) k_localmat_affine_bf16(AffineBf16Args a) 
       const int m = (mb0 + i) * 16 + 4 * kq + r;
       if (mb0 + i < MB && m < NP) Y[m] = acc[i][r];
     }
+}
+
+template <int SH, int P, int OP, int NPART>
+__global__ void __launch_bounds__(256) k_localmat_affine_bf16(AffineBf16Args a) {
+  bf16_wave<SH, P, OP, NPART>(a, (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+}
+
+// Every block of one order in one launch: block b owns the work-groups from
+// wg0[b] (each block's waves rounded up to whole work-groups, so that a
+// work-group's shape is uniform and the blocks' launches overlap).
+constexpr int BF16_MAX_BLOCKS = 8;
+struct AffineBf16Mesh {
+  AffineBf16Args blk[BF16_MAX_BLOCKS];
+  long long wg0[BF16_MAX_BLOCKS + 1];
+  int shape[BF16_MAX_BLOCKS];
+  int nblk;
+};
+
+template <int P, int OP, int NPART>
+__global__ void __launch_bounds__(256) k_localmat_affine_bf16_mesh(AffineBf16Mesh m) {
+  const long long g = blockIdx.x;
+  int b = 0;
+  while (b + 1 < m.nblk && g >= m.wg0[b + 1]) ++b;
+  const long long w = (g - m.wg0[b]) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  switch (m.shape[b]) {
+    case HEX: bf16_wave<HEX, P, OP, NPART>(m.blk[b], w); break;
+    case PRISM: bf16_wave<PRISM, P, OP, NPART>(m.blk[b], w); break;
+    case PYR: bf16_wave<PYR, P, OP, NPART>(m.blk[b], w); break;
+    default: bf16_wave<TET, P, OP, NPART>(m.blk[b], w); break;
+  }
 }
 
 }  // namespace shp

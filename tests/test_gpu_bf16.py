@@ -133,12 +133,16 @@ def test_bf16_action_vs_oracle(shp, shape, P, prec):
     say(f"    worst {worst:.2e} of the scale")
 
 
-def test_bf16_whole_mesh_equals_blocks(shp):
-    """blk = -1 over affine blocks of every shape (and of two orders) equals the
-    per-block launches bit for bit, in both split widths."""
-    say("[bf16] whole mesh == per block")
-    blocks = [(s, P, W.shape_batch(s, n)) for s, P, n in
-              (("hex", 2, 5), ("prism", 3, 17), ("pyr", 4, 33), ("tet", 1, 40), ("tet", 4, 21))]
+@pytest.mark.parametrize("orders", ["one", "mixed"])
+def test_bf16_whole_mesh_equals_blocks(shp, orders):
+    """blk = -1 over affine blocks of every shape equals the per-block launches
+    bit for bit, in both split widths: one launch over all blocks when they
+    share P (block sizes not multiples of the 4-wave work-group), one launch
+    per block when the orders differ."""
+    say(f"[bf16] whole mesh == per block ({orders} order)")
+    sizes = (("hex", 2, 5), ("prism", 3, 17), ("pyr", 4, 33), ("tet", 1, 40), ("tet", 4, 21)) if orders == "mixed" \
+        else (("hex", 4, 37), ("prism", 4, 17), ("pyr", 4, 33), ("tet", 4, 70))
+    blocks = [(s, P, W.shape_batch(s, n)) for s, P, n in sizes]
     plan = affine_plan(shp, blocks)
     nc, _ = plan.totals()
     x = torch.from_numpy(W.coeffs(1, nc, 910)[0].astype(np.float32)).cuda()
