@@ -170,28 +170,34 @@ __global__ void __launch_bounds__(256) k_localmat_affine(AffineMatArgs a) {
   const long long rem = a.n_elem - e0;
   const int ne = rem < 16 ? (int)rem : 16;
   const bool live = col < ne;
+  // dead lanes read a live element: no branches around the loads, so that
+  // a step's loads are in flight together
+  const long long ec = live ? e0 + col : e0;
   double c[NAFF];
 #pragma unroll
-  for (int k = 0; k < NAFF; ++k) c[k] = live ? a.coef[(e0 + col) * NAFF + k] : 0.0;
+  for (int k = 0; k < NAFF; ++k) c[k] = live ? a.coef[ec * NAFF + k] : 0.0;
   if (OP == OPK_HELM) c[0] *= a.lambda;
   dbl4 acc[MB];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) acc[mb] = dbl4{0.0, 0.0, 0.0, 0.0};
   const gptr_t Af = as_global(a.afrag) + lane;
-  const gptr_t X = as_global(a.in) + e0 * NP + (long long)col * NP;
+  const gptr_t X = as_global(a.in) + ec * NP;
   // K steps of 4 up to N_P only: the columns of A_k past N_P are zero padding
   // (at N_P = 4 that is one step of the four a 16-wide padding would take)
+  double xn = X[kq < NP ? kq : NP - 1];
   for (int kb = 0; kb < (NP + 3) / 4; ++kb) {
     const int n = 4 * kb + kq;
-    const double xb = (live && n < NP) ? X[n] : 0.0;
+    const double xb = (live && n < NP) ? xn : 0.0;
+    const int nn = n + 4 < NP ? n + 4 : NP - 1;
+    xn = X[nn];  // the next step's value, in flight during this one
 #pragma unroll
     for (int k = K0; k < K1; ++k) {
+      double av[MB];  // the step's fragments of A_k, loaded together
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) av[mb] = Af[(long long)((kb * NAFF + k) * MB + mb) * 64];
       const double b = xb * c[k];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const double av = Af[(long long)((kb * NAFF + k) * MB + mb) * 64];
-        acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, acc[mb], 0, 0, 0);
-      }
+      for (int mb = 0; mb < MB; ++mb) acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mb], b, acc[mb], 0, 0, 0);
     }
   }
   double* Y = a.out + (e0 + col) * NP;
