@@ -48,11 +48,13 @@ struct AffineBf16Args {
 // output row blocks per wave: at most 4, so that a tile's rows spread over
 // several waves (a block of a few thousand elements still fills the chip)
 // while a K step's MFMA work (MBW x 3 or 6) keeps up with forming its split B
-// operand (about 70 VALU instructions per step)
+// operand (about 70 VALU instructions per step); the rows shared evenly
+// among the tile's waves
 template <int SH, int P>
 constexpr int bf16_mbw() {
   constexpr int MB = (num_modes(SH, P) + 15) / 16;
-  return MB < 4 ? MB : 4;
+  constexpr int NW = (MB + 3) / 4;
+  return (MB + NW - 1) / NW;
 }
 
 // waves of a block: (MB / MBW) per 16-element tile
