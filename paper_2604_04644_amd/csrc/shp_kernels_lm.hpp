@@ -61,48 +61,48 @@ __device__ void localmat_tile(const LocalMatArgs& a, long long e0, int ne, doubl
     dbl4 u[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) u[d] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // U_d = Bcat_d[qb] X
+    // U_d = Bcat_d[qb] X (a step's fragments loaded together)
     for (int kb = 0; kb < Kp / 4; ++kb) {
       const double b = X[(4 * kb + kq) * 16 + col];
+      double av[ND];
 #pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        const double av = B[(long long)(d * Q3p + qb * 16 + col) * Kp + 4 * kb + kq];
-        u[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b, u[d], 0, 0, 0);
-      }
+      for (int d = 0; d < ND; ++d) av[d] = B[(long long)(d * Q3p + qb * 16 + col) * Kp + 4 * kb + kq];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) u[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d], b, u[d], 0, 0, 0);
     }
-    // metric at the lane's 4 points of this element
+    // metric at the lane's 4 points of this element: loads from clamped
+    // indices without branches, dead lanes and padding points zeroed after
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int pt = qb * 16 + 4 * i + kq;
-      if (live && pt < Q3) {
-        const gptr_t g = G + col * (NFAC * Q3) + pt;
-        const double jw = g[0];
-        if (OP == OPK_MASS) {
-          u[0][i] = jw * u[0][i];
-        } else {
-          const double g00 = g[1 * Q3], g01 = g[2 * Q3], g02 = g[3 * Q3];
-          const double g11 = g[4 * Q3], g12 = g[5 * Q3], g22 = g[6 * Q3];
-          const double d0 = u[1][i], d1 = u[2][i], d2 = u[3][i];
-          u[1][i] = g00 * d0 + g01 * d1 + g02 * d2;
-          u[2][i] = g01 * d0 + g11 * d1 + g12 * d2;
-          u[3][i] = g02 * d0 + g12 * d1 + g22 * d2;
-          u[0][i] = (OP == OPK_HELM) ? a.lambda * jw * u[0][i] : 0.0;
-        }
+      const bool on = live && pt < Q3;
+      const gptr_t g = G + (live ? col : 0) * (NFAC * Q3) + (pt < Q3 ? pt : Q3 - 1);
+      const double jw = g[0];
+      if (OP == OPK_MASS) {
+        u[0][i] = on ? jw * u[0][i] : 0.0;
       } else {
-#pragma unroll
-        for (int d = 0; d < 4; ++d) u[d][i] = 0.0;
+        const double g00 = g[1 * Q3], g01 = g[2 * Q3], g02 = g[3 * Q3];
+        const double g11 = g[4 * Q3], g12 = g[5 * Q3], g22 = g[6 * Q3];
+        const double d0 = u[1][i], d1 = u[2][i], d2 = u[3][i];
+        u[1][i] = on ? g00 * d0 + g01 * d1 + g02 * d2 : 0.0;
+        u[2][i] = on ? g01 * d0 + g11 * d1 + g12 * d2 : 0.0;
+        u[3][i] = on ? g02 * d0 + g12 * d1 + g22 * d2 : 0.0;
+        u[0][i] = (OP == OPK_HELM && on) ? a.lambda * jw * u[0][i] : 0.0;
       }
     }
     // Y += Bcat_d[qb]^T U'_d; the K-slab kb of this block is register kb
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+    for (int mb = 0; mb < MB; ++mb) {
+      double av[ND][4];
 #pragma unroll
       for (int d = D0; d < ND; ++d)
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-          const double av = B[(long long)(d * Q3p + qb * 16 + 4 * kb + kq) * Kp + mb * 16 + col];
-          y[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, u[d][kb], y[mb], 0, 0, 0);
-        }
+        for (int kb = 0; kb < 4; ++kb) av[d][kb] = B[(long long)(d * Q3p + qb * 16 + 4 * kb + kq) * Kp + mb * 16 + col];
+#pragma unroll
+      for (int d = D0; d < ND; ++d)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) y[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d][kb], u[d][kb], y[mb], 0, 0, 0);
+    }
   }
   // sum the waves' partial results in a fixed order
   const int nw = (int)(blockDim.x >> 6);
