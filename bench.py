@@ -491,6 +491,39 @@ def leg_2d(torch, shp, W, flush, cases=((512, 2), (512, 4), (256, 8)), steps: in
     return out
 
 
+OP_BYTES = {  # algorithmic HBM bytes per element (N_P modes, N_Q points)
+    "bwd": lambda nm, nq: 8 * nm + 8 * nq,
+    "iprod": lambda nm, nq: 8 * nq + 8 * nq + 8 * nm,            # f and jw in, y out
+    "physderiv": lambda nm, nq: 8 * nq + 72 * nq + 24 * nq,      # u and 9 metric terms in, 3 fields out
+    "iprod_deriv": lambda nm, nq: 24 * nq + 80 * nq + 8 * nm,    # 3 fields, 9 metric terms and jw in
+    "mass": lambda nm, nq: 16 * nm + 8 * nq,
+}
+
+
+def ops_leg(torch, shp, W, flush, plan, mesh, P: int, steps: int = 20):
+    """The other operators on the same mesh (curved, P as the headline): every
+    operator as one whole-mesh call with the collocated sum-factorisation and
+    with the local matrices (FP64 MFMA; P <= 4), HIP-event medians after a
+    cache flush, and the fraction of 8 TB/s of each operator's algorithmic
+    bytes."""
+    nc, npnt = plan.totals()
+    dev = torch.device("cuda")
+    out = {}
+    for op in OP_BYTES:
+        nb = sum(len(mesh[s]) * OP_BYTES[op](plan.n_modes[b], plan.n_points[b]) for b, s in enumerate(SHAPES))
+        nin = {"bwd": nc, "mass": nc, "iprod": npnt, "physderiv": npnt, "iprod_deriv": 3 * npnt}[op]
+        x = torch.from_numpy(np.ascontiguousarray(W.point_values(1, nin, 77)[0])).to(dev)
+        row = {"bytes": int(nb)}
+        for st in ("sumfac_coll", "localmat") if P <= 4 else ("sumfac_coll",):
+            _, _, med = time_launches(torch, lambda: plan.apply(-1, op, x, strategy=st), steps, 3, flush=flush)
+            row[st] = {"ms": round(med, 5), "GDOF/s": round(nc / (med * 1e-3) / 1e9, 3),
+                       "hbm_frac": round(nb / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        out[op] = row
+        log(f"  operator {op}: {row}")
+        del x
+    return out
+
+
 def adr_leg(torch, plan, mesh, x, y, helm_ms: float, steps: int = 20):
     """The advection-diffusion-reaction action (Helmholtz plus b . grad u tested
     with the basis) on the same mesh, velocity U[-1,1] at every point: launch
@@ -673,6 +706,8 @@ def main():
                     help="also time collocated vs non-collocated Helmholtz per shape (block launches)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg (P=6 mesh)")
     ap.add_argument("--no-adr", action="store_true", help="skip the advection-diffusion-reaction action")
+    ap.add_argument("--no-ops", action="store_true",
+                    help="skip the other operators (BwdTrans, IProduct, PhysDeriv, IProductDeriv, mass)")
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the split-BF16 leg (affine mesh, P=4: actions and solves per inner precision)")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D quadrilateral/triangle leg")
@@ -729,6 +764,7 @@ def main():
         f"{fl_mean_ms:.3f} ms (median {fl_med_ms:.3f}); {value:.2f} GDOF/s, {achieved:.0f} GB/s; "
         f"copy {copy_gbs:.0f} GB/s")
     adr = None if a.no_adr else adr_leg(torch, plan, mesh, x, y, ev_mean_ms)
+    ops = None if a.no_ops else ops_leg(torch, shp, W, flush, plan, mesh, P)
     strategies = None
     if a.strategies:
         strategies = {}
@@ -818,6 +854,8 @@ def main():
         out["c0_assembled"] = c0
     if adr is not None:
         out["adr_action"] = adr
+    if ops is not None:
+        out["other_operators"] = ops
     if iso is not None:
         out["isoparametric_vs_precomputed"] = iso
     if bf16 is not None:

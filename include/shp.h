@@ -110,14 +110,19 @@ typedef enum {
                           loaded, Laplacian and Helmholtz), else SHP_SUMFAC_COLL */
   SHP_SUMFAC = 1,      /* sum-factorisation, non-collocated derivatives (Alg. 5)  */
   SHP_SUMFAC_COLL = 2, /* sum-factorisation, collocated derivatives (Alg. 6)      */
-  SHP_LOCALMAT = 3     /* local matrices on FP64 MFMA (Alg. 1, StdMat): curved
-                          blocks apply [B; d_d B] with the per-point metric (the
+  SHP_LOCALMAT = 3     /* local matrices on FP64 MFMA (Alg. 1, StdMat), P <= 4
+                          (higher orders: SHP_ERR_UNSUPPORTED).  BwdTrans is one
+                          GEMM U = B X over the block; IProduct B^T (jw F);
+                          IProductDeriv sum_d (d_d B)^T (jw sum_i d eta_d/d x_i
+                          F_i); PhysDeriv applies the dense collocation
+                          derivative matrices of the tensor points (its input is
+                          values at the points) and the metric d eta/d x.  Mass,
+                          Laplacian and Helmholtz: curved blocks apply
+                          [B; d_d B] with the per-point metric (the
                           non-collocated form); affine blocks apply
                           H_e = lambda |J| A_0 + sum_k c_{e,k} A_k with 7 shared
                           reference matrices (mass and the xi-space stiffness
-                          blocks) and 7 coefficients per element.  Mass,
-                          Laplacian and Helmholtz at P <= 4; other operators and
-                          orders: SHP_ERR_UNSUPPORTED */
+                          blocks) and 7 coefficients per element */
 } shp_strategy;
 
 typedef struct {

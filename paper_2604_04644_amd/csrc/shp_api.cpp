@@ -57,6 +57,8 @@ struct Block {
   std::vector<int> itab;
   size_t off_tab = 0, off_itab = 0, off_fac = 0, off_dxi = 0, off_lm = 0, off_tabf = 0;
   std::vector<double> lm;  // [B; d_d B] for the local-matrix strategy (P <= 4)
+  std::vector<double> dm;  // dense collocation derivatives [3][Q3p][Q3p] (local-matrix PhysDeriv)
+  size_t off_dm = 0;
   std::vector<double> am;  // affine blocks: 7 reference matrices, MFMA fragment order
   size_t off_am = 0, off_coef = 0;
   std::vector<uint16_t> am16;  // the same as BF16 parts, BF16 MFMA fragment order
@@ -115,12 +117,15 @@ int opk_of(int op, int strategy, int* opk) {
   if (strategy < SHP_AUTO || strategy > SHP_LOCALMAT) return fail(SHP_ERR_INVALID_ARG, "bad strategy %d", strategy);
   if (strategy == SHP_LOCALMAT) {
     switch (op) {
+      case SHP_OP_BWDTRANS: *opk = OPK_BWD_LM; return SHP_OK;
+      case SHP_OP_IPRODUCT: *opk = OPK_IPR_LM; return SHP_OK;
+      case SHP_OP_PHYSDERIV: *opk = OPK_DERIV_LM; return SHP_OK;
+      case SHP_OP_IPRODUCT_DERIV: *opk = OPK_IPRD_LM; return SHP_OK;
       case SHP_OP_MASS: *opk = OPK_MASS_LM; return SHP_OK;
       case SHP_OP_LAPLACIAN: *opk = OPK_LAP_LM; return SHP_OK;
       case SHP_OP_HELMHOLTZ: *opk = OPK_HELM_LM; return SHP_OK;
     }
-    if (op < 0 || op > SHP_OP_HELMHOLTZ) return fail(SHP_ERR_INVALID_ARG, "bad operator %d", op);
-    return fail(SHP_ERR_UNSUPPORTED, "the local-matrix strategy covers mass, Laplacian and Helmholtz");
+    return fail(SHP_ERR_INVALID_ARG, "bad operator %d", op);
   }
   switch (op) {
     case SHP_OP_BWDTRANS: *opk = OPK_BWD; return SHP_OK;
@@ -139,12 +144,13 @@ int opk_of(int op, int strategy, int* opk) {
   return fail(SHP_ERR_INVALID_ARG, "bad operator %d", op);
 }
 
+bool is_xform_lm(int opk) { return opk >= OPK_BWD_LM && opk <= OPK_IPRD_LM; }
+bool is_localmat(int opk) { return (opk >= OPK_MASS_LM && opk <= OPK_HELM_LM) || is_xform_lm(opk); }
 bool in_is_modes(int opk) {
   return opk == OPK_BWD || opk == OPK_MASS || opk == OPK_LAP || opk == OPK_HELM || opk == OPK_HELM_NC ||
-         opk == OPK_LAP_NC || opk >= OPK_MASS_LM;
+         opk == OPK_LAP_NC || (opk >= OPK_MASS_LM && opk <= OPK_HELM_LM) || opk == OPK_BWD_LM;
 }
-bool is_localmat(int opk) { return opk >= OPK_MASS_LM; }
-bool out_is_modes(int opk) { return !(opk == OPK_BWD || opk == OPK_DERIV); }
+bool out_is_modes(int opk) { return !(opk == OPK_BWD || opk == OPK_DERIV || opk == OPK_BWD_LM || opk == OPK_DERIV_LM); }
 
 // Default launch shape: as many elements per work-group as fit an LDS budget
 // (at most 16; several work-groups share a CU), 256 threads, and for the
@@ -345,6 +351,7 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     if (B.d.P <= LOCALMAT_MAX_P && !B.iso()) {
       int q3p, kp;
       build_localmat(B.d.shape, B.d.P, B.d.pts, B.lm, q3p, kp);
+      build_dense_deriv(B.d.shape, B.d.P, B.d.pts, B.dm, q3p);
       if (B.d.geom == SHP_AFFINE) {
         build_affine_mats(B.d.shape, B.d.P, B.d.pts, B.am, kp);
         int npp, ks, mb;
@@ -375,6 +382,8 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     off = align_up(off + sizeof(int) * B.itab.size());
     B.off_lm = off;
     off = align_up(off + sizeof(double) * B.lm.size());
+    B.off_dm = off;
+    off = align_up(off + sizeof(double) * B.dm.size());
     B.off_tabf = off;
     off = align_up(off + sizeof(float) * B.tab.size());
     B.off_am = off;
@@ -476,6 +485,8 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
       e = hipMemcpyAsync(p->ws + B.off_itab, B.itab.data(), sizeof(int) * B.itab.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.lm.empty())
       e = hipMemcpyAsync(p->ws + B.off_lm, B.lm.data(), sizeof(double) * B.lm.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !B.dm.empty())
+      e = hipMemcpyAsync(p->ws + B.off_dm, B.dm.data(), sizeof(double) * B.dm.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.am.empty())
       e = hipMemcpyAsync(p->ws + B.off_am, B.am.data(), sizeof(double) * B.am.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.am16.empty())
@@ -889,7 +900,7 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
   if (!in || !out) return fail(SHP_ERR_INVALID_ARG, "null in/out");
   if (!std::isfinite(lambda)) return fail(SHP_ERR_INVALID_ARG, "lambda not finite");
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
-  const bool needs_geom = !(opk == OPK_BWD);
+  const bool needs_geom = !(opk == OPK_BWD || opk == OPK_BWD_LM);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (is_2d(p->blocks[0].d.shape)) {
     // quadrilaterals and triangles: the collocated sum-factorisation
@@ -970,10 +981,26 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
     for (int b = b0; b < b1; ++b) {
       const Block& B = p->blocks[b];
       if (B.d.P > LOCALMAT_MAX_P) return fail(SHP_ERR_UNSUPPORTED, "local-matrix strategy needs P <= %d", LOCALMAT_MAX_P);
-      if (!B.geom_ok) return fail(SHP_ERR_STATE, "block %d: geometry not set", b);
+      if (needs_geom && !B.geom_ok) return fail(SHP_ERR_STATE, "block %d: geometry not set", b);
     }
     for (int b = b0; b < b1; ++b) {
       const Block& B = p->blocks[b];
+      if (is_xform_lm(opk)) {
+        // the transforms: [B; d_d B] (or the dense collocation derivatives)
+        // with the per-point factors, for affine and curved blocks alike
+        LocalXformArgs xa;
+        xa.bcat = reinterpret_cast<const double*>(p->ws + B.off_lm);
+        xa.dmat = reinterpret_cast<const double*>(p->ws + B.off_dm);
+        xa.fac = reinterpret_cast<const double*>(p->ws + B.off_fac);
+        xa.dxi = reinterpret_cast<const double*>(p->ws + B.off_dxi);
+        xa.in = in + (blk >= 0 ? 0 : (in_is_modes(opk) ? B.coeff_off : B.phys_off));
+        xa.out = out + (blk >= 0 ? 0 : (out_is_modes(opk) ? B.coeff_off : B.phys_off));
+        xa.n_elem = B.d.n_elem;
+        xa.in_cs = xa.out_cs = (blk >= 0) ? B.d.n_elem * (long long)B.NQ : p->total_phys;
+        hipError_t e = launch_localmat_xform(B.d.shape, B.d.P, opk, xa, s);
+        if (e != hipSuccess) return dev_fail(e, "local-matrix transform launch");
+        continue;
+      }
       if (!B.am.empty()) {
         // affine block: 7 reference matrices and 7 coefficients per element
         AffineMatArgs aa;
@@ -1246,7 +1273,7 @@ int shp_tune(shp_plan p, int blk, int op, const double* in, double* out, double*
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool helm = (op == SHP_OP_HELMHOLTZ || op == SHP_OP_LAPLACIAN);
-  bool lm_ok = (helm || op == SHP_OP_MASS);
+  bool lm_ok = true;  // every operator has a local-matrix form up to LOCALMAT_MAX_P
   if (blk >= 0)
     lm_ok = lm_ok && p->blocks[blk].d.P <= LOCALMAT_MAX_P;
   else

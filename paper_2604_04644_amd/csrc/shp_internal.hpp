@@ -18,6 +18,7 @@ struct Tile;
 struct GeomArgs;
 struct LocalMatArgs;
 struct AffineMatArgs;
+struct LocalXformArgs;
 
 // Static per-block data of a mixed launch (device copy in the workspace).
 struct BlockStatic {
@@ -44,6 +45,9 @@ void rule_1d(int Q, int alpha, int pts, double* x, double* w);
 void build_tables(int sh, int P, int pts, std::vector<double>& tab, std::vector<int>& itab);
 void reference_points(int sh, int Q, int pts, double* xi, double* w);
 void build_localmat(int sh, int P, int pts, std::vector<double>& bcat, int& Q3p, int& Kp);
+// dense collocation derivative matrices of the tensor points, [3][Q3p][Q3p]
+// (d/d eta_d of the Lagrange interpolant; zero padding past Q^3)
+void build_dense_deriv(int sh, int P, int pts, std::vector<double>& dm, int& Q3p);
 // tables of the sum-factorised Helmholtz diagonal (see shp_tables.cpp)
 void build_diag_tables(int sh, int P, int pts, std::vector<double>& dt, std::vector<int>& di, int& n1, int& n12);
 // diag(lambda M + L) of n_elem elements of one block from its factors
@@ -85,6 +89,8 @@ hipError_t launch_block(int sh, int P, int opk, const OpArgs& a, int threads, in
 hipError_t launch_geometry(int sh, int P, const GeomArgs& g, hipStream_t s);
 hipError_t launch_localmat(int sh, int P, int opk, const LocalMatArgs& a, hipStream_t s);
 hipError_t launch_localmat_affine(int sh, int P, int opk, const AffineMatArgs& a, hipStream_t s);
+// local-matrix BwdTrans, IProduct, PhysDeriv, IProductDeriv (opk OPK_*_LM)
+hipError_t launch_localmat_xform(int sh, int P, int opk, const LocalXformArgs& a, hipStream_t s);
 hipError_t launch_affine_coef(const double* jac, double* coef, long long n, int* status, hipStream_t s);
 // whole-mesh advection-diffusion-reaction action (FP64, geometry-prefetch launch)
 // and the advection factors of one block

@@ -25,6 +25,21 @@ hipError_t launch_localmat_affine_prism(int P, int opk, const AffineMatArgs& a, 
 hipError_t launch_localmat_affine_pyr(int P, int opk, const AffineMatArgs& a, hipStream_t s);
 hipError_t launch_localmat_affine_tet(int P, int opk, const AffineMatArgs& a, hipStream_t s);
 
+hipError_t launch_localmat_xform_hex(int P, int opk, const LocalXformArgs& a, hipStream_t s);
+hipError_t launch_localmat_xform_prism(int P, int opk, const LocalXformArgs& a, hipStream_t s);
+hipError_t launch_localmat_xform_pyr(int P, int opk, const LocalXformArgs& a, hipStream_t s);
+hipError_t launch_localmat_xform_tet(int P, int opk, const LocalXformArgs& a, hipStream_t s);
+
+hipError_t launch_localmat_xform(int sh, int P, int opk, const LocalXformArgs& a, hipStream_t s) {
+  switch (sh) {
+    case HEX: return launch_localmat_xform_hex(P, opk, a, s);
+    case PRISM: return launch_localmat_xform_prism(P, opk, a, s);
+    case PYR: return launch_localmat_xform_pyr(P, opk, a, s);
+    case TET: return launch_localmat_xform_tet(P, opk, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_localmat_affine(int sh, int P, int opk, const AffineMatArgs& a, hipStream_t s) {
   switch (sh) {
     case HEX: return launch_localmat_affine_hex(P, opk, a, s);

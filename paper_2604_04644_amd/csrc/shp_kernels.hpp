@@ -45,7 +45,11 @@ enum : int {
   OPK_ADR = 12,     // advection-diffusion-reaction: Helmholtz plus b . grad u tested with the basis
   OPK_HELM_ISO = 13,  // iso-parametric blocks, geometry recomputed in the launch: Helmholtz
   OPK_LAP_ISO = 14,   //   Laplacian
-  OPK_COUNT = 15
+  OPK_BWD_LM = 15,    // local-matrix strategy (FP64 MFMA): backward transform
+  OPK_IPR_LM = 16,    //   inner product
+  OPK_DERIV_LM = 17,  //   physical derivative
+  OPK_IPRD_LM = 18,   //   inner product with the derivatives
+  OPK_COUNT = 19
 };
 
 // Arguments of one block for one operator call.

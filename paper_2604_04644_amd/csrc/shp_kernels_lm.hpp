@@ -210,6 +210,152 @@ __global__ void __launch_bounds__(256) k_localmat_affine(AffineMatArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Local-matrix forms of the transforms (Sec. 3.3.1, Alg. 1: the backward
+// transform as one GEMM over all elements, no element-wise scaling)
+// ---------------------------------------------------------------------------
+// One wave owns a 16-element tile (the N = 16 columns), 4 waves per
+// work-group, no LDS.  With Bcat = [B; d_1 B; d_2 B; d_3 B] (rows: points
+// padded to Q3p, columns: modes padded to Kp) and per point jw and
+// d eta_d / d x_i:
+//   BwdTrans       U = B X                          (M = points, K = modes)
+//   IProduct       Y = B^T (jw F)                   (M = modes, K = points)
+//   IProductDeriv  Y = sum_d (d_d B)^T (jw sum_i d eta_d/d x_i F_i)
+//   PhysDeriv      dU/dx_i = sum_d d eta_d/d x_i (D_d U), D_d the dense
+//                  collocation derivative matrices (Q3p x Q3p) of the tensor
+//                  points, since PhysDeriv acts on values at the points.
+// Loads sit outside branches (clamped indices, values masked after), so that
+// a step's fragments are in flight together.
+
+struct LocalXformArgs {
+  const double* bcat;  // [4 Q3p][Kp]
+  const double* dmat;  // [3][Q3p][Q3p] (PhysDeriv)
+  const double* fac;   // [n][NFAC][Q3]
+  const double* dxi;   // [n][NDXI][Q3]
+  const double* in;
+  double* out;
+  long long n_elem;
+  long long in_cs, out_cs;  // component strides of vector fields at the points
+};
+
+template <int SH, int P, int OP>
+__global__ void __launch_bounds__(256) k_localmat_xform(LocalXformArgs a) {
+  constexpr int Q = P + 2, Q3 = Q * Q * Q;
+  constexpr int Q3p = (Q3 + 15) / 16 * 16;
+  constexpr int NP = num_modes(SH, P);
+  constexpr int Kp = (NP + 15) / 16 * 16;
+  constexpr int MB = Kp / 16, QB = Q3p / 16;
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, kq = lane >> 4;
+  const long long e0 = ((long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16;
+  if (e0 >= a.n_elem) return;  // whole waves only
+  const long long e = e0 + col;
+  const bool live = e < a.n_elem;
+  const long long ec = live ? e : e0;
+  const gptr_t Bc = as_global(a.bcat);
+  if constexpr (OP == OPK_BWD) {
+    // the tile's coefficients in registers: xr[kb] = x_e[4 kb + kq]
+    constexpr int KS = Kp / 4;
+    double xr[KS];
+#pragma unroll
+    for (int kb = 0; kb < KS; ++kb) {
+      const int n = 4 * kb + kq;
+      const double v = a.in[ec * NP + (n < NP ? n : NP - 1)];
+      xr[kb] = (live && n < NP) ? v : 0.0;
+    }
+    for (int qb = 0; qb < QB; ++qb) {
+      dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+      double av[KS];
+#pragma unroll
+      for (int kb = 0; kb < KS; ++kb) av[kb] = Bc[(long long)(qb * 16 + col) * Kp + 4 * kb + kq];
+#pragma unroll
+      for (int kb = 0; kb < KS; ++kb) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kb], xr[kb], acc, 0, 0, 0);
+      if (live)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int pt = qb * 16 + 4 * i + kq;
+          if (pt < Q3) a.out[e * Q3 + pt] = acc[i];
+        }
+    }
+  } else if constexpr (OP == OPK_IPR || OP == OPK_IPRD) {
+    constexpr int ND = (OP == OPK_IPR) ? 1 : 3;
+    constexpr int D0 = (OP == OPK_IPR) ? 0 : 1;  // Bcat row block of the first table
+    dbl4 acc[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[mb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const double* fac = a.fac + ec * (long long)(NFAC * Q3);
+    const double* dxi = a.dxi + ec * (long long)(NDXI * Q3);
+    for (int kb = 0; kb < Q3p / 4; ++kb) {
+      const int pt = 4 * kb + kq;
+      const int pc = pt < Q3 ? pt : Q3 - 1;
+      const bool on = live && pt < Q3;
+      const double jw = fac[pc];
+      double g[ND];
+      if constexpr (OP == OPK_IPR) {
+        g[0] = on ? jw * a.in[ec * Q3 + pc] : 0.0;
+      } else {
+        const double f0 = a.in[0 * a.in_cs + ec * Q3 + pc];
+        const double f1 = a.in[1 * a.in_cs + ec * Q3 + pc];
+        const double f2 = a.in[2 * a.in_cs + ec * Q3 + pc];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double v = dxi[(d * 3 + 0) * Q3 + pc] * f0 + dxi[(d * 3 + 1) * Q3 + pc] * f1 +
+                           dxi[(d * 3 + 2) * Q3 + pc] * f2;
+          g[d] = on ? jw * v : 0.0;
+        }
+      }
+      double av[ND][MB];
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) av[d][mb] = Bc[(long long)((D0 + d) * Q3p + pt) * Kp + mb * 16 + col];
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d][mb], g[d], acc[mb], 0, 0, 0);
+    }
+    if (live)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = mb * 16 + 4 * i + kq;
+          if (m < NP) a.out[e * NP + m] = acc[mb][i];
+        }
+  } else {
+    static_assert(OP == OPK_DERIV, "local-matrix transform");
+    const gptr_t Dm = as_global(a.dmat);
+    const double* dxi = a.dxi + ec * (long long)(NDXI * Q3);
+    for (int qb = 0; qb < QB; ++qb) {
+      dbl4 acc[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) acc[d] = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int kb = 0; kb < Q3p / 4; ++kb) {
+        const int pin = 4 * kb + kq;
+        const double u = a.in[ec * Q3 + (pin < Q3 ? pin : Q3 - 1)];
+        const double ub = (live && pin < Q3) ? u : 0.0;
+        double av[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) av[d] = Dm[((long long)d * Q3p + qb * 16 + col) * Q3p + 4 * kb + kq];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d], ub, acc[d], 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pt = qb * 16 + 4 * i + kq;
+        const int pc = pt < Q3 ? pt : Q3 - 1;
+        double m[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) m[c] = dxi[c * Q3 + pc];
+        if (live && pt < Q3)
+#pragma unroll
+          for (int x = 0; x < 3; ++x)
+            a.out[x * a.out_cs + e * Q3 + pt] = m[0 * 3 + x] * acc[0][i] + m[1 * 3 + x] * acc[1][i] + m[2 * 3 + x] * acc[2][i];
+      }
+    }
+  }
+}
+
 template <int SH, int P>
 constexpr size_t lds_bytes_localmat() {
   constexpr int Kp = (num_modes(SH, P) + 15) / 16 * 16;

@@ -265,6 +265,28 @@ static double factor_value(const Factor& f, double x, bool der) {
 // for the local-matrix strategy: row d*Q3p + q, column m; rows padded to a
 // multiple of 16, columns to a multiple of 16 (zeros).  Each mode's 1D factors
 // are differentiated factor by factor.
+void build_dense_deriv(int sh, int P, int pts, std::vector<double>& dm, int& Q3p) {
+  std::vector<double> tab;
+  std::vector<int> itab;
+  build_tables(sh, P, pts, tab, itab);
+  const TabLayout L = tab_layout(sh, P);
+  const int Q = P + 2, Q3 = Q * Q * Q;
+  Q3p = (Q3 + 15) / 16 * 16;
+  dm.assign((size_t)3 * Q3p * Q3p, 0.0);
+  // point (i0, i1, i2) at (i0 Q + i1) Q + i2; D_d couples points that differ
+  // in index d only, with the 1D entry D^(d)[i_d][j_d]
+  for (int p0 = 0; p0 < Q3; ++p0) {
+    const int i[3] = {p0 / (Q * Q), (p0 / Q) % Q, p0 % Q};
+    for (int d = 0; d < 3; ++d)
+      for (int j = 0; j < Q; ++j) {
+        int k[3] = {i[0], i[1], i[2]};
+        k[d] = j;
+        const int p1 = (k[0] * Q + k[1]) * Q + k[2];
+        dm[((size_t)d * Q3p + p0) * Q3p + p1] = tab[L.D + d * Q * Q + i[d] * Q + j];
+      }
+  }
+}
+
 void build_localmat(int sh, int P, int pts, std::vector<double>& bcat, int& Q3p, int& Kp) {
   const int Q = P + 2, Q3 = Q * Q * Q, NP = num_modes(sh, P);
   Q3p = (Q3 + 15) / 16 * 16;

@@ -109,20 +109,25 @@ def test_noncollocated_vs_oracle(shp, shape, P):
 
 
 @pytest.mark.parametrize("shape,P", [(s, P) for s in O.SHAPES for P in (1, 2, 3, 4)])
-def test_localmat_vs_oracle(shp, shape, P):
-    """The local-matrix strategy on FP64 MFMA (mass, Laplacian, Helmholtz) on a
-    ragged batch (not a multiple of the 16-element tile)."""
+@pytest.mark.parametrize("curved", [True, False])
+def test_localmat_vs_oracle(shp, shape, P, curved):
+    """The local-matrix strategy on FP64 MFMA, every operator (BwdTrans as one
+    GEMM, IProduct, PhysDeriv with dense collocation derivatives,
+    IProductDeriv, mass, Laplacian, Helmholtz) on a ragged batch (not a
+    multiple of the 16-element tile nor of the 4-wave work-group), curved and
+    affine blocks."""
     ne = 37
-    say(f"[parity] local matrix shape={shape} P={P}")
+    say(f"[parity] local matrix shape={shape} P={P} curved={curved}")
     maps = W.shape_batch(shape, ne)
-    plan = shp.Plan([(shape, P, ne, "curved")])
-    plan.set_geometry(0, gpu_geometry(shp, maps, shape, P, True))
-    jo = oracle_geometry(maps, shape, P, True)
-    for k, op in enumerate(("mass", "laplacian", "helmholtz")):
-        x = W.coeffs(ne, plan.n_modes[0], 500 + k)
+    NP, NQ = O.num_modes(shape, P), (P + 2) ** 3
+    plan = shp.Plan([(shape, P, ne, "curved" if curved else "affine")])
+    plan.set_geometry(0, gpu_geometry(shp, maps, shape, P, curved))
+    jo = oracle_geometry(maps, shape, P, curved)
+    for k, op in enumerate(OPS):
+        x = op_input(op, ne, NP, NQ, 500 + k)
         ref = O.apply_op(op, shape, P, P + 2, jo, x, lam=1.7)
-        y = plan.apply(0, op, torch.from_numpy(x).cuda(), lam=1.7, strategy="localmat").cpu().numpy()
-        e = rel(y, ref)
+        y = plan.apply(0, op, torch.from_numpy(np.ascontiguousarray(x)).cuda(), lam=1.7, strategy="localmat").cpu().numpy()
+        e = rel(y.reshape(ref.shape), ref)
         say(f"    {op:12s} rel={e:.2e}")
         assert e <= TOL, (shape, P, op, e)
 
@@ -138,9 +143,19 @@ def test_localmat_whole_mesh_and_limits(shp):
         ne, NP = len(mesh[s]), plan.n_modes[b]
         ref = O.apply_op("helmholtz", s, 2, 4, oracle_geometry(mesh[s], s, 2, True), x[co:co + ne * NP].reshape(ne, NP))
         assert rel(y[co:co + ne * NP].reshape(ne, NP), ref) <= TOL
-    with pytest.raises(shp.ShpError) as ei:      # BwdTrans has no local-matrix form here
-        plan.apply(-1, "bwd", torch.from_numpy(x).cuda(), strategy="localmat")
-    assert ei.value.code == -2
+    # the transforms over the whole mesh equal the per-block launches, and
+    # BwdTrans (one GEMM per block) equals the oracle
+    u = plan.apply(-1, "bwd", torch.from_numpy(x).cuda(), strategy="localmat").cpu().numpy()
+    for b, s in enumerate(O.SHAPES):
+        co, po = plan.offsets(b)
+        ne, NP, NQ = len(mesh[s]), plan.n_modes[b], plan.n_points[b]
+        ref = O.apply_op("bwd", s, 2, 4, oracle_geometry(mesh[s], s, 2, True), x[co:co + ne * NP].reshape(ne, NP))
+        assert rel(u[po:po + ne * NQ].reshape(ne, NQ), ref) <= TOL
+    nc, npnt = plan.totals()
+    f3 = torch.from_numpy(np.ascontiguousarray(W.point_values(1, 3 * npnt, 43)[0])).cuda()
+    g = plan.apply(-1, "iprod_deriv", f3, strategy="localmat").cpu().numpy()
+    gs = plan.apply(-1, "iprod_deriv", f3, strategy="sumfac_coll").cpu().numpy()
+    assert rel(g, gs) <= TOL
     maps = W.shape_batch("hex", 3)
     p5 = shp.Plan([("hex", 5, 3, "curved")])
     p5.set_geometry(0, gpu_geometry(shp, maps, "hex", 5, True))
