@@ -193,6 +193,18 @@ Tiling default_tiling(int sh, int P, int opk, size_t lds_budget = 40 * 1024) {
     t.persist = 0;
     return t;
   }
+  if (opk == OPK_BWD || opk == OPK_IPR || opk == OPK_DERIV || opk == OPK_IPRD || opk == OPK_MASS) {
+    // the plain collocated tile is bound by the latency of its staged line
+    // stages: about 1500 points per work-group, 512 threads from 768 points
+    // (the tuner's choices for these operators on the 32^3-cell mixed mesh
+    // at P = 2, 4, 6 were 640-960, 1512 and 2048 points)
+    int E = std::max(1, std::min(12, (int)((1536 + Q3 / 2) / Q3)));
+    while (E > 1 && op_lds_bytes(sh, P, opk, E, 2) > 64 * 1024) --E;
+    t.E = E;
+    t.NT = E * Q3 > 768 ? 512 : 256;
+    t.persist = 0;
+    return t;
+  }
   if (helm && P >= 7) {
     t.E = HI_E[sh][P - 7];
     t.NT = HI_NT[sh][P - 7];

@@ -790,11 +790,14 @@ __device__ void ipr_chain(const Tile_<SH, P, R>& T, int ne, int mask) {
   __syncthreads();
 }
 
+// The tile of every collocated operator: the stages read their tables through
+// the constant path except the tet's eta2 table and the column table, which
+// are all the (compact) LDS head holds.
 template <int SH, int P, int OP, typename R>
 __device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH, P, R>& T) {
   using D = Dims<SH, P>;
   constexpr int Q3 = D::Q3;
-  load_tables<SH, P>(a, T);
+  load_tables_helm<SH, P>(a, T);
   if (OP == OPK_BWD || OP == OPK_MASS || OP == OPK_LAP || OP == OPK_HELM) {
     load_modes<SH, P>(T, reinterpret_cast<const R*>(a.in), e0, ne, 0);
     __syncthreads();
@@ -993,7 +996,7 @@ __global__ void __launch_bounds__(512) k_block(OpArgs a) {
   const long long rem = a.n_elem - e0;
   const int ne = rem < a.E ? (int)rem : a.E;
   if (ne <= 0) return;
-  const Tile_<SH, P> T = make_tile<SH, P>(smem, a.tab);
+  const Tile_<SH, P> T = make_tile_h<SH, P, double>(smem, a.tab);
   tile_body<SH, P, OP>(a, e0, ne, T);
 }
 
@@ -1026,10 +1029,10 @@ __global__ void __launch_bounds__(512) k_mixed(const BlockStatic* __restrict__ b
   a.E = b.E;
   a.pad_ = 0;
   switch (b.shape) {
-    case HEX: tile_body<HEX, P, OP>(a, tl.e0, tl.ne, make_tile<HEX, P>(smem, a.tab)); break;
-    case PRISM: tile_body<PRISM, P, OP>(a, tl.e0, tl.ne, make_tile<PRISM, P>(smem, a.tab)); break;
-    case PYR: tile_body<PYR, P, OP>(a, tl.e0, tl.ne, make_tile<PYR, P>(smem, a.tab)); break;
-    default: tile_body<TET, P, OP>(a, tl.e0, tl.ne, make_tile<TET, P>(smem, a.tab)); break;
+    case HEX: tile_body<HEX, P, OP>(a, tl.e0, tl.ne, make_tile_h<HEX, P, double>(smem, a.tab)); break;
+    case PRISM: tile_body<PRISM, P, OP>(a, tl.e0, tl.ne, make_tile_h<PRISM, P, double>(smem, a.tab)); break;
+    case PYR: tile_body<PYR, P, OP>(a, tl.e0, tl.ne, make_tile_h<PYR, P, double>(smem, a.tab)); break;
+    default: tile_body<TET, P, OP>(a, tl.e0, tl.ne, make_tile_h<TET, P, double>(smem, a.tab)); break;
   }
 }
 
