@@ -798,6 +798,22 @@ __device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH,
   using D = Dims<SH, P>;
   constexpr int Q3 = D::Q3;
   load_tables_helm<SH, P>(a, T);
+  // the mass's jw at a thread's first PF points, loaded at the start so that
+  // the loads overlap the line stages (points past PF nthr() are read where
+  // they are used; prefetching the 9 d eta/d x of the physical derivative the
+  // same way costs it occupancy and time)
+  constexpr int PF = 4;
+  double gpf[PF];
+  if constexpr (OP == OPK_MASS) {
+    const double* g = a.fac + e0 * (long long)(NFAC * Q3);
+#pragma unroll
+    for (int it = 0; it < PF; ++it) {
+      const int t = tid() + it * nthr();
+      const int tc = t < ne * Q3 ? t : 0;  // in bounds; unused when t is past the tile
+      const int e = tc / Q3, pt = tc - e * Q3;
+      gpf[it] = g[e * (NFAC * Q3) + pt];
+    }
+  }
   if (OP == OPK_BWD || OP == OPK_MASS || OP == OPK_LAP || OP == OPK_HELM) {
     load_modes<SH, P>(T, reinterpret_cast<const R*>(a.in), e0, ne, 0);
     __syncthreads();
@@ -818,9 +834,14 @@ __device__ void tile_body(const OpArgs& a, long long e0, int ne, const Tile_<SH,
   if (OP == OPK_IPR || OP == OPK_MASS) {
     const double* fac = a.fac + e0 * (long long)(NFAC * Q3);
     const R* src = reinterpret_cast<const R*>(a.in) + e0 * Q3;
-    for (int t = tid(); t < ne * Q3; t += nthr()) {
+    int it = 0;
+    for (int t = tid(); t < ne * Q3; t += nthr(), ++it) {
       const int e = t / Q3, pt = t - e * Q3;
-      const double jw = fac[e * (NFAC * Q3) + pt];
+      double jw;
+      if constexpr (OP == OPK_MASS)
+        jw = it < PF ? gpf[it < PF ? it : 0] : fac[e * (NFAC * Q3) + pt];
+      else
+        jw = fac[e * (NFAC * Q3) + pt];
       R* u = T.U(e) + lds_pt<SH, P>(pt);
       const double f = (OP == OPK_IPR) ? src[t] : *u;
       *u = jw * f;
