@@ -298,6 +298,9 @@ def affine_leg(torch, shp, W, flush=None, dof: float = 4e6, Ps=(1, 2, 3, 4)):
                                           flush=flush)
                 row[st] = round(ne * nm / (med * 1e-3) / 1e9, 2)
             row["localmat_speedup"] = round(row["localmat"] / row["sumfac_coll"], 3)
+            _, _, med = time_launches(torch, lambda: plan.apply_prec("helmholtz", x32, out=y32, prec="fp32", blk=0,
+                                                                     strategy="localmat"), 20, 3, flush=flush)
+            row["localmat_fp32"] = round(ne * nm / (med * 1e-3) / 1e9, 2)
             for pr in ("bf16", "bf16x3"):
                 _, _, med = time_launches(torch, lambda: plan.apply_prec("helmholtz", x32, out=y32, prec=pr, blk=0),
                                           20, 3, flush=flush)
@@ -326,7 +329,8 @@ def bf16_leg(torch, shp, W, flush, ncell: int = 32, P: int = 4, lam: float = 1.0
     """Split-BF16 MFMA contractions on the mixed mesh made affine (each element
     its affine map, no curvature), P = 4: the Helmholtz action as FP64
     collocated sum-factorisation, FP64 local matrices (FP64 MFMA), FP32
-    collocated sum-factorisation, and split-BF16 local matrices with three
+    collocated sum-factorisation, FP32 local matrices on the FP32 matrix
+    cores, and split-BF16 local matrices with three
     parts (six products, "bf16") and two parts (three products, "bf16x3"),
     HIP-event medians after a cache flush; then the Jacobi-PCG with FP64
     reliable updates to the error targets 1e-6 and 1e-10 with each inner
@@ -349,12 +353,14 @@ def bf16_leg(torch, shp, W, flush, ncell: int = 32, P: int = 4, lam: float = 1.0
             ("fp64_sumfac", lambda: plan.apply(-1, "helmholtz", x64, out=y64, lam=lam, strategy="sumfac_coll"), y64),
             ("fp64_localmat", lambda: plan.apply(-1, "helmholtz", x64, out=y64, lam=lam, strategy="localmat"), y64),
             ("fp32_sumfac", lambda: plan.apply_prec("helmholtz", x32, out=y32, lam=lam, prec="fp32"), y32),
+            ("fp32_localmat", lambda: plan.apply_prec("helmholtz", x32, out=y32, lam=lam, prec="fp32",
+                                                      strategy="localmat"), y32),
             ("bf16", lambda: plan.apply_prec("helmholtz", x32, out=y32, lam=lam, prec="bf16"), y32),
             ("bf16x3", lambda: plan.apply_prec("helmholtz", x32, out=y32, lam=lam, prec="bf16x3"), y32)):
         _, _, med = time_launches(torch, fn, steps, 3, flush=flush)
         dev = float((out.double() - ref).abs().max() / ref.abs().max())
         row = {"ms": round(med, 5), "GDOF/s": round(nc / (med * 1e-3) / 1e9, 3), "maxrel_vs_fp64": dev}
-        if name.startswith("bf16") or name == "fp64_localmat":
+        if name.startswith("bf16") or name.endswith("_localmat"):
             row["useful_TFLOP/s"] = round(useful / (med * 1e-3) / 1e12, 2)
         if name.startswith("bf16"):
             parts = 3 if name == "bf16" else 2

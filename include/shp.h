@@ -221,15 +221,18 @@ int shp_apply(shp_plan plan, int blk, int op, int strategy, const double* in /* 
 typedef enum { SHP_FP64 = 0, SHP_FP32 = 1, SHP_BF16 = 2, SHP_BF16X3 = 3 } shp_prec;
 
 /* shp_apply with a contraction precision: in/out are device arrays of doubles
- * (SHP_FP64) or floats (the others) in the same layouts.  SHP_FP32 covers the
- * collocated Laplacian and Helmholtz actions as a whole-mesh launch (blk = -1,
- * one P for all blocks).  SHP_BF16 and SHP_BF16X3 cover the mass, Laplacian
- * and Helmholtz actions of affine 3D blocks with P <= 4 in the local-matrix
- * form (strategy SHP_AUTO or SHP_LOCALMAT; Sec. 3.3.1): y_e = sum_k c_{e,k}
- * A_k x_e as one contraction over the 7 reference matrices, with B operand
- * c_{e,k} x_e rounded to FP32 before the split; one block (blk >= 0, its own
- * buffers) or every block (blk = -1, whole-mesh buffers, one launch per
- * block).  Other combinations return SHP_ERR_UNSUPPORTED. */
+ * (SHP_FP64) or floats (the others) in the same layouts.  SHP_FP32 with
+ * strategy SHP_AUTO or SHP_SUMFAC_COLL covers the collocated Laplacian and
+ * Helmholtz actions as a whole-mesh launch (blk = -1, one P for all blocks).
+ * SHP_BF16 and SHP_BF16X3 (strategy SHP_AUTO or SHP_LOCALMAT), and SHP_FP32
+ * with strategy SHP_LOCALMAT (on v_mfma_f32_16x16x4f32, the matrices rounded to
+ * FP32), cover the mass, Laplacian and Helmholtz actions of affine 3D blocks
+ * with P <= 4 in the local-matrix form (Sec. 3.3.1): y_e = sum_k c_{e,k} A_k x_e
+ * as one contraction over the 7 reference matrices, with B operand c_{e,k} x_e
+ * rounded to FP32 (before the split for BF16); one block (blk >= 0, its own
+ * buffers) or every block (blk = -1, whole-mesh buffers; the BF16 kernels take
+ * every block of one order in one launch).  Other combinations return
+ * SHP_ERR_UNSUPPORTED. */
 int shp_apply_prec(shp_plan plan, int blk, int op, int strategy, int prec, const void* in /* device */,
                    void* out /* device */, double lambda, void* stream);
 

@@ -63,6 +63,8 @@ struct Block {
   size_t off_am = 0, off_coef = 0;
   std::vector<uint16_t> am16;  // the same as BF16 parts, BF16 MFMA fragment order
   size_t off_am16 = 0;
+  std::vector<float> am32;     // the FP64 fragments rounded to FP32 (FP32 MFMA)
+  size_t off_am32 = 0;
   std::vector<float> tabf; // the reference tables rounded to FP32
   std::vector<double> dtab; // sum-factorised Helmholtz diagonal: 1D factor tables
   std::vector<int> ditab;   //   and their pair and mode indices
@@ -366,6 +368,7 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
       build_dense_deriv(B.d.shape, B.d.P, B.d.pts, B.dm, q3p);
       if (B.d.geom == SHP_AFFINE) {
         build_affine_mats(B.d.shape, B.d.P, B.d.pts, B.am, kp);
+        B.am32.assign(B.am.begin(), B.am.end());
         int npp, ks, mb;
         build_affine_mats_bf16(B.d.shape, B.d.P, B.d.pts, B.am16, npp, ks, mb);
       }
@@ -402,6 +405,8 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     off = align_up(off + sizeof(double) * B.am.size());
     B.off_am16 = off;
     off = align_up(off + sizeof(uint16_t) * B.am16.size());
+    B.off_am32 = off;
+    off = align_up(off + sizeof(float) * B.am32.size());
     B.off_dtab = off;
     off = align_up(off + sizeof(double) * B.dtab.size());
     B.off_ditab = off;
@@ -501,6 +506,8 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
       e = hipMemcpyAsync(p->ws + B.off_dm, B.dm.data(), sizeof(double) * B.dm.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.am.empty())
       e = hipMemcpyAsync(p->ws + B.off_am, B.am.data(), sizeof(double) * B.am.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !B.am32.empty())
+      e = hipMemcpyAsync(p->ws + B.off_am32, B.am32.data(), sizeof(float) * B.am32.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.am16.empty())
       e = hipMemcpyAsync(p->ws + B.off_am16, B.am16.data(), sizeof(uint16_t) * B.am16.size(), hipMemcpyHostToDevice,
                          s);
@@ -1099,20 +1106,22 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
 }
 
 
-// split-BF16 affine local-matrix actions of one block or of every block
+// affine local-matrix actions in split BF16 (SHP_BF16, SHP_BF16X3) or in FP32
+// on the FP32 matrix cores (SHP_FP32), of one block or of every block
 static int apply_bf16(shp_plan p, int blk, int op, int strategy, int prec, const void* in, void* out, double lambda,
                       void* stream) {
   if (op != SHP_OP_MASS && op != SHP_OP_LAPLACIAN && op != SHP_OP_HELMHOLTZ)
-    return fail(SHP_ERR_UNSUPPORTED, "BF16 contractions cover the mass, Laplacian and Helmholtz actions");
+    return fail(SHP_ERR_UNSUPPORTED, "local-matrix contractions below FP64 cover the mass, Laplacian and Helmholtz actions");
   if (strategy != SHP_AUTO && strategy != SHP_LOCALMAT)
     return fail(SHP_ERR_UNSUPPORTED, "BF16 contractions use the affine local matrices (SHP_LOCALMAT)");
+  const bool f32 = prec == SHP_FP32;
   if (blk < -1 || blk >= (int)p->blocks.size()) return fail(SHP_ERR_INVALID_ARG, "bad block %d", blk);
   if (!in || !out) return fail(SHP_ERR_INVALID_ARG, "null in/out");
   if (!std::isfinite(lambda)) return fail(SHP_ERR_INVALID_ARG, "lambda not finite");
   const int b0 = blk >= 0 ? blk : 0, b1 = blk >= 0 ? blk + 1 : (int)p->blocks.size();
   for (int b = b0; b < b1; ++b)
     if (p->blocks[b].am16.empty())
-      return fail(SHP_ERR_UNSUPPORTED, "block %d: BF16 contractions need an affine 3D block with P <= %d", b,
+      return fail(SHP_ERR_UNSUPPORTED, "block %d: BF16 and FP32 local-matrix contractions need an affine 3D block with P <= %d", b,
                   LOCALMAT_MAX_P);
   if (!p->ws) return fail(SHP_ERR_STATE, "no workspace bound");
   for (int b = b0; b < b1; ++b)
@@ -1120,6 +1129,18 @@ static int apply_bf16(shp_plan p, int blk, int op, int strategy, int prec, const
   const int opk = op == SHP_OP_MASS ? OPK_MASS_LM : op == SHP_OP_LAPLACIAN ? OPK_LAP_LM : OPK_HELM_LM;
   const int nparts = prec == SHP_BF16 ? 3 : 2;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (f32) {
+    for (int b = b0; b < b1; ++b) {
+      const Block& B = p->blocks[b];
+      const long long off = blk >= 0 ? 0 : B.coeff_off;
+      hipError_t e = launch_localmat_affine_f32(
+          B.d.shape, B.d.P, opk, reinterpret_cast<const float*>(p->ws + B.off_am32),
+          reinterpret_cast<const double*>(p->ws + B.off_coef), static_cast<const float*>(in) + off,
+          static_cast<float*>(out) + off, B.d.n_elem, lambda, s);
+      if (e != hipSuccess) return dev_fail(e, "FP32 local-matrix launch");
+    }
+    return SHP_OK;
+  }
   bool one_p = b1 - b0 <= 8;
   for (int b = b0; b < b1; ++b) one_p = one_p && p->blocks[b].d.P == p->blocks[b0].d.P;
   if (blk < 0 && one_p) {
@@ -1163,6 +1184,7 @@ int shp_apply_prec(shp_plan p, int blk, int op, int strategy, int prec, const vo
     return shp_apply(p, blk, op, strategy, static_cast<const double*>(in), static_cast<double*>(out), lambda, stream);
   if (prec == SHP_BF16 || prec == SHP_BF16X3) return apply_bf16(p, blk, op, strategy, prec, in, out, lambda, stream);
   if (prec != SHP_FP32) return fail(SHP_ERR_INVALID_ARG, "bad precision %d", prec);
+  if (strategy == SHP_LOCALMAT) return apply_bf16(p, blk, op, strategy, prec, in, out, lambda, stream);
   if (op != SHP_OP_HELMHOLTZ && op != SHP_OP_LAPLACIAN)
     return fail(SHP_ERR_UNSUPPORTED, "FP32 contractions cover the Laplacian and Helmholtz actions");
   if (strategy != SHP_AUTO && strategy != SHP_SUMFAC_COLL)

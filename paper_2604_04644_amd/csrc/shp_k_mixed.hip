@@ -4,6 +4,7 @@
 #include <algorithm>
 
 #include "shp_kernels.hpp"
+#include "shp_kernels_lm.hpp"
 
 namespace shp {
 
@@ -36,6 +37,29 @@ hipError_t launch_localmat_xform(int sh, int P, int opk, const LocalXformArgs& a
     case PRISM: return launch_localmat_xform_prism(P, opk, a, s);
     case PYR: return launch_localmat_xform_pyr(P, opk, a, s);
     case TET: return launch_localmat_xform_tet(P, opk, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_localmat_affine_f32_hex(int P, int opk, const AffineMatArgs32& a, hipStream_t s);
+hipError_t launch_localmat_affine_f32_prism(int P, int opk, const AffineMatArgs32& a, hipStream_t s);
+hipError_t launch_localmat_affine_f32_pyr(int P, int opk, const AffineMatArgs32& a, hipStream_t s);
+hipError_t launch_localmat_affine_f32_tet(int P, int opk, const AffineMatArgs32& a, hipStream_t s);
+
+hipError_t launch_localmat_affine_f32(int sh, int P, int opk, const float* afrag, const double* coef, const float* in,
+                                      float* out, long long n_elem, double lambda, hipStream_t s) {
+  AffineMatArgs32 a;
+  a.afrag = afrag;
+  a.coef = coef;
+  a.in = in;
+  a.out = out;
+  a.n_elem = n_elem;
+  a.lambda = lambda;
+  switch (sh) {
+    case HEX: return launch_localmat_affine_f32_hex(P, opk, a, s);
+    case PRISM: return launch_localmat_affine_f32_prism(P, opk, a, s);
+    case PYR: return launch_localmat_affine_f32_pyr(P, opk, a, s);
+    case TET: return launch_localmat_affine_f32_tet(P, opk, a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -356,6 +356,74 @@ __global__ void __launch_bounds__(256) k_localmat_xform(LocalXformArgs a) {
   }
 }
 
+// The same contraction in FP32 on v_mfma_f32_16x16x4f32 (FP32 vectors, the
+// fragment-ordered matrices rounded to FP32, coefficients rounded to FP32):
+// the operand layouts are those of the FP64 instruction, the accumulator's
+// register i holds row 4 (l/16) + i.
+typedef float flt4_ __attribute__((ext_vector_type(4)));
+
+struct AffineMatArgs32 {
+  const float* afrag;  // the FP64 fragments rounded to FP32, same order
+  const double* coef;  // [n][7]
+  const float* in;     // [n][NP]
+  float* out;          // [n][NP]
+  long long n_elem;
+  double lambda;
+};
+
+template <int SH, int P, int OP>
+__global__ void __launch_bounds__(256) k_localmat_affine_f32(AffineMatArgs32 a) {
+  constexpr int NP = num_modes(SH, P);
+  constexpr int Kp = (NP + 15) / 16 * 16;
+  constexpr int MB = Kp / 16;
+  constexpr int K0 = (OP == OPK_LAP) ? 1 : 0;
+  constexpr int K1 = (OP == OPK_MASS) ? 1 : NAFF;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const long long e0 = ((long long)blockIdx.x * (blockDim.x >> 6) + wave) * 16;
+  if (e0 >= a.n_elem) return;
+  const long long rem = a.n_elem - e0;
+  const int ne = rem < 16 ? (int)rem : 16;
+  const bool live = col < ne;
+  const long long ec = live ? e0 + col : e0;
+  float c[NAFF];
+#pragma unroll
+  for (int k = 0; k < NAFF; ++k) {
+    double cd = a.coef[ec * NAFF + k];
+    if (OP == OPK_HELM && k == 0) cd *= a.lambda;
+    c[k] = live ? (float)cd : 0.0f;
+  }
+  flt4_ acc[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) acc[mb] = flt4_{0.0f, 0.0f, 0.0f, 0.0f};
+  const float* Af = a.afrag + lane;
+  const float* X = a.in + ec * NP;
+  float xn = X[kq < NP ? kq : NP - 1];
+  for (int kb = 0; kb < (NP + 3) / 4; ++kb) {
+    const int n = 4 * kb + kq;
+    const float xb = (live && n < NP) ? xn : 0.0f;
+    xn = X[n + 4 < NP ? n + 4 : NP - 1];
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+      float av[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) av[mb] = Af[(long long)((kb * NAFF + k) * MB + mb) * 64];
+      const float b = xb * c[k];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], b, acc[mb], 0, 0, 0);
+    }
+  }
+  if (!live) return;
+  float* Y = a.out + (e0 + col) * NP;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = mb * 16 + 4 * kq + i;
+      if (m < NP) Y[m] = acc[mb][i];
+    }
+}
+
 template <int SH, int P>
 constexpr size_t lds_bytes_localmat() {
   constexpr int Kp = (num_modes(SH, P) + 15) / 16 * 16;

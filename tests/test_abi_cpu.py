@@ -141,6 +141,7 @@ def test_error_paths_without_device(L):
     assert L.shp_apply_prec(h, -1, 6, 3, 2, p, p, 1.0, None) == -2    # BF16 on curved blocks
     assert L.shp_apply_prec(h, 0, 6, 3, 3, p, p, 1.0, None) == -2     # BF16x3 on a curved block
     assert L.shp_apply_prec(h, -1, 1, 3, 2, p, p, 1.0, None) == -2    # BF16 inner product
+    assert L.shp_apply_prec(h, -1, 6, 3, 1, p, p, 1.0, None) == -2    # FP32 local matrices, curved blocks
     assert L.shp_apply_prec(h, -1, 6, 2, 5, p, p, 1.0, None) == -1    # bad precision
     assert L.shp_apply_prec(h, -1, 4, 2, 1, p, p, 1.0, None) == -2    # FP32 mass
     assert L.shp_apply_prec(h, 0, 6, 2, 1, p, p, 1.0, None) == -2     # FP32 per block

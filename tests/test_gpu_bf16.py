@@ -133,6 +133,35 @@ def test_bf16_action_vs_oracle(shp, shape, P, prec):
     say(f"    worst {worst:.2e} of the scale")
 
 
+@pytest.mark.parametrize("shape,P", [(s, P) for s in O.SHAPES for P in (1, 2, 3, 4)])
+def test_fp32_localmat_vs_oracle(shp, shape, P):
+    """The affine local matrices in FP32 on the FP32 matrix cores (matrices
+    and coefficients rounded to FP32, FP32 accumulation): the error of the FP32
+    roundings (2^-24 of each matrix entry, coefficient and product) and of the
+    accumulation over K = 7 N_P terms, under the three-part BF16 bar; whole
+    mesh and single block launches agree."""
+    ne = 83
+    say(f"[fp32 localmat] shape={shape} P={P} n_elem={ne}")
+    maps = W.shape_batch(shape, ne)
+    NP = O.num_modes(shape, P)
+    plan = affine_plan(shp, [(shape, P, maps)])
+    jac = W.affine_jacobian(maps)
+    worst = 0.0
+    for k, op in enumerate(("mass", "laplacian", "helmholtz")):
+        x = W.coeffs(ne, NP, 920 + k).astype(np.float32)
+        xt = torch.from_numpy(x).cuda()
+        y = plan.apply_prec(op, xt, lam=LAM, prec="fp32", blk=0, strategy="localmat").cpu().numpy()
+        yw = plan.apply_prec(op, xt.reshape(-1), lam=LAM, prec="fp32", strategy="localmat").cpu().numpy()
+        assert np.array_equal(y.ravel(), yw.ravel())
+        x64 = x.astype(np.float64)
+        ref = O.apply_op(op, shape, P, P + 2, jac, x64, lam=LAM)
+        s = scale(shape, P, jac, x64, op, LAM)
+        e = float(np.abs(y.astype(np.float64) - ref).max() / s.max())
+        worst = max(worst, e)
+        assert e <= BAR["bf16"], (shape, op, e)
+    say(f"    worst {worst:.2e} of the scale")
+
+
 @pytest.mark.parametrize("orders", ["one", "mixed"])
 def test_bf16_whole_mesh_equals_blocks(shp, orders):
     """blk = -1 over affine blocks of every shape equals the per-block launches
