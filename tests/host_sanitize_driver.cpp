@@ -84,6 +84,32 @@ int main() {
           build_localmat(sh, P, pts, bcat, Q3p, Kp);
           build_affine_mats(sh, P, pts, acat, Ka);
           CHECK(!bcat.empty() && !acat.empty() && (int)acat.size() == NAFF * Ka * Ka);
+          // dense collocation derivatives: every row sums to zero (the
+          // derivative of a constant), the padding rows are zero, and a row
+          // couples only points that differ in index d
+          std::vector<double> dm;
+          int q3p = 0;
+          build_dense_deriv(sh, P, pts, dm, q3p);
+          CHECK((int)dm.size() == 3 * q3p * q3p);
+          const int Q3n = Q * Q * Q;
+          for (int d = 0; d < 3; ++d)
+            for (int r = 0; r < q3p; ++r) {
+              double rs = 0.0, ra = 0.0;
+              int off = 0;
+              for (int c = 0; c < q3p; ++c) {
+                const double v = dm[((size_t)d * q3p + r) * q3p + c];
+                rs += v;
+                ra += std::fabs(v);
+                if (v != 0.0 && r < Q3n && c < Q3n) {
+                  const int ri[3] = {r / (Q * Q), (r / Q) % Q, r % Q}, ci[3] = {c / (Q * Q), (c / Q) % Q, c % Q};
+                  for (int o = 0; o < 3; ++o)
+                    if (o != d && ri[o] != ci[o]) ++off;
+                }
+              }
+              CHECK(std::fabs(rs) <= 1e-10 * (1.0 + ra));
+              CHECK(r < Q3n || ra == 0.0);
+              CHECK(off == 0);
+            }
           // the BF16 parts sum to the FP64 matrices within 2^-26 of each
           // entry (or 1e-38 where the last part falls among FP32's subnormals:
           // entries of 1e-34 are rounding noise of zero), and the padding is zero
