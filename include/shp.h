@@ -306,7 +306,9 @@ int shp_helmholtz_diag(shp_plan plan, double lambda, double* diag /* device out 
  * by r = b - H x from the FP64 action; the iteration then continues from it
  * with its search direction kept, or restarts the direction when the true
  * residual exceeds the recursive one twice over (rounding near the floor of
- * the FP64 residual).  The residual enters the inner precision scaled by
+ * the FP64 residual).  The FP64 actions follow the plan's SHP_AUTO choice for
+ * the whole mesh (tuned, set with shp_set_auto_strategy, or a loaded cost
+ * model's; by default the collocated sum-factorisation).  The residual enters the inner precision scaled by
  * 1/max|r_0|.  An update that does not lower the FP64 residual is undone
  * (the direction restarts from the previous x); five in a row end the solve,
  * as do max_outer updates or max_inner iterations, and x then holds the

@@ -260,12 +260,14 @@ int apply_inner(shp_plan plan, const T* in, T* out, double lambda, int prec, hip
       return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_LOCALMAT, prec, in, out, lambda, s);
     return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, SHP_FP32, in, out, lambda, s);
   } else {
-    return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, SHP_FP64, in, out, lambda, s);
+    return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_AUTO, SHP_FP64, in, out, lambda, s);
   }
 }
 
 // The operators of the solve: the FP64 action apply64 and the action in the
-// inner type.  ElemOp is the block-diagonal elemental H; C0Op the assembled
+// inner type.  The FP64 actions take the plan's SHP_AUTO choice for the whole
+// mesh (tuned or set, or a loaded cost model's; by default the collocated
+// sum-factorisation), e.g. the local matrices of an affine mesh.  ElemOp is the block-diagonal elemental H; C0Op the assembled
 // operator A^T H A of a local-to-global map A (gather, elemental action,
 // scatter-sum).
 struct ElemOp {
@@ -273,7 +275,7 @@ struct ElemOp {
   double lambda;
   int prec;  // inner precision
   int apply64(const double* x, double* y, hipStream_t s) const {
-    return shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, x, y, lambda, s);
+    return shp_apply(plan, -1, SHP_OP_HELMHOLTZ, SHP_AUTO, x, y, lambda, s);
   }
   template <typename T>
   int apply(const T* x, T* y, hipStream_t s) const {
