@@ -7,7 +7,7 @@ namespace shp {
 
 template <int SH, int P, int OP, int NPART>
 static hipError_t launch_bf16_op(const AffineBf16Args& a, hipStream_t s) {
-  const long long nwave = (a.n_elem + 15) / 16 * bf16_waves_per_tile<SH, P>();
+  const long long nwave = bf16_waves<SH, P>((a.n_elem + 15) / 16);
   if (nwave <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_localmat_affine_bf16<SH, P, OP, NPART>), dim3((unsigned)((nwave + 3) / 4)), dim3(256), 0, s,
                      a);
@@ -15,12 +15,12 @@ static hipError_t launch_bf16_op(const AffineBf16Args& a, hipStream_t s) {
 }
 
 template <int P>
-static int waves_per_tile(int sh) {
+static long long block_waves(int sh, long long ntile) {
   switch (sh) {
-    case HEX: return bf16_waves_per_tile<HEX, P>();
-    case PRISM: return bf16_waves_per_tile<PRISM, P>();
-    case PYR: return bf16_waves_per_tile<PYR, P>();
-    default: return bf16_waves_per_tile<TET, P>();
+    case HEX: return bf16_waves<HEX, P>(ntile);
+    case PRISM: return bf16_waves<PRISM, P>(ntile);
+    case PYR: return bf16_waves<PYR, P>(ntile);
+    default: return bf16_waves<TET, P>(ntile);
   }
 }
 
@@ -29,7 +29,7 @@ static hipError_t launch_bf16_mesh_pn(int opk, AffineBf16Mesh& m, hipStream_t s)
   long long g = 0;
   for (int b = 0; b < m.nblk; ++b) {
     m.wg0[b] = g;
-    g += ((m.blk[b].n_elem + 15) / 16 * waves_per_tile<P>(m.shape[b]) + 3) / 4;
+    g += (block_waves<P>(m.shape[b], (m.blk[b].n_elem + 15) / 16) + 3) / 4;
   }
   m.wg0[m.nblk] = g;
   if (g <= 0) return hipSuccess;

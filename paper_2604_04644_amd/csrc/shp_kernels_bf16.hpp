@@ -57,11 +57,20 @@ constexpr int bf16_mbw() {
   return (MB + NW - 1) / NW;
 }
 
-// waves of a block: (MB / MBW) per 16-element tile
+// tiles of 16 elements per wave: each A fragment a wave loads serves
+// BF16_G tiles' MFMAs
+constexpr int BF16_G = 2;
+
+// waves of a block of ntile 16-element tiles: (MB / MBW) per group of BF16_G
 template <int SH, int P>
 constexpr int bf16_waves_per_tile() {
   constexpr int MB = (num_modes(SH, P) + 15) / 16;
   return (MB + bf16_mbw<SH, P>() - 1) / bf16_mbw<SH, P>();
+}
+
+template <int SH, int P>
+constexpr long long bf16_waves(long long ntile) {
+  return (ntile + BF16_G - 1) / BF16_G * bf16_waves_per_tile<SH, P>();
 }
 
 // wave w of one block
@@ -72,59 +81,74 @@ __device__ __forceinline__ void bf16_wave(const AffineBf16Args& a, long long w) 
   constexpr int MB = (NP + 15) / 16;
   constexpr int MBW = bf16_mbw<SH, P>();
   constexpr int NMW = bf16_waves_per_tile<SH, P>();
+  constexpr int G = BF16_G;
   constexpr int K0 = (OP == OPK_LAP) ? NPp : 0;           // the Laplacian has no mass term
   constexpr int K1 = (OP == OPK_MASS) ? NPp : NAFF * NPp;  // the mass has only A_0
   constexpr int KB0 = K0 / 32, KB1 = (K1 + 31) / 32;
   const int lane = threadIdx.x & 63;
-  const long long e0 = (w / NMW) * 16;
+  const long long eg = (w / NMW) * (16 * G);  // first element of the wave's tiles
   const int mb0 = (int)(w % NMW) * MBW;
-  if (e0 >= a.n_elem) return;  // whole waves only
+  if (eg >= a.n_elem) return;  // whole waves only
   const int col = lane & 15, kq = lane >> 4;
-  const long long e = e0 + col;
-  const bool live = e < a.n_elem;
-  const long long ec = live ? e : e0;  // dead lanes read a live element (no branches around loads)
-  float c[NAFF];
+  bool live[G];
+  long long ee[G];
+  float c[G][NAFF];
+  const float* X[G];
 #pragma unroll
-  for (int k = 0; k < NAFF; ++k) {
-    double cd = a.coef[ec * NAFF + k];
-    if (OP == OPK_HELM && k == 0) cd *= a.lambda;
-    c[k] = live ? (float)cd : 0.0f;
+  for (int g = 0; g < G; ++g) {
+    ee[g] = eg + 16 * g + col;
+    live[g] = ee[g] < a.n_elem;
+    const long long ec = live[g] ? ee[g] : eg;  // dead lanes read a live element (no branches around loads)
+#pragma unroll
+    for (int k = 0; k < NAFF; ++k) {
+      double cd = a.coef[ec * NAFF + k];
+      if (OP == OPK_HELM && k == 0) cd *= a.lambda;
+      c[g][k] = live[g] ? (float)cd : 0.0f;
+    }
+    X[g] = a.in + ec * NP;
   }
-  const float* X = a.in + ec * NP;
-  flt4 acc[MBW];
+  flt4 acc[G][MBW];
 #pragma unroll
-  for (int i = 0; i < MBW; ++i) acc[i] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int i = 0; i < MBW; ++i) acc[g][i] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
   // this lane's 8 K values of step kb: matrix k = kappa / NPp, modes n0 .. n0
   // + 7; loads from clamped (in-bounds) indices without branches, so that a
   // step's loads are in flight together and the next step's during this one
-  auto load = [&](int kb, float* v) {
+  auto load = [&](int kb, float (*v)[8]) {
     const int kap0 = 32 * kb + 8 * kq;
     const int n0 = kap0 - (kap0 / NPp) * NPp;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = X[n0 + j < NP ? n0 + j : NP - 1];
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[g][j] = X[g][n0 + j < NP ? n0 + j : NP - 1];
   };
-  float xv[8];
+  float xv[G][8];
   load(KB0, xv);
   for (int kb = KB0; kb < KB1; ++kb) {
-    float xn[8];
+    float xn[G][8];
     load(kb + 1 < KB1 ? kb + 1 : kb, xn);
     const int kap0 = 32 * kb + 8 * kq;
     const int k = kap0 / NPp, n0 = kap0 - k * NPp;
-    const bool on = kap0 >= K0 && kap0 < K1 && live;
-    float ck = c[0];
+    const bool kin = kap0 >= K0 && kap0 < K1;
+    u32x4 bw[G][NPART];
 #pragma unroll
-    for (int kk = 1; kk < NAFF; ++kk) ck = (k == kk) ? c[kk] : ck;
-    u32x4 bw[NPART];
+    for (int g = 0; g < G; ++g) {
+      float ck = c[g][0];
 #pragma unroll
-    for (int j2 = 0; j2 < 4; ++j2) {
-      float v0 = (on && n0 + 2 * j2 < NP) ? ck * xv[2 * j2] : 0.0f;
-      float v1 = (on && n0 + 2 * j2 + 1 < NP) ? ck * xv[2 * j2 + 1] : 0.0f;
+      for (int kk = 1; kk < NAFF; ++kk) ck = (k == kk) ? c[g][kk] : ck;
+      const bool on = kin && live[g];
 #pragma unroll
-      for (int pt = 0; pt < NPART; ++pt) {
-        const unsigned u0 = __float_as_uint(v0) & 0xFFFF0000u, u1 = __float_as_uint(v1) & 0xFFFF0000u;
-        bw[pt][j2] = (u0 >> 16) | u1;  // K value 2 j2 in the low half, 2 j2 + 1 in the high half
-        v0 -= __uint_as_float(u0);
-        v1 -= __uint_as_float(u1);
+      for (int j2 = 0; j2 < 4; ++j2) {
+        float v0 = (on && n0 + 2 * j2 < NP) ? ck * xv[g][2 * j2] : 0.0f;
+        float v1 = (on && n0 + 2 * j2 + 1 < NP) ? ck * xv[g][2 * j2 + 1] : 0.0f;
+#pragma unroll
+        for (int pt = 0; pt < NPART; ++pt) {
+          const unsigned u0 = __float_as_uint(v0) & 0xFFFF0000u, u1 = __float_as_uint(v1) & 0xFFFF0000u;
+          bw[g][pt][j2] = (u0 >> 16) | u1;  // K value 2 j2 in the low half, 2 j2 + 1 in the high half
+          v0 -= __uint_as_float(u0);
+          v1 -= __uint_as_float(u1);
+        }
       }
     }
     const bf16x8* Af = a.afrag + ((long long)kb * MB + mb0) * (BF16_PARTS * 64) + lane;
@@ -136,21 +160,29 @@ __device__ __forceinline__ void bf16_wave(const AffineBf16Args& a, long long w) 
         const bf16x8 av = Af[(i * BF16_PARTS + pa) * 64];
 #pragma unroll
         for (int pb = 0; pb + pa < NPART; ++pb)
-          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, bw[pb]), acc[i], 0, 0, 0);
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+            acc[g][i] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, bw[g][pb]), acc[g][i], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) xv[j] = xn[j];
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xv[g][j] = xn[g][j];
   }
-  if (!live) return;
-  float* Y = a.out + e * NP;
 #pragma unroll
-  for (int i = 0; i < MBW; ++i)
+  for (int g = 0; g < G; ++g) {
+    if (!live[g]) continue;
+    float* Y = a.out + ee[g] * NP;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = (mb0 + i) * 16 + 4 * kq + r;
-      if (mb0 + i < MB && m < NP) Y[m] = acc[i][r];
-    }
+    for (int i = 0; i < MBW; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = (mb0 + i) * 16 + 4 * kq + r;
+        if (mb0 + i < MB && m < NP) Y[m] = acc[g][i][r];
+      }
+  }
 }
 
 template <int SH, int P, int OP, int NPART>
