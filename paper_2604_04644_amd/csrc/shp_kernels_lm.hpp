@@ -141,11 +141,51 @@ __global__ void __launch_bounds__(256) k_localmat(LocalMatArgs a) {
 // reference matrices, H_e = lambda |J| A_0 + sum_{k=1..6} c_{e,k} A_k (mass and
 // the xi-space stiffness blocks, built from the same quadrature), so
 //   Y = [A_0 ... A_6] [c_0 X; ...; c_6 X]
-// is one dense FP64 contraction with K = 7 N_P per 16-element tile.  Each
-// wave owns a tile: its B operand is the tile's coefficients scaled by the
-// element's c_k, and the A fragments stream from a fragment-ordered copy of
-// the matrices (64 consecutive doubles per fragment, one per lane):
+// is one dense FP64 contraction with K = 7 N_P per 16-element tile.  A
+// tile's B operand is its coefficients scaled by the element's c_k, and the A
+// fragments stream from a fragment-ordered copy of the matrices (64
+// consecutive doubles per fragment, one per lane):
 //   afrag[((kb * 7 + k) * MB + mb) * 64 + lane] = A_k[16 mb + lane%16][4 kb + lane/16].
+
+// Work per wave of the affine kernels: G 16-element tiles that share every A
+// fragment the wave loads (G MFMAs per fragment load), and MBW of the tile's
+// row blocks (the tile's rows are split among MB / MBW waves).  Every MFMA
+// takes its own A fragment, so a row split repeats only the cheap B operand;
+// it gives a mesh block of a few thousand elements enough waves to hide the
+// fragment loads from L2.  Measured on every shape at P = 3 and 4, at the
+// mesh blocks' sizes and at 4M DOF: one row block and two tiles per wave is
+// fastest in FP64 at every order (hex P = 4, 8192 elements: 95 -> 47 us;
+// 32000: 172 -> 157 us), except on tetrahedra, whose few row blocks stay in
+// one wave (and at P = 4 one tile per wave).  Uneven splits (a last wave
+// with fewer row blocks) measured far slower and are not offered.
+template <int SH, int P>
+__host__ __device__ constexpr int lm_row_blocks() {
+  return (num_modes(SH, P) + 15) / 16;
+}
+template <int SH, int P>
+__host__ __device__ constexpr int lm_rows_per_wave() {
+  return SH == TET ? lm_row_blocks<SH, P>() : 1;
+}
+template <int SH, int P>
+__host__ __device__ constexpr int lm_tiles_per_wave() {
+  return (SH == TET && P == 4) ? 1 : 2;
+}
+// The FP32 kernel (half the fragment bytes) gains from the split and the
+// shared fragments at P = 4 only (and hex P = 3 from two tiles per wave);
+// below, one tile and all its row blocks per wave measured fastest.
+template <int SH, int P>
+__host__ __device__ constexpr int lm32_rows_per_wave() {
+  return (P == 4 && SH != TET) ? 1 : lm_row_blocks<SH, P>();
+}
+template <int SH, int P>
+__host__ __device__ constexpr int lm32_tiles_per_wave() {
+  return ((P == 4 && SH != TET) || (P == 3 && SH == HEX)) ? 2 : 1;
+}
+// waves of a launch over n_elem elements with G tiles and MBW row blocks per wave
+template <int SH, int P>
+__host__ __device__ constexpr long long lm_waves(long long n_elem, int G, int MBW) {
+  return ((n_elem + 15) / 16 + G - 1) / G * (lm_row_blocks<SH, P>() / MBW);
+}
 
 struct AffineMatArgs {
   const double* afrag;  // fragment-ordered reference matrices
@@ -156,58 +196,78 @@ struct AffineMatArgs {
   double lambda;
 };
 
-template <int SH, int P, int OP>
+template <int SH, int P, int OP, int G = lm_tiles_per_wave<SH, P>(), int MBW = lm_rows_per_wave<SH, P>()>
 __global__ void __launch_bounds__(256) k_localmat_affine(AffineMatArgs a) {
   constexpr int NP = num_modes(SH, P);
-  constexpr int Kp = (NP + 15) / 16 * 16;
-  constexpr int MB = Kp / 16;
+  constexpr int MB = lm_row_blocks<SH, P>();
+  static_assert(MB % MBW == 0, "a tile's row blocks split evenly among its waves");
+  constexpr int W = MB / MBW;
   constexpr int K0 = (OP == OPK_LAP) ? 1 : 0;     // the Laplacian has no mass term
   constexpr int K1 = (OP == OPK_MASS) ? 1 : NAFF;  // the mass has only A_0
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
-  const long long e0 = ((long long)blockIdx.x * (blockDim.x >> 6) + wave) * 16;
+  const long long gw = (long long)blockIdx.x * (blockDim.x >> 6) + wave;
+  const long long e0 = gw / W * (16 * G);  // the wave's first element
+  const int mb0 = (int)(gw % W) * MBW;     // and first row block
   if (e0 >= a.n_elem) return;  // whole waves only: no barriers below
-  const long long rem = a.n_elem - e0;
-  const int ne = rem < 16 ? (int)rem : 16;
-  const bool live = col < ne;
-  // dead lanes read a live element: no branches around the loads, so that
-  // a step's loads are in flight together
-  const long long ec = live ? e0 + col : e0;
-  double c[NAFF];
+  bool live[G];
+  long long ec[G];
+  double c[G][NAFF];
 #pragma unroll
-  for (int k = 0; k < NAFF; ++k) c[k] = live ? a.coef[ec * NAFF + k] : 0.0;
-  if (OP == OPK_HELM) c[0] *= a.lambda;
-  dbl4 acc[MB];
+  for (int g = 0; g < G; ++g) {
+    live[g] = e0 + 16 * g + col < a.n_elem;
+    // dead lanes read a live element: no branches around the loads, so that
+    // a step's loads are in flight together
+    ec[g] = live[g] ? e0 + 16 * g + col : e0;
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) acc[mb] = dbl4{0.0, 0.0, 0.0, 0.0};
-  const gptr_t Af = as_global(a.afrag) + lane;
-  const gptr_t X = as_global(a.in) + ec * NP;
+    for (int k = 0; k < NAFF; ++k) c[g][k] = live[g] ? a.coef[ec[g] * NAFF + k] : 0.0;
+    if (OP == OPK_HELM) c[g][0] *= a.lambda;
+  }
+  dbl4 acc[G][MBW];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int j = 0; j < MBW; ++j) acc[g][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const gptr_t Af = as_global(a.afrag) + (long long)mb0 * 64 + lane;
+  const gptr_t X = as_global(a.in);
   // K steps of 4 up to N_P only: the columns of A_k past N_P are zero padding
   // (at N_P = 4 that is one step of the four a 16-wide padding would take)
-  double xn = X[kq < NP ? kq : NP - 1];
+  double xn[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) xn[g] = X[ec[g] * NP + (kq < NP ? kq : NP - 1)];
   for (int kb = 0; kb < (NP + 3) / 4; ++kb) {
     const int n = 4 * kb + kq;
-    const double xb = (live && n < NP) ? xn : 0.0;
     const int nn = n + 4 < NP ? n + 4 : NP - 1;
-    xn = X[nn];  // the next step's value, in flight during this one
+    double xb[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      xb[g] = (live[g] && n < NP) ? xn[g] : 0.0;
+      xn[g] = X[ec[g] * NP + nn];  // the next step's value, in flight during this one
+    }
 #pragma unroll
     for (int k = K0; k < K1; ++k) {
-      double av[MB];  // the step's fragments of A_k, loaded together
+      double av[MBW];  // the step's fragments of A_k, loaded together
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) av[mb] = Af[(long long)((kb * NAFF + k) * MB + mb) * 64];
-      const double b = xb * c[k];
+      for (int j = 0; j < MBW; ++j) av[j] = Af[(long long)((kb * NAFF + k) * MB + j) * 64];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mb], b, acc[mb], 0, 0, 0);
+      for (int g = 0; g < G; ++g) {
+        const double b = xb[g] * c[g][k];
+#pragma unroll
+        for (int j = 0; j < MBW; ++j) acc[g][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], b, acc[g][j], 0, 0, 0);
+      }
     }
   }
-  double* Y = a.out + (e0 + col) * NP;
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
+  for (int g = 0; g < G; ++g) {
+    double* Y = a.out + (e0 + 16 * g + col) * NP;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int m = mb * 16 + 4 * i + kq;
-      if (live && m < NP) Y[m] = acc[mb][i];
-    }
+    for (int j = 0; j < MBW; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = (mb0 + j) * 16 + 4 * i + kq;
+        if (live[g] && m < NP) Y[m] = acc[g][j][i];
+      }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -371,57 +431,78 @@ struct AffineMatArgs32 {
   double lambda;
 };
 
-template <int SH, int P, int OP>
+template <int SH, int P, int OP, int G = lm32_tiles_per_wave<SH, P>(), int MBW = lm32_rows_per_wave<SH, P>()>
 __global__ void __launch_bounds__(256) k_localmat_affine_f32(AffineMatArgs32 a) {
   constexpr int NP = num_modes(SH, P);
-  constexpr int Kp = (NP + 15) / 16 * 16;
-  constexpr int MB = Kp / 16;
+  constexpr int MB = lm_row_blocks<SH, P>();
+  static_assert(MB % MBW == 0, "a tile's row blocks split evenly among its waves");
+  constexpr int W = MB / MBW;
   constexpr int K0 = (OP == OPK_LAP) ? 1 : 0;
   constexpr int K1 = (OP == OPK_MASS) ? 1 : NAFF;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
-  const long long e0 = ((long long)blockIdx.x * (blockDim.x >> 6) + wave) * 16;
+  const long long gw = (long long)blockIdx.x * (blockDim.x >> 6) + wave;
+  const long long e0 = gw / W * (16 * G);
+  const int mb0 = (int)(gw % W) * MBW;
   if (e0 >= a.n_elem) return;
-  const long long rem = a.n_elem - e0;
-  const int ne = rem < 16 ? (int)rem : 16;
-  const bool live = col < ne;
-  const long long ec = live ? e0 + col : e0;
-  float c[NAFF];
+  bool live[G];
+  long long ec[G];
+  float c[G][NAFF];
 #pragma unroll
-  for (int k = 0; k < NAFF; ++k) {
-    double cd = a.coef[ec * NAFF + k];
-    if (OP == OPK_HELM && k == 0) cd *= a.lambda;
-    c[k] = live ? (float)cd : 0.0f;
+  for (int g = 0; g < G; ++g) {
+    live[g] = e0 + 16 * g + col < a.n_elem;
+    ec[g] = live[g] ? e0 + 16 * g + col : e0;
+#pragma unroll
+    for (int k = 0; k < NAFF; ++k) {
+      double cd = a.coef[ec[g] * NAFF + k];
+      if (OP == OPK_HELM && k == 0) cd *= a.lambda;
+      c[g][k] = live[g] ? (float)cd : 0.0f;
+    }
   }
-  flt4_ acc[MB];
+  flt4_ acc[G][MBW];
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) acc[mb] = flt4_{0.0f, 0.0f, 0.0f, 0.0f};
-  const float* Af = a.afrag + lane;
-  const float* X = a.in + ec * NP;
-  float xn = X[kq < NP ? kq : NP - 1];
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int j = 0; j < MBW; ++j) acc[g][j] = flt4_{0.0f, 0.0f, 0.0f, 0.0f};
+  const float* Af = a.afrag + (long long)mb0 * 64 + lane;
+  const float* X = a.in;
+  float xn[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) xn[g] = X[ec[g] * NP + (kq < NP ? kq : NP - 1)];
   for (int kb = 0; kb < (NP + 3) / 4; ++kb) {
     const int n = 4 * kb + kq;
-    const float xb = (live && n < NP) ? xn : 0.0f;
-    xn = X[n + 4 < NP ? n + 4 : NP - 1];
+    const int nn = n + 4 < NP ? n + 4 : NP - 1;
+    float xb[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      xb[g] = (live[g] && n < NP) ? xn[g] : 0.0f;
+      xn[g] = X[ec[g] * NP + nn];
+    }
 #pragma unroll
     for (int k = K0; k < K1; ++k) {
-      float av[MB];
+      float av[MBW];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) av[mb] = Af[(long long)((kb * NAFF + k) * MB + mb) * 64];
-      const float b = xb * c[k];
+      for (int j = 0; j < MBW; ++j) av[j] = Af[(long long)((kb * NAFF + k) * MB + j) * 64];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], b, acc[mb], 0, 0, 0);
+      for (int g = 0; g < G; ++g) {
+        const float b = xb[g] * c[g][k];
+#pragma unroll
+        for (int j = 0; j < MBW; ++j) acc[g][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], b, acc[g][j], 0, 0, 0);
+      }
     }
   }
-  if (!live) return;
-  float* Y = a.out + (e0 + col) * NP;
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
+  for (int g = 0; g < G; ++g) {
+    if (!live[g]) continue;
+    float* Y = a.out + (e0 + 16 * g + col) * NP;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int m = mb * 16 + 4 * kq + i;
-      if (m < NP) Y[m] = acc[mb][i];
-    }
+    for (int j = 0; j < MBW; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = (mb0 + j) * 16 + 4 * kq + i;
+        if (m < NP) Y[m] = acc[g][j][i];
+      }
+  }
 }
 
 template <int SH, int P>
