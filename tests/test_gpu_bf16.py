@@ -162,6 +162,45 @@ def test_fp32_localmat_vs_oracle(shp, shape, P):
     say(f"    worst {worst:.2e} of the scale")
 
 
+@pytest.mark.parametrize("shape,P", [(s, P) for s in O.SHAPES for P in (1, 3, 4)])
+def test_affine_localmat_wide_launch(shp, shape, P):
+    """Affine blocks large enough that the local-matrix launches take their
+    wide form (two 16-element tiles per wave sharing every A fragment, a
+    tile's row blocks split among waves): 33013 elements, a ragged last
+    tile.  FP64 and FP32 Helmholtz against the oracle on sampled elements
+    (the first 40, the last 21, 24 random ones), and the first 37 elements
+    bit for bit equal to a 37-element launch (one tile per wave)."""
+    ne, ns = 33013, 37
+    say(f"[localmat wide] shape={shape} P={P} n_elem={ne}")
+    maps = W.shape_batch(shape, ne)
+    NP = O.num_modes(shape, P)
+    jac = np.ascontiguousarray(W.affine_jacobian(maps))
+    plan = shp.Plan([(shape, P, ne, "affine")])
+    plan.set_geometry(0, torch.from_numpy(jac).cuda())
+    small = shp.Plan([(shape, P, ns, "affine")])
+    small.set_geometry(0, torch.from_numpy(np.ascontiguousarray(jac[:ns])).cuda())
+    rng = np.random.default_rng(941)
+    idx = np.unique(np.concatenate([np.arange(40), np.arange(ne - 21, ne), rng.integers(0, ne, 24)]))
+    x = W.coeffs(ne, NP, 940)
+    for prec, bar in (("fp64", 1e-12), ("fp32", BAR["bf16"])):
+        xs = x if prec == "fp64" else x.astype(np.float32)
+        xt = torch.from_numpy(np.ascontiguousarray(xs)).cuda()
+        if prec == "fp64":
+            y = plan.apply(0, "helmholtz", xt, lam=LAM, strategy="localmat")
+            ys = small.apply(0, "helmholtz", xt[:ns].contiguous(), lam=LAM, strategy="localmat")
+        else:
+            y = plan.apply_prec("helmholtz", xt, lam=LAM, prec="fp32", blk=0, strategy="localmat")
+            ys = small.apply_prec("helmholtz", xt[:ns].contiguous(), lam=LAM, prec="fp32", blk=0, strategy="localmat")
+        y, ys = y.cpu().numpy().reshape(ne, NP), ys.cpu().numpy().reshape(ns, NP)
+        assert np.array_equal(y[:ns], ys), (shape, P, prec)
+        x64 = xs[idx].astype(np.float64)
+        ref = O.apply_op("helmholtz", shape, P, P + 2, jac[idx], x64, lam=LAM)
+        s = scale(shape, P, jac[idx], x64, "helmholtz", LAM)
+        e = float(np.abs(y[idx].astype(np.float64) - ref).max() / s.max())
+        say(f"    {prec} {e:.2e} of the scale")
+        assert e <= bar, (shape, P, prec, e)
+
+
 @pytest.mark.parametrize("orders", ["one", "mixed"])
 def test_bf16_whole_mesh_equals_blocks(shp, orders):
     """blk = -1 over affine blocks of every shape equals the per-block launches
