@@ -57,8 +57,10 @@ struct Block {
   std::vector<int> itab;
   size_t off_tab = 0, off_itab = 0, off_fac = 0, off_dxi = 0, off_lm = 0, off_tabf = 0;
   std::vector<double> lm;  // [B; d_d B] for the local-matrix strategy (P <= 4)
-  std::vector<double> dm;  // dense collocation derivatives [3][Q3p][Q3p] (local-matrix PhysDeriv)
+  std::vector<double> dm;  // dense collocation derivatives, each transposed: [3][Q3p in][Q3p out] (local-matrix PhysDeriv)
   size_t off_dm = 0;
+  std::vector<double> bt;  // B transposed, [Kp][Q3p] (local-matrix BwdTrans)
+  size_t off_bt = 0;
   std::vector<double> am;  // affine blocks: 7 reference matrices, MFMA fragment order
   size_t off_am = 0, off_coef = 0;
   std::vector<uint16_t> am16;  // the same as BF16 parts, BF16 MFMA fragment order
@@ -366,6 +368,16 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
       int q3p, kp;
       build_localmat(B.d.shape, B.d.P, B.d.pts, B.lm, q3p, kp);
       build_dense_deriv(B.d.shape, B.d.P, B.d.pts, B.dm, q3p);
+      // the BwdTrans and PhysDeriv kernels read their matrices with the
+      // output point fastest across lanes: store B and each D_d transposed
+      B.bt.assign((size_t)kp * q3p, 0.0);
+      for (int pt = 0; pt < q3p; ++pt)
+        for (int m = 0; m < kp; ++m) B.bt[(size_t)m * q3p + pt] = B.lm[(size_t)pt * kp + m];
+      for (int d = 0; d < 3; ++d) {
+        double* D = B.dm.data() + (size_t)d * q3p * q3p;
+        for (int i = 0; i < q3p; ++i)
+          for (int j = i + 1; j < q3p; ++j) std::swap(D[(size_t)i * q3p + j], D[(size_t)j * q3p + i]);
+      }
       if (B.d.geom == SHP_AFFINE) {
         build_affine_mats(B.d.shape, B.d.P, B.d.pts, B.am, kp);
         B.am32.assign(B.am.begin(), B.am.end());
@@ -399,6 +411,8 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
     off = align_up(off + sizeof(double) * B.lm.size());
     B.off_dm = off;
     off = align_up(off + sizeof(double) * B.dm.size());
+    B.off_bt = off;
+    off = align_up(off + sizeof(double) * B.bt.size());
     B.off_tabf = off;
     off = align_up(off + sizeof(float) * B.tab.size());
     B.off_am = off;
@@ -504,6 +518,8 @@ int shp_plan_bind_workspace(shp_plan p, void* ws, size_t ws_bytes, void* stream)
       e = hipMemcpyAsync(p->ws + B.off_lm, B.lm.data(), sizeof(double) * B.lm.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.dm.empty())
       e = hipMemcpyAsync(p->ws + B.off_dm, B.dm.data(), sizeof(double) * B.dm.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !B.bt.empty())
+      e = hipMemcpyAsync(p->ws + B.off_bt, B.bt.data(), sizeof(double) * B.bt.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.am.empty())
       e = hipMemcpyAsync(p->ws + B.off_am, B.am.data(), sizeof(double) * B.am.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B.am32.empty())
@@ -1010,12 +1026,14 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
         LocalXformArgs xa;
         xa.bcat = reinterpret_cast<const double*>(p->ws + B.off_lm);
         xa.dmat = reinterpret_cast<const double*>(p->ws + B.off_dm);
+        xa.bt = reinterpret_cast<const double*>(p->ws + B.off_bt);
         xa.fac = reinterpret_cast<const double*>(p->ws + B.off_fac);
         xa.dxi = reinterpret_cast<const double*>(p->ws + B.off_dxi);
         xa.in = in + (blk >= 0 ? 0 : (in_is_modes(opk) ? B.coeff_off : B.phys_off));
         xa.out = out + (blk >= 0 ? 0 : (out_is_modes(opk) ? B.coeff_off : B.phys_off));
         xa.n_elem = B.d.n_elem;
         xa.in_cs = xa.out_cs = (blk >= 0) ? B.d.n_elem * (long long)B.NQ : p->total_phys;
+        xa.wpt = 1;  // the launcher chooses the waves per tile
         hipError_t e = launch_localmat_xform(B.d.shape, B.d.P, opk, xa, s);
         if (e != hipSuccess) return dev_fail(e, "local-matrix transform launch");
         continue;

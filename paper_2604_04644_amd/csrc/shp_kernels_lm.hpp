@@ -289,13 +289,15 @@ __global__ void __launch_bounds__(256) k_localmat_affine(AffineMatArgs a) {
 
 struct LocalXformArgs {
   const double* bcat;  // [4 Q3p][Kp]
-  const double* dmat;  // [3][Q3p][Q3p] (PhysDeriv)
+  const double* dmat;  // [3][Q3p][Q3p] (PhysDeriv), each D_d transposed: [in][out]
+  const double* bt;    // [Kp][Q3p] B transposed (BwdTrans)
   const double* fac;   // [n][NFAC][Q3]
   const double* dxi;   // [n][NDXI][Q3]
   const double* in;
   double* out;
   long long n_elem;
   long long in_cs, out_cs;  // component strides of vector fields at the points
+  int wpt;                  // waves per tile (BwdTrans, PhysDeriv: they share the point row blocks)
 };
 
 template <int SH, int P, int OP>
@@ -307,13 +309,17 @@ __global__ void __launch_bounds__(256) k_localmat_xform(LocalXformArgs a) {
   constexpr int MB = Kp / 16, QB = Q3p / 16;
   const int lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
-  const long long e0 = ((long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16;
+  // a tile's point row blocks qb = w0, w0 + wpt, ... go to its wpt waves
+  const long long gw = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const long long e0 = gw / a.wpt * 16;
+  const int w0 = (int)(gw % a.wpt);
   if (e0 >= a.n_elem) return;  // whole waves only
   const long long e = e0 + col;
   const bool live = e < a.n_elem;
   const long long ec = live ? e : e0;
   const gptr_t Bc = as_global(a.bcat);
   if constexpr (OP == OPK_BWD) {
+    const gptr_t Bt = as_global(a.bt);
     // the tile's coefficients in registers: xr[kb] = x_e[4 kb + kq]
     constexpr int KS = Kp / 4;
     double xr[KS];
@@ -323,11 +329,11 @@ __global__ void __launch_bounds__(256) k_localmat_xform(LocalXformArgs a) {
       const double v = a.in[ec * NP + (n < NP ? n : NP - 1)];
       xr[kb] = (live && n < NP) ? v : 0.0;
     }
-    for (int qb = 0; qb < QB; ++qb) {
+    for (int qb = w0; qb < QB; qb += a.wpt) {
       dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
       double av[KS];
 #pragma unroll
-      for (int kb = 0; kb < KS; ++kb) av[kb] = Bc[(long long)(qb * 16 + col) * Kp + 4 * kb + kq];
+      for (int kb = 0; kb < KS; ++kb) av[kb] = Bt[(long long)(4 * kb + kq) * Q3p + qb * 16 + col];
 #pragma unroll
       for (int kb = 0; kb < KS; ++kb) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kb], xr[kb], acc, 0, 0, 0);
       if (live)
@@ -386,7 +392,7 @@ __global__ void __launch_bounds__(256) k_localmat_xform(LocalXformArgs a) {
     static_assert(OP == OPK_DERIV, "local-matrix transform");
     const gptr_t Dm = as_global(a.dmat);
     const double* dxi = a.dxi + ec * (long long)(NDXI * Q3);
-    for (int qb = 0; qb < QB; ++qb) {
+    for (int qb = w0; qb < QB; qb += a.wpt) {
       dbl4 acc[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) acc[d] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -396,7 +402,7 @@ __global__ void __launch_bounds__(256) k_localmat_xform(LocalXformArgs a) {
         const double ub = (live && pin < Q3) ? u : 0.0;
         double av[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) av[d] = Dm[((long long)d * Q3p + qb * 16 + col) * Q3p + 4 * kb + kq];
+        for (int d = 0; d < 3; ++d) av[d] = Dm[((long long)d * Q3p + 4 * kb + kq) * Q3p + qb * 16 + col];
 #pragma unroll
         for (int d = 0; d < 3; ++d) acc[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d], ub, acc[d], 0, 0, 0);
       }
