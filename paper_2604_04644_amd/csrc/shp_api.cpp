@@ -59,7 +59,7 @@ struct Block {
   std::vector<double> lm;  // [B; d_d B] for the local-matrix strategy (P <= 4)
   std::vector<double> dm;  // dense collocation derivatives, each transposed: [3][Q3p in][Q3p out] (local-matrix PhysDeriv)
   size_t off_dm = 0;
-  std::vector<double> bt;  // B transposed, [Kp][Q3p] (local-matrix BwdTrans)
+  std::vector<double> bt;  // [B; d_d B] transposed, [Kp][4 Q3p] (local-matrix U = B X products)
   size_t off_bt = 0;
   std::vector<double> am;  // affine blocks: 7 reference matrices, MFMA fragment order
   size_t off_am = 0, off_coef = 0;
@@ -368,11 +368,12 @@ int shp_plan_create(shp_plan* out, const shp_block_desc* blk, int nblk) {
       int q3p, kp;
       build_localmat(B.d.shape, B.d.P, B.d.pts, B.lm, q3p, kp);
       build_dense_deriv(B.d.shape, B.d.P, B.d.pts, B.dm, q3p);
-      // the BwdTrans and PhysDeriv kernels read their matrices with the
-      // output point fastest across lanes: store B and each D_d transposed
-      B.bt.assign((size_t)kp * q3p, 0.0);
-      for (int pt = 0; pt < q3p; ++pt)
-        for (int m = 0; m < kp; ++m) B.bt[(size_t)m * q3p + pt] = B.lm[(size_t)pt * kp + m];
+      // the products U = B X (BwdTrans, the curved local matrices) and
+      // PhysDeriv read their matrices with the output point fastest across
+      // lanes: store [B; d_d B] and each D_d transposed as well
+      B.bt.assign((size_t)kp * 4 * q3p, 0.0);
+      for (int r = 0; r < 4 * q3p; ++r)
+        for (int m = 0; m < kp; ++m) B.bt[(size_t)m * 4 * q3p + r] = B.lm[(size_t)r * kp + m];
       for (int d = 0; d < 3; ++d) {
         double* D = B.dm.data() + (size_t)d * q3p * q3p;
         for (int i = 0; i < q3p; ++i)
@@ -1053,6 +1054,7 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
       }
       LocalMatArgs la;
       la.bcat = reinterpret_cast<const double*>(p->ws + B.off_lm);
+      la.bt = reinterpret_cast<const double*>(p->ws + B.off_bt);
       la.fac = reinterpret_cast<const double*>(p->ws + B.off_fac);
       la.in = in + (blk >= 0 ? 0 : B.coeff_off);
       la.out = out + (blk >= 0 ? 0 : B.coeff_off);

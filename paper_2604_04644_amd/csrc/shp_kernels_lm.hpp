@@ -25,6 +25,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 struct LocalMatArgs {
   const double* bcat;  // [4*Q3p][Kp]
+  const double* bt;    // the same transposed, [Kp][4*Q3p]
   const double* fac;   // [n][NFAC][Q3]
   const double* in;    // [n][NP]
   double* out;         // [n][NP]
@@ -52,6 +53,7 @@ __device__ void localmat_tile(const LocalMatArgs& a, long long e0, int ne, doubl
   }
   __syncthreads();
   const gptr_t B = as_global(a.bcat);
+  const gptr_t Bt = as_global(a.bt);
   const gptr_t G = as_global(a.fac) + e0 * (long long)(NFAC * Q3);
   const bool live = col < ne;
   dbl4 y[MB];
@@ -61,12 +63,13 @@ __device__ void localmat_tile(const LocalMatArgs& a, long long e0, int ne, doubl
     dbl4 u[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) u[d] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // U_d = Bcat_d[qb] X (a step's fragments loaded together)
+    // U_d = Bcat_d[qb] X (a step's fragments loaded together, from the
+    // transposed copy: the point index runs across lanes)
     for (int kb = 0; kb < Kp / 4; ++kb) {
       const double b = X[(4 * kb + kq) * 16 + col];
       double av[ND];
 #pragma unroll
-      for (int d = 0; d < ND; ++d) av[d] = B[(long long)(d * Q3p + qb * 16 + col) * Kp + 4 * kb + kq];
+      for (int d = 0; d < ND; ++d) av[d] = Bt[(long long)(4 * kb + kq) * (4 * Q3p) + d * Q3p + qb * 16 + col];
 #pragma unroll
       for (int d = 0; d < ND; ++d) u[d] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d], b, u[d], 0, 0, 0);
     }
@@ -290,7 +293,7 @@ __global__ void __launch_bounds__(256) k_localmat_affine(AffineMatArgs a) {
 struct LocalXformArgs {
   const double* bcat;  // [4 Q3p][Kp]
   const double* dmat;  // [3][Q3p][Q3p] (PhysDeriv), each D_d transposed: [in][out]
-  const double* bt;    // [Kp][Q3p] B transposed (BwdTrans)
+  const double* bt;    // [Kp][4 Q3p] Bcat transposed (BwdTrans reads its B part)
   const double* fac;   // [n][NFAC][Q3]
   const double* dxi;   // [n][NDXI][Q3]
   const double* in;
@@ -333,7 +336,7 @@ __global__ void __launch_bounds__(256) k_localmat_xform(LocalXformArgs a) {
       dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
       double av[KS];
 #pragma unroll
-      for (int kb = 0; kb < KS; ++kb) av[kb] = Bt[(long long)(4 * kb + kq) * Q3p + qb * 16 + col];
+      for (int kb = 0; kb < KS; ++kb) av[kb] = Bt[(long long)(4 * kb + kq) * (4 * Q3p) + qb * 16 + col];
 #pragma unroll
       for (int kb = 0; kb < KS; ++kb) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kb], xr[kb], acc, 0, 0, 0);
       if (live)
