@@ -132,6 +132,39 @@ def test_localmat_vs_oracle(shp, shape, P, curved):
         assert e <= TOL, (shape, P, op, e)
 
 
+@pytest.mark.parametrize("shape", ["hex", "tet"])
+def test_localmat_transforms_large_block(shp, shape):
+    """The local-matrix transforms on a curved P = 4 block of 65549 elements
+    (4097 tiles, a ragged last one): there BwdTrans and PhysDeriv take one
+    wave per tile, the launch form that smaller blocks split among up to 8
+    waves.  Every transform against the oracle on sampled elements (the
+    first 40, the last 21, 24 random ones)."""
+    ne, P = 65549, 4
+    say(f"[parity] local-matrix transforms, large block shape={shape} P={P} n_elem={ne}")
+    maps = W.shape_batch(shape, ne)
+    NP, NQ = O.num_modes(shape, P), (P + 2) ** 3
+    plan = shp.Plan([(shape, P, ne, "curved")])
+    plan.set_geometry(0, gpu_geometry(shp, maps, shape, P, True))
+    rng = np.random.default_rng(705)
+    idx = np.unique(np.concatenate([np.arange(40), np.arange(ne - 21, ne), rng.integers(0, ne, 24)]))
+    jo = oracle_geometry(maps.take(idx), shape, P, True)
+    for k, op in enumerate(("bwd", "iprod", "physderiv", "iprod_deriv")):
+        x = op_input(op, ne, NP, NQ, 700 + k)
+        y = plan.apply(0, op, torch.from_numpy(np.ascontiguousarray(x)).cuda(), strategy="localmat").cpu().numpy()
+        if op == "iprod_deriv":
+            ref = O.apply_op(op, shape, P, P + 2, jo, x[:, idx])
+            got = y.reshape(ne, NP)[idx]
+        elif op == "physderiv":
+            ref = O.apply_op(op, shape, P, P + 2, jo, x[idx])
+            got = y.reshape(3, ne, NQ)[:, idx]
+        else:
+            ref = O.apply_op(op, shape, P, P + 2, jo, x[idx])
+            got = y.reshape(ne, -1)[idx]
+        e = rel(got, ref)
+        say(f"    {op:12s} rel={e:.2e}")
+        assert e <= TOL, (shape, op, e)
+
+
 def test_localmat_whole_mesh_and_limits(shp):
     say("[parity] local matrix whole mesh and limits")
     mesh, plan = _mixed_plan(shp, 4, 2)
