@@ -389,18 +389,20 @@ def bf16_leg(torch, shp, W, flush, ncell: int = 32, P: int = 4, lam: float = 1.0
             row[inner] = st
             sols[inner] = xs
             log(f"  solve tol={tol:g} {inner}: {st}")
-        # the FP64 solve with the local matrices as the plan's whole-mesh choice
+        # the FP64 and FP32-inner solves with the local matrices as the plan's
+        # whole-mesh choice
         plan.set_auto_strategy(-1, "helmholtz", "localmat")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        xs, st = plan.solve(b, lam=lam, tol=tol, check=False, inner="fp64", max_outer=100, max_inner=30000)
-        torch.cuda.synchronize()
-        st["s"] = round(time.perf_counter() - t0, 4)
+        for inner in ("fp64", "fp32"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xs, st = plan.solve(b, lam=lam, tol=tol, check=False, inner=inner, max_outer=100, max_inner=30000)
+            torch.cuda.synchronize()
+            st["s"] = round(time.perf_counter() - t0, 4)
+            row[f"{inner}_localmat"] = st
+            sols[f"{inner}_localmat"] = xs
+            log(f"  solve tol={tol:g} {inner} with local matrices: {st}")
         plan.set_auto_strategy(-1, "helmholtz", "sumfac_coll")
-        row["fp64_localmat"] = st
-        sols["fp64_localmat"] = xs
-        log(f"  solve tol={tol:g} fp64 with local matrices: {st}")
-        for inner in ("fp32", "bf16", "bf16x3", "fp64_localmat"):
+        for inner in ("fp32", "bf16", "bf16x3", "fp64_localmat", "fp32_localmat"):
             row[f"speedup_{inner}"] = round(row["fp64"]["s"] / row[inner]["s"], 3)
             row[f"{inner}_vs_fp64_rel2"] = float((sols[inner] - sols["fp64"]).norm() / sols["fp64"].norm())
         row["resid_tol"] = tol

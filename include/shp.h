@@ -223,7 +223,10 @@ typedef enum { SHP_FP64 = 0, SHP_FP32 = 1, SHP_BF16 = 2, SHP_BF16X3 = 3 } shp_pr
 /* shp_apply with a contraction precision: in/out are device arrays of doubles
  * (SHP_FP64) or floats (the others) in the same layouts.  SHP_FP32 with
  * strategy SHP_AUTO or SHP_SUMFAC_COLL covers the collocated Laplacian and
- * Helmholtz actions as a whole-mesh launch (blk = -1, one P for all blocks).
+ * Helmholtz actions as a whole-mesh launch (blk = -1, one P for all blocks);
+ * with SHP_AUTO and blk = -1 it takes the FP32 local matrices below instead
+ * when the plan's whole-mesh choice for the operator is SHP_LOCALMAT and
+ * every block is affine with P <= 4.
  * SHP_BF16 and SHP_BF16X3 (strategy SHP_AUTO or SHP_LOCALMAT), and SHP_FP32
  * with strategy SHP_LOCALMAT (on v_mfma_f32_16x16x4f32, the matrices rounded to
  * FP32), cover the mass, Laplacian and Helmholtz actions of affine 3D blocks
@@ -297,7 +300,7 @@ int shp_helmholtz_diag(shp_plan plan, double lambda, double* diag /* device out 
 
 /* Mixed-precision solve: a Jacobi-preconditioned conjugate-gradient iteration
  * whose operator actions, vectors and updates run in inner_prec (SHP_FP64;
- * SHP_FP32 through shp_apply_prec's collocated action; SHP_BF16 or SHP_BF16X3
+ * SHP_FP32 through shp_apply_prec's SHP_AUTO action; SHP_BF16 or SHP_BF16X3
  * through its split-BF16 affine local matrices, FP32 vectors) with FP64 dot
  * products, refined in FP64
  * by reliable updates: whenever the recursive residual has fallen by the factor

@@ -1205,6 +1205,13 @@ int shp_apply_prec(shp_plan p, int blk, int op, int strategy, int prec, const vo
   if (prec == SHP_BF16 || prec == SHP_BF16X3) return apply_bf16(p, blk, op, strategy, prec, in, out, lambda, stream);
   if (prec != SHP_FP32) return fail(SHP_ERR_INVALID_ARG, "bad precision %d", prec);
   if (strategy == SHP_LOCALMAT) return apply_bf16(p, blk, op, strategy, prec, in, out, lambda, stream);
+  if (strategy == SHP_AUTO && blk == -1 && op >= 0 && op <= SHP_OP_HELMHOLTZ && p->auto_mixed[op] == SHP_LOCALMAT) {
+    // the plan's whole-mesh choice is the local matrices: FP32 on the matrix
+    // cores when every block has them (affine, P <= 4)
+    bool all = !p->blocks.empty();
+    for (const auto& B : p->blocks) all = all && !B.am32.empty();
+    if (all) return apply_bf16(p, blk, op, SHP_LOCALMAT, prec, in, out, lambda, stream);
+  }
   if (op != SHP_OP_HELMHOLTZ && op != SHP_OP_LAPLACIAN)
     return fail(SHP_ERR_UNSUPPORTED, "FP32 contractions cover the Laplacian and Helmholtz actions");
   if (strategy != SHP_AUTO && strategy != SHP_SUMFAC_COLL)

@@ -258,7 +258,7 @@ int apply_inner(shp_plan plan, const T* in, T* out, double lambda, int prec, hip
   if constexpr (sizeof(T) == sizeof(float)) {
     if (prec == SHP_BF16 || prec == SHP_BF16X3)
       return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_LOCALMAT, prec, in, out, lambda, s);
-    return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_SUMFAC_COLL, SHP_FP32, in, out, lambda, s);
+    return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_AUTO, SHP_FP32, in, out, lambda, s);
   } else {
     return shp_apply_prec(plan, -1, SHP_OP_HELMHOLTZ, SHP_AUTO, SHP_FP64, in, out, lambda, s);
   }
@@ -267,7 +267,9 @@ int apply_inner(shp_plan plan, const T* in, T* out, double lambda, int prec, hip
 // The operators of the solve: the FP64 action apply64 and the action in the
 // inner type.  The FP64 actions take the plan's SHP_AUTO choice for the whole
 // mesh (tuned or set, or a loaded cost model's; by default the collocated
-// sum-factorisation), e.g. the local matrices of an affine mesh.  ElemOp is the block-diagonal elemental H; C0Op the assembled
+// sum-factorisation), e.g. the local matrices of an affine mesh; the FP32
+// inner actions take the FP32 local matrices when that choice is the local
+// matrices and every block has them, else the FP32 sum-factorisation.  ElemOp is the block-diagonal elemental H; C0Op the assembled
 // operator A^T H A of a local-to-global map A (gather, elemental action,
 // scatter-sum).
 struct ElemOp {

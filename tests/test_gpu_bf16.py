@@ -261,22 +261,22 @@ def affine_problem(shp):
     return mesh, plan, np.concatenate([b[s].ravel() for s in O.SHAPES]), xref
 
 
-@pytest.mark.parametrize("inner", ["bf16", "bf16x3", "fp32", "fp64-localmat"])
+@pytest.mark.parametrize("inner", ["bf16", "bf16x3", "fp32", "fp64-localmat", "fp32-localmat"])
 @pytest.mark.parametrize("target", [1e-6, 1e-10])
 def test_bf16_solve_vs_oracle(shp, affine_problem, inner, target):
     """Jacobi-PCG with split-BF16 inner actions and FP64 reliable updates on
     the affine mesh reaches both error targets against the oracle's solution
     (max over elements of ||x_e - x*_e|| / ||x*_e||); the FP32
     sum-factorisation inner actions on the same problem for comparison; and
-    the FP64 PCG whose actions take the local matrices as the plan's
-    whole-mesh choice."""
+    the FP64 PCG and the FP32-inner PCG whose actions take the local matrices
+    as the plan's whole-mesh choice."""
     mesh, plan, b, xref = affine_problem
     say(f"[bf16] solve inner={inner} target={target:g}")
-    lm = inner == "fp64-localmat"
+    lm = inner.endswith("-localmat")
     if lm:
         plan.set_auto_strategy(-1, "helmholtz", "localmat")
     try:
-        x, st = plan.solve(torch.from_numpy(b).cuda(), lam=1.0, inner="fp64" if lm else inner, tol=RESID_TOL[target],
+        x, st = plan.solve(torch.from_numpy(b).cuda(), lam=1.0, inner=inner.split("-")[0], tol=RESID_TOL[target],
                            max_outer=80, max_inner=20000)
     finally:
         if lm:
