@@ -49,19 +49,25 @@ struct AffineBf16Args {
 // several waves (a block of a few thousand elements still fills the chip)
 // while a K step's MFMA work (MBW x 3 or 6) keeps up with forming its split B
 // operand (about 70 VALU instructions per step); the rows shared evenly
-// among the tile's waves
+// among the tile's waves.  Measured exception: the prism at P = 4 (5 row
+// blocks) keeps them in one wave, as a 3 + 2 split ran up to 1.6x slower.
 template <int SH, int P>
 constexpr int bf16_mbw() {
   constexpr int MB = (num_modes(SH, P) + 15) / 16;
   constexpr int NW = (MB + 3) / 4;
-  return (MB + NW - 1) / NW;
+  return (SH == PRISM && P == 4) ? MB : (MB + NW - 1) / NW;
 }
 
-// tiles of 16 elements per wave: each A fragment a wave loads serves
-// BF16_G tiles' MFMAs
-constexpr int BF16_G = 2;
+// tiles of 16 elements per wave: each A fragment a wave loads serves G
+// tiles' MFMAs; 2, and 4 for the prism and the tetrahedron at P = 4 (their
+// waves then form 4 tiles' split operands per A fragment; measured 1.2-1.6x
+// faster on both the mixed mesh's blocks and 4M-DOF blocks)
+template <int SH, int P>
+constexpr int bf16_g() {
+  return ((SH == PRISM || SH == TET) && P == 4) ? 4 : 2;
+}
 
-// waves of a block of ntile 16-element tiles: (MB / MBW) per group of BF16_G
+// waves of a block of ntile 16-element tiles: (MB / MBW) per group of G
 template <int SH, int P>
 constexpr int bf16_waves_per_tile() {
   constexpr int MB = (num_modes(SH, P) + 15) / 16;
@@ -70,18 +76,16 @@ constexpr int bf16_waves_per_tile() {
 
 template <int SH, int P>
 constexpr long long bf16_waves(long long ntile) {
-  return (ntile + BF16_G - 1) / BF16_G * bf16_waves_per_tile<SH, P>();
+  return (ntile + bf16_g<SH, P>() - 1) / bf16_g<SH, P>() * bf16_waves_per_tile<SH, P>();
 }
 
 // wave w of one block
-template <int SH, int P, int OP, int NPART>
+template <int SH, int P, int OP, int NPART, int MBW = bf16_mbw<SH, P>(), int G = bf16_g<SH, P>()>
 __device__ __forceinline__ void bf16_wave(const AffineBf16Args& a, long long w) {
   constexpr int NP = num_modes(SH, P);
   constexpr int NPp = (NP + 7) / 8 * 8;
   constexpr int MB = (NP + 15) / 16;
-  constexpr int MBW = bf16_mbw<SH, P>();
-  constexpr int NMW = bf16_waves_per_tile<SH, P>();
-  constexpr int G = BF16_G;
+  constexpr int NMW = (MB + MBW - 1) / MBW;  // waves per tile
   constexpr int K0 = (OP == OPK_LAP) ? NPp : 0;           // the Laplacian has no mass term
   constexpr int K1 = (OP == OPK_MASS) ? NPp : NAFF * NPp;  // the mass has only A_0
   constexpr int KB0 = K0 / 32, KB1 = (K1 + 31) / 32;
