@@ -326,7 +326,9 @@ class Plan:
     def apply_prec(self, op: str, x, out=None, lam: float = 1.0, prec: str = "fp32", blk: int = -1,
                    strategy: str | None = None):
         """The action of op with contractions in prec: "fp32" (whole-mesh
-        collocated Laplacian/Helmholtz), "bf16" / "bf16x3" (split-BF16 affine
+        collocated Laplacian/Helmholtz; with strategy "localmat" the affine
+        local matrices on the FP32 matrix cores; with "auto" those when they
+        are the plan's whole-mesh choice), "bf16" / "bf16x3" (split-BF16 affine
         local matrices: mass, Laplacian, Helmholtz of block blk or, blk = -1,
         every block) or "fp64"; x and out are float32 device tensors (float64
         for fp64)."""

@@ -261,6 +261,26 @@ def affine_problem(shp):
     return mesh, plan, np.concatenate([b[s].ravel() for s in O.SHAPES]), xref
 
 
+def test_fp32_auto_follows_plan_choice(shp, affine_problem):
+    """The FP32 whole-mesh action with SHP_AUTO is the FP32 sum-factorisation
+    by default and the FP32 local matrices once they are the plan's
+    whole-mesh choice, bit for bit (what the FP32-inner solves call)."""
+    mesh, plan, b, xref = affine_problem
+    nc, _ = plan.totals()
+    x = torch.from_numpy(W.coeffs(1, nc, 950)[0].astype(np.float32)).cuda()
+    y_sf = plan.apply_prec("helmholtz", x, lam=LAM, prec="fp32", strategy="sumfac_coll").cpu().numpy()
+    y_lm = plan.apply_prec("helmholtz", x, lam=LAM, prec="fp32", strategy="localmat").cpu().numpy()
+    y_auto = plan.apply_prec("helmholtz", x, lam=LAM, prec="fp32", strategy="auto").cpu().numpy()
+    assert np.array_equal(y_auto, y_sf)
+    plan.set_auto_strategy(-1, "helmholtz", "localmat")
+    try:
+        y_auto = plan.apply_prec("helmholtz", x, lam=LAM, prec="fp32", strategy="auto").cpu().numpy()
+    finally:
+        plan.set_auto_strategy(-1, "helmholtz", "sumfac_coll")
+    assert np.array_equal(y_auto, y_lm)
+    assert not np.array_equal(y_lm, y_sf)
+
+
 @pytest.mark.parametrize("inner", ["bf16", "bf16x3", "fp32", "fp64-localmat", "fp32-localmat"])
 @pytest.mark.parametrize("target", [1e-6, 1e-10])
 def test_bf16_solve_vs_oracle(shp, affine_problem, inner, target):
