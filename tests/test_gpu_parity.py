@@ -135,10 +135,10 @@ def test_localmat_vs_oracle(shp, shape, P, curved):
 @pytest.mark.parametrize("shape", ["hex", "tet"])
 def test_localmat_transforms_large_block(shp, shape):
     """The local-matrix transforms on a curved P = 4 block of 65549 elements
-    (4097 tiles, a ragged last one): there BwdTrans and PhysDeriv take one
-    wave per tile, the launch form that smaller blocks split among up to 8
-    waves.  Every transform against the oracle on sampled elements (the
-    first 40, the last 21, 24 random ones)."""
+    (4097 tiles, a ragged last one): there BwdTrans takes one wave per tile,
+    the launch form that smaller blocks split among up to 8 waves.  Every
+    transform against the oracle on sampled elements (the first 40, the last
+    21, 24 random ones)."""
     ne, P = 65549, 4
     say(f"[parity] local-matrix transforms, large block shape={shape} P={P} n_elem={ne}")
     maps = W.shape_batch(shape, ne)
