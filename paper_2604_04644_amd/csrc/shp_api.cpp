@@ -1019,6 +1019,29 @@ int shp_apply(shp_plan p, int blk, int op, int strategy, const double* in, doubl
       if (B.d.P > LOCALMAT_MAX_P) return fail(SHP_ERR_UNSUPPORTED, "local-matrix strategy needs P <= %d", LOCALMAT_MAX_P);
       if (needs_geom && !B.geom_ok) return fail(SHP_ERR_STATE, "block %d: geometry not set", b);
     }
+    if (blk < 0 && !is_xform_lm(opk) && p->uniform_P && b1 - b0 >= 1 && b1 - b0 <= 8) {
+      // every block affine: one launch over all of them
+      bool all = true;
+      for (int b = b0; b < b1; ++b) all = all && !p->blocks[b].am.empty();
+      if (all) {
+        AffineMatArgs arr[8];
+        int shp_of[8];
+        for (int b = b0; b < b1; ++b) {
+          const Block& B = p->blocks[b];
+          AffineMatArgs& aa = arr[b - b0];
+          aa.afrag = reinterpret_cast<const double*>(p->ws + B.off_am);
+          aa.coef = reinterpret_cast<const double*>(p->ws + B.off_coef);
+          aa.in = in + B.coeff_off;
+          aa.out = out + B.coeff_off;
+          aa.n_elem = B.d.n_elem;
+          aa.lambda = lambda;
+          shp_of[b - b0] = B.d.shape;
+        }
+        hipError_t e = launch_localmat_affine_mesh(p->blocks[b0].d.P, opk, b1 - b0, shp_of, arr, s);
+        if (e != hipSuccess) return dev_fail(e, "affine local-matrix mesh launch");
+        return SHP_OK;
+      }
+    }
     for (int b = b0; b < b1; ++b) {
       const Block& B = p->blocks[b];
       if (is_xform_lm(opk)) {

@@ -199,17 +199,17 @@ struct AffineMatArgs {
   double lambda;
 };
 
-template <int SH, int P, int OP, int G = lm_tiles_per_wave<SH, P>(), int MBW = lm_rows_per_wave<SH, P>()>
-__global__ void __launch_bounds__(256) k_localmat_affine(AffineMatArgs a) {
+// wave gw of one affine block
+template <int SH, int P, int OP, int G, int MBW>
+__device__ __forceinline__ void lma_wave(const AffineMatArgs& a, long long gw) {
   constexpr int NP = num_modes(SH, P);
   constexpr int MB = lm_row_blocks<SH, P>();
   static_assert(MB % MBW == 0, "a tile's row blocks split evenly among its waves");
   constexpr int W = MB / MBW;
   constexpr int K0 = (OP == OPK_LAP) ? 1 : 0;     // the Laplacian has no mass term
   constexpr int K1 = (OP == OPK_MASS) ? 1 : NAFF;  // the mass has only A_0
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
-  const long long gw = (long long)blockIdx.x * (blockDim.x >> 6) + wave;
   const long long e0 = gw / W * (16 * G);  // the wave's first element
   const int mb0 = (int)(gw % W) * MBW;     // and first row block
   if (e0 >= a.n_elem) return;  // whole waves only: no barriers below
@@ -270,6 +270,36 @@ __global__ void __launch_bounds__(256) k_localmat_affine(AffineMatArgs a) {
         const int m = (mb0 + j) * 16 + 4 * i + kq;
         if (live[g] && m < NP) Y[m] = acc[g][j][i];
       }
+  }
+}
+
+template <int SH, int P, int OP, int G = lm_tiles_per_wave<SH, P>(), int MBW = lm_rows_per_wave<SH, P>()>
+__global__ void __launch_bounds__(256) k_localmat_affine(AffineMatArgs a) {
+  lma_wave<SH, P, OP, G, MBW>(a, (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+}
+
+// Every affine block of one order in one launch: block b owns the
+// work-groups from wg0[b] (its waves rounded up to whole work-groups), so
+// the blocks run side by side instead of one launch after another.
+constexpr int AFF_MESH_MAX = 8;
+struct AffineMatMesh {
+  AffineMatArgs blk[AFF_MESH_MAX];
+  long long wg0[AFF_MESH_MAX + 1];
+  int shape[AFF_MESH_MAX];
+  int nblk;
+};
+
+template <int P, int OP>
+__global__ void __launch_bounds__(256) k_localmat_affine_mesh(AffineMatMesh m) {
+  const long long g = blockIdx.x;
+  int b = 0;
+  while (b + 1 < m.nblk && g >= m.wg0[b + 1]) ++b;
+  const long long w = (g - m.wg0[b]) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  switch (m.shape[b]) {
+    case HEX: lma_wave<HEX, P, OP, lm_tiles_per_wave<HEX, P>(), lm_rows_per_wave<HEX, P>()>(m.blk[b], w); break;
+    case PRISM: lma_wave<PRISM, P, OP, lm_tiles_per_wave<PRISM, P>(), lm_rows_per_wave<PRISM, P>()>(m.blk[b], w); break;
+    case PYR: lma_wave<PYR, P, OP, lm_tiles_per_wave<PYR, P>(), lm_rows_per_wave<PYR, P>()>(m.blk[b], w); break;
+    default: lma_wave<TET, P, OP, lm_tiles_per_wave<TET, P>(), lm_rows_per_wave<TET, P>()>(m.blk[b], w); break;
   }
 }
 

@@ -201,6 +201,28 @@ def test_affine_localmat_wide_launch(shp, shape, P):
         assert e <= bar, (shape, P, prec, e)
 
 
+def test_fp64_localmat_mesh_launch_equals_blocks(shp):
+    """The FP64 affine local matrices over the whole mesh (one launch over
+    every block of one order, each with its own tiles per wave) equal the
+    per-block launches bit for bit, for the mass, Laplacian and Helmholtz;
+    block sizes that are not multiples of the tile pair nor of the 4-wave
+    work-group, and small enough that the per-block launches take one tile
+    per wave."""
+    say("[localmat] FP64 affine whole mesh == per block")
+    sizes = (("hex", 4, 37), ("prism", 4, 17), ("pyr", 4, 33), ("tet", 4, 70))
+    blocks = [(s, P, W.shape_batch(s, n)) for s, P, n in sizes]
+    plan = affine_plan(shp, blocks)
+    nc, _ = plan.totals()
+    x = torch.from_numpy(W.coeffs(1, nc, 960)[0]).cuda()
+    for op in ("mass", "laplacian", "helmholtz"):
+        yw = plan.apply(-1, op, x, lam=LAM, strategy="localmat").cpu().numpy()
+        for b in range(len(sizes)):
+            co, _ = plan.offsets(b)
+            n = len(blocks[b][2]) * plan.n_modes[b]
+            yb = plan.apply(b, op, x[co:co + n].contiguous(), lam=LAM, strategy="localmat").cpu().numpy()
+            assert np.array_equal(yw[co:co + n], yb.ravel()), (op, sizes[b])
+
+
 @pytest.mark.parametrize("orders", ["one", "mixed"])
 def test_bf16_whole_mesh_equals_blocks(shp, orders):
     """blk = -1 over affine blocks of every shape equals the per-block launches
