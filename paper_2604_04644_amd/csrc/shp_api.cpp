@@ -1173,6 +1173,25 @@ static int apply_bf16(shp_plan p, int blk, int op, int strategy, int prec, const
   const int nparts = prec == SHP_BF16 ? 3 : 2;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (f32) {
+    if (blk < 0 && p->uniform_P && b1 - b0 >= 1 && b1 - b0 <= 8) {
+      // every block in one launch
+      AffineMatArgs32 arr[8];
+      int shp_of[8];
+      for (int b = b0; b < b1; ++b) {
+        const Block& B = p->blocks[b];
+        AffineMatArgs32& aa = arr[b - b0];
+        aa.afrag = reinterpret_cast<const float*>(p->ws + B.off_am32);
+        aa.coef = reinterpret_cast<const double*>(p->ws + B.off_coef);
+        aa.in = static_cast<const float*>(in) + B.coeff_off;
+        aa.out = static_cast<float*>(out) + B.coeff_off;
+        aa.n_elem = B.d.n_elem;
+        aa.lambda = lambda;
+        shp_of[b - b0] = B.d.shape;
+      }
+      hipError_t e = launch_localmat_affine_f32_mesh(p->blocks[b0].d.P, opk, b1 - b0, shp_of, arr, s);
+      if (e != hipSuccess) return dev_fail(e, "FP32 local-matrix mesh launch");
+      return SHP_OK;
+    }
     for (int b = b0; b < b1; ++b) {
       const Block& B = p->blocks[b];
       const long long off = blk >= 0 ? 0 : B.coeff_off;

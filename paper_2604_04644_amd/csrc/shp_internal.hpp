@@ -92,6 +92,9 @@ hipError_t launch_localmat_affine(int sh, int P, int opk, const AffineMatArgs& a
 // every affine block of one order in one launch (nblk <= 8, blocks' args in order)
 hipError_t launch_localmat_affine_mesh(int P, int opk, int nblk, const int* shape, const AffineMatArgs* blk,
                                        hipStream_t s);
+struct AffineMatArgs32;
+hipError_t launch_localmat_affine_f32_mesh(int P, int opk, int nblk, const int* shape, const AffineMatArgs32* blk,
+                                           hipStream_t s);
 // the affine local-matrix action in FP32 on the FP32 matrix cores: afrag the
 // FP64 fragments rounded to FP32 (same order), FP32 in/out
 hipError_t launch_localmat_affine_f32(int sh, int P, int opk, const float* afrag, const double* coef, const float* in,

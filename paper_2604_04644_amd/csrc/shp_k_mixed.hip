@@ -110,6 +110,52 @@ hipError_t launch_localmat_affine_mesh(int P, int opk, int nblk, const int* shap
   return hipErrorInvalidValue;
 }
 
+template <int P>
+static long long aff32_waves(int sh, long long n) {
+  switch (sh) {
+    case HEX: return lm_waves<HEX, P>(n, lm32_tiles_per_wave<HEX, P>(), lm32_rows_per_wave<HEX, P>());
+    case PRISM: return lm_waves<PRISM, P>(n, lm32_tiles_per_wave<PRISM, P>(), lm32_rows_per_wave<PRISM, P>());
+    case PYR: return lm_waves<PYR, P>(n, lm32_tiles_per_wave<PYR, P>(), lm32_rows_per_wave<PYR, P>());
+    default: return lm_waves<TET, P>(n, lm32_tiles_per_wave<TET, P>(), lm32_rows_per_wave<TET, P>());
+  }
+}
+
+template <int P>
+static hipError_t launch_aff32_mesh_p(int opk, AffineMatMesh32& m, hipStream_t s) {
+  long long g = 0;
+  for (int b = 0; b < m.nblk; ++b) {
+    m.wg0[b] = g;
+    g += (aff32_waves<P>(m.shape[b], m.blk[b].n_elem) + 3) / 4;
+  }
+  m.wg0[m.nblk] = g;
+  if (g <= 0) return hipSuccess;
+  switch (opk) {
+    case OPK_MASS_LM: hipLaunchKernelGGL((k_localmat_affine_f32_mesh<P, OPK_MASS>), dim3((unsigned)g), dim3(256), 0, s, m); break;
+    case OPK_LAP_LM: hipLaunchKernelGGL((k_localmat_affine_f32_mesh<P, OPK_LAP>), dim3((unsigned)g), dim3(256), 0, s, m); break;
+    case OPK_HELM_LM: hipLaunchKernelGGL((k_localmat_affine_f32_mesh<P, OPK_HELM>), dim3((unsigned)g), dim3(256), 0, s, m); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_localmat_affine_f32_mesh(int P, int opk, int nblk, const int* shape, const AffineMatArgs32* blk,
+                                           hipStream_t s) {
+  if (nblk < 1 || nblk > AFF_MESH_MAX) return hipErrorInvalidValue;
+  AffineMatMesh32 m;
+  m.nblk = nblk;
+  for (int b = 0; b < nblk; ++b) {
+    m.blk[b] = blk[b];
+    m.shape[b] = shape[b];
+  }
+  switch (P) {
+    case 1: return launch_aff32_mesh_p<1>(opk, m, s);
+    case 2: return launch_aff32_mesh_p<2>(opk, m, s);
+    case 3: return launch_aff32_mesh_p<3>(opk, m, s);
+    case 4: return launch_aff32_mesh_p<4>(opk, m, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_localmat_affine(int sh, int P, int opk, const AffineMatArgs& a, hipStream_t s) {
   switch (sh) {
     case HEX: return launch_localmat_affine_hex(P, opk, a, s);

@@ -470,17 +470,16 @@ struct AffineMatArgs32 {
   double lambda;
 };
 
-template <int SH, int P, int OP, int G = lm32_tiles_per_wave<SH, P>(), int MBW = lm32_rows_per_wave<SH, P>()>
-__global__ void __launch_bounds__(256) k_localmat_affine_f32(AffineMatArgs32 a) {
+template <int SH, int P, int OP, int G, int MBW>
+__device__ __forceinline__ void lma32_wave(const AffineMatArgs32& a, long long gw) {
   constexpr int NP = num_modes(SH, P);
   constexpr int MB = lm_row_blocks<SH, P>();
   static_assert(MB % MBW == 0, "a tile's row blocks split evenly among its waves");
   constexpr int W = MB / MBW;
   constexpr int K0 = (OP == OPK_LAP) ? 1 : 0;
   constexpr int K1 = (OP == OPK_MASS) ? 1 : NAFF;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
-  const long long gw = (long long)blockIdx.x * (blockDim.x >> 6) + wave;
   const long long e0 = gw / W * (16 * G);
   const int mb0 = (int)(gw % W) * MBW;
   if (e0 >= a.n_elem) return;
@@ -541,6 +540,33 @@ __global__ void __launch_bounds__(256) k_localmat_affine_f32(AffineMatArgs32 a) 
         const int m = (mb0 + j) * 16 + 4 * kq + i;
         if (m < NP) Y[m] = acc[g][j][i];
       }
+  }
+}
+
+template <int SH, int P, int OP, int G = lm32_tiles_per_wave<SH, P>(), int MBW = lm32_rows_per_wave<SH, P>()>
+__global__ void __launch_bounds__(256) k_localmat_affine_f32(AffineMatArgs32 a) {
+  lma32_wave<SH, P, OP, G, MBW>(a, (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+}
+
+// every FP32 affine block of one order in one launch (as the FP64 one)
+struct AffineMatMesh32 {
+  AffineMatArgs32 blk[AFF_MESH_MAX];
+  long long wg0[AFF_MESH_MAX + 1];
+  int shape[AFF_MESH_MAX];
+  int nblk;
+};
+
+template <int P, int OP>
+__global__ void __launch_bounds__(256) k_localmat_affine_f32_mesh(AffineMatMesh32 m) {
+  const long long g = blockIdx.x;
+  int b = 0;
+  while (b + 1 < m.nblk && g >= m.wg0[b + 1]) ++b;
+  const long long w = (g - m.wg0[b]) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  switch (m.shape[b]) {
+    case HEX: lma32_wave<HEX, P, OP, lm32_tiles_per_wave<HEX, P>(), lm32_rows_per_wave<HEX, P>()>(m.blk[b], w); break;
+    case PRISM: lma32_wave<PRISM, P, OP, lm32_tiles_per_wave<PRISM, P>(), lm32_rows_per_wave<PRISM, P>()>(m.blk[b], w); break;
+    case PYR: lma32_wave<PYR, P, OP, lm32_tiles_per_wave<PYR, P>(), lm32_rows_per_wave<PYR, P>()>(m.blk[b], w); break;
+    default: lma32_wave<TET, P, OP, lm32_tiles_per_wave<TET, P>(), lm32_rows_per_wave<TET, P>()>(m.blk[b], w); break;
   }
 }
 

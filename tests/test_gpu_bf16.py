@@ -202,7 +202,7 @@ def test_affine_localmat_wide_launch(shp, shape, P):
 
 
 def test_fp64_localmat_mesh_launch_equals_blocks(shp):
-    """The FP64 affine local matrices over the whole mesh (one launch over
+    """The FP64 and FP32 affine local matrices over the whole mesh (one launch over
     every block of one order, each with its own tiles per wave) equal the
     per-block launches bit for bit, for the mass, Laplacian and Helmholtz;
     block sizes that are not multiples of the tile pair nor of the 4-wave
@@ -214,13 +214,18 @@ def test_fp64_localmat_mesh_launch_equals_blocks(shp):
     plan = affine_plan(shp, blocks)
     nc, _ = plan.totals()
     x = torch.from_numpy(W.coeffs(1, nc, 960)[0]).cuda()
+    x32 = x.float()
     for op in ("mass", "laplacian", "helmholtz"):
         yw = plan.apply(-1, op, x, lam=LAM, strategy="localmat").cpu().numpy()
+        yw32 = plan.apply_prec(op, x32, lam=LAM, prec="fp32", strategy="localmat").cpu().numpy()
         for b in range(len(sizes)):
             co, _ = plan.offsets(b)
             n = len(blocks[b][2]) * plan.n_modes[b]
             yb = plan.apply(b, op, x[co:co + n].contiguous(), lam=LAM, strategy="localmat").cpu().numpy()
             assert np.array_equal(yw[co:co + n], yb.ravel()), (op, sizes[b])
+            yb32 = plan.apply_prec(op, x32[co:co + n].contiguous(), lam=LAM, prec="fp32", blk=b,
+                                   strategy="localmat").cpu().numpy()
+            assert np.array_equal(yw32[co:co + n], yb32.ravel()), ("fp32", op, sizes[b])
 
 
 @pytest.mark.parametrize("orders", ["one", "mixed"])
